@@ -1,0 +1,133 @@
+"""Seeded synthetic inputs for CP decomposition workloads.
+
+This module only draws random numbers and builds planted tensors from factor
+matrices; it holds none of the decomposition's arithmetic.  It is the one
+piece of code that both the GPU path's callers (tests, benchmark) and the CPU
+oracle's callers use, so that both sides see the same inputs.
+
+Recipe (every workload):
+  * SeedSequence(seed).spawn(3) gives three independent streams: planted
+    factors, noise, initial factors.
+  * Planted factors are drawn mode by mode, one (s_n, R) array per mode.
+  * The noiseless tensor T0 = sum_r a^(0)_r o ... o a^(N-1)_r is built in FP64,
+    in row blocks of the first mode.
+  * Noise is iid Gaussian with sigma = rel * ||T0||_F / sqrt(numel), drawn in
+    the same row blocks (one standard_normal call per block, in order), so
+    that ||E||_F is close to rel * ||T0||_F.
+  * The stored tensor is (T0 + sigma * E) cast to the storage dtype.
+  * Initial factors are iid Uniform[0, 1) (the paper's initialization).
+
+Factor distributions:
+  "uniform"   iid Uniform[0, 1)
+  "lognorm"   iid N(0, 1) columns, normalized, scaled by 10**Uniform(-2, 0)
+  "collinear" per factor: g, z_r ~ N(0, I); column r = sqrt(c) g + sqrt(1-c) z_r,
+              then normalized (expected pairwise cosine close to c)
+  "normal"    iid N(0, 1)
+"""
+
+from dataclasses import dataclass
+
+import numpy as np
+
+
+@dataclass
+class Workload:
+    name: str
+    dims: tuple
+    R: int
+    T: np.ndarray          # stored tensor (storage dtype), C order
+    planted: list          # FP64 planted factors
+    init: list             # FP64 initial factors
+    sigma: float
+    norm_T0: float
+
+
+def _factors(rng, dims, R, kind, collinearity=0.9):
+    out = []
+    for s in dims:
+        if kind == "uniform":
+            A = rng.random((s, R))
+        elif kind == "normal":
+            A = rng.standard_normal((s, R))
+        elif kind == "lognorm":
+            A = rng.standard_normal((s, R))
+            A /= np.linalg.norm(A, axis=0, keepdims=True)
+            A *= 10.0 ** rng.uniform(-2.0, 0.0, size=R)[None, :]
+        elif kind == "collinear":
+            g = rng.standard_normal(s)
+            Z = rng.standard_normal((s, R))
+            A = np.sqrt(collinearity) * g[:, None] + np.sqrt(1.0 - collinearity) * Z
+            A /= np.linalg.norm(A, axis=0, keepdims=True)
+        else:
+            raise ValueError(kind)
+        out.append(A)
+    return out
+
+
+def _outer_rows(factors, rows):
+    """Rows `rows` of the first mode of the planted tensor, FP64, flattened."""
+    K = factors[1]
+    for F in factors[2:]:
+        K = (K[:, None, :] * F[None, :, :]).reshape(K.shape[0] * F.shape[0], K.shape[1])
+    return factors[0][rows] @ K.T
+
+
+def planted_tensor(dims, R, seed, kind="uniform", noise_rel=1e-2, dtype=np.float32,
+                   collinearity=0.9, block_elems=1 << 24, name="custom"):
+    dims = tuple(int(d) for d in dims)
+    rng_p, rng_e, rng_i = [np.random.default_rng(s) for s in np.random.SeedSequence(seed).spawn(3)]
+    planted = _factors(rng_p, dims, R, kind, collinearity)
+    init = [rng_i.random((s, R)) for s in dims]
+    rest = int(np.prod(dims[1:], dtype=np.int64))
+    K = planted[1]
+    for F in planted[2:]:
+        K = (K[:, None, :] * F[None, :, :]).reshape(K.shape[0] * F.shape[0], K.shape[1])
+    KT = np.ascontiguousarray(K.T)
+    rows_per_block = max(1, block_elems // rest)
+    T0 = np.empty((dims[0], rest), dtype=np.float64)
+    nrm2 = 0.0
+    for r0 in range(0, dims[0], rows_per_block):
+        blk = planted[0][r0:r0 + rows_per_block] @ KT
+        T0[r0:r0 + rows_per_block] = blk
+        nrm2 += float(np.sum(blk * blk))
+    del K, KT
+    norm_T0 = float(np.sqrt(nrm2))
+    numel = dims[0] * rest
+    sigma = noise_rel * norm_T0 / np.sqrt(numel) if noise_rel > 0 else 0.0
+    out = np.empty((dims[0], rest), dtype=dtype)
+    for r0 in range(0, dims[0], rows_per_block):
+        blk = T0[r0:r0 + rows_per_block]
+        if sigma > 0:
+            blk = blk + sigma * rng_e.standard_normal(blk.shape)
+        out[r0:r0 + rows_per_block] = blk.astype(dtype)
+    del T0
+    return Workload(name=name, dims=dims, R=R, T=out.reshape(dims), planted=planted, init=init,
+                    sigma=sigma, norm_T0=norm_T0)
+
+
+# Named workloads.  "small" variants keep each workload's structure (order,
+# factor distribution, noise level, storage precision) at sizes the FP64
+# oracle handles in seconds while still spanning several GPU tiles and a
+# ragged tail.
+WORKLOADS = {
+    # order-3 64^3 FP64, planted rank 16 uniform, noise 1e-3, R = 16
+    "o3_s64_r16_f64": dict(dims=(64, 64, 64), R=16, seed=1001, kind="uniform", noise_rel=1e-3,
+                           dtype=np.float64),
+    # order-4 128^4 FP32, planted rank 64 uniform, noise 1e-2, R = 64
+    "o4_s128_r64_f32": dict(dims=(128, 128, 128, 128), R=64, seed=2001, kind="uniform",
+                            noise_rel=1e-2, dtype=np.float32),
+    # order-6 24^6 FP32, planted rank 32 collinear (0.9), noise 1e-2, R = 32
+    "o6_s24_r32_f32_col": dict(dims=(24,) * 6, R=32, seed=4001, kind="collinear", noise_rel=1e-2,
+                               dtype=np.float32),
+    # reduced shapes of the same families
+    "o4_small_f32": dict(dims=(40, 37, 33, 29), R=20, seed=2002, kind="uniform", noise_rel=1e-2,
+                         dtype=np.float32),
+    "o3_small_f64": dict(dims=(37, 45, 29), R=12, seed=1002, kind="uniform", noise_rel=1e-3,
+                         dtype=np.float64),
+}
+
+
+def workload(name, **over):
+    cfg = dict(WORKLOADS[name])
+    cfg.update(over)
+    return planted_tensor(name=name, **cfg)

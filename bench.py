@@ -1,0 +1,325 @@
+#!/usr/bin/env python3
+"""Benchmark of the CP-ALS hot path on one MI355X.
+
+Workload: order-4 dense tensor 128^4 in FP32 (synthetic: planted rank-64
+factors iid Uniform[0,1) plus Gaussian noise at 1% of the norm), CP rank
+R = 64, factors initialised iid Uniform[0,1), all generated from a seed.
+
+One step = one pass of the whole hot path from the same initial factors:
+  DT    3 sweeps with the standard dimension tree (2 first-level TTMs each)
+  MSDT  3 sweeps with the multi-sweep dimension tree (one whole tree: 4 TTMs)
+  PP    PP-ALS on the MSDT plan: 1 regular sweep, PP initialization plus one
+        approximated sweep, then 3 approximated sweeps (a fixed schedule)
+Every sweep runs Gamma / inverse / solve / Gram / residual in FP64 on the
+GPU.  `value` is the step's effective throughput: each sweep is credited the
+flops of one standard-DT sweep of this workload, divided by the step time.
+
+Prints one JSON line on stdout; everything else goes to stderr.
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}  # MI355X dense matrix-core peaks
+PEAK_HBM_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def dt_sweep_flops(dims, R):
+    """Flops of one standard dimension-tree sweep (2 flops per multiply-add):
+    replay the tree's paths with node reuse, charging 2*numel(T)*R for a
+    first-level contraction and 2*numel(X) for a batched TTV out of node X."""
+    N = len(dims)
+
+    def prod(xs):
+        out = 1
+        for x in xs:
+            out *= x
+        return out
+
+    def path(n):
+        lo, hi, out = 0, N - 1, []
+        while lo < hi:
+            mid = lo + (hi - lo + 2) // 2 - 1
+            if n <= mid:
+                out += list(range(hi, mid, -1))
+                hi = mid
+            else:
+                out += list(range(lo, mid + 1))
+                lo = mid + 1
+        return out
+
+    numel = prod(dims)
+    ver = [0] * N
+    cache = {}
+    flops = 0
+    for n in range(N):
+        seq = path(n)
+        sets, kept = [], frozenset(range(N))
+        for m in seq:
+            kept = kept - {m}
+            sets.append(kept)
+
+        def stamp(s):
+            return tuple(ver[c] for c in range(N) if c not in s)
+
+        start = -1
+        for d in range(len(sets) - 2, -1, -1):
+            if cache.get(sets[d]) == stamp(sets[d]):
+                start = d
+                break
+        prev = frozenset(range(N)) if start < 0 else sets[start]
+        for d in range(start + 1, len(sets)):
+            flops += 2 * numel * R if d == 0 else 2 * R * prod(dims[k] for k in prev)
+            prev = sets[d]
+            if d < len(sets) - 1:
+                cache[sets[d]] = stamp(sets[d])
+        ver[n] += 1
+    return flops
+
+
+def kernel_sha():
+    h = hashlib.sha256()
+    with open(os.path.join(ROOT, "paper_2010_12056_amd", "csrc", "kernels.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()
+
+
+def load_traffic(sha):
+    """HBM bytes per first-level-contraction launch from the committed
+    rocprofv3 counter summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "ttm_o4_s128_r64_f32_counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("kernels_sha256") != sha:
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(w, budget_s, dt_flops):
+    """The FP64 oracle (test infrastructure) on the host cores: exact ALS
+    sweeps (naive explicit-KRP MTTKRP) on the same tensor and init, as many
+    as fit in the budget (at least one)."""
+    import numpy as np
+
+    import oracle
+
+    try:
+        from threadpoolctl import threadpool_info
+
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    except Exception:
+        threads = os.cpu_count()
+    T64 = w.T.astype(np.float64)
+    st = oracle.AlsState.start(T64, w.init)
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        oracle.als_sweep(st)
+        n += 1
+        if time.perf_counter() - t0 > budget_s or n >= 8:
+            break
+    dt = time.perf_counter() - t0
+    return {
+        "value": n * dt_flops / dt / 1e12,
+        "unit": "TFLOP/s (DT-equivalent)",
+        "cores": int(threads),
+        "kind": "oracle",
+        "sample": f"{n} exact FP64 ALS sweep(s) of the oracle (explicit-KRP MTTKRP) on the same "
+                  f"128^4 tensor and init, {dt:.2f} s, {dt / n * 1e3:.1f} ms/sweep",
+        "ms_per_sweep": dt / n * 1e3,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="o4_s128_r64_f32")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU; runs on more than one GPU are not part of this build "
+              "(--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2010_12056_amd import cpals, synth
+
+    if not os.path.exists(cpals.LIB_PATH):
+        from paper_2010_12056_amd import build_lib
+
+        build_lib.build()
+    dev = torch.device("cuda:0")
+    t_gen = time.perf_counter()
+    w = synth.workload(args.workload)
+    log(f"[bench] generated {args.workload} dims={w.dims} R={w.R} in {time.perf_counter() - t_gen:.1f}s")
+    prec = "f32" if w.T.dtype == np.float32 else "f64"
+    T = torch.from_numpy(w.T).to(dev)
+    A0 = [torch.from_numpy(a).to(dev) for a in w.init]
+    N = len(w.dims)
+    R = w.R
+    F_dt = dt_sweep_flops(w.dims, R)
+    numel = int(np.prod(w.dims))
+    ttm_flops = 2 * numel * R
+
+    plans = {
+        "dt": cpals.Plan(w.dims, R, prec=prec, tree="dt", device=dev),
+        "msdt": cpals.Plan(w.dims, R, prec=prec, tree="msdt", device=dev),
+    }
+    plans["pp"] = plans["msdt"]
+    for k in ("dt", "msdt"):
+        plans[k].set_tensor(T)
+    A = {k: [a.clone() for a in A0] for k in ("dt", "msdt", "pp")}
+    pp_sched = ["exact", "init", "approx", "approx", "approx"]
+    sweeps = {"dt": 3, "msdt": N - 1, "pp": len(pp_sched)}
+    stream = torch.cuda.current_stream(dev)
+
+    def one_step(ev=None):
+        for k in ("dt", "msdt", "pp"):
+            plan = plans[k]
+            for a, a0 in zip(A[k], A0):
+                a.copy_(a0)
+            plan.reset()
+            if ev is not None:
+                ev[k][0].record(stream)
+            if k == "pp":
+                for kind in pp_sched:
+                    plan.pp_sweep(A[k], mode=kind, info=False)
+            else:
+                for _ in range(sweeps[k]):
+                    plan.als_sweep(A[k], info=False)
+            if ev is not None:
+                ev[k][1].record(stream)
+
+    log("[bench] warmup")
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+    # per-kind timing of single sweeps (reported breakdown, separate from the timed steps)
+    log("[bench] timed region")
+    for k in ("dt", "msdt"):
+        plans[k].profile(True)
+        plans[k].profile_read()
+    evs = [{k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+            for k in ("dt", "msdt", "pp")} for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        one_step(evs[s])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    phase = {}
+    for k in ("dt", "msdt"):
+        for ph, (ms, cnt) in plans[k].profile_read().items():
+            a, b = phase.get(ph, (0.0, 0))
+            phase[ph] = (a + ms, b + cnt)
+        plans[k].profile(False)
+    var_ms = {k: sum(e[k][0].elapsed_time(e[k][1]) for e in evs) / args.steps for k in ("dt", "msdt", "pp")}
+    log(f"[bench] {args.steps} steps, {ms_step:.3f} ms/step; variants {var_ms}")
+
+    # fitness check of the last step's factors against the DT run (same math)
+    infos = {}
+    for k in ("dt", "msdt"):
+        plans[k].reset()
+        for a, a0 in zip(A[k], A0):
+            a.copy_(a0)
+        infos[k] = [plans[k].als_sweep(A[k])["fitness"] for _ in range(3)]
+    log(f"[bench] fitness dt {infos['dt']} msdt {infos['msdt']}")
+
+    # PP: one timed breakdown per sweep kind on the MSDT plan
+    plan = plans["pp"]
+    plan.reset()
+    for a, a0 in zip(A["pp"], A0):
+        a.copy_(a0)
+    kind_ms = {}
+    for kind in pp_sched:
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        plan.pp_sweep(A["pp"], mode=kind, info=False)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        kind_ms.setdefault(kind, []).append(e0.elapsed_time(e1))
+
+    n_sweeps = sum(sweeps.values())
+    value = n_sweeps * F_dt / (ms_step * 1e-3) / 1e12
+    ttm_ms, ttm_n = phase["ttm"]
+    ttm_avg_ms = ttm_ms / max(ttm_n, 1)
+    achieved = ttm_flops / (ttm_avg_ms * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[prec]
+    sha = kernel_sha()
+    traffic = load_traffic(sha)
+    variants = {}
+    for k in ("dt", "msdt", "pp"):
+        per = var_ms[k] / sweeps[k]
+        variants[k] = {"sweeps": sweeps[k], "ms_per_sweep": round(per, 4),
+                       "effective_tflops": round(F_dt / (per * 1e-3) / 1e12, 3)}
+    variants["pp"]["ms_by_kind"] = {k: round(float(np.mean(v)), 4) for k, v in kind_ms.items()}
+    variants["msdt"]["speedup_vs_dt"] = round(variants["dt"]["ms_per_sweep"] / variants["msdt"]["ms_per_sweep"], 3)
+    variants["pp"]["approx_speedup_vs_dt"] = round(
+        variants["dt"]["ms_per_sweep"] / variants["pp"]["ms_by_kind"]["approx"], 3)
+
+    out = {
+        "metric": "ALS sweep ms & effective TFLOP/s, order-4 s=128 R=64: MSDT/PP vs plain DT",
+        "value": round(value, 3),
+        "unit": "TFLOP/s (effective: DT-sweep flops per sweep / time)",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": prec,
+        "data": "synthetic",
+        "config": {"workload": f"order-{N} dense {'x'.join(map(str, w.dims))} {prec.upper()}, planted rank-{R}"
+                               f" uniform factors + 1% noise, CP rank {R}",
+                   "dims": list(w.dims), "rank": R, "sweeps_per_step": n_sweeps,
+                   "dt_sweep_gflop": round(F_dt / 1e9, 3), "parallelism": "1 GPU"},
+        "variants": variants,
+        "phase_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in phase.items()},
+        "fitness_3_sweeps": {"dt": infos["dt"][-1], "msdt": infos["msdt"][-1]},
+        "roofline": {
+            "kernel": "k_ttm (first-level contraction, FP32 MFMA)",
+            "bound": "mfma",
+            "achieved": round(achieved, 3),
+            "peak": peak,
+            "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 4),
+            "traffic": traffic,
+            "avg_launch_ms": round(ttm_avg_ms, 5),
+            "launches": ttm_n,
+            "flops_per_launch": ttm_flops,
+        },
+        "cpu_baseline": None,
+    }
+    for p in (plans["dt"], plans["msdt"]):
+        p.close()
+    del T
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget, F_dt)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

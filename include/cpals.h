@@ -1,0 +1,163 @@
+/*
+ * cpals.h - C ABI of the MI355X (gfx950) CP-ALS hot path: MTTKRP by dimension
+ * trees, the multi-sweep dimension tree (MSDT) schedule and pairwise
+ * perturbation (PP), after Ma and Solomonik, "Efficient parallel CP
+ * decomposition with pairwise perturbation and multi-sweep dimension tree".
+ *
+ * Conventions shared by every entry point
+ *   - Arrays are row-major (C order, last index fastest).  A tensor of order N
+ *     has dims s[0..N-1]; factor n is an s[n] x R matrix.
+ *   - Every array argument is a DEVICE pointer on the plan's device, owned by
+ *     the caller and borrowed for the duration of the call (the tensor is
+ *     borrowed from cp_set_tensor until the next cp_set_tensor or destroy).
+ *   - Factor matrices are always FP64 (the ALS state).  The tensor is stored
+ *     in the plan's precision (FP64 or FP32); contractions with it run in that
+ *     precision, every R x R operation (Gram matrices, their Hadamard
+ *     products, the SPD solve, norms, the residual) runs in FP64.
+ *   - All work is enqueued on the plan's HIP stream and the call returns
+ *     without waiting, unless it has to read a device result: a non-null
+ *     `info`, or cp_pp_sweep in CP_PP_AUTO mode (one small device-to-host
+ *     read of the factor-change norms before the sweep).
+ *   - Errors are returned as cp_status; nothing is thrown and nothing exits.
+ *     cp_last_error() gives a message for the last failing call on a plan.
+ *   - A plan is not thread-safe.  The library allocates no device memory: the
+ *     caller provides one workspace of the size the plan reports.
+ *   - Limits: 3 <= N <= 8, 1 <= R <= 128, every s[n] >= 1, numel < 2^40.
+ *     Anything else returns CP_ERR_UNSUPPORTED.
+ */
+#ifndef CPALS_H
+#define CPALS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cp_plan_s* cp_plan;
+
+typedef enum {
+  CP_OK = 0,
+  CP_ERR_ARG = 1,         /* null pointer, bad mode, bad size */
+  CP_ERR_STATE = 2,       /* call out of order (no workspace, no tensor, no PP operators) */
+  CP_ERR_UNSUPPORTED = 3, /* outside the stated limits */
+  CP_ERR_HIP = 4,         /* a HIP runtime call failed; see cp_last_error */
+  CP_ERR_NOT_SPD = 5,     /* a Gamma matrix was not numerically positive definite */
+  CP_ERR_NUMERIC = 6      /* the residual came out NaN or infinite */
+} cp_status;
+
+typedef enum { CP_F64 = 0, CP_F32 = 1 } cp_prec;
+
+typedef enum {
+  CP_TREE_DT = 0,   /* standard binary dimension tree, two first-level TTMs per sweep (Sec. II-C) */
+  CP_TREE_MSDT = 2  /* multi-sweep dimension tree, N first-level TTMs per N-1 sweeps (Sec. III) */
+} cp_tree;
+
+typedef enum {
+  CP_PP_AUTO = 0,          /* Alg. 2 state machine with tolerance pp_tol */
+  CP_PP_FORCE_EXACT = 1,   /* a regular sweep */
+  CP_PP_FORCE_APPROX = 2,  /* a PP-approximated sweep with the current operators */
+  CP_PP_FORCE_REINIT = 3   /* PP initialization, then a PP-approximated sweep */
+} cp_pp_mode;
+
+typedef enum { CP_SWEEP_EXACT = 0, CP_SWEEP_PP_INIT = 1, CP_SWEEP_PP_APPROX = 2 } cp_sweep_kind;
+
+typedef struct {
+  int kind;              /* cp_sweep_kind actually run */
+  int fitness_is_exact;  /* 0 when the residual came from an approximated M~^(N) */
+  double fitness;        /* f = 1 - r */
+  double r;              /* relative residual from Eq. (3), squared tensor norm */
+  double dA_rel[8];      /* ||dA^(i)||_F / ||A^(i)||_F after the sweep (Alg. 2 test inputs) */
+  int ttm_count;         /* first-level contractions with the tensor done in this call */
+  int reserved;
+} cp_sweep_info;
+
+/* Create a plan for an order-`order` tensor of dims `dims` (host array of
+ * `order` entries), CP rank `rank`, tensor precision `prec`, tree schedule
+ * `tree`, on HIP stream `hip_stream` (a hipStream_t; NULL is the null stream)
+ * of the current device.  *out receives the plan.  (Alg. 1 inputs, Sec. II-B.) */
+cp_status cp_plan_create(cp_plan* out, int order, const int64_t* dims, int rank, cp_prec prec,
+                         cp_tree tree, void* hip_stream);
+
+/* Bytes of device workspace the plan needs (intermediates of the trees, the
+ * PP operators, FP64 R x R state).  */
+cp_status cp_plan_workspace_size(cp_plan plan, size_t* bytes);
+
+/* Attach a device workspace of at least cp_plan_workspace_size bytes,
+ * 256-byte aligned, owned by the caller and kept alive while the plan is
+ * used.  Re-attaching drops every cached intermediate. */
+cp_status cp_plan_set_workspace(cp_plan plan, void* dptr, size_t bytes);
+
+/* Borrow the tensor T (device, plan precision, dims of the plan) and compute
+ * ||T||_F^2 in FP64, used by the residual (Eq. (3)).  Drops cached state. */
+cp_status cp_set_tensor(cp_plan plan, const void* T);
+
+/* M = MTTKRP of mode `mode` (0-based): M^(n) = T_(n) P^(n), the product of
+ * the mode-n unfolding with the Khatri-Rao product of every other factor
+ * (Sec. II-B).  A: host array of `order` device pointers to FP64 s[i] x R
+ * factors (A[mode] is not read); M: device FP64 s[mode] x R output.  Computed
+ * along the standard dimension tree path for that mode.  Stateless for the
+ * caller, but drops the plan's cached sweep state (as cp_reset). */
+cp_status cp_mttkrp(cp_plan plan, const double* const* A, int mode, double* M);
+
+/* As cp_mttkrp, but the first contraction with the tensor uses mode
+ * `root_mode` (!= mode), the rest of the path contracts the remaining modes
+ * one at a time in increasing distance from `mode`.  Exercises every
+ * first-level layout (Sec. III: T x_m A^(m) serves every MTTKRP except m). */
+cp_status cp_mttkrp_rooted(cp_plan plan, const double* const* A, int mode, int root_mode, double* M);
+
+/* One ALS sweep (Alg. 1, one pass of the loop body): for n = 0..N-1,
+ * Gamma^(n) by Eq. (1), M^(n) by the plan's tree, A^(n) <- M^(n) Gamma^(n)^-1,
+ * S^(n) <- A^(n)T A^(n); then the residual by Eq. (3).  A: host array of N
+ * device pointers to the FP64 factors, updated in place.  The factors must be
+ * the ones the plan last wrote (or call cp_reset after changing them).
+ * info may be NULL (no host synchronization). */
+cp_status cp_als_sweep(cp_plan plan, double* const* A, cp_sweep_info* info);
+
+/* One outer step of PP-CP-ALS (Alg. 2): depending on `mode` and, in
+ * CP_PP_AUTO, on the test ||dA^(i)||_F < pp_tol ||A^(i)||_F for every i,
+ * either a regular sweep with the plan's tree, or PP initialization (A_p <- A,
+ * dA <- 0, operators M_p^(i,j), M_p^(n) by the PP dimension tree of Fig. 1b)
+ * followed by an approximated sweep, or an approximated sweep alone
+ * (M~^(n) by Eqs. (5)-(8)).  Same argument rules as cp_als_sweep. */
+cp_status cp_pp_sweep(cp_plan plan, double* const* A, double pp_tol, cp_pp_mode mode,
+                      cp_sweep_info* info);
+
+/* Drop cached intermediates, the MSDT position and the PP state: the next
+ * sweep re-reads the factors and recomputes their Gram matrices. */
+cp_status cp_reset(cp_plan plan);
+
+/* Wait for the plan's stream and report a deferred device-side failure
+ * (CP_ERR_NOT_SPD from a solve, CP_ERR_NUMERIC from a residual). */
+cp_status cp_sync(cp_plan plan);
+
+/* Phase timers (the per-sweep breakdown of Sec. V-B).  Categories: */
+typedef enum {
+  CP_PHASE_TTM = 0,     /* first-level contractions of the tensor with one factor */
+  CP_PHASE_MTTV = 1,    /* batched TTVs down the trees (incl. PP operator levels) */
+  CP_PHASE_UPDATE = 2,  /* Hadamard products of Eqs. (1)/(7), Gamma inverse, solve, Gram, norms */
+  CP_PHASE_PP = 3,      /* first-order PP corrections, Eqs. (5)-(6) */
+  CP_PHASE_OTHER = 4,
+  CP_PHASE_COUNT = 5
+} cp_phase;
+
+/* on != 0: from now on, record a HIP event pair on the plan's stream around
+ * every group of launches, by category.  Costs two event records per group. */
+cp_status cp_profile_enable(cp_plan plan, int on);
+
+/* Wait for the plan's stream, then write the summed device time in
+ * milliseconds (ms[CP_PHASE_COUNT], host array) and the number of recorded
+ * groups (launches[CP_PHASE_COUNT]) since the last read, and reset them. */
+cp_status cp_profile_read(cp_plan plan, double* ms, int64_t* launches);
+
+/* Destroy the plan (does not free the caller's workspace). */
+cp_status cp_plan_destroy(cp_plan plan);
+
+const char* cp_status_str(cp_status s);
+const char* cp_last_error(cp_plan plan);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CPALS_H */

@@ -1,0 +1,213 @@
+"""ctypes binding of libcpals.so (declared in include/cpals.h).
+
+Argument marshalling only: PyTorch supplies device memory (the workspace,
+tensors, factors) and the HIP stream; every step of the computation runs in
+the HIP library.  There is no fallback: if the library is missing or no GPU
+is present, the calls raise.
+"""
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcpals.so")
+
+CP_OK, CP_ERR_ARG, CP_ERR_STATE, CP_ERR_UNSUPPORTED, CP_ERR_HIP, CP_ERR_NOT_SPD, CP_ERR_NUMERIC = range(7)
+CP_F64, CP_F32 = 0, 1
+CP_TREE_DT, CP_TREE_MSDT = 0, 2
+CP_PP_AUTO, CP_PP_FORCE_EXACT, CP_PP_FORCE_APPROX, CP_PP_FORCE_REINIT = range(4)
+KIND_NAMES = {0: "exact", 1: "init", 2: "approx"}
+PHASES = ["ttm", "mttv", "update", "pp", "other"]
+
+PRECS = {"f64": CP_F64, "f32": CP_F32}
+TREES = {"dt": CP_TREE_DT, "msdt": CP_TREE_MSDT}
+PP_MODES = {"auto": CP_PP_AUTO, "exact": CP_PP_FORCE_EXACT, "approx": CP_PP_FORCE_APPROX,
+            "init": CP_PP_FORCE_REINIT}
+TORCH_DTYPE = {CP_F64: torch.float64, CP_F32: torch.float32}
+
+
+class SweepInfo(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_int),
+        ("fitness_is_exact", ctypes.c_int),
+        ("fitness", ctypes.c_double),
+        ("r", ctypes.c_double),
+        ("dA_rel", ctypes.c_double * 8),
+        ("ttm_count", ctypes.c_int),
+        ("reserved", ctypes.c_int),
+    ]
+
+    def as_dict(self, order):
+        return {
+            "kind": KIND_NAMES[self.kind],
+            "fitness_is_exact": bool(self.fitness_is_exact),
+            "fitness": self.fitness,
+            "r": self.r,
+            "dA_rel": [self.dA_rel[i] for i in range(order)],
+            "ttm_count": self.ttm_count,
+        }
+
+
+class CpalsError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"cpals status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+EXPORTS = {
+    "cp_plan_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.POINTER(ctypes.c_int64),
+                                      ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]),
+    "cp_plan_workspace_size": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)]),
+    "cp_plan_set_workspace": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]),
+    "cp_set_tensor": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "cp_mttkrp": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_void_p]),
+    "cp_mttkrp_rooted": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p), ctypes.c_int,
+                                        ctypes.c_int, ctypes.c_void_p]),
+    "cp_als_sweep": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(SweepInfo)]),
+    "cp_pp_sweep": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p), ctypes.c_double,
+                                   ctypes.c_int, ctypes.POINTER(SweepInfo)]),
+    "cp_reset": (ctypes.c_int, [ctypes.c_void_p]),
+    "cp_sync": (ctypes.c_int, [ctypes.c_void_p]),
+    "cp_plan_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "cp_profile_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "cp_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_int64)]),
+    "cp_status_str": (ctypes.c_char_p, [ctypes.c_int]),
+    "cp_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
+}
+
+
+def lib():
+    """Load libcpals.so (built in-tree); raise if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built (run paper_2010_12056_amd.build_lib.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in EXPORTS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _ptrs(tensors):
+    arr = (ctypes.c_void_p * len(tensors))()
+    for i, t in enumerate(tensors):
+        arr[i] = None if t is None else ctypes.c_void_p(t.data_ptr())
+    return arr
+
+
+class Plan:
+    """A CP-ALS plan: tensor dims, rank, precision ("f64" / "f32") and tree
+    ("dt" / "msdt"), bound to the current HIP stream of `device`."""
+
+    def __init__(self, dims, rank, prec="f32", tree="dt", device="cuda"):
+        if not torch.cuda.is_available():
+            raise RuntimeError("cpals needs a GPU; none is visible")
+        self.L = lib()
+        self.dims = tuple(int(d) for d in dims)
+        self.order = len(self.dims)
+        self.rank = int(rank)
+        self.prec = PRECS[prec]
+        self.device = torch.device(device)
+        self.stream = torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        d = (ctypes.c_int64 * self.order)(*self.dims)
+        self._check(self.L.cp_plan_create(ctypes.byref(h), self.order, d, self.rank, self.prec,
+                                          TREES[tree], ctypes.c_void_p(self.stream.cuda_stream)), None)
+        self.h = h
+        nbytes = ctypes.c_size_t()
+        self._check(self.L.cp_plan_workspace_size(self.h, ctypes.byref(nbytes)))
+        self.workspace_bytes = int(nbytes.value)
+        self.ws = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.ws.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        self._check(self.L.cp_plan_set_workspace(self.h, ctypes.c_void_p(aligned), self.workspace_bytes))
+        self.T = None
+
+    def _check(self, status, h="self"):
+        if status != CP_OK:
+            hh = self.h if h == "self" else h
+            msg = self.L.cp_last_error(hh) if hh else b""
+            base = self.L.cp_status_str(status)
+            raise CpalsError(status, (base or b"").decode() + ": " + (msg or b"").decode())
+
+    def set_tensor(self, T):
+        if T.dtype != TORCH_DTYPE[self.prec] or tuple(T.shape) != self.dims or not T.is_contiguous():
+            raise ValueError("tensor must be contiguous with the plan's dims and precision")
+        if T.device != self.device and not (T.is_cuda and self.device.type == "cuda"):
+            raise ValueError("tensor must be on the plan's device")
+        self.T = T
+        self._check(self.L.cp_set_tensor(self.h, ctypes.c_void_p(T.data_ptr())))
+
+    def _factors(self, A, allow_none=None):
+        if len(A) != self.order:
+            raise ValueError("need one factor per mode")
+        for i, a in enumerate(A):
+            if a is None and i == allow_none:
+                continue
+            if a.dtype != torch.float64 or tuple(a.shape) != (self.dims[i], self.rank) or not a.is_contiguous() \
+                    or not a.is_cuda:
+                raise ValueError(f"factor {i} must be a contiguous FP64 CUDA tensor of shape "
+                                 f"({self.dims[i]}, {self.rank})")
+        return _ptrs(A)
+
+    def mttkrp(self, A, mode, root=None, out=None):
+        M = out if out is not None else torch.empty((self.dims[mode], self.rank), dtype=torch.float64,
+                                                   device=self.device)
+        p = self._factors(A, allow_none=mode)
+        if root is None:
+            self._check(self.L.cp_mttkrp(self.h, p, int(mode), ctypes.c_void_p(M.data_ptr())))
+        else:
+            self._check(self.L.cp_mttkrp_rooted(self.h, p, int(mode), int(root), ctypes.c_void_p(M.data_ptr())))
+        return M
+
+    def als_sweep(self, A, info=True):
+        p = self._factors(A)
+        if info:
+            si = SweepInfo()
+            self._check(self.L.cp_als_sweep(self.h, p, ctypes.byref(si)))
+            return si.as_dict(self.order)
+        self._check(self.L.cp_als_sweep(self.h, p, None))
+        return None
+
+    def pp_sweep(self, A, tol=0.2, mode="auto", info=True):
+        p = self._factors(A)
+        if info:
+            si = SweepInfo()
+            self._check(self.L.cp_pp_sweep(self.h, p, float(tol), PP_MODES[mode], ctypes.byref(si)))
+            return si.as_dict(self.order)
+        self._check(self.L.cp_pp_sweep(self.h, p, float(tol), PP_MODES[mode], None))
+        return None
+
+    def profile(self, on=True):
+        self._check(self.L.cp_profile_enable(self.h, 1 if on else 0))
+
+    def profile_read(self):
+        ms = (ctypes.c_double * 5)()
+        cnt = (ctypes.c_int64 * 5)()
+        self._check(self.L.cp_profile_read(self.h, ms, cnt))
+        return {PHASES[i]: (ms[i], int(cnt[i])) for i in range(5)}
+
+    def reset(self):
+        self._check(self.L.cp_reset(self.h))
+
+    def sync(self):
+        self._check(self.L.cp_sync(self.h))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.cp_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

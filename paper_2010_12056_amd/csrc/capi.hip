@@ -1,0 +1,866 @@
+// Host runtime and C ABI of the CP-ALS hot path (declarations and contracts
+// in include/cpals.h).
+//
+// The plan owns host-side state only: the schedule position, versions of the
+// factors, which intermediate sits in which workspace slot, the PP phase.
+// Device memory comes from one caller-provided workspace, carved at attach.
+//
+// Intermediates follow Eq. (4): the tensor contracted with every factor not
+// in a kept mode set.  Layout: kept modes in increasing order, rank index
+// last (row-major), so every contraction below the first one is the same
+// strided batched TTV, Y[p][q][r] = sum_i X[p][i][q][r] A[i][r].
+//
+// Slot d of the workspace holds one node with N - d kept modes (depth d of
+// a root-to-leaf path).  A node stays valid while every factor contracted
+// into it keeps the version it had when the node was built; a path reuses
+// its deepest valid node.  This gives the standard dimension tree's reuse
+// (Sec. II-C) and MSDT's reuse of a first-level node across sweeps
+// (Sec. III) from the same mechanism.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/cpals.h"
+#include "kernels.h"
+
+using namespace cpals;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kNormParts = 1024;
+
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Slot {
+  uint32_t set = 0;  // bitmask of kept modes
+  uint64_t ver[kMaxOrder] = {};
+  bool valid = false;
+};
+
+}  // namespace
+
+struct cp_plan_s {
+  int N = 0, R = 0;
+  int64_t dims[kMaxOrder] = {};
+  cp_prec prec = CP_F32;
+  cp_tree tree = CP_TREE_DT;
+  hipStream_t st = nullptr;
+  size_t esz = 4;
+  std::string err;
+
+  // workspace
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  size_t ws_need = 0;
+  struct Region {
+    size_t off, bytes;
+  };
+  std::vector<Region> regions;
+
+  void* Ash[kMaxOrder] = {};   // factor shadows, tensor precision
+  void* dAsh[kMaxOrder] = {};  // PP: shadows of dA = A - A_p
+  double* Ap[kMaxOrder] = {};  // PP: A_p, FP64
+  double* S[kMaxOrder] = {};   // Gram matrices, FP64
+  double* dS[kMaxOrder] = {};  // PP: A^T dA, FP64
+  double* Mp[kMaxOrder] = {};  // PP: M_p^(n), FP64
+  void* pair[kMaxOrder][kMaxOrder] = {};  // PP: M_p^(i,j), i < j, axes (s_i, s_j, R)
+  double *Gamma = nullptr, *Ginv = nullptr, *W = nullptr, *Mbuf = nullptr;
+  double *partS = nullptr, *partdS = nullptr, *partSc = nullptr, *normParts = nullptr;
+  DevStats* stats = nullptr;
+  void* slot_buf[kMaxOrder] = {};
+  size_t slot_cap[kMaxOrder] = {};
+  int nblk_max = 0;
+
+  // state
+  const void* T = nullptr;
+  bool state_ready = false;
+  uint64_t ver[kMaxOrder] = {};
+  Slot slot[kMaxOrder];
+  int64_t msdt_u = 0;
+  int phase = 0;  // 0: exact, 1: PP phase
+  bool have_ops = false;
+  bool fresh = true;  // no sweep since the state was (re)initialized: dA = A
+  int ttm_count = 0;
+
+  // phase timers: a HIP event pair around every launch group, by category
+  bool prof = false;
+  struct Mark {
+    hipEvent_t a, b;
+    int cat;
+  };
+  std::vector<Mark> marks;
+  std::vector<hipEvent_t> pool;
+};
+
+namespace {
+
+cp_status fail(cp_plan p, cp_status s, const char* fmt, ...) {
+  if (p) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    p->err = buf;
+  }
+  return s;
+}
+
+#define HIP_TRY(p, expr)                                                              \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail((p), CP_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));   \
+  } while (0)
+
+#define CP_TRY(expr)              \
+  do {                            \
+    cp_status s_ = (expr);        \
+    if (s_ != CP_OK) return s_;   \
+  } while (0)
+
+hipEvent_t get_event(cp_plan p) {
+  if (!p->pool.empty()) {
+    hipEvent_t e = p->pool.back();
+    p->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Records an event pair around the launches made during its lifetime when
+// the plan's phase timers are on.
+struct ProfScope {
+  cp_plan p;
+  int cat;
+  hipEvent_t a = nullptr;
+  ProfScope(cp_plan p_, int cat_) : p(p_), cat(cat_) {
+    if (p->prof) {
+      a = get_event(p);
+      if (a && hipEventRecord(a, p->st) != hipSuccess) a = nullptr;
+    }
+  }
+  ~ProfScope() {
+    if (!a) return;
+    hipEvent_t b = get_event(p);
+    if (b && hipEventRecord(b, p->st) == hipSuccess) p->marks.push_back({a, b, cat});
+  }
+};
+
+int64_t node_numel(cp_plan p, uint32_t set) {
+  int64_t n = p->R;
+  for (int m = 0; m < p->N; ++m)
+    if (set & (1u << m)) n *= p->dims[m];
+  return n;
+}
+
+void plan_layout(cp_plan p) {
+  const int N = p->N, R = p->R;
+  p->regions.clear();
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += align_up(bytes ? bytes : 1);
+    p->regions.push_back({o, bytes});
+    return o;
+  };
+  int64_t smax = 0;
+  for (int m = 0; m < N; ++m) smax = std::max(smax, p->dims[m]);
+  p->nblk_max = (int)((smax + kSolveRows - 1) / kSolveRows);
+  // fixed order of regions; set_workspace replays it
+  for (int m = 0; m < N; ++m) take((size_t)p->dims[m] * R * p->esz);      // Ash
+  for (int m = 0; m < N; ++m) take((size_t)p->dims[m] * R * p->esz);      // dAsh
+  for (int m = 0; m < N; ++m) take((size_t)p->dims[m] * R * 8);           // Ap
+  for (int m = 0; m < N; ++m) take((size_t)R * R * 8);                    // S
+  for (int m = 0; m < N; ++m) take((size_t)R * R * 8);                    // dS
+  for (int m = 0; m < N; ++m) take((size_t)p->dims[m] * R * 8);           // Mp
+  for (int i = 0; i < N; ++i)
+    for (int j = i + 1; j < N; ++j) take((size_t)p->dims[i] * p->dims[j] * R * p->esz);  // pairs
+  take((size_t)R * R * 8);                       // Gamma
+  take((size_t)R * R * 8);                       // Ginv
+  take((size_t)R * R * 8);                       // W
+  take((size_t)smax * R * 8);                    // Mbuf
+  take((size_t)p->nblk_max * R * R * 8);         // partS
+  take((size_t)p->nblk_max * R * R * 8);         // partdS
+  take((size_t)p->nblk_max * 4 * 8);             // partSc
+  take((size_t)kNormParts * 8);                  // normParts
+  take(sizeof(DevStats));                        // stats
+  // slots for depths 1..N-2 (depth d keeps N - d modes)
+  std::vector<int64_t> sorted(p->dims, p->dims + N);
+  std::sort(sorted.begin(), sorted.end(), std::greater<int64_t>());
+  for (int d = 1; d <= N - 2; ++d) {
+    int64_t n = R;
+    for (int m = 0; m < N - d; ++m) n *= sorted[m];
+    p->slot_cap[d] = (size_t)n * p->esz;
+    take(p->slot_cap[d]);
+  }
+  p->ws_need = off;
+}
+
+void plan_carve(cp_plan p) {
+  const int N = p->N;
+  size_t k = 0;
+  auto next = [&]() { return (void*)(p->ws + p->regions[k++].off); };
+  for (int m = 0; m < N; ++m) p->Ash[m] = next();
+  for (int m = 0; m < N; ++m) p->dAsh[m] = next();
+  for (int m = 0; m < N; ++m) p->Ap[m] = (double*)next();
+  for (int m = 0; m < N; ++m) p->S[m] = (double*)next();
+  for (int m = 0; m < N; ++m) p->dS[m] = (double*)next();
+  for (int m = 0; m < N; ++m) p->Mp[m] = (double*)next();
+  for (int i = 0; i < N; ++i)
+    for (int j = i + 1; j < N; ++j) p->pair[i][j] = next();
+  p->Gamma = (double*)next();
+  p->Ginv = (double*)next();
+  p->W = (double*)next();
+  p->Mbuf = (double*)next();
+  p->partS = (double*)next();
+  p->partdS = (double*)next();
+  p->partSc = (double*)next();
+  p->normParts = (double*)next();
+  p->stats = (DevStats*)next();
+  for (int d = 1; d <= N - 2; ++d) p->slot_buf[d] = next();
+}
+
+void drop_cache(cp_plan p) {
+  for (int d = 0; d < kMaxOrder; ++d) p->slot[d] = Slot();
+  p->msdt_u = 0;
+  p->phase = 0;
+  p->have_ops = false;
+  p->state_ready = false;
+  p->fresh = true;
+}
+
+uint32_t full_set(int N) { return (N >= 32) ? 0xffffffffu : ((1u << N) - 1u); }
+
+bool slot_valid(cp_plan p, int d, uint32_t set) {
+  const Slot& s = p->slot[d];
+  if (!s.valid || s.set != set) return false;
+  for (int m = 0; m < p->N; ++m)
+    if (!(set & (1u << m)) && s.ver[m] != p->ver[m]) return false;
+  return true;
+}
+
+void slot_record(cp_plan p, int d, uint32_t set) {
+  Slot& s = p->slot[d];
+  s.set = set;
+  s.valid = true;
+  for (int m = 0; m < p->N; ++m) s.ver[m] = p->ver[m];
+}
+
+// Shape of contracting mode c out of a node keeping `set` (tensor modes in
+// increasing order, rank index last): X viewed as [P][I][Q](R).
+void contract_shape(cp_plan p, uint32_t set, int c, int64_t* P, int64_t* I, int64_t* Q) {
+  int64_t pp = 1, qq = 1;
+  for (int m = 0; m < p->N; ++m) {
+    if (!(set & (1u << m))) continue;
+    if (m < c) pp *= p->dims[m];
+    if (m > c) qq *= p->dims[m];
+  }
+  *P = pp;
+  *I = p->dims[c];
+  *Q = qq;
+}
+
+// One contraction: input node `in` (or the tensor when in_set is the full
+// set) keeping in_set, contracting mode c, into `out` (tensor precision, or
+// FP64 when out_f64).
+template <typename TT>
+cp_status contract(cp_plan p, const void* in, uint32_t in_set, int c, void* out, bool out_f64) {
+  int64_t P, I, Q;
+  contract_shape(p, in_set, c, &P, &I, &Q);
+  const TT* A = (const TT*)p->Ash[c];
+  if (in_set == full_set(p->N)) {
+    if (out_f64) return fail(p, CP_ERR_STATE, "internal: first-level contraction into FP64");
+    ++p->ttm_count;
+    ProfScope ps(p, CP_PHASE_TTM);
+    HIP_TRY(p, launch_ttm<TT>((const TT*)in, A, (TT*)out, P, I, Q, p->R, p->st));
+  } else if (out_f64) {
+    ProfScope ps(p, CP_PHASE_MTTV);
+    HIP_TRY(p, (launch_mttv<TT, double>((const TT*)in, A, (double*)out, P, I, Q, p->R, p->st)));
+  } else {
+    ProfScope ps(p, CP_PHASE_MTTV);
+    HIP_TRY(p, (launch_mttv<TT, TT>((const TT*)in, A, (TT*)out, P, I, Q, p->R, p->st)));
+  }
+  return CP_OK;
+}
+
+cp_status contract_any(cp_plan p, const void* in, uint32_t in_set, int c, void* out, bool out_f64) {
+  if (p->prec == CP_F64) return contract<double>(p, in, in_set, c, out, out_f64);
+  return contract<float>(p, in, in_set, c, out, out_f64);
+}
+
+// Walk a root-to-leaf contraction sequence; M (FP64, s_leaf x R) receives the leaf.
+cp_status run_path(cp_plan p, const std::vector<int>& seq, double* M) {
+  const int N = p->N;
+  const int len = (int)seq.size();
+  if (len != N - 1) return fail(p, CP_ERR_STATE, "internal: path of length %d", len);
+  std::vector<uint32_t> sets(len + 1);
+  sets[0] = full_set(N);
+  for (int d = 1; d <= len; ++d) sets[d] = sets[d - 1] & ~(1u << seq[d - 1]);
+  int start = 0;
+  for (int d = len - 1; d >= 1; --d)
+    if (slot_valid(p, d, sets[d])) {
+      start = d;
+      break;
+    }
+  for (int d = start + 1; d <= len; ++d) {
+    const void* in = (d == 1) ? p->T : p->slot_buf[d - 1];
+    if (d == len) {
+      CP_TRY(contract_any(p, in, sets[d - 1], seq[d - 1], M, true));
+    } else {
+      if ((size_t)node_numel(p, sets[d]) * p->esz > p->slot_cap[d])
+        return fail(p, CP_ERR_STATE, "internal: slot %d too small", d);
+      CP_TRY(contract_any(p, in, sets[d - 1], seq[d - 1], p->slot_buf[d], false));
+      slot_record(p, d, sets[d]);
+    }
+  }
+  return CP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Schedules (host).  Positions of an ordered mode list are split in halves,
+// the left half taking ceil(len/2); leaving a range for its left child
+// contracts the right part from the far end inward, leaving it for its right
+// child contracts the left part from the far end inward.
+// ---------------------------------------------------------------------------
+std::vector<int> tree_path(const std::vector<int>& order, int leaf_pos) {
+  std::vector<int> out;
+  int lo = 0, hi = (int)order.size() - 1;
+  while (lo < hi) {
+    const int mid = lo + (hi - lo + 2) / 2 - 1;
+    if (leaf_pos <= mid) {
+      for (int q = hi; q > mid; --q) out.push_back(order[q]);
+      hi = mid;
+    } else {
+      for (int q = lo; q <= mid; ++q) out.push_back(order[q]);
+      lo = mid + 1;
+    }
+  }
+  return out;
+}
+
+// Standard dimension tree (Sec. II-C, Fig. 1a).
+std::vector<int> dt_path(int N, int n) {
+  std::vector<int> order(N);
+  for (int i = 0; i < N; ++i) order[i] = i;
+  return tree_path(order, n);
+}
+
+// MSDT (Sec. III, Fig. 2): subtree j = u / (N-1) has root mode
+// N-1 - (j mod N) (0-based) and a binary tree over the next N-1 modes in
+// cyclic order.
+std::vector<int> msdt_path(int N, int64_t u) {
+  const int64_t j = u / (N - 1);
+  const int m = (int)((N - 1) - (j % N));
+  std::vector<int> order;
+  for (int t = 1; t < N; ++t) order.push_back((m + t) % N);
+  const int t = (int)(u % (N - 1));
+  std::vector<int> out{m};
+  std::vector<int> rest = tree_path(order, t);
+  out.insert(out.end(), rest.begin(), rest.end());
+  return out;
+}
+
+// ---------------------------------------------------------------------------
+// Mode update (Alg. 1 / Alg. 2 inner body), M in p->Mbuf.
+// ---------------------------------------------------------------------------
+template <typename TT>
+cp_status update_mode_t(cp_plan p, int n, double* A, bool pp) {
+  const int R = p->R;
+  PrepArgs pa{};
+  for (int m = 0; m < p->N; ++m) {
+    pa.S[m] = p->S[m];
+    pa.dS[m] = p->dS[m];
+  }
+  pa.Gamma = p->Gamma;
+  pa.Ginv = p->Ginv;
+  pa.W = p->W;
+  pa.stats = p->stats;
+  pa.N = p->N;
+  pa.n = n;
+  pa.R = R;
+  pa.pp = pp ? 1 : 0;
+  ProfScope ps(p, CP_PHASE_UPDATE);
+  HIP_TRY(p, launch_prep(pa, p->st));
+  const int nblk = (int)((p->dims[n] + kSolveRows - 1) / kSolveRows);
+  SolveArgs<TT> sa{};
+  sa.M = p->Mbuf;
+  sa.A = A;
+  sa.Ash = (TT*)p->Ash[n];
+  sa.Ap = pp ? p->Ap[n] : nullptr;
+  sa.dAsh = pp ? (TT*)p->dAsh[n] : nullptr;
+  sa.W = pp ? p->W : nullptr;
+  sa.Ginv = p->Ginv;
+  sa.partS = p->partS;
+  sa.partdS = p->partdS;
+  sa.partSc = p->partSc;
+  sa.s = p->dims[n];
+  sa.R = R;
+  sa.pp = pa.pp;
+  HIP_TRY(p, launch_solve<TT>(sa, nblk, p->st));
+  FinalArgs fa{};
+  fa.partS = p->partS;
+  fa.partdS = p->partdS;
+  fa.partSc = p->partSc;
+  fa.Gamma = p->Gamma;
+  fa.S = p->S[n];
+  fa.dS = p->dS[n];
+  fa.stats = p->stats;
+  fa.nblk = nblk;
+  fa.R = R;
+  fa.n = n;
+  fa.last = (n == p->N - 1) ? 1 : 0;
+  fa.pp = pa.pp;
+  HIP_TRY(p, launch_finalize(fa, p->st));
+  ++p->ver[n];
+  return CP_OK;
+}
+
+cp_status update_mode(cp_plan p, int n, double* A, bool pp) {
+  if (p->prec == CP_F64) return update_mode_t<double>(p, n, A, pp);
+  return update_mode_t<float>(p, n, A, pp);
+}
+
+cp_status convert_factor(cp_plan p, const double* src, void* dst, int64_t n) {
+  if (p->prec == CP_F64) {
+    HIP_TRY(p, launch_convert<double>(src, (double*)dst, n, p->st));
+  } else {
+    HIP_TRY(p, launch_convert<float>(src, (float*)dst, n, p->st));
+  }
+  return CP_OK;
+}
+
+cp_status check_ready(cp_plan p) {
+  if (!p) return CP_ERR_ARG;
+  if (!p->ws) return fail(p, CP_ERR_STATE, "no workspace attached");
+  if (!p->T) return fail(p, CP_ERR_STATE, "no tensor set");
+  return CP_OK;
+}
+
+// Shadows and Gram matrices from the caller's factors.
+cp_status init_state(cp_plan p, double* const* A) {
+  for (int m = 0; m < p->N; ++m) {
+    CP_TRY(convert_factor(p, A[m], p->Ash[m], p->dims[m] * p->R));
+    HIP_TRY(p, launch_gram(A[m], p->dims[m], p->R, p->S[m], p->st));
+    HIP_TRY(p, launch_zero_f64(p->dS[m], (int64_t)p->R * p->R, p->st));
+    ++p->ver[m];
+  }
+  p->state_ready = true;
+  p->fresh = true;
+  return CP_OK;
+}
+
+cp_status read_stats(cp_plan p, DevStats* h) {
+  HIP_TRY(p, hipMemcpyAsync(h, p->stats, sizeof(DevStats), hipMemcpyDeviceToHost, p->st));
+  HIP_TRY(p, hipStreamSynchronize(p->st));
+  return CP_OK;
+}
+
+cp_status fill_info(cp_plan p, cp_sweep_info* info, int kind) {
+  DevStats h;
+  CP_TRY(read_stats(p, &h));
+  if (info) {
+    info->kind = kind;
+    info->fitness_is_exact = (kind == CP_SWEEP_EXACT) ? 1 : 0;
+    info->r = h.r;
+    info->fitness = 1.0 - h.r;
+    for (int m = 0; m < kMaxOrder; ++m)
+      info->dA_rel[m] = (m < p->N && h.normA2[m] > 0) ? std::sqrt(h.normdA2[m] / h.normA2[m]) : 0.0;
+    info->ttm_count = p->ttm_count;
+  }
+  if (h.status & 1) return fail(p, CP_ERR_NOT_SPD, "a Gamma matrix was not numerically positive definite");
+  if (h.status & 2) return fail(p, CP_ERR_NUMERIC, "non-finite residual");
+  return CP_OK;
+}
+
+cp_status exact_sweep(cp_plan p, double* const* A) {
+  for (int n = 0; n < p->N; ++n) {
+    std::vector<int> seq = (p->tree == CP_TREE_MSDT) ? msdt_path(p->N, p->msdt_u++) : dt_path(p->N, n);
+    CP_TRY(run_path(p, seq, p->Mbuf));
+    CP_TRY(update_mode(p, n, A[n], false));
+  }
+  p->phase = 0;
+  p->fresh = false;
+  return CP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// PP initialization (Alg. 2; Sec. II-D, Fig. 1b): operators M_p^(i,j) for all
+// pairs and M_p^(n) for all n at A_p = A, by the PP dimension tree.  Level l
+// keeps N - l modes; its nodes are position i together with the run of
+// N-l-1 positions starting at j, 1 <= i < j <= l+2 (C(l+2,2) nodes; the last
+// level is every pair).  Positions are mapped to modes through a cyclic
+// relabeling chosen so that the first root is the live first-level node of
+// the regular sweep when there is one (the footnote's amortized root).
+// ---------------------------------------------------------------------------
+struct PPNode {
+  uint32_t set;
+  int parent;  // index into the previous level
+};
+
+std::vector<std::vector<PPNode>> pp_tree(int N, const std::vector<int>& order) {
+  std::vector<std::vector<PPNode>> levels;
+  for (int l = 1; l <= N - 2; ++l) {
+    const int w = N - l - 1;
+    std::vector<PPNode> nodes;
+    for (int i = 1; i <= l + 2; ++i)
+      for (int j = i + 1; j <= l + 2; ++j) {
+        uint32_t s = 1u << order[i - 1];
+        for (int q = j; q < j + w; ++q) s |= 1u << order[q - 1];
+        int par = -1;
+        if (l > 1) {
+          const auto& prev = levels.back();
+          for (int k = 0; k < (int)prev.size(); ++k)
+            if ((prev[k].set & s) == s) {
+              par = k;
+              break;
+            }
+        }
+        nodes.push_back({s, par});
+      }
+    levels.push_back(nodes);
+  }
+  return levels;
+}
+
+int lowest_bit(uint32_t x) {
+  for (int b = 0; b < 32; ++b)
+    if (x & (1u << b)) return b;
+  return -1;
+}
+
+int pair_first(uint32_t set) { return lowest_bit(set); }
+int pair_second(uint32_t set) { return lowest_bit(set & ~(1u << lowest_bit(set))); }
+
+cp_status pp_node(cp_plan p, const std::vector<std::vector<PPNode>>& lv, int l, int k) {
+  const int N = p->N;
+  const uint32_t set = lv[l - 1][k].set;
+  const bool is_pair = (l == N - 2);
+  void* out = is_pair ? p->pair[pair_first(set)][pair_second(set)] : p->slot_buf[l];
+  if (l == 1) {
+    const int m = lowest_bit(full_set(N) & ~set);
+    if (!is_pair && slot_valid(p, 1, set)) {
+      // live first-level node of the regular sweep: reused, not recomputed
+    } else {
+      CP_TRY(contract_any(p, p->T, full_set(N), m, out, false));
+      if (!is_pair) slot_record(p, 1, set);
+    }
+  } else {
+    const uint32_t pset = lv[l - 2][lv[l - 1][k].parent].set;
+    const int m = lowest_bit(pset & ~set);
+    CP_TRY(contract_any(p, p->slot_buf[l - 1], pset, m, out, false));
+    if (!is_pair) slot_record(p, l, set);
+  }
+  if (!is_pair) {
+    for (int c = 0; c < (int)lv[l].size(); ++c)
+      if (lv[l][c].parent == k) CP_TRY(pp_node(p, lv, l + 1, c));
+  }
+  return CP_OK;
+}
+
+cp_status pp_init(cp_plan p, double* const* A) {
+  const int N = p->N;
+  for (int m = 0; m < N; ++m) {
+    HIP_TRY(p, launch_copy_f64(A[m], p->Ap[m], p->dims[m] * p->R, p->st));
+    HIP_TRY(p, launch_zero_f64(p->dS[m], (int64_t)p->R * p->R, p->st));
+  }
+  // relabel so that the first root is the live first-level node, if any
+  int live = -1;
+  for (int m = 0; m < N; ++m)
+    if (slot_valid(p, 1, full_set(N) & ~(1u << m))) live = m;
+  const int last = (live >= 0) ? live : N - 1;
+  std::vector<int> order(N);
+  for (int t = 0; t < N; ++t) order[t] = (last + 1 + t) % N;
+  auto lv = pp_tree(N, order);
+  for (int k = 0; k < (int)lv[0].size(); ++k) CP_TRY(pp_node(p, lv, 1, k));
+  // M_p^(n) from the pair {n, n+1 mod N}, contracting the other mode
+  for (int n = 0; n < N; ++n) {
+    const int x = (n + 1) % N;
+    const int a = std::min(n, x), b = std::max(n, x);
+    const uint32_t set = (1u << a) | (1u << b);
+    CP_TRY(contract_any(p, p->pair[a][b], set, x, p->Mp[n], true));
+  }
+  // dA <- 0 (its shadow feeds the first-order corrections)
+  for (int m = 0; m < N; ++m)
+    HIP_TRY(p, launch_zero_bytes(p->dAsh[m], (size_t)p->dims[m] * p->R * p->esz, p->st));
+  p->have_ops = true;
+  p->phase = 1;
+  return CP_OK;
+}
+
+template <typename TT>
+cp_status pp_first_order(cp_plan p, int n) {
+  PPArgs<TT> a{};
+  for (int i = 0; i < p->N; ++i) {
+    a.dims[i] = p->dims[i];
+    a.dA[i] = (const TT*)p->dAsh[i];
+    if (i == n) continue;
+    const int lo = std::min(n, i), hi = std::max(n, i);
+    a.pair[i] = (const TT*)p->pair[lo][hi];
+    a.pair_n_first[i] = (n < i) ? 1 : 0;
+  }
+  a.Mp = p->Mp[n];
+  a.M = p->Mbuf;
+  a.N = p->N;
+  a.n = n;
+  a.R = p->R;
+  ProfScope ps(p, CP_PHASE_PP);
+  HIP_TRY(p, launch_pp_mttkrp<TT>(a, p->st));
+  return CP_OK;
+}
+
+cp_status approx_sweep(cp_plan p, double* const* A) {
+  for (int n = 0; n < p->N; ++n) {
+    if (p->prec == CP_F64) {
+      CP_TRY(pp_first_order<double>(p, n));
+    } else {
+      CP_TRY(pp_first_order<float>(p, n));
+    }
+    CP_TRY(update_mode(p, n, A[n], true));
+  }
+  p->fresh = false;
+  return CP_OK;
+}
+
+bool check_factor_ptrs(double* const* A, int N) {
+  if (!A) return false;
+  for (int m = 0; m < N; ++m)
+    if (!A[m]) return false;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+cp_status cp_plan_create(cp_plan* out, int order, const int64_t* dims, int rank, cp_prec prec,
+                         cp_tree tree, void* hip_stream) {
+  if (!out || !dims) return CP_ERR_ARG;
+  *out = nullptr;
+  if (order < 3 || order > kMaxOrder) return CP_ERR_UNSUPPORTED;
+  if (rank < 1 || rank > kMaxRank) return CP_ERR_UNSUPPORTED;
+  if (prec != CP_F64 && prec != CP_F32) return CP_ERR_UNSUPPORTED;
+  if (tree != CP_TREE_DT && tree != CP_TREE_MSDT) return CP_ERR_UNSUPPORTED;
+  double numel = 1.0;
+  for (int m = 0; m < order; ++m) {
+    if (dims[m] < 1) return CP_ERR_ARG;
+    numel *= (double)dims[m];
+  }
+  if (numel * rank >= 1099511627776.0) return CP_ERR_UNSUPPORTED;
+  cp_plan p = new (std::nothrow) cp_plan_s();
+  if (!p) return CP_ERR_HIP;
+  p->N = order;
+  p->R = rank;
+  for (int m = 0; m < order; ++m) p->dims[m] = dims[m];
+  p->prec = prec;
+  p->tree = tree;
+  p->st = (hipStream_t)hip_stream;
+  p->esz = (prec == CP_F64) ? 8 : 4;
+  plan_layout(p);
+  *out = p;
+  return CP_OK;
+}
+
+cp_status cp_plan_workspace_size(cp_plan p, size_t* bytes) {
+  if (!p || !bytes) return CP_ERR_ARG;
+  *bytes = p->ws_need;
+  return CP_OK;
+}
+
+cp_status cp_plan_set_workspace(cp_plan p, void* dptr, size_t bytes) {
+  if (!p || !dptr) return CP_ERR_ARG;
+  if (bytes < p->ws_need) return fail(p, CP_ERR_ARG, "workspace of %zu bytes, need %zu", bytes, p->ws_need);
+  if (((uintptr_t)dptr) % kAlign) return fail(p, CP_ERR_ARG, "workspace not 256-byte aligned");
+  p->ws = (char*)dptr;
+  p->ws_bytes = bytes;
+  plan_carve(p);
+  drop_cache(p);
+  HIP_TRY(p, hipMemsetAsync(p->stats, 0, sizeof(DevStats), p->st));
+  return CP_OK;
+}
+
+cp_status cp_set_tensor(cp_plan p, const void* T) {
+  if (!p || !T) return CP_ERR_ARG;
+  if (!p->ws) return fail(p, CP_ERR_STATE, "no workspace attached");
+  p->T = T;
+  drop_cache(p);
+  HIP_TRY(p, hipMemsetAsync(&p->stats->status, 0, sizeof(int), p->st));
+  int64_t numel = 1;
+  for (int m = 0; m < p->N; ++m) numel *= p->dims[m];
+  if (p->prec == CP_F64) {
+    HIP_TRY(p, launch_norm2<double>((const double*)T, numel, p->normParts, kNormParts, p->stats, p->st));
+  } else {
+    HIP_TRY(p, launch_norm2<float>((const float*)T, numel, p->normParts, kNormParts, p->stats, p->st));
+  }
+  return CP_OK;
+}
+
+cp_status cp_mttkrp(cp_plan p, const double* const* A, int mode, double* M) {
+  CP_TRY(check_ready(p));
+  if (!A || !M || mode < 0 || mode >= p->N) return fail(p, CP_ERR_ARG, "bad argument");
+  for (int m = 0; m < p->N; ++m)
+    if (m != mode && !A[m]) return fail(p, CP_ERR_ARG, "null factor %d", m);
+  drop_cache(p);
+  for (int m = 0; m < p->N; ++m) {
+    if (m == mode) continue;
+    CP_TRY(convert_factor(p, A[m], p->Ash[m], p->dims[m] * p->R));
+    ++p->ver[m];
+  }
+  p->ttm_count = 0;
+  return run_path(p, dt_path(p->N, mode), M);
+}
+
+cp_status cp_mttkrp_rooted(cp_plan p, const double* const* A, int mode, int root_mode, double* M) {
+  CP_TRY(check_ready(p));
+  if (!A || !M || mode < 0 || mode >= p->N || root_mode < 0 || root_mode >= p->N || root_mode == mode)
+    return fail(p, CP_ERR_ARG, "bad argument");
+  for (int m = 0; m < p->N; ++m)
+    if (m != mode && !A[m]) return fail(p, CP_ERR_ARG, "null factor %d", m);
+  drop_cache(p);
+  for (int m = 0; m < p->N; ++m) {
+    if (m == mode) continue;
+    CP_TRY(convert_factor(p, A[m], p->Ash[m], p->dims[m] * p->R));
+    ++p->ver[m];
+  }
+  std::vector<int> seq{root_mode};
+  for (int m = 0; m < p->N; ++m)
+    if (m != mode && m != root_mode) seq.push_back(m);
+  p->ttm_count = 0;
+  return run_path(p, seq, M);
+}
+
+cp_status cp_als_sweep(cp_plan p, double* const* A, cp_sweep_info* info) {
+  CP_TRY(check_ready(p));
+  if (!check_factor_ptrs(A, p->N)) return fail(p, CP_ERR_ARG, "null factor pointer");
+  if (!p->state_ready) CP_TRY(init_state(p, A));
+  p->ttm_count = 0;
+  CP_TRY(exact_sweep(p, A));
+  if (info) return fill_info(p, info, CP_SWEEP_EXACT);
+  return CP_OK;
+}
+
+cp_status cp_pp_sweep(cp_plan p, double* const* A, double pp_tol, cp_pp_mode mode, cp_sweep_info* info) {
+  CP_TRY(check_ready(p));
+  if (!check_factor_ptrs(A, p->N)) return fail(p, CP_ERR_ARG, "null factor pointer");
+  if (mode < CP_PP_AUTO || mode > CP_PP_FORCE_REINIT) return fail(p, CP_ERR_ARG, "bad PP mode");
+  if (!p->state_ready) CP_TRY(init_state(p, A));
+  int kind;
+  if (mode == CP_PP_AUTO) {
+    if (!(pp_tol > 0.0)) return fail(p, CP_ERR_ARG, "pp_tol must be positive");
+    bool ok = false;
+    if (!p->fresh) {
+      DevStats h;
+      CP_TRY(read_stats(p, &h));
+      ok = true;
+      for (int m = 0; m < p->N; ++m)
+        if (!(std::sqrt(h.normdA2[m]) < pp_tol * std::sqrt(h.normA2[m]))) ok = false;
+    }
+    kind = !ok ? CP_SWEEP_EXACT : (p->phase == 1 ? CP_SWEEP_PP_APPROX : CP_SWEEP_PP_INIT);
+  } else if (mode == CP_PP_FORCE_EXACT) {
+    kind = CP_SWEEP_EXACT;
+  } else if (mode == CP_PP_FORCE_APPROX) {
+    if (!p->have_ops || p->phase != 1)
+      return fail(p, CP_ERR_STATE, "approximated sweep requested outside the PP phase");
+    kind = CP_SWEEP_PP_APPROX;
+  } else {
+    kind = CP_SWEEP_PP_INIT;
+  }
+  p->ttm_count = 0;
+  if (kind == CP_SWEEP_EXACT) {
+    CP_TRY(exact_sweep(p, A));
+  } else {
+    if (kind == CP_SWEEP_PP_INIT) CP_TRY(pp_init(p, A));
+    CP_TRY(approx_sweep(p, A));
+  }
+  if (info) return fill_info(p, info, kind);
+  return CP_OK;
+}
+
+cp_status cp_reset(cp_plan p) {
+  if (!p) return CP_ERR_ARG;
+  drop_cache(p);
+  if (p->ws) HIP_TRY(p, hipMemsetAsync(&p->stats->status, 0, sizeof(int), p->st));
+  return CP_OK;
+}
+
+cp_status cp_sync(cp_plan p) {
+  if (!p) return CP_ERR_ARG;
+  if (!p->ws) {
+    HIP_TRY(p, hipStreamSynchronize(p->st));
+    return CP_OK;
+  }
+  DevStats h;
+  CP_TRY(read_stats(p, &h));
+  if (h.status & 1) return fail(p, CP_ERR_NOT_SPD, "a Gamma matrix was not numerically positive definite");
+  if (h.status & 2) return fail(p, CP_ERR_NUMERIC, "non-finite residual");
+  return CP_OK;
+}
+
+cp_status cp_profile_enable(cp_plan p, int on) {
+  if (!p) return CP_ERR_ARG;
+  p->prof = (on != 0);
+  return CP_OK;
+}
+
+cp_status cp_profile_read(cp_plan p, double* ms, int64_t* launches) {
+  if (!p || !ms || !launches) return CP_ERR_ARG;
+  for (int c = 0; c < CP_PHASE_COUNT; ++c) {
+    ms[c] = 0.0;
+    launches[c] = 0;
+  }
+  HIP_TRY(p, hipStreamSynchronize(p->st));
+  cp_status st = CP_OK;
+  for (auto& m : p->marks) {
+    float t = 0.f;
+    hipError_t e = hipEventElapsedTime(&t, m.a, m.b);
+    if (e != hipSuccess && st == CP_OK)
+      st = fail(p, CP_ERR_HIP, "hipEventElapsedTime failed: %s", hipGetErrorString(e));
+    ms[m.cat] += t;
+    launches[m.cat] += 1;
+    p->pool.push_back(m.a);
+    p->pool.push_back(m.b);
+  }
+  p->marks.clear();
+  return st;
+}
+
+cp_status cp_plan_destroy(cp_plan p) {
+  if (!p) return CP_ERR_ARG;
+  for (auto& m : p->marks) {
+    hipEventDestroy(m.a);
+    hipEventDestroy(m.b);
+  }
+  for (auto e : p->pool) hipEventDestroy(e);
+  delete p;
+  return CP_OK;
+}
+
+const char* cp_status_str(cp_status s) {
+  switch (s) {
+    case CP_OK: return "ok";
+    case CP_ERR_ARG: return "invalid argument";
+    case CP_ERR_STATE: return "call out of order";
+    case CP_ERR_UNSUPPORTED: return "unsupported size or option";
+    case CP_ERR_HIP: return "HIP runtime error";
+    case CP_ERR_NOT_SPD: return "Gamma not positive definite";
+    case CP_ERR_NUMERIC: return "non-finite result";
+  }
+  return "unknown status";
+}
+
+const char* cp_last_error(cp_plan p) {
+  if (!p) return "null plan";
+  return p->err.c_str();
+}
+
+}  // extern "C"

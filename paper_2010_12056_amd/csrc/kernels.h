@@ -1,0 +1,112 @@
+// Internal launch interface of the gfx950 kernels (not part of the C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cpals {
+
+// Device-resident scalars of a plan.
+struct DevStats {
+  double normT2;      // ||T||_F^2
+  double fit_num;     // ||T||^2 + <Gamma^(N), S^(N)> - 2 <M^(N), A^(N)>
+  double r;           // relative residual, Eq. (3)
+  double normA2[8];   // ||A^(i)||_F^2 after its last update
+  double normdA2[8];  // ||dA^(i)||_F^2 (per-sweep change, or A - A_p in the PP phase)
+  int status;         // bit 0: a Gamma was not SPD; bit 1: non-finite residual
+  int pad;
+};
+
+constexpr int kMaxOrder = 8;
+constexpr int kMaxRank = 128;
+constexpr int kSolveRows = 16;  // factor rows per workgroup in the solve/Gram kernel
+
+// C[p][q][r] = sum_k X[p][k][q] * B[k][r]  (Q == 1: X is [P][K] row-major).
+template <typename T>
+hipError_t launch_ttm(const T* X, const T* B, T* C, int64_t P, int64_t K, int64_t Q, int R,
+                      hipStream_t st);
+
+// Y[p][q][r] = sum_i X[p][i][q][r] * A[i][r]; accumulation in the output type.
+template <typename TI, typename TO>
+hipError_t launch_mttv(const TI* X, const TI* A, TO* Y, int64_t P, int64_t I, int64_t Q, int R,
+                       hipStream_t st);
+
+// dst[i] = (T) src[i] for n elements.
+template <typename T>
+hipError_t launch_convert(const double* src, T* dst, int64_t n, hipStream_t st);
+
+// FP64 copy, dst[i] = src[i] (n elements).
+hipError_t launch_copy_f64(const double* src, double* dst, int64_t n, hipStream_t st);
+
+// ||T||^2 into stats->normT2 (two deterministic passes using `partials`).
+template <typename T>
+hipError_t launch_norm2(const T* X, int64_t n, double* partials, int nparts, DevStats* stats,
+                        hipStream_t st);
+
+// S = A^T A for an s x R FP64 matrix (one workgroup, fixed order).
+hipError_t launch_gram(const double* A, int64_t s, int R, double* S, hipStream_t st);
+
+// Gamma^(n) = Hadamard of S[m], m != n (Eq. (1)); Ginv = Gamma^-1 by in-place
+// Gauss-Jordan elimination (SPD, no pivoting, failure flagged in stats);
+// W = bracket of Eq. (7) when pp != 0.
+struct PrepArgs {
+  const double* S[kMaxOrder];
+  const double* dS[kMaxOrder];
+  double* Gamma;
+  double* Ginv;
+  double* W;
+  DevStats* stats;
+  int N, n, R, pp;
+};
+hipError_t launch_prep(const PrepArgs& a, hipStream_t st);
+
+// Row-block solve and partial reductions for one mode update.
+template <typename T>
+struct SolveArgs {
+  const double* M;    // s x R right-hand side (exact or first-order PP MTTKRP)
+  double* A;          // s x R FP64 factor, read (old) and overwritten (new)
+  T* Ash;             // s x R shadow of the new factor in tensor precision
+  const double* Ap;   // PP: A_p of this mode (else null)
+  T* dAsh;            // PP: shadow of dA = A - A_p (else null)
+  const double* W;    // PP: bracket of Eq. (7) (else null)
+  const double* Ginv;
+  double* partS;      // [nblk][R][R]
+  double* partdS;     // PP: [nblk][R][R]
+  double* partSc;     // [nblk][4]: ||A||^2, ||dA||^2, <M, A>
+  int64_t s;
+  int R, pp;
+};
+template <typename T>
+hipError_t launch_solve(const SolveArgs<T>& a, int nblk, hipStream_t st);
+
+struct FinalArgs {
+  const double* partS;
+  const double* partdS;
+  const double* partSc;
+  const double* Gamma;
+  double* S;   // S^(n) out
+  double* dS;  // PP: dS^(n) out
+  DevStats* stats;
+  int nblk, R, n, last, pp;
+};
+hipError_t launch_finalize(const FinalArgs& a, hipStream_t st);
+
+// Zero n doubles; zero `bytes` bytes (a multiple of 4) of any buffer.
+hipError_t launch_zero_f64(double* p, int64_t n, hipStream_t st);
+hipError_t launch_zero_bytes(void* p, size_t bytes, hipStream_t st);
+
+// First-order PP MTTKRP, Eqs. (5)-(6) without V:
+// M[x][r] = Mp[x][r] + sum_{i != n} sum_y P_(n,i)[x][y][r] dA_i[y][r]
+template <typename T>
+struct PPArgs {
+  const T* pair[kMaxOrder];  // operator of the pair {n, i} (null for i == n)
+  int pair_n_first[kMaxOrder];  // 1 if stored with n's axis first
+  const T* dA[kMaxOrder];
+  int64_t dims[kMaxOrder];
+  const double* Mp;
+  double* M;
+  int N, n, R;
+};
+template <typename T>
+hipError_t launch_pp_mttkrp(const PPArgs<T>& a, hipStream_t st);
+
+}  // namespace cpals

@@ -1,0 +1,82 @@
+"""The C ABI library builds, loads and exports every declared symbol; host-only
+argument checks (no device work, no GPU needed)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "cpals.h")
+
+
+def _lib():
+    from paper_2010_12056_amd import build_lib, cpals
+
+    if not os.path.exists(cpals.LIB_PATH):
+        build_lib.build()
+    return cpals.lib()
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cp_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_entry_points():
+    names = _declared()
+    for required in ("cp_mttkrp", "cp_als_sweep", "cp_pp_sweep", "cp_plan_create", "cp_set_tensor"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib()
+    for name in _declared():
+        assert hasattr(L, name), name
+    # and the binding declares a signature for each of them
+    from paper_2010_12056_amd import cpals
+
+    assert set(_declared()) == set(cpals.EXPORTS)
+
+
+def test_status_strings():
+    L = _lib()
+    for s in range(7):
+        assert L.cp_status_str(s)
+    assert L.cp_status_str(99) == b"unknown status"
+
+
+def test_plan_create_argument_checks():
+    from paper_2010_12056_amd import cpals
+
+    L = _lib()
+    h = ctypes.c_void_p()
+    dims = (ctypes.c_int64 * 4)(8, 8, 8, 8)
+    assert L.cp_plan_create(ctypes.byref(h), 2, dims, 4, cpals.CP_F32, cpals.CP_TREE_DT, None) == cpals.CP_ERR_UNSUPPORTED
+    assert L.cp_plan_create(ctypes.byref(h), 4, dims, 0, cpals.CP_F32, cpals.CP_TREE_DT, None) == cpals.CP_ERR_UNSUPPORTED
+    assert L.cp_plan_create(ctypes.byref(h), 4, dims, 129, cpals.CP_F32, cpals.CP_TREE_DT, None) == cpals.CP_ERR_UNSUPPORTED
+    assert L.cp_plan_create(ctypes.byref(h), 4, dims, 4, 7, cpals.CP_TREE_DT, None) == cpals.CP_ERR_UNSUPPORTED
+    bad = (ctypes.c_int64 * 4)(8, 0, 8, 8)
+    assert L.cp_plan_create(ctypes.byref(h), 4, bad, 4, cpals.CP_F32, cpals.CP_TREE_DT, None) == cpals.CP_ERR_ARG
+    assert L.cp_plan_create(None, 4, dims, 4, cpals.CP_F32, cpals.CP_TREE_DT, None) == cpals.CP_ERR_ARG
+
+
+def test_workspace_size_and_state_errors():
+    from paper_2010_12056_amd import cpals
+
+    L = _lib()
+    h = ctypes.c_void_p()
+    dims = (ctypes.c_int64 * 4)(128, 128, 128, 128)
+    assert L.cp_plan_create(ctypes.byref(h), 4, dims, 64, cpals.CP_F32, cpals.CP_TREE_MSDT, None) == cpals.CP_OK
+    n = ctypes.c_size_t()
+    assert L.cp_plan_workspace_size(h, ctypes.byref(n)) == cpals.CP_OK
+    # one first-level node (128^3 x 64 FP32 = 512 MiB) dominates
+    assert 512 * 2**20 < n.value < 600 * 2**20
+    # no workspace, no tensor: sweeps refuse before touching the device
+    A = (ctypes.c_void_p * 4)()
+    assert L.cp_als_sweep(h, A, None) == cpals.CP_ERR_STATE
+    assert b"workspace" in L.cp_last_error(h)
+    assert L.cp_plan_set_workspace(h, ctypes.c_void_p(256), 16) == cpals.CP_ERR_ARG
+    assert L.cp_plan_destroy(h) == cpals.CP_OK

@@ -1,0 +1,50 @@
+"""Full-size order-4 128^4 FP32 workload (R = 64) against the FP64 oracle."""
+
+import numpy as np
+import pytest
+
+from gpu_util import relerr, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _plan(w, prec, tree, dev):
+    from paper_2010_12056_amd import cpals
+
+    plan = cpals.Plan(w.dims, w.R, prec=prec, tree=tree, device=dev)
+    T = torch.from_numpy(w.T).to(dev)
+    plan.set_tensor(T)
+    return plan, T, to_dev(w.init, dev)
+
+
+def test_o4_s128_r64_dt_msdt_against_oracle(dev):
+    """Full-size order-4 128^4 FP32 workload, R = 64: three DT and three MSDT
+    sweeps against the FP64 oracle (free running, same init)."""
+    import oracle
+    from paper_2010_12056_amd import synth
+
+    say("case full-size o4_s128_r64_f32 sweeps")
+    w = synth.workload("o4_s128_r64_f32")
+    T64 = w.T.astype(np.float64)
+    st = oracle.AlsState.start(T64, w.init)
+    refs = [oracle.als_sweep(st) for _ in range(3)]
+    for tree in ("dt", "msdt"):
+        plan, T, A = _plan(w, "f32", tree, dev)
+        for s in range(3):
+            info = plan.als_sweep(A)
+            say(f"  {tree} sweep {s} r={info['r']:.10f} oracle={refs[s]:.10f}")
+            assert abs(info["r"] - refs[s]) <= 1e-6
+        for n in range(4):
+            assert relerr(A[n].cpu().numpy(), st.A[n]) <= 1e-4
+        plan.close()
+        del T
+        torch.cuda.empty_cache()

@@ -90,6 +90,11 @@ struct cp_plan_s {
   bool fresh = true;  // no sweep since the state was (re)initialized: dA = A
   int ttm_count = 0;
 
+  // second stream: the Gamma / inverse kernel of a mode update runs there,
+  // concurrently with that mode's MTTKRP on the plan stream (fork/join events)
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+
   // phase timers: a HIP event pair around every launch group, by category
   bool prof = false;
   struct Mark {
@@ -143,17 +148,19 @@ hipEvent_t get_event(cp_plan p) {
 struct ProfScope {
   cp_plan p;
   int cat;
+  hipStream_t st;
   hipEvent_t a = nullptr;
-  ProfScope(cp_plan p_, int cat_) : p(p_), cat(cat_) {
+  ProfScope(cp_plan p_, int cat_) : ProfScope(p_, cat_, p_->st) {}
+  ProfScope(cp_plan p_, int cat_, hipStream_t st_) : p(p_), cat(cat_), st(st_) {
     if (p->prof) {
       a = get_event(p);
-      if (a && hipEventRecord(a, p->st) != hipSuccess) a = nullptr;
+      if (a && hipEventRecord(a, st) != hipSuccess) a = nullptr;
     }
   }
   ~ProfScope() {
     if (!a) return;
     hipEvent_t b = get_event(p);
-    if (b && hipEventRecord(b, p->st) == hipSuccess) p->marks.push_back({a, b, cat});
+    if (b && hipEventRecord(b, st) == hipSuccess) p->marks.push_back({a, b, cat});
   }
 };
 
@@ -176,7 +183,7 @@ void plan_layout(cp_plan p) {
   };
   int64_t smax = 0;
   for (int m = 0; m < N; ++m) smax = std::max(smax, p->dims[m]);
-  p->nblk_max = (int)((smax + kSolveRows - 1) / kSolveRows);
+  p->nblk_max = (int)((smax + solve_rows(R) - 1) / solve_rows(R));
   // fixed order of regions; set_workspace replays it
   for (int m = 0; m < N; ++m) take((size_t)p->dims[m] * R * p->esz);      // Ash
   for (int m = 0; m < N; ++m) take((size_t)p->dims[m] * R * p->esz);      // dAsh
@@ -374,25 +381,56 @@ std::vector<int> msdt_path(int N, int64_t u) {
 // ---------------------------------------------------------------------------
 // Mode update (Alg. 1 / Alg. 2 inner body), M in p->Mbuf.
 // ---------------------------------------------------------------------------
-template <typename TT>
-cp_status update_mode_t(cp_plan p, int n, double* A, bool pp) {
-  const int R = p->R;
-  PrepArgs pa{};
-  for (int m = 0; m < p->N; ++m) {
-    pa.S[m] = p->S[m];
-    pa.dS[m] = p->dS[m];
+cp_status ensure_aux(cp_plan p) {
+  if (p->aux) return CP_OK;
+  HIP_TRY(p, hipStreamCreateWithFlags(&p->aux, hipStreamNonBlocking));
+  HIP_TRY(p, hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming));
+  HIP_TRY(p, hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming));
+  return CP_OK;
+}
+
+// Gamma^(n)^-1 on the second stream.  Gamma^(n) (and W^(n)) were formed by
+// the previous update's finalize (or at state setup), so the inverse depends
+// only on the Gram matrices and overlaps the MTTKRP of the same mode.
+cp_status launch_prep_forked(cp_plan p, int n, bool pp) {
+  (void)n;
+  (void)pp;
+  CP_TRY(ensure_aux(p));
+  HIP_TRY(p, hipEventRecord(p->ev_fork, p->st));
+  HIP_TRY(p, hipStreamWaitEvent(p->aux, p->ev_fork, 0));
+  {
+    ProfScope ps(p, CP_PHASE_UPDATE, p->aux);
+    HIP_TRY(p, launch_inverse(p->Gamma, p->Ginv, p->R, p->stats, p->aux));
   }
-  pa.Gamma = p->Gamma;
-  pa.Ginv = p->Ginv;
-  pa.W = p->W;
-  pa.stats = p->stats;
-  pa.N = p->N;
-  pa.n = n;
-  pa.R = R;
-  pa.pp = pp ? 1 : 0;
+  HIP_TRY(p, hipEventRecord(p->ev_join, p->aux));
+  return CP_OK;
+}
+
+// Gamma^(n) and W^(n) from the current Gram matrices (state setup).
+cp_status form_gamma(cp_plan p, int n, bool pp) {
+  GammaArgs ga{};
+  for (int m = 0; m < p->N; ++m) {
+    ga.S[m] = p->S[m];
+    ga.dS[m] = p->dS[m];
+  }
+  ga.Gamma = p->Gamma;
+  ga.W = p->W;
+  ga.N = p->N;
+  ga.n = n;
+  ga.R = p->R;
+  ga.pp = pp ? 1 : 0;
+  HIP_TRY(p, launch_gamma(ga, p->st));
+  return CP_OK;
+}
+
+// Rest of a mode update on the plan stream once the prep has joined:
+// A^(n) <- M Gamma^-1 (with V^(n) in PP), shadows, Gram, norms, residual.
+template <typename TT>
+cp_status finish_update_t(cp_plan p, int n, double* A, bool pp) {
+  const int R = p->R;
+  HIP_TRY(p, hipStreamWaitEvent(p->st, p->ev_join, 0));
   ProfScope ps(p, CP_PHASE_UPDATE);
-  HIP_TRY(p, launch_prep(pa, p->st));
-  const int nblk = (int)((p->dims[n] + kSolveRows - 1) / kSolveRows);
+  const int nblk = (int)((p->dims[n] + solve_rows(R) - 1) / solve_rows(R));
   SolveArgs<TT> sa{};
   sa.M = p->Mbuf;
   sa.A = A;
@@ -401,34 +439,39 @@ cp_status update_mode_t(cp_plan p, int n, double* A, bool pp) {
   sa.dAsh = pp ? (TT*)p->dAsh[n] : nullptr;
   sa.W = pp ? p->W : nullptr;
   sa.Ginv = p->Ginv;
+  sa.Gamma = p->Gamma;
   sa.partS = p->partS;
   sa.partdS = p->partdS;
   sa.partSc = p->partSc;
   sa.s = p->dims[n];
   sa.R = R;
-  sa.pp = pa.pp;
+  sa.pp = pp ? 1 : 0;
   HIP_TRY(p, launch_solve<TT>(sa, nblk, p->st));
   FinalArgs fa{};
   fa.partS = p->partS;
   fa.partdS = p->partdS;
   fa.partSc = p->partSc;
+  for (int m = 0; m < p->N; ++m) {
+    fa.S[m] = p->S[m];
+    fa.dS[m] = p->dS[m];
+  }
   fa.Gamma = p->Gamma;
-  fa.S = p->S[n];
-  fa.dS = p->dS[n];
+  fa.W = p->W;
   fa.stats = p->stats;
   fa.nblk = nblk;
   fa.R = R;
   fa.n = n;
+  fa.N = p->N;
   fa.last = (n == p->N - 1) ? 1 : 0;
-  fa.pp = pa.pp;
+  fa.pp = sa.pp;
   HIP_TRY(p, launch_finalize(fa, p->st));
   ++p->ver[n];
   return CP_OK;
 }
 
-cp_status update_mode(cp_plan p, int n, double* A, bool pp) {
-  if (p->prec == CP_F64) return update_mode_t<double>(p, n, A, pp);
-  return update_mode_t<float>(p, n, A, pp);
+cp_status finish_update(cp_plan p, int n, double* A, bool pp) {
+  if (p->prec == CP_F64) return finish_update_t<double>(p, n, A, pp);
+  return finish_update_t<float>(p, n, A, pp);
 }
 
 cp_status convert_factor(cp_plan p, const double* src, void* dst, int64_t n) {
@@ -455,6 +498,8 @@ cp_status init_state(cp_plan p, double* const* A) {
     HIP_TRY(p, launch_zero_f64(p->dS[m], (int64_t)p->R * p->R, p->st));
     ++p->ver[m];
   }
+  CP_TRY(form_gamma(p, 0, false));
+  HIP_TRY(p, launch_zero_f64(p->W, (int64_t)p->R * p->R, p->st));
   p->state_ready = true;
   p->fresh = true;
   return CP_OK;
@@ -486,8 +531,9 @@ cp_status fill_info(cp_plan p, cp_sweep_info* info, int kind) {
 cp_status exact_sweep(cp_plan p, double* const* A) {
   for (int n = 0; n < p->N; ++n) {
     std::vector<int> seq = (p->tree == CP_TREE_MSDT) ? msdt_path(p->N, p->msdt_u++) : dt_path(p->N, n);
+    CP_TRY(launch_prep_forked(p, n, false));
     CP_TRY(run_path(p, seq, p->Mbuf));
-    CP_TRY(update_mode(p, n, A[n], false));
+    CP_TRY(finish_update(p, n, A[n], false));
   }
   p->phase = 0;
   p->fresh = false;
@@ -574,6 +620,8 @@ cp_status pp_init(cp_plan p, double* const* A) {
     HIP_TRY(p, launch_copy_f64(A[m], p->Ap[m], p->dims[m] * p->R, p->st));
     HIP_TRY(p, launch_zero_f64(p->dS[m], (int64_t)p->R * p->R, p->st));
   }
+  // dA = 0, so dS = 0 and W^(0) = 0; Gamma^(0) is current (S unchanged)
+  HIP_TRY(p, launch_zero_f64(p->W, (int64_t)p->R * p->R, p->st));
   // relabel so that the first root is the live first-level node, if any
   int live = -1;
   for (int m = 0; m < N; ++m)
@@ -621,12 +669,13 @@ cp_status pp_first_order(cp_plan p, int n) {
 
 cp_status approx_sweep(cp_plan p, double* const* A) {
   for (int n = 0; n < p->N; ++n) {
+    CP_TRY(launch_prep_forked(p, n, true));
     if (p->prec == CP_F64) {
       CP_TRY(pp_first_order<double>(p, n));
     } else {
       CP_TRY(pp_first_order<float>(p, n));
     }
-    CP_TRY(update_mode(p, n, A[n], true));
+    CP_TRY(finish_update(p, n, A[n], true));
   }
   p->fresh = false;
   return CP_OK;
@@ -819,6 +868,7 @@ cp_status cp_profile_read(cp_plan p, double* ms, int64_t* launches) {
     launches[c] = 0;
   }
   HIP_TRY(p, hipStreamSynchronize(p->st));
+  if (p->aux) HIP_TRY(p, hipStreamSynchronize(p->aux));
   cp_status st = CP_OK;
   for (auto& m : p->marks) {
     float t = 0.f;
@@ -841,6 +891,12 @@ cp_status cp_plan_destroy(cp_plan p) {
     hipEventDestroy(m.b);
   }
   for (auto e : p->pool) hipEventDestroy(e);
+  if (p->aux) {
+    hipStreamSynchronize(p->aux);
+    hipStreamDestroy(p->aux);
+    hipEventDestroy(p->ev_fork);
+    hipEventDestroy(p->ev_join);
+  }
   delete p;
   return CP_OK;
 }

@@ -18,7 +18,8 @@ struct DevStats {
 
 constexpr int kMaxOrder = 8;
 constexpr int kMaxRank = 128;
-constexpr int kSolveRows = 16;  // factor rows per workgroup in the solve/Gram kernel
+// factor rows per workgroup in the solve/Gram kernel (one 16-row MFMA block)
+__host__ __device__ inline int solve_rows(int) { return 16; }
 
 // C[p][q][r] = sum_k X[p][k][q] * B[k][r]  (Q == 1: X is [P][K] row-major).
 template <typename T>
@@ -45,19 +46,20 @@ hipError_t launch_norm2(const T* X, int64_t n, double* partials, int nparts, Dev
 // S = A^T A for an s x R FP64 matrix (one workgroup, fixed order).
 hipError_t launch_gram(const double* A, int64_t s, int R, double* S, hipStream_t st);
 
-// Gamma^(n) = Hadamard of S[m], m != n (Eq. (1)); Ginv = Gamma^-1 by in-place
-// Gauss-Jordan elimination (SPD, no pivoting, failure flagged in stats);
-// W = bracket of Eq. (7) when pp != 0.
-struct PrepArgs {
+// Gamma^(n) = Hadamard product of S[m], m != n (Eq. (1)) and, when pp != 0,
+// W^(n) = the bracket of Eq. (7), both entrywise into Gamma / W.
+struct GammaArgs {
   const double* S[kMaxOrder];
   const double* dS[kMaxOrder];
   double* Gamma;
-  double* Ginv;
   double* W;
-  DevStats* stats;
   int N, n, R, pp;
 };
-hipError_t launch_prep(const PrepArgs& a, hipStream_t st);
+hipError_t launch_gamma(const GammaArgs& a, hipStream_t st);
+
+// Ginv = Gamma^-1 (Gamma SPD; Gauss-Jordan without pivoting in one
+// workgroup; a non-positive pivot sets bit 0 of stats->status and zeroes Ginv).
+hipError_t launch_inverse(const double* Gamma, double* Ginv, int R, DevStats* stats, hipStream_t st);
 
 // Row-block solve and partial reductions for one mode update.
 template <typename T>
@@ -69,24 +71,29 @@ struct SolveArgs {
   T* dAsh;            // PP: shadow of dA = A - A_p (else null)
   const double* W;    // PP: bracket of Eq. (7) (else null)
   const double* Ginv;
+  const double* Gamma;  // for this block's <Gamma, S_part>
   double* partS;      // [nblk][R][R]
   double* partdS;     // PP: [nblk][R][R]
-  double* partSc;     // [nblk][4]: ||A||^2, ||dA||^2, <M, A>
+  double* partSc;     // [nblk][4]: ||A||^2, ||dA||^2, <M, A>, <Gamma, S_part>
   int64_t s;
   int R, pp;
 };
 template <typename T>
 hipError_t launch_solve(const SolveArgs<T>& a, int nblk, hipStream_t st);
 
+// Sums the row-block partials of mode n into S^(n) (and dS^(n)), the
+// norms and (after the last mode) the residual; then forms Gamma and W of the
+// next mode, nx = (n + 1) mod N, from the updated Gram matrices.
 struct FinalArgs {
   const double* partS;
   const double* partdS;
   const double* partSc;
-  const double* Gamma;
-  double* S;   // S^(n) out
-  double* dS;  // PP: dS^(n) out
+  double* S[kMaxOrder];   // S^(m); S[n] is written
+  double* dS[kMaxOrder];  // dS^(m); dS[n] is written when pp
+  double* Gamma;          // out: Gamma^(nx)
+  double* W;              // out: W^(nx) (from the current dS, meaningful in PP sweeps)
   DevStats* stats;
-  int nblk, R, n, last, pp;
+  int nblk, R, n, N, last, pp;
 };
 hipError_t launch_finalize(const FinalArgs& a, hipStream_t st);
 

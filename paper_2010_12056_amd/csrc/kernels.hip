@@ -50,6 +50,8 @@ struct Mma<double> {
   __device__ static inline int row(int lane, int v) { return (lane >> 4) + 4 * v; }
 };
 
+constexpr int kTtmWaves = 8;  // waves per workgroup of the resident-factor kernels
+constexpr int kTtmThreads = kTtmWaves * 64;
 constexpr int TBM = 128;  // output rows per workgroup (4 waves x 32)
 constexpr int TBN = 64;   // output columns (rank entries) per workgroup
 constexpr int TBK = 32;   // contraction depth per LDS stage
@@ -141,6 +143,296 @@ __global__ __launch_bounds__(256) void k_ttm(const T* __restrict__ X, const T* _
       }
 }
 
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<float> {
+  typedef f32x4 type;
+};
+template <>
+struct Vec16<double> {
+  typedef double __attribute__((ext_vector_type(2))) type;
+};
+
+// First-level contraction with the factor resident in LDS (K <= 256).
+//   C[p][q][r] = sum_k X[p][k][q] * B[k][r]
+// The factor sits transposed (Bt[c][k], row pitch Kp + V) for the whole
+// workgroup.  Each wave owns 32-row x 16*NCB-column output tiles and walks
+// them grid-stride.  The contraction index is permuted so that a lane feeds
+// V = 16 / sizeof(T) consecutive k values to V consecutive MFMA steps: lane
+// (row, g = lane / 16) supplies k = kc + t*4V + g*V + u at step (t, u), which
+// turns the row-contiguous case (KC) into one 16-byte load per lane and the
+// factor side into one 16-byte LDS read per lane.
+template <typename T, bool KC, int NCB>
+__global__ __launch_bounds__(512) void k_ttm_rb(const T* __restrict__ X, const T* __restrict__ B,
+                                                T* __restrict__ C, int64_t P, int64_t K, int64_t Q,
+                                                int R, int64_t tilesQ, int64_t ntiles, int Kp, int vec) {
+  constexpr int V = 16 / sizeof(T);
+  constexpr int KT = 4 * V;
+  constexpr int NTS = KC ? 8 : 4;  // t steps per register chunk (NTS * KT k values)
+  typedef typename Vec16<T>::type VT;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  T* Bt = (T*)lds_raw;
+  const int pitch = Kp + V;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, l16 = lane & 15;
+  const int c0 = blockIdx.y * NCB * 16;
+  constexpr int NC = NCB * 16;
+  for (int idx = tid; idx < Kp * NC; idx += kTtmThreads) {
+    const int k = idx / NC, col = idx - k * NC;
+    Bt[col * pitch + k] = (k < K && c0 + col < R) ? B[(int64_t)k * R + c0 + col] : T(0);
+  }
+  __syncthreads();
+  for (int64_t tile = (int64_t)blockIdx.x * kTtmWaves + wave; tile < ntiles;
+       tile += (int64_t)gridDim.x * kTtmWaves) {
+    // keep the factor reads inside the loop (re-read from LDS per tile rather
+    // than hoisted into registers), which keeps occupancy high
+    asm volatile("" ::: "memory");
+    int64_t rowbase, nrows;
+    const T* Xb;
+    T* Cb;
+    if (KC) {
+      rowbase = tile * 32;
+      nrows = P;
+      Xb = X;
+      Cb = C;
+    } else {
+      const int64_t p = tile / tilesQ;
+      rowbase = (tile - p * tilesQ) * 32;
+      nrows = Q;
+      Xb = X + p * K * Q;
+      Cb = C + p * Q * R;
+    }
+    typename Mma<T>::acc_t acc[2][NCB];
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) acc[rb][cb] = Mma<T>::zero();
+    for (int kc = 0; kc < Kp; kc += NTS * KT) {
+      VT a[2][NTS];
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb) {
+        const int64_t row = rowbase + rb * 16 + l16;
+        const bool rin = row < nrows;
+        if (KC) {
+          const T* xr = Xb + row * K;
+#pragma unroll
+          for (int t = 0; t < NTS; ++t) {
+            const int64_t k = kc + t * KT + g * V;
+            if (vec && rin && k + V <= K) {
+              a[rb][t] = *(const VT*)(xr + k);
+            } else {
+#pragma unroll
+              for (int u = 0; u < V; ++u) a[rb][t][u] = (rin && k + u < K) ? xr[k + u] : T(0);
+            }
+          }
+        } else {
+          // lane pointer at (k = kc + g*V, q = row); steps add uniform multiples of Q
+          const int kl = kc + g * V;
+          const T* xl = Xb + (int64_t)kl * Q + row;
+#pragma unroll
+          for (int t = 0; t < NTS; ++t)
+#pragma unroll
+            for (int u = 0; u < V; ++u) {
+              const int k = kl + t * KT + u;
+              a[rb][t][u] = (rin && k < K) ? xl[(int64_t)(t * KT + u) * Q] : T(0);
+            }
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < NTS; ++t) {
+        VT b[NCB];
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb)
+          b[cb] = *(const VT*)(Bt + (cb * 16 + l16) * pitch + kc + t * KT + g * V);
+#pragma unroll
+        for (int u = 0; u < V; ++u)
+#pragma unroll
+          for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) acc[rb][cb] = Mma<T>::mma(a[rb][t][u], b[cb][u], acc[rb][cb]);
+      }
+    }
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t row = rowbase + rb * 16 + Mma<T>::row(lane, v);
+          const int c = c0 + cb * 16 + l16;
+          if (row < nrows && c < R) Cb[row * R + c] = acc[rb][cb][v];
+        }
+  }
+}
+
+// First-level contraction over the last mode for K <= 8 * 4V (one register
+// chunk): X is P x K row-major.  16-row output tiles per wave, eight waves
+// per workgroup, the factor transposed in LDS and re-read per tile.  Lane
+// (row, g = lane / 16) feeds k = t*4V + g*V + u at MFMA step (t, u) from one
+// 16-byte load per t.  Rows beyond P are clamped for loads and masked for
+// stores; k beyond K meets zero rows of the staged factor.
+template <typename T, int NCB, bool FULLK>
+__global__ __launch_bounds__(512) void k_ttm_kc(const T* __restrict__ X, const T* __restrict__ B,
+                                                T* __restrict__ C, int64_t P, int64_t K_, int R,
+                                                int64_t ntiles, int vec) {
+  constexpr int V = 16 / sizeof(T);
+  constexpr int KT = 4 * V;
+  constexpr int NTS = 8;
+  constexpr int KP = NTS * KT;
+  constexpr int pitch = KP + V;
+  constexpr int NC = NCB * 16;
+  const int64_t K = FULLK ? (int64_t)KP : K_;  // FULLK: K == KP, 16-byte aligned rows
+  typedef typename Vec16<T>::type VT;
+  __shared__ __align__(16) T Bt[NC * pitch];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, l16 = lane & 15;
+  const int c0 = blockIdx.y * NC;
+  for (int idx = tid; idx < KP * NC; idx += kTtmThreads) {
+    const int k = idx / NC, col = idx - k * NC;
+    Bt[col * pitch + k] = (k < K && c0 + col < R) ? B[(int64_t)k * R + c0 + col] : T(0);
+  }
+  __syncthreads();
+  for (int64_t tile = (int64_t)blockIdx.x * kTtmWaves + wave; tile < ntiles;
+       tile += (int64_t)gridDim.x * kTtmWaves) {
+    asm volatile("" ::: "memory");  // factor reads stay in the loop
+    const bool full_tile = (tile + 1) * 16 <= P;
+    // per-tile base pointers (uniform, 64-bit) and 32-bit lane offsets
+    const T* xt = X + tile * 16 * K;
+    T* ct = C + tile * 16 * R;
+    int lrow = l16;
+    if (!full_tile) {
+      const int64_t last = P - 1 - tile * 16;
+      lrow = lrow < last ? lrow : (int)last;
+    }
+    const T* xr = xt + lrow * (int)K + g * V;
+    VT a[NTS];
+#pragma unroll
+    for (int t = 0; t < NTS; ++t) {
+      const int k = t * KT + g * V;
+      if (FULLK) {
+        a[t] = *(const VT*)(xr + t * KT);
+      } else if (vec) {
+        if (k + V <= K) a[t] = *(const VT*)(xr + t * KT);
+        else a[t] = VT{};
+      } else {
+#pragma unroll
+        for (int u = 0; u < V; ++u) a[t][u] = (k + u < K) ? xr[t * KT + u] : T(0);
+      }
+    }
+    typename Mma<T>::acc_t acc[NCB];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) acc[cb] = Mma<T>::zero();
+#pragma unroll
+    for (int t = 0; t < NTS; ++t) {
+      VT b[NCB];
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) b[cb] = *(const VT*)(Bt + (cb * 16 + l16) * pitch + t * KT + g * V);
+#pragma unroll
+      for (int u = 0; u < V; ++u)
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) acc[cb] = Mma<T>::mma(a[t][u], b[cb][u], acc[cb]);
+    }
+    if (full_tile && c0 + NC <= R) {
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) ct[Mma<T>::row(lane, v) * R + c0 + cb * 16 + l16] = acc[cb][v];
+    } else {
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = Mma<T>::row(lane, v);
+          const int c = c0 + cb * 16 + l16;
+          if (tile * 16 + r < P && c < R) ct[r * R + c] = acc[cb][v];
+        }
+    }
+  }
+}
+
+// First-level contraction when the contracted mode is not the last one
+// (X[p] is K x Q with q contiguous), FP32, factor resident in LDS (K <= 256).
+// A wave owns 64 consecutive q and 16*NCB rank columns.  Lane (i = lane % 16,
+// g = lane / 16) loads X[k][q0 + 4i .. 4i + 3] as one 16-byte load for
+// k = kc + 4t + g, and feeds its four values to four MFMAs u = 0..3 in which
+// it plays row i; MFMA u therefore produces output rows q0 + 4i + u.  A
+// 16-lane group reads 256 contiguous bytes per load.  The factor is stored
+// transposed with k permuted inside each 32-wide chunk (k = kc + 4t + g at
+// position kc + 8g + t) so a lane reads its eight t-values with two 16-byte
+// LDS reads.
+template <int NCB>
+__global__ __launch_bounds__(512) void k_ttm_q(const float* __restrict__ X, const float* __restrict__ B,
+                                               float* __restrict__ C, int64_t P, int64_t K, int64_t Q,
+                                               int R, int64_t tilesQ, int64_t ntiles, int Kp, int vec) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  float* Bt = (float*)lds_raw;
+  const int pitch = Kp + 4;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, l16 = lane & 15;
+  const int c0 = blockIdx.y * NCB * 16;
+  constexpr int NC = NCB * 16;
+  for (int idx = tid; idx < Kp * NC; idx += kTtmThreads) {
+    const int k = idx / NC, col = idx - k * NC;
+    const int kc = k & ~31, kr = k & 31;            // k = kc + 4t + g
+    const int pos = kc + 8 * (kr & 3) + (kr >> 2);  // -> kc + 8g + t
+    Bt[col * pitch + pos] = (k < K && c0 + col < R) ? B[(int64_t)k * R + c0 + col] : 0.f;
+  }
+  __syncthreads();
+  for (int64_t tile = (int64_t)blockIdx.x * kTtmWaves + wave; tile < ntiles;
+       tile += (int64_t)gridDim.x * kTtmWaves) {
+    asm volatile("" ::: "memory");  // factor reads stay in the loop (see k_ttm_rb)
+    const int64_t p = tile / tilesQ;
+    const int64_t q0 = (tile - p * tilesQ) * 64;
+    const float* Xb = X + p * K * Q;
+    float* Cb = C + p * Q * R;
+    const int64_t qa = q0 + 4 * l16;  // this lane's four rows qa .. qa + 3
+    const bool full = vec && qa + 4 <= Q;
+    f32x4 acc[4][NCB];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) acc[u][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int kc = 0; kc < Kp; kc += 32) {
+      f32x4 a[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int64_t k = kc + 4 * t + g;
+        const float* src = Xb + k * Q + qa;
+        if (k < K && full) {
+          a[t] = *(const f32x4*)src;
+        } else {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) a[t][u] = (k < K && qa + u < Q) ? src[u] : 0.f;
+        }
+      }
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) {
+        const float* bp = Bt + (cb * 16 + l16) * pitch + kc + 8 * g;
+        const f32x4 b0 = *(const f32x4*)bp;
+        const f32x4 b1 = *(const f32x4*)(bp + 4);
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          const float bv = t < 4 ? b0[t & 3] : b1[t & 3];
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            acc[u][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t][u], bv, acc[u][cb], 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t q = q0 + 16 * g + 4 * v + u;
+          const int c = c0 + cb * 16 + l16;
+          if (q < Q && c < R) Cb[q * R + c] = acc[u][cb][v];
+        }
+  }
+}
+
 // Y[p][q][r] = sum_i X[p][i][q][r] * A[i][r]; one thread per output element.
 template <typename TI, typename TO>
 __global__ __launch_bounds__(256) void k_mttv(const TI* __restrict__ X, const TI* __restrict__ A,
@@ -161,6 +453,42 @@ __global__ __launch_bounds__(256) void k_mttv(const TI* __restrict__ X, const TI
   }
   for (; i < I; ++i) acc0 += (TO)x[i * QR] * (TO)A[i * R + r];
   Y[g] = (acc0 + acc1) + (acc2 + acc3);
+}
+
+// As k_mttv with four consecutive outputs per thread (R % 4 == 0): 16-byte
+// loads of X and of the factor row.
+template <typename TO>
+__global__ __launch_bounds__(256) void k_mttv4(const float* __restrict__ X, const float* __restrict__ A,
+                                               TO* __restrict__ Y, int64_t total4, int64_t I,
+                                               int64_t QR, int R) {
+  const int64_t g4 = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (g4 >= total4) return;
+  const int64_t g = g4 * 4;
+  const int64_t p = g / QR, j = g - p * QR;
+  const int r = (int)(j % R);
+  const float* x = X + p * I * QR + j;
+  const float* a = A + r;
+  TO s0[4] = {0, 0, 0, 0}, s1[4] = {0, 0, 0, 0};
+  int64_t i = 0;
+  for (; i + 2 <= I; i += 2) {
+    const f32x4 x0 = *(const f32x4*)(x + i * QR);
+    const f32x4 x1 = *(const f32x4*)(x + (i + 1) * QR);
+    const f32x4 a0 = *(const f32x4*)(a + i * R);
+    const f32x4 a1 = *(const f32x4*)(a + (i + 1) * R);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      s0[u] += (TO)x0[u] * (TO)a0[u];
+      s1[u] += (TO)x1[u] * (TO)a1[u];
+    }
+  }
+  if (i < I) {
+    const f32x4 x0 = *(const f32x4*)(x + i * QR);
+    const f32x4 a0 = *(const f32x4*)(a + i * R);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) s0[u] += (TO)x0[u] * (TO)a0[u];
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) Y[g + u] = s0[u] + s1[u];
 }
 
 template <typename T>
@@ -231,165 +559,291 @@ __global__ __launch_bounds__(256) void k_gram(const double* __restrict__ A, int6
   S[e] = acc;
 }
 
-// Gamma^(n), its inverse and (PP) the bracket of Eq. (7).  One workgroup.
-__global__ __launch_bounds__(256) void k_prep(PrepArgs a) {
-  extern __shared__ double lds[];
-  double* g = lds;              // R x R, inverted in place
-  double* col = lds + a.R * a.R;  // R
-  __shared__ int fail;
-  __shared__ double maxdiag;
-  const int tid = threadIdx.x, R = a.R, RR = R * R;
-  for (int e = tid; e < RR; e += 256) {
-    double v = 1.0;
-    for (int m = 0; m < a.N; ++m)
-      if (m != a.n) v *= a.S[m][e];
-    g[e] = v;
-    a.Gamma[e] = v;
-    if (a.pp) {
-      // coefficient of t^2 in the Hadamard product over m != n of (S + t dS)
-      double e0 = 1.0, e1 = 0.0, e2 = 0.0;
-      for (int m = 0; m < a.N; ++m) {
-        if (m == a.n) continue;
-        const double s = a.S[m][e], ds = a.dS[m][e];
-        e2 = e2 * s + e1 * ds;
-        e1 = e1 * s + e0 * ds;
-        e0 = e0 * s;
-      }
-      a.W[e] = e2;
-    }
+// Entry e of Gamma^(n) and of W^(n): the product over m != n of S[m][e]
+// (Eq. (1)) and the coefficient of t^2 in the product over m != n of
+// (S[m][e] + t dS[m][e]), which is the bracket of Eq. (7).
+__device__ inline void gamma_entry(const double* const* S, const double* const* dS, int N, int n,
+                                   int e, bool pp, double* g_out, double* w_out) {
+  double sv[kMaxOrder], dv[kMaxOrder];
+#pragma unroll
+  for (int m = 0; m < kMaxOrder; ++m) {
+    const bool in = (m < N) && (m != n);
+    sv[m] = in ? S[m][e] : 1.0;
+    dv[m] = (in && pp) ? dS[m][e] : 0.0;
   }
-  if (tid == 0) fail = 0;
-  __syncthreads();
-  if (tid == 0) {
-    double m = 0.0;
-    for (int i = 0; i < R; ++i) m = fmax(m, g[i * R + i]);
-    maxdiag = m;
+  double v = 1.0, f0 = 1.0, f1 = 0.0, f2 = 0.0;
+#pragma unroll
+  for (int m = 0; m < kMaxOrder; ++m) {
+    v *= sv[m];
+    f2 = f2 * sv[m] + f1 * dv[m];
+    f1 = f1 * sv[m] + f0 * dv[m];
+    f0 = f0 * sv[m];
   }
-  __syncthreads();
-  const double tol = maxdiag * (double)R * 2.220446049250313e-16;
-  // Gauss-Jordan inversion without pivoting (Gamma is SPD; pivots are the
-  // positive Schur-complement diagonals).
-  for (int k = 0; k < R; ++k) {
-    const double piv = g[k * R + k];
-    if (!(piv > tol)) {  // uniform across the block: every thread read the same value
-      if (tid == 0) fail = 1;
-      break;
-    }
-    for (int i = tid; i < R; i += 256) col[i] = g[i * R + k];
-    __syncthreads();
-    for (int j = tid; j < R; j += 256) g[k * R + j] = (j == k ? 1.0 : g[k * R + j]) / piv;
-    __syncthreads();
-    for (int e = tid; e < RR; e += 256) {
-      const int i = e / R, j = e - i * R;
-      if (i != k) g[e] = (j == k ? 0.0 : g[e]) - col[i] * g[k * R + j];
-    }
-    __syncthreads();
-  }
-  __syncthreads();
-  if (fail) {
-    for (int e = tid; e < RR; e += 256) a.Ginv[e] = 0.0;
-    if (tid == 0) a.stats->status |= 1;
-  } else {
-    // symmetrize the result (the exact inverse is symmetric)
-    for (int e = tid; e < RR; e += 256) {
-      const int i = e / R, j = e - i * R;
-      a.Ginv[e] = 0.5 * (g[e] + g[j * R + i]);
-    }
-  }
+  *g_out = v;
+  *w_out = f2;
 }
 
+__global__ __launch_bounds__(256) void k_gamma(GammaArgs a) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= a.R * a.R) return;
+  double g, w;
+  gamma_entry(a.S, a.dS, a.N, a.n, e, a.pp != 0, &g, &w);
+  a.Gamma[e] = g;
+  if (a.pp) a.W[e] = w;
+}
+
+// Ginv = Gamma^-1 by Gauss-Jordan elimination without pivoting (Gamma is
+// SPD; each pivot is a positive Schur-complement diagonal).  Gamma is padded
+// to RP x RP with the identity.  Lane j of every wave owns column j (and
+// j + 64 when RP = 128); wave w owns rows 16 w .. 16 w + 15, in registers.
+// Step k: the wave holding row k publishes it through double-buffered LDS
+// (one barrier per step); each wave reads the column-k entries of its own
+// rows from lane k with readlane.
+template <int RP>
+__global__ __launch_bounds__(RP > 64 ? 512 : (RP / 16) * 64) void k_inv(const double* __restrict__ Gm,
+                                                                        double* __restrict__ Gi, int R,
+                                                                        DevStats* stats) {
+  constexpr int NW = RP / 16;
+  constexpr int NC = RP > 64 ? 2 : 1;
+  __shared__ double rowbuf[2][RP];
+  __shared__ double diag[RP];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double g[NC][16];
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int i = 16 * w + r, j = lane + 64 * c;
+      double v = (i == j) ? 1.0 : 0.0;
+      if (i < R && j < R) v = Gm[i * R + j];
+      g[c][r] = v;
+      if (i == j && j < RP) diag[i] = v;
+    }
+  __syncthreads();
+  double dmax = 0.0;
+  for (int d = 0; d < R; ++d) dmax = fmax(dmax, diag[d]);
+  const double tol = dmax * (double)R * 2.220446049250313e-16;
+  bool failed = false;
+  for (int kw = 0; kw < NW && !failed; ++kw) {
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      const int k = 16 * kw + kk;
+      const int b = kk & 1;
+      if (w == kw) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+          if (lane + 64 * c < RP) rowbuf[b][lane + 64 * c] = g[c][kk];
+      }
+      __syncthreads();
+      const double piv = rowbuf[b][k];
+      if (!(piv > tol)) {  // same value in every thread: uniform exit
+        failed = true;
+        break;
+      }
+      double rinv = __builtin_amdgcn_rcp(piv);  // refined by two Newton steps
+      rinv = fma(rinv, fma(-piv, rinv, 1.0), rinv);
+      rinv = fma(rinv, fma(-piv, rinv, 1.0), rinv);
+      double rk[NC];
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const int jc = lane + 64 * c;
+        rk[c] = (jc == k) ? rinv : ((jc < RP) ? rowbuf[b][jc] : 0.0) * rinv;
+      }
+      // column k of this wave's rows, from lane k % 64 of column set k / 64
+      const int kc = k >> 6, kl = k & 63;
+      double ck[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        double src = g[0][r];
+        if (NC == 2 && kc == 1) src = g[NC - 1][r];
+        const int lo = __builtin_amdgcn_readlane(__double2loint(src), kl);
+        const int hi = __builtin_amdgcn_readlane(__double2hiint(src), kl);
+        ck[r] = __hiloint2double(hi, lo);
+      }
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const int jc = lane + 64 * c;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          if (r == kk && w == kw) {
+            g[c][r] = rk[c];
+          } else {
+            g[c][r] = ((jc == k) ? 0.0 : g[c][r]) - ck[r] * rk[c];
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int i = 16 * w + r, j = lane + 64 * c;
+      if (i < R && j < R) Gi[i * R + j] = failed ? 0.0 : g[c][r];
+    }
+  if (failed && threadIdx.x == 0) stats->status |= 1;
+}
+
+// One 16-row block of a mode update on the matrix cores (f64 16x16x4):
+//   M~ = M (+ A_old W in PP),  A_new = M~ Ginv,
+// then the shadows, dA and this block's partial Gram A^T A, dS = A^T dA,
+// ||A||^2, ||dA||^2, <M~, A_new> and <Gamma, S_part>.  R is padded to RP, a
+// multiple of 16, with zeros; the R x R operand (W, Ginv, Gamma) is staged in
+// LDS in column chunks of at most 64.  Wave w handles column blocks
+// w, w + 4, ... of each chunk.
 template <typename T>
 __global__ __launch_bounds__(256) void k_solve(SolveArgs<T> a) {
-  __shared__ double Mt[kSolveRows * kMaxRank];
-  __shared__ double An[kSolveRows * kMaxRank];
-  __shared__ double dAn[kSolveRows * kMaxRank];
+  extern __shared__ double lds[];
   __shared__ double sh[256];
-  const int tid = threadIdx.x, R = a.R;
-  const int64_t r0 = (int64_t)blockIdx.x * kSolveRows;
-  const int rows = (int)((a.s - r0) < kSolveRows ? (a.s - r0) : kSolveRows);
-  const int nel = rows * R;
-  for (int e = tid; e < nel; e += 256) {
-    Mt[e] = a.M[r0 * R + e];
-    if (a.pp) An[e] = a.A[r0 * R + e];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l16 = lane & 15, lg = lane >> 4;
+  const int R = a.R, RP = (R + 15) & ~15, CH = RP < 64 ? RP : 64;
+  const int PG = CH + 1, PM = RP + 1;
+  double* Gs = lds;              // RP x CH chunk of an R x R operand, pitch PG
+  double* Mt = Gs + RP * PG;     // 16 x RP, pitch PM
+  double* An = Mt + 16 * PM;     // 16 x RP
+  double* dAn = An + 16 * PM;    // 16 x RP
+  const int64_t r0 = (int64_t)blockIdx.x * 16;
+  const int rows = (int)((a.s - r0) < 16 ? (a.s - r0) : 16);
+  for (int e = tid; e < 16 * RP; e += 256) {
+    const int r = e / RP, c = e - r * RP;
+    const bool in = r < rows && c < R;
+    Mt[r * PM + c] = in ? a.M[(r0 + r) * R + c] : 0.0;
+    An[r * PM + c] = (in && a.pp) ? a.A[(r0 + r) * R + c] : 0.0;
   }
-  __syncthreads();
+  auto stage = [&](const double* src, int c0) {
+    for (int e = tid; e < RP * CH; e += 256) {
+      const int k = e / CH, c = e - k * CH;
+      Gs[k * PG + c] = (k < R && c0 + c < R) ? src[k * R + c0 + c] : 0.0;
+    }
+  };
+  // X (16 x RP, pitch PM) times the staged chunk -> 16 x 16 block at column cb
+  auto block_mm = [&](const double* X, int cbl) {
+    Mma<double>::acc_t acc = Mma<double>::zero();
+    for (int ks = 0; ks < RP / 4; ++ks) {
+      const int k = ks * 4 + lg;
+      acc = Mma<double>::mma(X[l16 * PM + k], Gs[k * PG + cbl * 16 + l16], acc);
+    }
+    return acc;
+  };
   if (a.pp) {
     // M~ = M + V^(n), V^(n) = A^(n) W with the current (old) A^(n)  (Eq. (7))
-    for (int e = tid; e < nel; e += 256) {
-      const int r = e / R, c = e - r * R;
-      double v = 0.0;
-      for (int j = 0; j < R; ++j) v += An[r * R + j] * a.W[j * R + c];
-      Mt[e] += v;
+    for (int c0 = 0; c0 < RP; c0 += CH) {
+      stage(a.W, c0);
+      __syncthreads();
+      for (int cbl = wave; cbl < CH / 16; cbl += 4) {
+        const Mma<double>::acc_t acc = block_mm(An, cbl);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Mt[(lg + 4 * v) * PM + c0 + cbl * 16 + l16] += acc[v];
+      }
+      __syncthreads();
+    }
+  }
+  double nA2 = 0.0, nd2 = 0.0, ma = 0.0;
+  for (int c0 = 0; c0 < RP; c0 += CH) {
+    stage(a.Ginv, c0);
+    __syncthreads();
+    for (int cbl = wave; cbl < CH / 16; cbl += 4) {
+      const Mma<double>::acc_t acc = block_mm(Mt, cbl);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = lg + 4 * v, c = c0 + cbl * 16 + l16;
+        double val = 0.0, d = 0.0;
+        if (r < rows && c < R) {
+          val = acc[v];
+          const int64_t gi = (r0 + r) * R + c;
+          if (a.pp) {
+            d = val - a.Ap[gi];
+            a.dAsh[gi] = (T)d;
+          } else {
+            d = val - a.A[gi];
+          }
+          a.A[gi] = val;
+          a.Ash[gi] = (T)val;
+          nA2 += val * val;
+          nd2 += d * d;
+          ma += Mt[r * PM + c] * val;
+        }
+        An[r * PM + c] = val;
+        dAn[r * PM + c] = d;
+      }
     }
     __syncthreads();
   }
-  double nA2 = 0.0, nd2 = 0.0, ma = 0.0;
-  for (int e = tid; e < nel; e += 256) {
-    const int r = e / R, c = e - r * R;
-    double v = 0.0;
-    for (int j = 0; j < R; ++j) v += Mt[r * R + j] * a.Ginv[j * R + c];
-    const int64_t gi = r0 * R + e;
-    double d;
-    if (a.pp) {
-      d = v - a.Ap[gi];
-      a.dAsh[gi] = (T)d;
-    } else {
-      d = v - a.A[gi];
+  // partial Gram (and dS) over this block's rows, with <Gamma, S_part>
+  const int ncb = RP / 16;
+  double* pS = a.partS + (int64_t)blockIdx.x * R * R;
+  double* pdS = a.pp ? a.partdS + (int64_t)blockIdx.x * R * R : nullptr;
+  double gs = 0.0;
+  for (int c0 = 0; c0 < RP; c0 += CH) {
+    stage(a.Gamma, c0);
+    __syncthreads();
+    const int nbl = CH / 16;
+    for (int blk = wave; blk < ncb * nbl; blk += 4) {
+      const int ab = blk / nbl, bbl = blk - ab * nbl;
+      const int bcol = c0 + bbl * 16 + l16;
+      Mma<double>::acc_t s = Mma<double>::zero(), ds = Mma<double>::zero();
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) {
+        const int r = ks * 4 + lg;
+        const double x = An[r * PM + ab * 16 + l16];
+        s = Mma<double>::mma(x, An[r * PM + bcol], s);
+        if (a.pp) ds = Mma<double>::mma(x, dAn[r * PM + bcol], ds);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int ar = ab * 16 + lg + 4 * v;
+        if (ar < R && bcol < R) {
+          pS[ar * R + bcol] = s[v];
+          if (a.pp) pdS[ar * R + bcol] = ds[v];
+          gs += Gs[ar * PG + bbl * 16 + l16] * s[v];
+        }
+      }
     }
-    a.A[gi] = v;
-    a.Ash[gi] = (T)v;
-    An[e] = v;
-    dAn[e] = d;
-    nA2 += v * v;
-    nd2 += d * d;
-    ma += Mt[e] * v;
-  }
-  __syncthreads();
-  const int RR = R * R;
-  double* pS = a.partS + (int64_t)blockIdx.x * RR;
-  double* pdS = a.pp ? a.partdS + (int64_t)blockIdx.x * RR : nullptr;
-  for (int e = tid; e < RR; e += 256) {
-    const int i = e / R, j = e - i * R;
-    double s = 0.0, ds = 0.0;
-    for (int r = 0; r < rows; ++r) {
-      s += An[r * R + i] * An[r * R + j];
-      if (a.pp) ds += An[r * R + i] * dAn[r * R + j];
-    }
-    pS[e] = s;
-    if (a.pp) pdS[e] = ds;
+    __syncthreads();
   }
   const double t0 = block_sum(nA2, sh);
   const double t1 = block_sum(nd2, sh);
   const double t2 = block_sum(ma, sh);
+  const double t3 = block_sum(gs, sh);
   if (tid == 0) {
     a.partSc[blockIdx.x * 4 + 0] = t0;
     a.partSc[blockIdx.x * 4 + 1] = t1;
     a.partSc[blockIdx.x * 4 + 2] = t2;
-    a.partSc[blockIdx.x * 4 + 3] = 0.0;
+    a.partSc[blockIdx.x * 4 + 3] = t3;
   }
 }
 
+// S^(n) (and dS^(n)) = sum of the block partials in block order, one thread
+// per entry, which then forms entry e of Gamma and W of the next mode;
+// block 0 also sums the scalars and, after the last mode, forms the
+// residual of Eq. (3).
 __global__ __launch_bounds__(256) void k_finalize(FinalArgs a) {
-  __shared__ double sh[256];
-  const int tid = threadIdx.x, RR = a.R * a.R;
-  double g = 0.0;
-  for (int e = tid; e < RR; e += 256) {
-    double s = 0.0, ds = 0.0;
-    for (int b = 0; b < a.nblk; ++b) {
-      s += a.partS[(int64_t)b * RR + e];
-      if (a.pp) ds += a.partdS[(int64_t)b * RR + e];
+  const int RR = a.R * a.R;
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e < RR) {
+    double sv = 0.0, ds = 0.0;
+#pragma unroll 8
+    for (int b = 0; b < a.nblk; ++b) sv += a.partS[(int64_t)b * RR + e];
+    if (a.pp) {
+#pragma unroll 8
+      for (int b = 0; b < a.nblk; ++b) ds += a.partdS[(int64_t)b * RR + e];
     }
-    a.S[e] = s;
-    if (a.pp) a.dS[e] = ds;
-    if (a.last) g += a.Gamma[e] * s;
+    a.S[a.n][e] = sv;
+    if (a.pp) a.dS[a.n][e] = ds;
+    const int nx = (a.n + 1) % a.N;
+    double g, w;
+    gamma_entry(a.S, a.dS, a.N, nx, e, true, &g, &w);
+    a.Gamma[e] = g;
+    a.W[e] = w;
   }
-  const double gs = block_sum(g, sh);
-  if (tid == 0) {
-    double nA2 = 0.0, nd2 = 0.0, ma = 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    double nA2 = 0.0, nd2 = 0.0, ma = 0.0, gs = 0.0;
     for (int b = 0; b < a.nblk; ++b) {
       nA2 += a.partSc[b * 4 + 0];
       nd2 += a.partSc[b * 4 + 1];
       ma += a.partSc[b * 4 + 2];
+      gs += a.partSc[b * 4 + 3];
     }
     a.stats->normA2[a.n] = nA2;
     a.stats->normdA2[a.n] = nd2;
@@ -406,37 +860,177 @@ __global__ __launch_bounds__(256) void k_finalize(FinalArgs a) {
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_pp_mttkrp(PPArgs<T> a) {
-  const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  __shared__ double red[256];
+  const int tid = threadIdx.x, R = a.R;
+  const int G = 256 / R;
+  const int r = tid % R, yg = tid / R;
+  const int64_t x = blockIdx.x;
   const int64_t sn = a.dims[a.n];
-  if (g >= sn * a.R) return;
-  const int64_t x = g / a.R;
-  const int r = (int)(g - x * a.R);
-  double acc = a.Mp[g];
-  for (int i = 0; i < a.N; ++i) {
-    if (i == a.n) continue;
-    const int64_t si = a.dims[i];
-    const T* P = a.pair[i];
-    const T* d = a.dA[i];
-    double u = 0.0;
-    if (a.pair_n_first[i]) {
-      const T* p = P + x * si * a.R + r;  // P[x][y][r]
-      for (int64_t y = 0; y < si; ++y) u += (double)p[y * a.R] * (double)d[y * a.R + r];
-    } else {
-      const T* p = P + x * a.R + r;  // P[y][x][r]
-      for (int64_t y = 0; y < si; ++y) u += (double)p[y * sn * a.R] * (double)d[y * a.R + r];
+  double u = 0.0;
+  if (yg < G) {
+    for (int i = 0; i < a.N; ++i) {
+      if (i == a.n) continue;
+      const int64_t si = a.dims[i];
+      const T* d = a.dA[i] + r;
+      const T* p;
+      int64_t ys;  // stride between consecutive y
+      if (a.pair_n_first[i]) {
+        p = a.pair[i] + x * si * R + r;  // P[x][y][r]
+        ys = R;
+      } else {
+        p = a.pair[i] + x * R + r;  // P[y][x][r]
+        ys = sn * R;
+      }
+      int64_t y = yg;
+      double u0 = 0.0, u1 = 0.0;
+      for (; y + G < si; y += 2 * G) {
+        u0 += (double)p[y * ys] * (double)d[y * R];
+        u1 += (double)p[(y + G) * ys] * (double)d[(y + G) * R];
+      }
+      if (y < si) u0 += (double)p[y * ys] * (double)d[y * R];
+      u += u0 + u1;
     }
-    acc += u;
   }
-  a.M[g] = acc;
+  red[tid] = u;
+  __syncthreads();
+  if (tid < R) {
+    double acc = a.Mp[x * R + tid];
+    for (int k = 0; k < G; ++k) acc += red[k * R + tid];
+    a.M[x * R + tid] = acc;
+  }
+}
+
+// Small contractions (few outputs, e.g. the leaves): Y[p][j] =
+// sum_i X[p][i][j] A[i][j % R] with the i range split over 4 thread groups
+// of one workgroup and added in a fixed order.  Block = (p, 64 outputs).
+template <typename TI, typename TO>
+__global__ __launch_bounds__(256) void k_mttv_split(const TI* __restrict__ X, const TI* __restrict__ A,
+                                                    TO* __restrict__ Y, int64_t I, int64_t QR, int R,
+                                                    int64_t jblocks) {
+  __shared__ TO red[4][64];
+  const int tid = threadIdx.x, jj = tid & 63, ig = tid >> 6;
+  const int64_t p = blockIdx.x / jblocks;
+  const int64_t j = (blockIdx.x - p * jblocks) * 64 + jj;
+  TO s = 0;
+  if (j < QR) {
+    const int r = (int)(j % R);
+    const TI* x = X + p * I * QR + j;
+    TO s0 = 0, s1 = 0;
+    int64_t i = ig;
+    for (; i + 4 < I; i += 8) {
+      s0 += (TO)x[i * QR] * (TO)A[i * R + r];
+      s1 += (TO)x[(i + 4) * QR] * (TO)A[(i + 4) * R + r];
+    }
+    if (i < I) s0 += (TO)x[i * QR] * (TO)A[i * R + r];
+    s = s0 + s1;
+  }
+  red[ig][jj] = s;
+  __syncthreads();
+  if (ig == 0 && j < QR) Y[p * QR + j] = (red[0][jj] + red[1][jj]) + (red[2][jj] + red[3][jj]);
 }
 
 inline unsigned nblocks(int64_t n) { return (unsigned)((n + 255) / 256); }
 
+
+
 }  // namespace
+
+template <typename T, bool KC, int NCB>
+hipError_t launch_ttm_rb(const T* X, const T* B, T* C, int64_t P, int64_t K, int64_t Q, int R,
+                         hipStream_t st) {
+  constexpr int V = 16 / sizeof(T);
+  constexpr int CH = 8 * 4 * V;
+  const int Kp = (int)((K + CH - 1) / CH * CH);
+  const size_t lds = (size_t)NCB * 16 * (Kp + V) * sizeof(T);
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_ttm_rb<T, KC, NCB>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  const int64_t tilesQ = KC ? 1 : (Q + 31) / 32;
+  const int64_t ntiles = KC ? (P + 31) / 32 : P * tilesQ;
+  const int64_t want = (ntiles + kTtmWaves - 1) / kTtmWaves;
+  const unsigned nx = (unsigned)(want < 2048 ? want : 2048);
+  const unsigned ny = (unsigned)((R + NCB * 16 - 1) / (NCB * 16));
+  const int vec = (K % V == 0 && ((uintptr_t)X % 16) == 0) ? 1 : 0;
+  hipLaunchKernelGGL((k_ttm_rb<T, KC, NCB>), dim3(nx, ny), dim3(kTtmThreads), lds, st, X, B, C, P, K, Q, R,
+                     tilesQ, ntiles, Kp, vec);
+  return hipGetLastError();
+}
+
+template <typename T, int NCB>
+hipError_t launch_ttm_kc(const T* X, const T* B, T* C, int64_t P, int64_t K, int R, hipStream_t st) {
+  constexpr int V = 16 / sizeof(T);
+  const int64_t ntiles = (P + 15) / 16;
+  const int64_t want = (ntiles + kTtmWaves - 1) / kTtmWaves;
+  const unsigned nx = (unsigned)(want < 1024 ? want : 1024);
+  const unsigned ny = (unsigned)((R + NCB * 16 - 1) / (NCB * 16));
+  const int vec = (K % V == 0 && ((uintptr_t)X % 16) == 0) ? 1 : 0;
+  if (vec && K == 32 * V) {
+    hipLaunchKernelGGL((k_ttm_kc<T, NCB, true>), dim3(nx, ny), dim3(kTtmThreads), 0, st, X, B, C, P, K, R, ntiles,
+                       vec);
+  } else {
+    hipLaunchKernelGGL((k_ttm_kc<T, NCB, false>), dim3(nx, ny), dim3(kTtmThreads), 0, st, X, B, C, P, K, R, ntiles,
+                       vec);
+  }
+  return hipGetLastError();
+}
+
+template <int NCB>
+hipError_t launch_ttm_q(const float* X, const float* B, float* C, int64_t P, int64_t K, int64_t Q, int R,
+                        hipStream_t st) {
+  const int Kp = (int)((K + 31) / 32 * 32);
+  const size_t lds = (size_t)NCB * 16 * (Kp + 4) * sizeof(float);
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_ttm_q<NCB>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       160 * 1024);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  const int64_t tilesQ = (Q + 63) / 64;
+  const int64_t ntiles = P * tilesQ;
+  const int64_t want = (ntiles + kTtmWaves - 1) / kTtmWaves;
+  const unsigned nx = (unsigned)(want < 2048 ? want : 2048);
+  const unsigned ny = (unsigned)((R + NCB * 16 - 1) / (NCB * 16));
+  const int vec = (Q % 4 == 0 && ((uintptr_t)X % 16) == 0) ? 1 : 0;
+  hipLaunchKernelGGL((k_ttm_q<NCB>), dim3(nx, ny), dim3(kTtmThreads), lds, st, X, B, C, P, K, Q, R, tilesQ, ntiles, Kp,
+                     vec);
+  return hipGetLastError();
+}
+
+template <typename T, bool KC>
+hipError_t launch_ttm_rb_ncb(const T* X, const T* B, T* C, int64_t P, int64_t K, int64_t Q, int R,
+                             hipStream_t st) {
+  if (R <= 16) return launch_ttm_rb<T, KC, 1>(X, B, C, P, K, Q, R, st);
+  if (R <= 32) return launch_ttm_rb<T, KC, 2>(X, B, C, P, K, Q, R, st);
+  if (R <= 64) return launch_ttm_rb<T, KC, 4>(X, B, C, P, K, Q, R, st);
+  return launch_ttm_rb<T, KC, 8>(X, B, C, P, K, Q, R, st);
+}
 
 template <typename T>
 hipError_t launch_ttm(const T* X, const T* B, T* C, int64_t P, int64_t K, int64_t Q, int R,
                       hipStream_t st) {
+  if (Q == 1 && K <= 32 * (int64_t)(16 / sizeof(T)) && R <= 64) {
+    if (R <= 16) return launch_ttm_kc<T, 1>(X, B, C, P, K, R, st);
+    if (R <= 32) return launch_ttm_kc<T, 2>(X, B, C, P, K, R, st);
+    return launch_ttm_kc<T, 4>(X, B, C, P, K, R, st);
+  }
+  if (K <= 256) {
+    if (Q == 1) return launch_ttm_rb_ncb<T, true>(X, B, C, P, K, Q, R, st);
+    if (sizeof(T) == 4 && Q >= 64) {
+      const float* Xf = (const float*)X;
+      const float* Bf = (const float*)B;
+      float* Cf = (float*)C;
+      if (R <= 16) return launch_ttm_q<1>(Xf, Bf, Cf, P, K, Q, R, st);
+      if (R <= 32) return launch_ttm_q<2>(Xf, Bf, Cf, P, K, Q, R, st);
+      if (R <= 64) return launch_ttm_q<4>(Xf, Bf, Cf, P, K, Q, R, st);
+      return launch_ttm_q<8>(Xf, Bf, Cf, P, K, Q, R, st);
+    }
+    return launch_ttm_rb_ncb<T, false>(X, B, C, P, K, Q, R, st);
+  }
   const unsigned ny = (unsigned)((R + TBN - 1) / TBN);
   if (Q == 1) {
     const int64_t nx = (P + TBM - 1) / TBM;
@@ -454,6 +1048,17 @@ template <typename TI, typename TO>
 hipError_t launch_mttv(const TI* X, const TI* A, TO* Y, int64_t P, int64_t I, int64_t Q, int R,
                        hipStream_t st) {
   const int64_t total = P * Q * R;
+  if (total <= (int64_t)1 << 17) {
+    const int64_t jb = (Q * R + 63) / 64;
+    hipLaunchKernelGGL((k_mttv_split<TI, TO>), dim3((unsigned)(P * jb)), dim3(256), 0, st, X, A, Y, I,
+                       Q * R, R, jb);
+    return hipGetLastError();
+  }
+  if (sizeof(TI) == 4 && R % 4 == 0 && ((uintptr_t)X % 16) == 0 && ((uintptr_t)A % 16) == 0) {
+    hipLaunchKernelGGL((k_mttv4<TO>), dim3(nblocks(total / 4)), dim3(256), 0, st, (const float*)X,
+                       (const float*)A, Y, total / 4, I, Q * R, R);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL((k_mttv<TI, TO>), dim3(nblocks(total)), dim3(256), 0, st, X, A, Y, total, I,
                      Q * R, R);
   return hipGetLastError();
@@ -496,34 +1101,45 @@ hipError_t launch_gram(const double* A, int64_t s, int R, double* S, hipStream_t
   return hipGetLastError();
 }
 
-hipError_t launch_prep(const PrepArgs& a, hipStream_t st) {
-  const size_t lds = ((size_t)a.R * a.R + a.R) * sizeof(double);
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_prep, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)(((size_t)kMaxRank * kMaxRank + kMaxRank) * sizeof(double)));
-    if (e != hipSuccess) return e;
-    attr_set = true;
+hipError_t launch_gamma(const GammaArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(k_gamma, dim3(nblocks((int64_t)a.R * a.R)), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_inverse(const double* Gamma, double* Ginv, int R, DevStats* stats, hipStream_t st) {
+  if (R <= 32) {
+    hipLaunchKernelGGL(k_inv<32>, dim3(1), dim3(128), 0, st, Gamma, Ginv, R, stats);
+  } else if (R <= 64) {
+    hipLaunchKernelGGL(k_inv<64>, dim3(1), dim3(256), 0, st, Gamma, Ginv, R, stats);
+  } else {
+    hipLaunchKernelGGL(k_inv<128>, dim3(1), dim3(512), 0, st, Gamma, Ginv, R, stats);
   }
-  hipLaunchKernelGGL(k_prep, dim3(1), dim3(256), lds, st, a);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_solve(const SolveArgs<T>& a, int nblk, hipStream_t st) {
-  hipLaunchKernelGGL((k_solve<T>), dim3(nblk), dim3(256), 0, st, a);
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_solve<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       150 * 1024);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  const int RP = (a.R + 15) & ~15, CH = RP < 64 ? RP : 64;
+  const size_t lds = ((size_t)RP * (CH + 1) + 3 * 16 * (size_t)(RP + 1)) * sizeof(double);
+  hipLaunchKernelGGL((k_solve<T>), dim3(nblk), dim3(256), lds, st, a);
   return hipGetLastError();
 }
 
 hipError_t launch_finalize(const FinalArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(k_finalize, dim3(nblocks((int64_t)a.R * a.R)), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_pp_mttkrp(const PPArgs<T>& a, hipStream_t st) {
-  const int64_t n = a.dims[a.n] * a.R;
-  hipLaunchKernelGGL((k_pp_mttkrp<T>), dim3(nblocks(n)), dim3(256), 0, st, a);
+  hipLaunchKernelGGL((k_pp_mttkrp<T>), dim3((unsigned)a.dims[a.n]), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 

@@ -152,6 +152,9 @@ def main():
     ap.add_argument("--workload", default="o4_s128_r64_f32")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--counters-workload", action="store_true",
+                    help="run only what the HBM-counter passes read: one MTTKRP per first-level layout "
+                         "on the workload, then a plain 512 MiB device copy as the calibration kernel")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU; runs on more than one GPU are not part of this build "
@@ -179,6 +182,18 @@ def main():
     F_dt = dt_sweep_flops(w.dims, R)
     numel = int(np.prod(w.dims))
     ttm_flops = 2 * numel * R
+    if args.counters_workload:
+        plan = cpals.Plan(w.dims, R, prec=prec, tree="dt", device=dev)
+        plan.set_tensor(T)
+        for mode in (0, N - 1):  # first-level contraction over the last mode, then over mode 0
+            plan.mttkrp(A0, mode)
+        torch.cuda.synchronize()
+        src = torch.empty(128 * 2**20, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)  # calibration: reads and writes exactly 512 MiB each
+        torch.cuda.synchronize()
+        log("[bench] counters workload done")
+        return
 
     plans = {
         "dt": cpals.Plan(w.dims, R, prec=prec, tree="dt", device=dev),

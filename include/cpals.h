@@ -58,7 +58,9 @@ typedef enum {
   CP_PP_AUTO = 0,          /* Alg. 2 state machine with tolerance pp_tol */
   CP_PP_FORCE_EXACT = 1,   /* a regular sweep */
   CP_PP_FORCE_APPROX = 2,  /* a PP-approximated sweep with the current operators */
-  CP_PP_FORCE_REINIT = 3   /* PP initialization, then a PP-approximated sweep */
+  CP_PP_FORCE_REINIT = 3,  /* PP initialization, then a PP-approximated sweep */
+  CP_PP_LEARNED = 4        /* as CP_PP_AUTO, with the test replaced by the learned switch
+                              (cp_pp_set_switch); not from the paper */
 } cp_pp_mode;
 
 typedef enum { CP_SWEEP_EXACT = 0, CP_SWEEP_PP_INIT = 1, CP_SWEEP_PP_APPROX = 2 } cp_sweep_kind;
@@ -68,7 +70,8 @@ typedef struct {
   int fitness_is_exact;  /* 0 when the residual came from an approximated M~^(N) */
   double fitness;        /* f = 1 - r */
   double r;              /* relative residual from Eq. (3), squared tensor norm */
-  double dA_rel[8];      /* ||dA^(i)||_F / ||A^(i)||_F after the sweep (Alg. 2 test inputs) */
+  double dA_rel[8];      /* ||dA^(i)||_F / ||A^(i)||_F after the sweep (Alg. 2 test inputs);
+                            1 for a zero factor, 0 past the tensor order */
   int ttm_count;         /* first-level contractions with the tensor done in this call */
   int reserved;
 } cp_sweep_info;
@@ -123,6 +126,45 @@ cp_status cp_als_sweep(cp_plan plan, double* const* A, cp_sweep_info* info);
  * (M~^(n) by Eqs. (5)-(8)).  Same argument rules as cp_als_sweep. */
 cp_status cp_pp_sweep(cp_plan plan, double* const* A, double pp_tol, cp_pp_mode mode,
                       cp_sweep_info* info);
+
+/* Exact fitness f = 1 - r (Eq. (3) with an exact MTTKRP of the last mode)
+ * of the given FP64 factors (host array of N device pointers).  Used to audit
+ * approximated sweeps.  Synchronizes; drops the plan's cached sweep state. */
+cp_status cp_fitness(cp_plan plan, const double* const* A, double* fitness);
+
+/* Learned PP switch (not from the paper; it replaces the hand threshold of
+ * Alg. 2 in CP_PP_LEARNED mode).  A perceptron D = N + 3 -> H -> H -> 1 with
+ * tanh hidden units and a sigmoid output; parameters theta (device FP32,
+ * layout W1 (D x H), b1, W2 (H x H), b2, w3 (H), b3, owned by the caller and
+ * kept alive).  Before each outer step (except the first) the plan forms
+ *   x_i     = log10(max(||dA_i||_F / ||A_i||_F, 1e-12)),       i < N
+ *   x_{N+j} = log10(max(|f_j - f_{j+1}|, 1e-12)), j = 0,1,2,   f_0 the newest
+ *             fitness (a delta not yet available counts as 1),
+ * normalizes (x - shift) / scale (host arrays of D), and runs a PP step when
+ * the network's probability exceeds `threshold`, a regular sweep otherwise.
+ * theta == NULL removes the switch. */
+cp_status cp_pp_set_switch(cp_plan plan, const float* theta, int hidden, const double* shift,
+                           const double* scale, double threshold);
+
+/* Features (unnormalized, D = N + 3 values, host array) and probability of the
+ * last learned decision. */
+cp_status cp_pp_last_decision(cp_plan plan, double* features, double* probability);
+
+/* Training and inference kernels of the switch network (device FP32 arrays,
+ * stream as in cp_plan_create).  D <= 16, H <= 128, B >= 1.
+ * cp_mlp_forward: p[b] = sigmoid(net(X[b])) for B rows of X (B x D).
+ * cp_mlp_grad: grad[0..n) = gradient of the mean binary cross-entropy over the
+ *   B samples (labels y in {0,1}), grad[n] = the loss; n = cp_mlp_param_count;
+ *   scratch of cp_mlp_scratch_floats(B, H) floats.  Sums over samples run in
+ *   sample order (bitwise reproducible).
+ * cp_mlp_adam: one Adam step (Kingma and Ba) on n parameters, t counting from 1. */
+size_t cp_mlp_param_count(int D, int H);
+size_t cp_mlp_scratch_floats(int B, int H);
+cp_status cp_mlp_forward(const float* X, int B, int D, int H, const float* theta, float* p, void* stream);
+cp_status cp_mlp_grad(const float* X, const float* y, int B, int D, int H, const float* theta, float* grad,
+                      float* scratch, void* stream);
+cp_status cp_mlp_adam(float* theta, const float* grad, float* m, float* v, int n, int t, float lr,
+                      float beta1, float beta2, float eps, void* stream);
 
 /* Drop cached intermediates, the MSDT position and the PP state: the next
  * sweep re-reads the factors and recomputes their Gram matrices. */

@@ -17,14 +17,14 @@ LIB_PATH = os.path.join(_HERE, "libcpals.so")
 CP_OK, CP_ERR_ARG, CP_ERR_STATE, CP_ERR_UNSUPPORTED, CP_ERR_HIP, CP_ERR_NOT_SPD, CP_ERR_NUMERIC = range(7)
 CP_F64, CP_F32 = 0, 1
 CP_TREE_DT, CP_TREE_MSDT = 0, 2
-CP_PP_AUTO, CP_PP_FORCE_EXACT, CP_PP_FORCE_APPROX, CP_PP_FORCE_REINIT = range(4)
+CP_PP_AUTO, CP_PP_FORCE_EXACT, CP_PP_FORCE_APPROX, CP_PP_FORCE_REINIT, CP_PP_LEARNED = range(5)
 KIND_NAMES = {0: "exact", 1: "init", 2: "approx"}
 PHASES = ["ttm", "mttv", "update", "pp", "other"]
 
 PRECS = {"f64": CP_F64, "f32": CP_F32}
 TREES = {"dt": CP_TREE_DT, "msdt": CP_TREE_MSDT}
 PP_MODES = {"auto": CP_PP_AUTO, "exact": CP_PP_FORCE_EXACT, "approx": CP_PP_FORCE_APPROX,
-            "init": CP_PP_FORCE_REINIT}
+            "init": CP_PP_FORCE_REINIT, "learned": CP_PP_LEARNED}
 TORCH_DTYPE = {CP_F64: torch.float64, CP_F32: torch.float32}
 
 
@@ -76,6 +76,20 @@ EXPORTS = {
     "cp_profile_enable": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "cp_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_int64)]),
+    "cp_fitness": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_double)]),
+    "cp_pp_set_switch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_double), ctypes.c_double]),
+    "cp_pp_last_decision": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(ctypes.c_double)]),
+    "cp_mlp_param_count": (ctypes.c_size_t, [ctypes.c_int, ctypes.c_int]),
+    "cp_mlp_scratch_floats": (ctypes.c_size_t, [ctypes.c_int, ctypes.c_int]),
+    "cp_mlp_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_void_p]),
+    "cp_mlp_grad": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "cp_mlp_adam": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                   ctypes.c_int, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                   ctypes.c_void_p]),
     "cp_status_str": (ctypes.c_char_p, [ctypes.c_int]),
     "cp_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
 }
@@ -186,6 +200,32 @@ class Plan:
         self._check(self.L.cp_pp_sweep(self.h, p, float(tol), PP_MODES[mode], None))
         return None
 
+    def fitness(self, A):
+        """Exact fitness of the given factors (audit of approximated sweeps)."""
+        f = ctypes.c_double()
+        self._check(self.L.cp_fitness(self.h, self._factors(A), ctypes.byref(f)))
+        return f.value
+
+    def set_switch(self, theta, hidden, shift, scale, threshold=0.5):
+        """Attach the learned PP switch (theta: FP32 device tensor, kept alive)."""
+        if theta is None:
+            self._switch = None
+            self._check(self.L.cp_pp_set_switch(self.h, None, 0, None, None, 0.0))
+            return
+        D = self.order + 3
+        sh = (ctypes.c_double * D)(*[float(x) for x in shift])
+        sc = (ctypes.c_double * D)(*[float(x) for x in scale])
+        self._switch = theta
+        self._check(self.L.cp_pp_set_switch(self.h, ctypes.c_void_p(theta.data_ptr()), int(hidden), sh, sc,
+                                            float(threshold)))
+
+    def last_decision(self):
+        D = self.order + 3
+        f = (ctypes.c_double * D)()
+        pr = ctypes.c_double()
+        self._check(self.L.cp_pp_last_decision(self.h, f, ctypes.byref(pr)))
+        return [f[i] for i in range(D)], pr.value
+
     def profile(self, on=True):
         self._check(self.L.cp_profile_enable(self.h, 1 if on else 0))
 
@@ -211,3 +251,44 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def _mlp_check(status):
+    if status != CP_OK:
+        raise CpalsError(status, (lib().cp_status_str(status) or b"").decode())
+
+
+def mlp_param_count(D, H):
+    return int(lib().cp_mlp_param_count(D, H))
+
+
+def mlp_forward(X, theta, H, stream=None):
+    """Probabilities of the switch network for the rows of X (FP32 CUDA tensors)."""
+    B, D = X.shape
+    p = torch.empty(B, dtype=torch.float32, device=X.device)
+    st = (stream or torch.cuda.current_stream(X.device)).cuda_stream
+    _mlp_check(lib().cp_mlp_forward(ctypes.c_void_p(X.data_ptr()), B, D, H, ctypes.c_void_p(theta.data_ptr()),
+                                    ctypes.c_void_p(p.data_ptr()), ctypes.c_void_p(st)))
+    return p
+
+
+def mlp_grad(X, y, theta, H, scratch=None, out=None, stream=None):
+    """Gradient of the mean BCE (out[:n]) and the loss (out[n])."""
+    B, D = X.shape
+    n = mlp_param_count(D, H)
+    if out is None:
+        out = torch.empty(n + 1, dtype=torch.float32, device=X.device)
+    if scratch is None:
+        scratch = torch.empty(int(lib().cp_mlp_scratch_floats(B, H)), dtype=torch.float32, device=X.device)
+    st = (stream or torch.cuda.current_stream(X.device)).cuda_stream
+    _mlp_check(lib().cp_mlp_grad(ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(y.data_ptr()), B, D, H,
+                                 ctypes.c_void_p(theta.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                 ctypes.c_void_p(scratch.data_ptr()), ctypes.c_void_p(st)))
+    return out
+
+
+def mlp_adam(theta, grad, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    st = (stream or torch.cuda.current_stream(theta.device)).cuda_stream
+    _mlp_check(lib().cp_mlp_adam(ctypes.c_void_p(theta.data_ptr()), ctypes.c_void_p(grad.data_ptr()),
+                                 ctypes.c_void_p(m.data_ptr()), ctypes.c_void_p(v.data_ptr()), theta.numel(), int(t),
+                                 float(lr), float(beta1), float(beta2), float(eps), ctypes.c_void_p(st)))

@@ -90,6 +90,21 @@ struct cp_plan_s {
   bool fresh = true;  // no sweep since the state was (re)initialized: dA = A
   int ttm_count = 0;
 
+  // learned PP switch (set by cp_pp_set_switch)
+  const float* sw_theta = nullptr;
+  int sw_H = 0;
+  double sw_shift[16] = {}, sw_scale[16] = {};
+  double sw_thresh = 0.5;
+  bool sw_set = false;
+  float* sw_in = nullptr;   // workspace: normalized features
+  float* sw_out = nullptr;  // workspace: probability
+  double fit_hist[4] = {};  // fitness after the most recent sweeps, newest first
+  int n_hist = 0;
+  bool pending_fit = false;  // a sweep ran whose fitness is not in fit_hist yet
+  double last_feat[16] = {};
+  int last_feat_n = 0;
+  double last_prob = -1.0;
+
   // second stream: the Gamma / inverse kernel of a mode update runs there,
   // concurrently with that mode's MTTKRP on the plan stream (fork/join events)
   hipStream_t aux = nullptr;
@@ -202,6 +217,8 @@ void plan_layout(cp_plan p) {
   take((size_t)p->nblk_max * 4 * 8);             // partSc
   take((size_t)kNormParts * 8);                  // normParts
   take(sizeof(DevStats));                        // stats
+  take(16 * sizeof(float));                      // sw_in
+  take(16 * sizeof(float));                      // sw_out
   // slots for depths 1..N-2 (depth d keeps N - d modes)
   std::vector<int64_t> sorted(p->dims, p->dims + N);
   std::sort(sorted.begin(), sorted.end(), std::greater<int64_t>());
@@ -235,10 +252,14 @@ void plan_carve(cp_plan p) {
   p->partSc = (double*)next();
   p->normParts = (double*)next();
   p->stats = (DevStats*)next();
+  p->sw_in = (float*)next();
+  p->sw_out = (float*)next();
   for (int d = 1; d <= N - 2; ++d) p->slot_buf[d] = next();
 }
 
 void drop_cache(cp_plan p) {
+  p->n_hist = 0;
+  p->pending_fit = false;
   for (int d = 0; d < kMaxOrder; ++d) p->slot[d] = Slot();
   p->msdt_u = 0;
   p->phase = 0;
@@ -511,16 +532,24 @@ cp_status read_stats(cp_plan p, DevStats* h) {
   return CP_OK;
 }
 
+void note_fitness(cp_plan p, double r) {
+  for (int k = 3; k > 0; --k) p->fit_hist[k] = p->fit_hist[k - 1];
+  p->fit_hist[0] = 1.0 - r;
+  if (p->n_hist < 4) ++p->n_hist;
+  p->pending_fit = false;
+}
+
 cp_status fill_info(cp_plan p, cp_sweep_info* info, int kind) {
   DevStats h;
   CP_TRY(read_stats(p, &h));
+  if (p->pending_fit) note_fitness(p, h.r);
   if (info) {
     info->kind = kind;
     info->fitness_is_exact = (kind == CP_SWEEP_EXACT) ? 1 : 0;
     info->r = h.r;
     info->fitness = 1.0 - h.r;
     for (int m = 0; m < kMaxOrder; ++m)
-      info->dA_rel[m] = (m < p->N && h.normA2[m] > 0) ? std::sqrt(h.normdA2[m] / h.normA2[m]) : 0.0;
+      info->dA_rel[m] = m >= p->N ? 0.0 : (h.normA2[m] > 0 ? std::sqrt(h.normdA2[m] / h.normA2[m]) : 1.0);
     info->ttm_count = p->ttm_count;
   }
   if (h.status & 1) return fail(p, CP_ERR_NOT_SPD, "a Gamma matrix was not numerically positive definite");
@@ -688,6 +717,40 @@ bool check_factor_ptrs(double* const* A, int N) {
   return true;
 }
 
+// Learned switch decision: features from the norms of the last updates and
+// the fitness history, normalized, through the network on the GPU.
+//   x_i = log10(max(||dA_i|| / ||A_i||, 1e-12))            i < N
+//   x_{N+j} = log10(max(|f_j - f_{j+1}|, 1e-12))           j = 0, 1, 2 (newest first;
+//                                                          a missing delta counts as 1)
+cp_status switch_decide(cp_plan p, bool* pp) {
+  DevStats h;
+  CP_TRY(read_stats(p, &h));
+  const int N = p->N, D = N + 3;
+  double x[16];
+  for (int i = 0; i < N; ++i) {
+    const double rel = h.normA2[i] > 0.0 ? std::sqrt(h.normdA2[i] / h.normA2[i]) : 1.0;
+    x[i] = std::log10(std::max(rel, 1e-12));
+  }
+  for (int j = 0; j < 3; ++j) {
+    const double d = (p->n_hist >= j + 2) ? std::fabs(p->fit_hist[j] - p->fit_hist[j + 1]) : 1.0;
+    x[N + j] = std::log10(std::max(d, 1e-12));
+  }
+  float xf[16];
+  for (int i = 0; i < D; ++i) {
+    p->last_feat[i] = x[i];
+    xf[i] = (float)((x[i] - p->sw_shift[i]) / p->sw_scale[i]);
+  }
+  p->last_feat_n = D;
+  HIP_TRY(p, hipMemcpyAsync(p->sw_in, xf, D * sizeof(float), hipMemcpyHostToDevice, p->st));
+  CP_TRY(cp_mlp_forward(p->sw_in, 1, D, p->sw_H, p->sw_theta, p->sw_out, p->st));
+  float prob = 0.f;
+  HIP_TRY(p, hipMemcpyAsync(&prob, p->sw_out, sizeof(float), hipMemcpyDeviceToHost, p->st));
+  HIP_TRY(p, hipStreamSynchronize(p->st));
+  p->last_prob = prob;
+  *pp = prob > p->sw_thresh;
+  return CP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -792,8 +855,14 @@ cp_status cp_als_sweep(cp_plan p, double* const* A, cp_sweep_info* info) {
   CP_TRY(check_ready(p));
   if (!check_factor_ptrs(A, p->N)) return fail(p, CP_ERR_ARG, "null factor pointer");
   if (!p->state_ready) CP_TRY(init_state(p, A));
+  if (p->sw_set && p->pending_fit) {
+    DevStats h;
+    CP_TRY(read_stats(p, &h));
+    note_fitness(p, h.r);
+  }
   p->ttm_count = 0;
   CP_TRY(exact_sweep(p, A));
+  p->pending_fit = true;
   if (info) return fill_info(p, info, CP_SWEEP_EXACT);
   return CP_OK;
 }
@@ -801,8 +870,14 @@ cp_status cp_als_sweep(cp_plan p, double* const* A, cp_sweep_info* info) {
 cp_status cp_pp_sweep(cp_plan p, double* const* A, double pp_tol, cp_pp_mode mode, cp_sweep_info* info) {
   CP_TRY(check_ready(p));
   if (!check_factor_ptrs(A, p->N)) return fail(p, CP_ERR_ARG, "null factor pointer");
-  if (mode < CP_PP_AUTO || mode > CP_PP_FORCE_REINIT) return fail(p, CP_ERR_ARG, "bad PP mode");
+  if (mode < CP_PP_AUTO || mode > CP_PP_LEARNED) return fail(p, CP_ERR_ARG, "bad PP mode");
+  if (mode == CP_PP_LEARNED && !p->sw_set) return fail(p, CP_ERR_STATE, "no learned switch set");
   if (!p->state_ready) CP_TRY(init_state(p, A));
+  if ((p->sw_set || mode == CP_PP_LEARNED) && p->pending_fit) {
+    DevStats h;
+    CP_TRY(read_stats(p, &h));
+    note_fitness(p, h.r);
+  }
   int kind;
   if (mode == CP_PP_AUTO) {
     if (!(pp_tol > 0.0)) return fail(p, CP_ERR_ARG, "pp_tol must be positive");
@@ -815,6 +890,10 @@ cp_status cp_pp_sweep(cp_plan p, double* const* A, double pp_tol, cp_pp_mode mod
         if (!(std::sqrt(h.normdA2[m]) < pp_tol * std::sqrt(h.normA2[m]))) ok = false;
     }
     kind = !ok ? CP_SWEEP_EXACT : (p->phase == 1 ? CP_SWEEP_PP_APPROX : CP_SWEEP_PP_INIT);
+  } else if (mode == CP_PP_LEARNED) {
+    bool pp = false;
+    if (!p->fresh) CP_TRY(switch_decide(p, &pp));
+    kind = !pp ? CP_SWEEP_EXACT : (p->phase == 1 ? CP_SWEEP_PP_APPROX : CP_SWEEP_PP_INIT);
   } else if (mode == CP_PP_FORCE_EXACT) {
     kind = CP_SWEEP_EXACT;
   } else if (mode == CP_PP_FORCE_APPROX) {
@@ -831,7 +910,60 @@ cp_status cp_pp_sweep(cp_plan p, double* const* A, double pp_tol, cp_pp_mode mod
     if (kind == CP_SWEEP_PP_INIT) CP_TRY(pp_init(p, A));
     CP_TRY(approx_sweep(p, A));
   }
+  p->pending_fit = true;
   if (info) return fill_info(p, info, kind);
+  return CP_OK;
+}
+
+cp_status cp_pp_set_switch(cp_plan p, const float* theta, int hidden, const double* shift, const double* scale,
+                           double threshold) {
+  if (!p) return CP_ERR_ARG;
+  if (!theta) {
+    p->sw_set = false;
+    p->sw_theta = nullptr;
+    return CP_OK;
+  }
+  if (!shift || !scale || hidden < 1 || hidden > 128 || p->N + 3 > 16)
+    return fail(p, CP_ERR_ARG, "bad switch arguments");
+  const int D = p->N + 3;
+  for (int i = 0; i < D; ++i) {
+    if (!(scale[i] > 0.0)) return fail(p, CP_ERR_ARG, "feature scale must be positive");
+    p->sw_shift[i] = shift[i];
+    p->sw_scale[i] = scale[i];
+  }
+  p->sw_theta = theta;
+  p->sw_H = hidden;
+  p->sw_thresh = threshold;
+  p->sw_set = true;
+  return CP_OK;
+}
+
+cp_status cp_pp_last_decision(cp_plan p, double* features, double* probability) {
+  if (!p || !features || !probability) return CP_ERR_ARG;
+  for (int i = 0; i < p->last_feat_n; ++i) features[i] = p->last_feat[i];
+  *probability = p->last_prob;
+  return CP_OK;
+}
+
+cp_status cp_fitness(cp_plan p, const double* const* A, double* fitness) {
+  CP_TRY(check_ready(p));
+  if (!A || !fitness) return fail(p, CP_ERR_ARG, "bad argument");
+  for (int m = 0; m < p->N; ++m)
+    if (!A[m]) return fail(p, CP_ERR_ARG, "null factor %d", m);
+  drop_cache(p);
+  const int n = p->N - 1;
+  for (int m = 0; m < p->N; ++m) {
+    CP_TRY(convert_factor(p, A[m], p->Ash[m], p->dims[m] * p->R));
+    HIP_TRY(p, launch_gram(A[m], p->dims[m], p->R, p->S[m], p->st));
+    ++p->ver[m];
+  }
+  CP_TRY(form_gamma(p, n, false));
+  CP_TRY(run_path(p, dt_path(p->N, n), p->Mbuf));
+  HIP_TRY(p, launch_fitness(p->Mbuf, A[n], p->dims[n], p->R, p->Gamma, p->S[n], p->stats, p->st));
+  DevStats h;
+  CP_TRY(read_stats(p, &h));
+  *fitness = 1.0 - h.r;
+  drop_cache(p);
   return CP_OK;
 }
 

@@ -97,6 +97,11 @@ struct FinalArgs {
 };
 hipError_t launch_finalize(const FinalArgs& a, hipStream_t st);
 
+// r of Eq. (3) for given factors into stats->r: M is the exact MTTKRP of the
+// last mode, A its factor (s x R), Gamma / S of that mode.
+hipError_t launch_fitness(const double* M, const double* A, int64_t s, int R, const double* Gamma,
+                          const double* S, DevStats* stats, hipStream_t st);
+
 // Zero n doubles; zero `bytes` bytes (a multiple of 4) of any buffer.
 hipError_t launch_zero_f64(double* p, int64_t n, hipStream_t st);
 hipError_t launch_zero_bytes(void* p, size_t bytes, hipStream_t st);

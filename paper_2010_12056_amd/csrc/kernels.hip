@@ -272,13 +272,12 @@ __global__ __launch_bounds__(512) void k_ttm_rb(const T* __restrict__ X, const T
 // (row, g = lane / 16) feeds k = t*4V + g*V + u at MFMA step (t, u) from one
 // 16-byte load per t.  Rows beyond P are clamped for loads and masked for
 // stores; k beyond K meets zero rows of the staged factor.
-template <typename T, int NCB, bool FULLK>
+template <typename T, int NCB, int NTS, bool FULLK>
 __global__ __launch_bounds__(512) void k_ttm_kc(const T* __restrict__ X, const T* __restrict__ B,
                                                 T* __restrict__ C, int64_t P, int64_t K_, int R,
                                                 int64_t ntiles, int vec) {
   constexpr int V = 16 / sizeof(T);
   constexpr int KT = 4 * V;
-  constexpr int NTS = 8;
   constexpr int KP = NTS * KT;
   constexpr int pitch = KP + V;
   constexpr int NC = NCB * 16;
@@ -929,6 +928,24 @@ __global__ __launch_bounds__(256) void k_mttv_split(const TI* __restrict__ X, co
   if (ig == 0 && j < QR) Y[p * QR + j] = (red[0][jj] + red[1][jj]) + (red[2][jj] + red[3][jj]);
 }
 
+// r of Eq. (3) for given factors: <M, A> and <Gamma, S> in one workgroup.
+__global__ __launch_bounds__(256) void k_fitness(const double* __restrict__ M, const double* __restrict__ A,
+                                                 int64_t n, const double* __restrict__ G, const double* __restrict__ S,
+                                                 int RR, DevStats* stats) {
+  __shared__ double sh[256];
+  double ma = 0.0, gs = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) ma += M[i] * A[i];
+  for (int i = threadIdx.x; i < RR; i += 256) gs += G[i] * S[i];
+  const double tma = block_sum(ma, sh);
+  const double tgs = block_sum(gs, sh);
+  if (threadIdx.x == 0) {
+    const double t2 = stats->normT2;
+    const double num = t2 + tgs - 2.0 * tma;
+    stats->fit_num = num;
+    stats->r = sqrt((num > 0.0 ? num : 0.0) / t2);
+  }
+}
+
 inline unsigned nblocks(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 
@@ -968,12 +985,23 @@ hipError_t launch_ttm_kc(const T* X, const T* B, T* C, int64_t P, int64_t K, int
   const unsigned nx = (unsigned)(want < 1024 ? want : 1024);
   const unsigned ny = (unsigned)((R + NCB * 16 - 1) / (NCB * 16));
   const int vec = (K % V == 0 && ((uintptr_t)X % 16) == 0) ? 1 : 0;
-  if (vec && K == 32 * V) {
-    hipLaunchKernelGGL((k_ttm_kc<T, NCB, true>), dim3(nx, ny), dim3(kTtmThreads), 0, st, X, B, C, P, K, R, ntiles,
-                       vec);
+  // NTS t-steps of 4V contraction indices: the padded depth follows K
+  const int64_t KT = 4 * V;
+  if (K <= 2 * KT) {
+    if (vec && K == 2 * KT)
+      hipLaunchKernelGGL((k_ttm_kc<T, NCB, 2, true>), dim3(nx, ny), dim3(kTtmThreads), 0, st, X, B, C, P, K, R, ntiles, vec);
+    else
+      hipLaunchKernelGGL((k_ttm_kc<T, NCB, 2, false>), dim3(nx, ny), dim3(kTtmThreads), 0, st, X, B, C, P, K, R, ntiles, vec);
+  } else if (K <= 4 * KT) {
+    if (vec && K == 4 * KT)
+      hipLaunchKernelGGL((k_ttm_kc<T, NCB, 4, true>), dim3(nx, ny), dim3(kTtmThreads), 0, st, X, B, C, P, K, R, ntiles, vec);
+    else
+      hipLaunchKernelGGL((k_ttm_kc<T, NCB, 4, false>), dim3(nx, ny), dim3(kTtmThreads), 0, st, X, B, C, P, K, R, ntiles, vec);
   } else {
-    hipLaunchKernelGGL((k_ttm_kc<T, NCB, false>), dim3(nx, ny), dim3(kTtmThreads), 0, st, X, B, C, P, K, R, ntiles,
-                       vec);
+    if (vec && K == 8 * KT)
+      hipLaunchKernelGGL((k_ttm_kc<T, NCB, 8, true>), dim3(nx, ny), dim3(kTtmThreads), 0, st, X, B, C, P, K, R, ntiles, vec);
+    else
+      hipLaunchKernelGGL((k_ttm_kc<T, NCB, 8, false>), dim3(nx, ny), dim3(kTtmThreads), 0, st, X, B, C, P, K, R, ntiles, vec);
   }
   return hipGetLastError();
 }
@@ -1078,6 +1106,12 @@ hipError_t launch_copy_f64(const double* src, double* dst, int64_t n, hipStream_
 hipError_t launch_zero_f64(double* p, int64_t n, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_zero_f64, dim3(nblocks(n)), dim3(256), 0, st, p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_fitness(const double* M, const double* A, int64_t s, int R, const double* Gamma,
+                          const double* S, DevStats* stats, hipStream_t st) {
+  hipLaunchKernelGGL(k_fitness, dim3(1), dim3(256), 0, st, M, A, s * R, Gamma, S, R * R, stats);
   return hipGetLastError();
 }
 

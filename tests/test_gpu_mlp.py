@@ -1,0 +1,221 @@
+"""GPU parity of the learned PP switch: the network's forward, backward and
+Adam kernels against the FP64 reference in oracle.mlp, the exact fitness
+audit against the explicit residual, and the switch's plumbing in the plan
+(decisions, features and the sweeps it selects)."""
+
+import math
+
+import numpy as np
+import pytest
+
+from gpu_util import relerr, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _net_case(B, D, H, seed):
+    from oracle import mlp
+
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((B, D)).astype(np.float32)
+    y = (rng.random(B) < 0.35).astype(np.float32)
+    theta = (mlp.init_params(D, H, seed) + 0.1 * rng.standard_normal(mlp.n_params(D, H))).astype(np.float32)
+    return X, y, theta
+
+
+# B = 300 spans two 256-thread blocks with a ragged tail; H = 64 is the switch's width
+NET_CASES = [(300, 9, 64, 11), (1, 9, 64, 12), (257, 7, 17, 13), (40, 16, 128, 14)]
+
+
+@pytest.mark.parametrize("B,D,H,seed", NET_CASES)
+def test_mlp_forward_matches_oracle(dev, B, D, H, seed):
+    from oracle import mlp
+    from paper_2010_12056_amd import cpals
+
+    say(f"case mlp forward B={B} D={D} H={H}")
+    X, _, theta = _net_case(B, D, H, seed)
+    p = cpals.mlp_forward(torch.from_numpy(X).to(dev), torch.from_numpy(theta).to(dev), H).cpu().numpy()
+    p_ref, _ = mlp.forward(theta.astype(np.float64), X.astype(np.float64), D, H)
+    assert np.max(np.abs(p - p_ref)) <= 2e-6
+
+
+@pytest.mark.parametrize("B,D,H,seed", NET_CASES)
+def test_mlp_grad_matches_oracle(dev, B, D, H, seed):
+    from oracle import mlp
+    from paper_2010_12056_amd import cpals
+
+    say(f"case mlp grad B={B} D={D} H={H}")
+    X, y, theta = _net_case(B, D, H, seed)
+    Xd, yd, thd = (torch.from_numpy(a).to(dev) for a in (X, y, theta))
+    out = cpals.mlp_grad(Xd, yd, thd, H).cpu().numpy().astype(np.float64)
+    n = mlp.n_params(D, H)
+    assert out.shape == (n + 1,)
+    g_ref = mlp.grad(theta.astype(np.float64), X.astype(np.float64), y.astype(np.float64), D, H)
+    l_ref = mlp.loss(theta.astype(np.float64), X.astype(np.float64), y.astype(np.float64), D, H)
+    # FP32 sums over B samples and H hidden units: error ~ B * 6e-8 relative to the largest term
+    assert np.max(np.abs(out[:n] - g_ref)) <= 2e-5 * max(np.max(np.abs(g_ref)), 1e-3)
+    assert relerr(out[:n], g_ref) <= 1e-5
+    assert abs(out[n] - l_ref) <= 1e-5 * max(1.0, abs(l_ref))
+    # fixed summation order: a second call is bitwise equal
+    again = cpals.mlp_grad(Xd, yd, thd, H).cpu().numpy().astype(np.float64)
+    assert np.array_equal(out, again)
+
+
+def test_mlp_adam_matches_oracle(dev):
+    from oracle import mlp
+    from paper_2010_12056_amd import cpals
+
+    say("case mlp adam")
+    rng = np.random.default_rng(5)
+    n = 4993
+    th = rng.standard_normal(n).astype(np.float32)
+    g = (rng.standard_normal(n) * 10.0 ** rng.uniform(-6, 0, n)).astype(np.float32)
+    m = (0.1 * rng.standard_normal(n)).astype(np.float32)
+    v = (0.01 * (0.5 + rng.random(n))).astype(np.float32)
+    td, gd, md, vd = (torch.from_numpy(a.copy()).to(dev) for a in (th, g, m, v))
+    cpals.mlp_adam(td, gd, md, vd, 7, lr=3e-3)
+    # the kernel receives the hyperparameters as FP32; the reference gets the same values
+    f32 = lambda x: float(np.float32(x))  # noqa: E731
+    th_ref, m_ref, v_ref = mlp.adam_step(th.astype(np.float64), g.astype(np.float64), m.astype(np.float64),
+                                         v.astype(np.float64), 7, lr=f32(3e-3), beta1=f32(0.9),
+                                         beta2=f32(0.999), eps=f32(1e-8))
+    assert np.max(np.abs(md.cpu().numpy() - m_ref)) <= 1e-6 * np.max(np.abs(m_ref))
+    assert np.max(np.abs(vd.cpu().numpy() - v_ref)) <= 1e-6 * np.max(np.abs(v_ref))
+    # the step is lr * mh / (sqrt(vh) + eps), at most a few lr; FP32 rounding of theta dominates
+    assert np.max(np.abs(td.cpu().numpy() - th_ref)) <= 1e-6 + 1e-6 * np.max(np.abs(th_ref))
+
+
+def test_gpu_training_follows_oracle_and_fits(dev):
+    """Full-batch Adam with the GPU kernels on a separable rule: the loss curve
+    tracks the FP64 reference's, and the trained network separates the data."""
+    from oracle import mlp
+    from paper_2010_12056_amd import cpals
+
+    say("case mlp training")
+    D, H, B = 3, 16, 400
+    rng = np.random.default_rng(0)
+    X = rng.standard_normal((B, D))
+    y = (X[:, 0] - 0.5 * X[:, 1] + 0.2 > 0).astype(np.float64)
+    th0 = mlp.init_params(D, H, 5)
+    Xd = torch.tensor(X, dtype=torch.float32, device=dev)
+    yd = torch.tensor(y, dtype=torch.float32, device=dev)
+    thd = torch.tensor(th0, dtype=torch.float32, device=dev)
+    md = torch.zeros_like(thd)
+    vd = torch.zeros_like(thd)
+    n = thd.numel()
+    th, m, v = th0.copy(), np.zeros_like(th0), np.zeros_like(th0)
+    X32 = Xd.double().cpu().numpy()
+    gpu_loss, ref_loss = [], []
+    for t in range(1, 301):
+        out = cpals.mlp_grad(Xd, yd, thd, H)
+        cpals.mlp_adam(thd, out[:n], md, vd, t, lr=0.02)
+        gpu_loss.append(float(out[n].item()))
+        ref_loss.append(mlp.loss(th, X32, y, D, H))
+        th, m, v = mlp.adam_step(th, mlp.grad(th, X32, y, D, H), m, v, t, lr=0.02)
+    assert abs(gpu_loss[0] - ref_loss[0]) <= 1e-5
+    assert max(abs(a - b) for a, b in zip(gpu_loss[:50], ref_loss[:50])) <= 2e-3
+    assert gpu_loss[-1] < 0.15 * gpu_loss[0]
+    p = cpals.mlp_forward(Xd, thd, H).cpu().numpy()
+    assert np.mean((p > 0.5) == (y > 0.5)) > 0.97
+
+
+def _fit_tol(prec, r):
+    # FP64: rounding only.  FP32 tensor and contractions: a relative error e of
+    # <M, A> moves r^2 by about 2e, so r by e / r; e = 1e-8 after the sums over
+    # s * R terms with independent rounding errors.
+    return 1e-12 if prec == "f64" else 1e-6 + 1e-8 / r
+
+
+@pytest.mark.parametrize("name,prec", [("o3_small_f64", "f64"), ("o4_small_f32", "f32")])
+def test_fitness_audit_matches_explicit_residual(dev, name, prec):
+    import oracle
+    from paper_2010_12056_amd import cpals, synth
+
+    say(f"case fitness {name}")
+    w = synth.workload(name)
+    plan = cpals.Plan(w.dims, w.R, prec=prec, tree="msdt", device=dev)
+    T = torch.from_numpy(w.T).to(dev)
+    plan.set_tensor(T)
+    rng = np.random.default_rng(8)
+    T64 = w.T.astype(np.float64)
+    for trial in range(3):
+        # near-solution factors (planted plus noise) and the uniform initial guess
+        if trial < 2:
+            A = [a + 0.05 * trial * rng.standard_normal(a.shape) for a in w.planted]
+        else:
+            A = [a.copy() for a in w.init]
+        Ad = to_dev(A, dev)
+        before = [a.clone() for a in Ad]
+        f = plan.fitness(Ad)
+        r_ref = oracle.residual_explicit(T64, A)
+        f_ref = 1.0 - r_ref
+        say(f"  trial {trial}: r {r_ref:.3e}, |f - f_ref| {abs(f - f_ref):.2e}")
+        assert abs(f - f_ref) <= _fit_tol(prec, r_ref), (trial, f, f_ref)
+        assert all(torch.equal(a, b) for a, b in zip(Ad, before))
+    # after a regular sweep the audit agrees with the sweep's own residual
+    Ad = to_dev(w.init, dev)
+    plan.reset()
+    info = plan.als_sweep(Ad)
+    assert abs(plan.fitness(Ad) - info["fitness"]) <= 2 * _fit_tol(prec, info["r"])
+    plan.close()
+
+
+def _switch_theta(D, H, bias):
+    from oracle import mlp
+
+    th = np.zeros(mlp.n_params(D, H), dtype=np.float32)
+    th[-1] = bias  # b3: the network outputs sigmoid(bias) for every input
+    return th
+
+
+def test_learned_switch_schedules_and_features(dev):
+    """A constant network reproduces the forced schedules bit for bit (always
+    PP: regular, init, approx, ...; never PP: regular sweeps only), and the
+    features the plan feeds it are those of the sweep records."""
+    from paper_2010_12056_amd import cpals, learned_switch, synth
+
+    say("case learned switch plumbing")
+    w = synth.workload("o4_small_f32")
+    N = len(w.dims)
+    D, H = N + 3, 8
+    T = torch.from_numpy(w.T).to(dev)
+
+    def plan():
+        p = cpals.Plan(w.dims, w.R, prec="f32", tree="msdt", device=dev)
+        p.set_tensor(T)
+        return p
+
+    sweeps = 7
+    for bias, forced in ((10.0, ["exact", "init"] + ["approx"] * (sweeps - 2)), (-10.0, ["exact"] * sweeps)):
+        pl, ref = plan(), plan()
+        theta = torch.from_numpy(_switch_theta(D, H, bias)).to(dev)
+        pl.set_switch(theta, H, [0.0] * D, [1.0] * D, 0.5)
+        A, Aref = to_dev(w.init, dev), to_dev(w.init, dev)
+        hist = []
+        for s in range(sweeps):
+            info = pl.pp_sweep(A, mode="learned")
+            if s > 0:
+                feat, prob = pl.last_decision()
+                assert abs(prob - 1.0 / (1.0 + math.exp(-bias))) <= 1e-6
+                want = learned_switch.features(prev["dA_rel"], hist)
+                assert np.max(np.abs(np.array(feat) - np.array(want))) <= 1e-12
+            info_ref = ref.pp_sweep(Aref, mode=forced[s])
+            assert info["kind"] == forced[s] == info_ref["kind"], (bias, s)
+            assert info["fitness"] == info_ref["fitness"]
+            for a, b in zip(A, Aref):
+                assert torch.equal(a, b)
+            hist.insert(0, info["fitness"])
+            del hist[4:]
+            prev = info
+        pl.set_switch(None, 0, None, None)
+        pl.close()
+        ref.close()

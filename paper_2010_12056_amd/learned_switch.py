@@ -35,6 +35,8 @@ from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 
+from .cpals import CpalsError
+
 HERE = os.path.dirname(os.path.abspath(__file__))
 MODEL_DIR = os.path.join(HERE, "models")
 DEFAULT_MODEL = os.path.join(MODEL_DIR, "pp_switch_o6_s24_r32.json")
@@ -130,6 +132,7 @@ def collect_seed(b, seed, steps, behavior_eps, log=print):
     hist = []  # reported fitness after each sweep of the run, newest first
     last = None
     f_cur = None  # audited fitness of the current factors
+    stop = ""
     for _ in range(steps):
         if last is None:
             last = b.main.pp_sweep(A, mode="exact")
@@ -141,22 +144,40 @@ def collect_seed(b, seed, steps, behavior_eps, log=print):
         in_pp = last["kind"] in ("init", "approx")
         Ae = _copy(A)
         b.side.reset()
-        b.side.als_sweep(Ae)
+        try:
+            b.side.als_sweep(Ae)
+        except CpalsError as e:
+            # a regular sweep from this state breaks down (Gamma not positive definite):
+            # the trajectory has degenerated and ends here
+            stop = f", stopped: regular sweep failed ({e.status})"
+            break
         fe = b.audit(Ae)
         if not in_pp:
             Ap = _copy(A)
             b.side.reset()
-            b.side.pp_sweep(Ap, mode="init")
-            fp = b.audit(Ap)
+            try:
+                b.side.pp_sweep(Ap, mode="init")
+                fp = b.audit(Ap)
+            except CpalsError:
+                fp = -math.inf  # the PP step broke down: certainly worse than the regular sweep
             X.append(x)
             Y.append(1.0 if fp - f_cur >= GAIN_RATIO * (fe - f_cur) else 0.0)
             G.append((fe - f_cur, fp - f_cur))
             K.append(0)
-            info = b.main.pp_sweep(A, mode="init" if allowed else "exact")
-            f_next = fp if allowed else fe
+            use_pp = allowed and fp > -math.inf
+            info = b.main.pp_sweep(A, mode="init" if use_pp else "exact")
+            f_next = fp if use_pp else fe
         elif allowed:
-            info = b.main.pp_sweep(A, mode="approx")
-            fp = b.audit(A)
+            try:
+                info = b.main.pp_sweep(A, mode="approx")
+                fp = b.audit(A)
+            except CpalsError as e:
+                X.append(x)
+                Y.append(0.0)
+                G.append((fe - f_cur, -math.inf))
+                K.append(1)
+                stop = f", stopped: approximated sweep failed ({e.status})"
+                break
             X.append(x)
             Y.append(1.0 if fp - f_cur >= GAIN_RATIO * (fe - f_cur) else 0.0)
             G.append((fe - f_cur, fp - f_cur))
@@ -171,7 +192,7 @@ def collect_seed(b, seed, steps, behavior_eps, log=print):
         f_cur = f_next
     n = len(Y)
     log(f"[collect] seed {seed} eps {behavior_eps}: {n} samples ({sum(K)} approx), {int(sum(Y))} positive, "
-        f"final audited fitness {f_cur:.6f}")
+        f"last audited fitness {f_cur:.6f}{stop}")
     return (np.array(X, dtype=np.float64).reshape(n, -1), np.array(Y), np.array(G).reshape(n, 2),
             np.array(K, dtype=np.int32))
 
@@ -253,15 +274,20 @@ def run_policy(b, policy, sweeps, eps=None, target=None):
     kinds, times, fits = [], [], []
     reached = False
     f_audit = None
+    failed = ""
     for _ in range(sweeps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        if policy == "exact":
-            info = plan.pp_sweep(A, mode="exact")
-        elif policy == "eps":
-            info = plan.pp_sweep(A, tol=eps, mode="auto")
-        else:
-            info = plan.pp_sweep(A, mode="learned")
+        try:
+            if policy == "exact":
+                info = plan.pp_sweep(A, mode="exact")
+            elif policy == "eps":
+                info = plan.pp_sweep(A, tol=eps, mode="auto")
+            else:
+                info = plan.pp_sweep(A, mode="learned")
+        except CpalsError as e:
+            failed = f"sweep {len(kinds)}: status {e.status}"
+            break
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t0)
         kinds.append(info["kind"])
@@ -272,8 +298,9 @@ def run_policy(b, policy, sweeps, eps=None, target=None):
                 reached = True
                 break
     if not reached:
-        f_audit = b.audit(A)
-    return {"kinds": kinds, "times": times, "fitness": fits, "audited": f_audit, "reached": reached}
+        f_audit = b.audit(A) if not failed else float("nan")
+    return {"kinds": kinds, "times": times, "fitness": fits, "audited": f_audit, "reached": reached,
+            "failed": failed}
 
 
 def summarize(run, t_regular):
@@ -281,7 +308,7 @@ def summarize(run, t_regular):
     return {"steps": len(kinds), "time_s": float(sum(run["times"])),
             "regular_equiv": float(sum(run["times"]) / t_regular), "reached": run["reached"],
             "n_exact": kinds.count("exact"), "n_init": kinds.count("init"), "n_approx": kinds.count("approx"),
-            "audited_fitness": run["audited"]}
+            "audited_fitness": run["audited"], "failed": run["failed"]}
 
 
 def evaluate_workload(b, model, sweeps=200, margin=1e-4):

@@ -179,8 +179,10 @@ def _switch_theta(D, H, bias):
 
 def test_learned_switch_schedules_and_features(dev):
     """A constant network reproduces the forced schedules bit for bit (always
-    PP: regular, init, approx, ...; never PP: regular sweeps only), and the
-    features the plan feeds it are those of the sweep records."""
+    PP: PP initialization, then approximated sweeps; never PP: regular sweeps
+    only), and the features the plan feeds it are those of the sweep records.
+    Both runs start after regular sweeps that bring the factors near the
+    solution, where PP steps are meaningful."""
     from paper_2010_12056_amd import cpals, learned_switch, synth
 
     say("case learned switch plumbing")
@@ -194,20 +196,24 @@ def test_learned_switch_schedules_and_features(dev):
         p.set_tensor(T)
         return p
 
-    sweeps = 7
-    for bias, forced in ((10.0, ["exact", "init"] + ["approx"] * (sweeps - 2)), (-10.0, ["exact"] * sweeps)):
+    warm, sweeps = 10, 6
+    for bias, forced in ((10.0, ["init"] + ["approx"] * (sweeps - 1)), (-10.0, ["exact"] * sweeps)):
         pl, ref = plan(), plan()
         theta = torch.from_numpy(_switch_theta(D, H, bias)).to(dev)
         pl.set_switch(theta, H, [0.0] * D, [1.0] * D, 0.5)
         A, Aref = to_dev(w.init, dev), to_dev(w.init, dev)
         hist = []
+        for s in range(warm):
+            prev = pl.als_sweep(A)
+            assert ref.als_sweep(Aref)["fitness"] == prev["fitness"]
+            hist.insert(0, prev["fitness"])
+            del hist[4:]
         for s in range(sweeps):
             info = pl.pp_sweep(A, mode="learned")
-            if s > 0:
-                feat, prob = pl.last_decision()
-                assert abs(prob - 1.0 / (1.0 + math.exp(-bias))) <= 1e-6
-                want = learned_switch.features(prev["dA_rel"], hist)
-                assert np.max(np.abs(np.array(feat) - np.array(want))) <= 1e-12
+            feat, prob = pl.last_decision()
+            assert abs(prob - 1.0 / (1.0 + math.exp(-bias))) <= 1e-6
+            want = learned_switch.features(prev["dA_rel"], hist)
+            assert np.max(np.abs(np.array(feat) - np.array(want))) <= 1e-12
             info_ref = ref.pp_sweep(Aref, mode=forced[s])
             assert info["kind"] == forced[s] == info_ref["kind"], (bias, s)
             assert info["fitness"] == info_ref["fitness"]
@@ -216,6 +222,7 @@ def test_learned_switch_schedules_and_features(dev):
             hist.insert(0, info["fitness"])
             del hist[4:]
             prev = info
+        say(f"  bias {bias}: fitness {prev['fitness']:.6f}")
         pl.set_switch(None, 0, None, None)
         pl.close()
         ref.close()

@@ -43,11 +43,20 @@ typedef enum {
   CP_ERR_STATE = 2,       /* call out of order (no workspace, no tensor, no PP operators) */
   CP_ERR_UNSUPPORTED = 3, /* outside the stated limits */
   CP_ERR_HIP = 4,         /* a HIP runtime call failed; see cp_last_error */
-  CP_ERR_NOT_SPD = 5,     /* a Gamma matrix was not numerically positive definite */
+  CP_ERR_NOT_SPD = 5,     /* a Gamma matrix had non-finite entries (a singular Gamma is
+                             handled by its pseudo-inverse, as Alg. 1 writes it) */
   CP_ERR_NUMERIC = 6      /* the residual came out NaN or infinite */
 } cp_status;
 
-typedef enum { CP_F64 = 0, CP_F32 = 1 } cp_prec;
+/* Tensor precision.  CP_F64 and CP_F32: the tensor, the tree intermediates
+ * and the factor shadows in that type, FP64 for everything of size R x R and
+ * for the factors.  CP_BF16 and CP_BF16X2 (not from the paper): the tensor is
+ * stored in BF16 (raw bits, the upper half of an FP32 value) and its first
+ * contraction runs on the BF16 matrix cores with FP32 accumulation, the
+ * factor rounded to BF16 (CP_BF16) or split into two BF16 parts B_hi + B_lo
+ * (CP_BF16X2, about 16 significant bits); the levels below are FP32 as in
+ * CP_F32. */
+typedef enum { CP_F64 = 0, CP_F32 = 1, CP_BF16 = 2, CP_BF16X2 = 3 } cp_prec;
 
 typedef enum {
   CP_TREE_DT = 0,   /* standard binary dimension tree, two first-level TTMs per sweep (Sec. II-C) */
@@ -73,7 +82,9 @@ typedef struct {
   double dA_rel[8];      /* ||dA^(i)||_F / ||A^(i)||_F after the sweep (Alg. 2 test inputs);
                             1 for a zero factor, 0 past the tensor order */
   int ttm_count;         /* first-level contractions with the tensor done in this call */
-  int reserved;
+  int pinv_updates;      /* factor updates since the last report whose Gamma^(n) was singular to
+                            working precision, so that its pseudo-inverse (Alg. 1) came from the
+                            eigendecomposition instead of the elimination */
 } cp_sweep_info;
 
 /* Create a plan for an order-`order` tensor of dims `dims` (host array of

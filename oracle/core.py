@@ -18,7 +18,6 @@ Pins (tests marked "not gpu"):
 import itertools
 
 import numpy as np
-import scipy.linalg
 
 
 def krp(mats):
@@ -107,20 +106,21 @@ def gamma(S, n):
 
 
 def spd_solve(G, M):
-    """A = M G^dagger for a symmetric positive (semi)definite G (Alg. 1 update
-    of A^(i)).  Cholesky factorization and triangular solves; when Cholesky
-    fails, a symmetric-eigen pseudo-inverse with eigenvalues at or below
-    R * eps * lambda_max treated as zero.  Returns (A, used_pinv)."""
+    """A = M G^dagger, the update of A^(i) in Alg. 1 (and Alg. 2), with the
+    Moore-Penrose pseudo-inverse of the symmetric positive semidefinite
+    G = Gamma^(i) taken by its definition: G = V diag(w) V^T (symmetric
+    eigendecomposition), eigenvalues at or below R * eps * lambda_max treated
+    as zero.  For a well-conditioned G this is G^-1.  Returns
+    (A, rank_deficient) where rank_deficient says an eigenvalue was dropped."""
     G = np.asarray(G, dtype=np.float64)
     M = np.asarray(M, dtype=np.float64)
-    try:
-        c = scipy.linalg.cho_factor(G, lower=True, check_finite=True)
-        return scipy.linalg.cho_solve(c, M.T).T, False
-    except np.linalg.LinAlgError:
-        w, V = np.linalg.eigh(G)
-        cut = G.shape[0] * np.finfo(np.float64).eps * max(w.max(), 0.0)
-        winv = np.where(w > cut, 1.0 / np.where(w > cut, w, 1.0), 0.0)
-        return M @ ((V * winv) @ V.T), True
+    if not np.all(np.isfinite(G)):
+        raise np.linalg.LinAlgError("non-finite Gamma")
+    w, V = np.linalg.eigh(G)
+    cut = G.shape[0] * np.finfo(np.float64).eps * max(w.max(), 0.0)
+    keep = w > cut
+    winv = np.where(keep, 1.0 / np.where(keep, w, 1.0), 0.0)
+    return M @ ((V * winv) @ V.T), bool(not keep.all())
 
 
 def residual_fast(normT2, G_last, S_last, M_last, A_last):

@@ -15,17 +15,17 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcpals.so")
 
 CP_OK, CP_ERR_ARG, CP_ERR_STATE, CP_ERR_UNSUPPORTED, CP_ERR_HIP, CP_ERR_NOT_SPD, CP_ERR_NUMERIC = range(7)
-CP_F64, CP_F32 = 0, 1
+CP_F64, CP_F32, CP_BF16, CP_BF16X2 = 0, 1, 2, 3
 CP_TREE_DT, CP_TREE_MSDT = 0, 2
 CP_PP_AUTO, CP_PP_FORCE_EXACT, CP_PP_FORCE_APPROX, CP_PP_FORCE_REINIT, CP_PP_LEARNED = range(5)
 KIND_NAMES = {0: "exact", 1: "init", 2: "approx"}
 PHASES = ["ttm", "mttv", "update", "pp", "other"]
 
-PRECS = {"f64": CP_F64, "f32": CP_F32}
+PRECS = {"f64": CP_F64, "f32": CP_F32, "bf16": CP_BF16, "bf16x2": CP_BF16X2}
 TREES = {"dt": CP_TREE_DT, "msdt": CP_TREE_MSDT}
 PP_MODES = {"auto": CP_PP_AUTO, "exact": CP_PP_FORCE_EXACT, "approx": CP_PP_FORCE_APPROX,
             "init": CP_PP_FORCE_REINIT, "learned": CP_PP_LEARNED}
-TORCH_DTYPE = {CP_F64: torch.float64, CP_F32: torch.float32}
+TORCH_DTYPE = {CP_F64: torch.float64, CP_F32: torch.float32, CP_BF16: torch.bfloat16, CP_BF16X2: torch.bfloat16}
 
 
 class SweepInfo(ctypes.Structure):
@@ -36,7 +36,7 @@ class SweepInfo(ctypes.Structure):
         ("r", ctypes.c_double),
         ("dA_rel", ctypes.c_double * 8),
         ("ttm_count", ctypes.c_int),
-        ("reserved", ctypes.c_int),
+        ("pinv_updates", ctypes.c_int),
     ]
 
     def as_dict(self, order):
@@ -47,6 +47,7 @@ class SweepInfo(ctypes.Structure):
             "r": self.r,
             "dA_rel": [self.dA_rel[i] for i in range(order)],
             "ttm_count": self.ttm_count,
+            "pinv_updates": self.pinv_updates,
         }
 
 

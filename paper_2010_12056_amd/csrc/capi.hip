@@ -98,6 +98,9 @@ struct cp_plan_s {
   bool sw_set = false;
   float* sw_in = nullptr;   // workspace: normalized features
   float* sw_out = nullptr;  // workspace: probability
+  uint16_t* Bt_hi = nullptr;  // BF16 plans: transposed BF16 factor of the first contraction
+  uint16_t* Bt_lo = nullptr;  // BF16X2 plans: its remainder part
+  int pinv_seen = 0;         // stats->pinv_count at the last report
   double fit_hist[4] = {};  // fitness after the most recent sweeps, newest first
   int n_hist = 0;
   bool pending_fit = false;  // a sweep ran whose fitness is not in fit_hist yet
@@ -219,6 +222,9 @@ void plan_layout(cp_plan p) {
   take(sizeof(DevStats));                        // stats
   take(16 * sizeof(float));                      // sw_in
   take(16 * sizeof(float));                      // sw_out
+  const bool bf = (p->prec == CP_BF16 || p->prec == CP_BF16X2);
+  take(bf ? (size_t)R * bf16_factor_pitch(smax) * 2 : 0);                               // Bt_hi
+  take(p->prec == CP_BF16X2 ? (size_t)R * bf16_factor_pitch(smax) * 2 : 0);             // Bt_lo
   // slots for depths 1..N-2 (depth d keeps N - d modes)
   std::vector<int64_t> sorted(p->dims, p->dims + N);
   std::sort(sorted.begin(), sorted.end(), std::greater<int64_t>());
@@ -254,6 +260,9 @@ void plan_carve(cp_plan p) {
   p->stats = (DevStats*)next();
   p->sw_in = (float*)next();
   p->sw_out = (float*)next();
+  p->Bt_hi = (uint16_t*)next();
+  void* lo = next();
+  p->Bt_lo = (p->prec == CP_BF16X2) ? (uint16_t*)lo : nullptr;
   for (int d = 1; d <= N - 2; ++d) p->slot_buf[d] = next();
 }
 
@@ -311,7 +320,12 @@ cp_status contract(cp_plan p, const void* in, uint32_t in_set, int c, void* out,
     if (out_f64) return fail(p, CP_ERR_STATE, "internal: first-level contraction into FP64");
     ++p->ttm_count;
     ProfScope ps(p, CP_PHASE_TTM);
-    HIP_TRY(p, launch_ttm<TT>((const TT*)in, A, (TT*)out, P, I, Q, p->R, p->st));
+    if (p->prec == CP_BF16 || p->prec == CP_BF16X2) {
+      HIP_TRY(p, launch_split_factor((const float*)A, I, p->R, p->Bt_hi, p->Bt_lo, p->st));
+      HIP_TRY(p, launch_ttm_bf16((const uint16_t*)in, p->Bt_hi, p->Bt_lo, (float*)out, P, I, Q, p->R, p->st));
+    } else {
+      HIP_TRY(p, launch_ttm<TT>((const TT*)in, A, (TT*)out, P, I, Q, p->R, p->st));
+    }
   } else if (out_f64) {
     ProfScope ps(p, CP_PHASE_MTTV);
     HIP_TRY(p, (launch_mttv<TT, double>((const TT*)in, A, (double*)out, P, I, Q, p->R, p->st)));
@@ -543,6 +557,8 @@ cp_status fill_info(cp_plan p, cp_sweep_info* info, int kind) {
   DevStats h;
   CP_TRY(read_stats(p, &h));
   if (p->pending_fit) note_fitness(p, h.r);
+  const int pinv_seen = p->pinv_seen;
+  p->pinv_seen = h.pinv_count;
   if (info) {
     info->kind = kind;
     info->fitness_is_exact = (kind == CP_SWEEP_EXACT) ? 1 : 0;
@@ -551,8 +567,9 @@ cp_status fill_info(cp_plan p, cp_sweep_info* info, int kind) {
     for (int m = 0; m < kMaxOrder; ++m)
       info->dA_rel[m] = m >= p->N ? 0.0 : (h.normA2[m] > 0 ? std::sqrt(h.normdA2[m] / h.normA2[m]) : 1.0);
     info->ttm_count = p->ttm_count;
+    info->pinv_updates = h.pinv_count - pinv_seen;
   }
-  if (h.status & 1) return fail(p, CP_ERR_NOT_SPD, "a Gamma matrix was not numerically positive definite");
+  if (h.status & 1) return fail(p, CP_ERR_NOT_SPD, "a Gamma matrix had non-finite entries");
   if (h.status & 2) return fail(p, CP_ERR_NUMERIC, "non-finite residual");
   return CP_OK;
 }
@@ -761,7 +778,7 @@ cp_status cp_plan_create(cp_plan* out, int order, const int64_t* dims, int rank,
   *out = nullptr;
   if (order < 3 || order > kMaxOrder) return CP_ERR_UNSUPPORTED;
   if (rank < 1 || rank > kMaxRank) return CP_ERR_UNSUPPORTED;
-  if (prec != CP_F64 && prec != CP_F32) return CP_ERR_UNSUPPORTED;
+  if (prec != CP_F64 && prec != CP_F32 && prec != CP_BF16 && prec != CP_BF16X2) return CP_ERR_UNSUPPORTED;
   if (tree != CP_TREE_DT && tree != CP_TREE_MSDT) return CP_ERR_UNSUPPORTED;
   double numel = 1.0;
   for (int m = 0; m < order; ++m) {
@@ -811,6 +828,8 @@ cp_status cp_set_tensor(cp_plan p, const void* T) {
   for (int m = 0; m < p->N; ++m) numel *= p->dims[m];
   if (p->prec == CP_F64) {
     HIP_TRY(p, launch_norm2<double>((const double*)T, numel, p->normParts, kNormParts, p->stats, p->st));
+  } else if (p->prec == CP_BF16 || p->prec == CP_BF16X2) {
+    HIP_TRY(p, launch_norm2<bf16>((const bf16*)T, numel, p->normParts, kNormParts, p->stats, p->st));
   } else {
     HIP_TRY(p, launch_norm2<float>((const float*)T, numel, p->normParts, kNormParts, p->stats, p->st));
   }
@@ -982,7 +1001,7 @@ cp_status cp_sync(cp_plan p) {
   }
   DevStats h;
   CP_TRY(read_stats(p, &h));
-  if (h.status & 1) return fail(p, CP_ERR_NOT_SPD, "a Gamma matrix was not numerically positive definite");
+  if (h.status & 1) return fail(p, CP_ERR_NOT_SPD, "a Gamma matrix had non-finite entries");
   if (h.status & 2) return fail(p, CP_ERR_NUMERIC, "non-finite residual");
   return CP_OK;
 }
@@ -1040,7 +1059,7 @@ const char* cp_status_str(cp_status s) {
     case CP_ERR_STATE: return "call out of order";
     case CP_ERR_UNSUPPORTED: return "unsupported size or option";
     case CP_ERR_HIP: return "HIP runtime error";
-    case CP_ERR_NOT_SPD: return "Gamma not positive definite";
+    case CP_ERR_NOT_SPD: return "Gamma not finite";
     case CP_ERR_NUMERIC: return "non-finite result";
   }
   return "unknown status";

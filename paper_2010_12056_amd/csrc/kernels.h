@@ -12,8 +12,16 @@ struct DevStats {
   double r;           // relative residual, Eq. (3)
   double normA2[8];   // ||A^(i)||_F^2 after its last update
   double normdA2[8];  // ||dA^(i)||_F^2 (per-sweep change, or A - A_p in the PP phase)
-  int status;         // bit 0: a Gamma was not SPD; bit 1: non-finite residual
+  int status;         // bit 0: a Gamma had non-finite entries; bit 1: non-finite residual
+  int pinv_pending;   // set by the elimination when a pivot fell below its tolerance
+  int pinv_count;     // updates that used the pseudo-inverse (cumulative)
   int pad;
+};
+
+// A BF16 tensor element: the upper 16 bits of an FP32 value.
+struct bf16 {
+  uint16_t bits;
+  __device__ explicit operator double() const { return (double)__uint_as_float((uint32_t)bits << 16); }
 };
 
 constexpr int kMaxOrder = 8;
@@ -25,6 +33,14 @@ __host__ __device__ inline int solve_rows(int) { return 16; }
 template <typename T>
 hipError_t launch_ttm(const T* X, const T* B, T* C, int64_t P, int64_t K, int64_t Q, int R,
                       hipStream_t st);
+
+// BF16 tensor path of the first contraction (FP32 accumulation, FP32 C):
+// the factor is first written transposed in BF16, Bt[c][k] with pitch
+// bf16_factor_pitch(K), and, for the split product, its remainder Blo.
+int bf16_factor_pitch(int64_t K);
+hipError_t launch_split_factor(const float* A, int64_t K, int R, uint16_t* hi, uint16_t* lo, hipStream_t st);
+hipError_t launch_ttm_bf16(const uint16_t* X, const uint16_t* Bhi, const uint16_t* Blo, float* C, int64_t P,
+                           int64_t K, int64_t Q, int R, hipStream_t st);
 
 // Y[p][q][r] = sum_i X[p][i][q][r] * A[i][r]; accumulation in the output type.
 template <typename TI, typename TO>
@@ -57,8 +73,12 @@ struct GammaArgs {
 };
 hipError_t launch_gamma(const GammaArgs& a, hipStream_t st);
 
-// Ginv = Gamma^-1 (Gamma SPD; Gauss-Jordan without pivoting in one
-// workgroup; a non-positive pivot sets bit 0 of stats->status and zeroes Ginv).
+// Ginv = Gamma^dagger (Alg. 1): Gauss-Jordan elimination without pivoting in
+// one workgroup; when a pivot is at or below R eps max(diag), the symmetric
+// eigendecomposition (cyclic Jacobi, a second one-workgroup kernel that
+// returns at once otherwise) gives the pseudo-inverse with eigenvalues at or
+// below R eps lambda_max dropped.  Non-finite entries set bit 0 of
+// stats->status and zero Ginv.
 hipError_t launch_inverse(const double* Gamma, double* Ginv, int R, DevStats* stats, hipStream_t st);
 
 // Row-block solve and partial reductions for one mode update.

@@ -680,7 +680,138 @@ __global__ __launch_bounds__(RP > 64 ? 512 : (RP / 16) * 64) void k_inv(const do
       const int i = 16 * w + r, j = lane + 64 * c;
       if (i < R && j < R) Gi[i * R + j] = failed ? 0.0 : g[c][r];
     }
-  if (failed && threadIdx.x == 0) stats->status |= 1;
+  if (failed && threadIdx.x == 0) stats->pinv_pending = 1;
+}
+
+// Gamma^dagger when k_inv gave up (stats->pinv_pending): the cyclic Jacobi
+// eigenvalue method (Golub and Van Loan, Matrix Computations, Sec. 8.5) in
+// parallel round-robin order.  Each round rotates R/2 disjoint index pairs
+// (p, q), chosen by the circle method (with a bye for odd R), with the
+// rotation that zeroes A[p][q]; rows, then columns of the working matrix A
+// (LDS, pitch R + 1) and the columns of V (kept in Ginv's memory) are
+// updated.  A pair with |A[p][q]| <= eps sqrt(|A[p][p] A[q][q]|) is not
+// rotated (its entry is set to zero); the sweeps stop when none rotates.
+// Then Ginv = V diag(w+) V^T with w+ = 1 / w for w > R eps max(w), else 0.
+__global__ __launch_bounds__(512) void k_pinv(const double* __restrict__ Gm, double* __restrict__ Gi, int R,
+                                              DevStats* stats) {
+  if (stats->pinv_pending == 0) return;  // uniform
+  constexpr double eps = 2.220446049250313e-16;
+  extern __shared__ double lds_d[];
+  const int pitch = R + 1;
+  double* A = lds_d;                     // R x pitch
+  double* w = A + (size_t)R * pitch;     // R eigenvalues
+  double* cs = w + R;                    // 2 x 64 rotation (c, s)
+  int* pq = (int*)(cs + 128);            // 2 x 64 pair indices
+  __shared__ int bad, rot;
+  const int tid = threadIdx.x;
+  const int RR = R * R;
+  if (tid == 0) bad = 0;
+  __syncthreads();
+  for (int e = tid; e < RR; e += 512) {
+    const int i = e / R, j = e - i * R;
+    const double v = Gm[e];
+    if (!isfinite(v)) bad = 1;
+    A[i * pitch + j] = v;
+    Gi[e] = (i == j) ? 1.0 : 0.0;  // V = I
+  }
+  __syncthreads();
+  if (bad) {
+    for (int e = tid; e < RR; e += 512) Gi[e] = 0.0;
+    if (tid == 0) {
+      stats->status |= 1;
+      stats->pinv_pending = 0;
+    }
+    return;
+  }
+  const int n = R + (R & 1);  // players; index R is the bye when R is odd
+  const int npair = n / 2;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    if (tid == 0) rot = 0;
+    __syncthreads();
+    for (int round = 0; round < n - 1; ++round) {
+      if (tid < npair) {
+        const int k = tid;
+        const int a = (round + k) % (n - 1);
+        const int b = (k == 0) ? n - 1 : (round - k + n - 1) % (n - 1);
+        const int p = a < b ? a : b, q = a < b ? b : a;
+        double c = 1.0, sn = 0.0;
+        if (q < R) {
+          const double apq = A[p * pitch + q], app = A[p * pitch + p], aqq = A[q * pitch + q];
+          if (apq != 0.0 && fabs(apq) > eps * sqrt(fabs(app * aqq))) {
+            const double tau = (aqq - app) / (2.0 * apq);
+            const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            c = 1.0 / sqrt(1.0 + t * t);
+            sn = t * c;
+            rot = 1;
+          }
+        }
+        pq[2 * k] = p;
+        pq[2 * k + 1] = q < R ? q : p;  // the bye pairs p with itself: identity
+        cs[2 * k] = c;
+        cs[2 * k + 1] = sn;
+      }
+      __syncthreads();
+      // rows p, q of A
+      for (int e = tid; e < npair * R; e += 512) {
+        const int k = e / R, j = e - k * R;
+        const int p = pq[2 * k], q = pq[2 * k + 1];
+        if (p == q) continue;
+        const double c = cs[2 * k], sn = cs[2 * k + 1];
+        const double x = A[p * pitch + j], y = A[q * pitch + j];
+        A[p * pitch + j] = c * x - sn * y;
+        A[q * pitch + j] = sn * x + c * y;
+      }
+      __syncthreads();
+      // columns p, q of A and of V
+      for (int e = tid; e < npair * R; e += 512) {
+        const int k = e / R, i = e - k * R;
+        const int p = pq[2 * k], q = pq[2 * k + 1];
+        if (p == q) continue;
+        const double c = cs[2 * k], sn = cs[2 * k + 1];
+        const double x = A[i * pitch + p], y = A[i * pitch + q];
+        A[i * pitch + p] = c * x - sn * y;
+        A[i * pitch + q] = sn * x + c * y;
+        const double vx = Gi[i * R + p], vy = Gi[i * R + q];
+        Gi[i * R + p] = c * vx - sn * vy;
+        Gi[i * R + q] = sn * vx + c * vy;
+      }
+      __syncthreads();
+      if (tid < npair) {
+        const int p = pq[2 * tid], q = pq[2 * tid + 1];
+        if (p != q) {
+          A[p * pitch + q] = 0.0;
+          A[q * pitch + p] = 0.0;
+        }
+      }
+      __syncthreads();
+    }
+    const bool done = (rot == 0);  // read after the round's last barrier
+    __syncthreads();
+    if (done) break;
+  }
+  for (int i = tid; i < R; i += 512) w[i] = A[i * pitch + i];
+  __syncthreads();
+  double wmax = 0.0;
+  for (int i = 0; i < R; ++i) wmax = fmax(wmax, w[i]);
+  const double cut = (double)R * eps * wmax;
+  __syncthreads();
+  for (int i = tid; i < R; i += 512) w[i] = (w[i] > cut) ? 1.0 / w[i] : 0.0;
+  __syncthreads();
+  for (int e = tid; e < RR; e += 512) {
+    const int i = e / R, j = e - i * R;
+    double acc = 0.0;
+    for (int k = 0; k < R; ++k) acc += Gi[i * R + k] * w[k] * Gi[j * R + k];
+    A[i * pitch + j] = acc;
+  }
+  __syncthreads();
+  for (int e = tid; e < RR; e += 512) {
+    const int i = e / R, j = e - i * R;
+    Gi[e] = A[i * pitch + j];
+  }
+  if (tid == 0) {
+    stats->pinv_pending = 0;
+    stats->pinv_count += 1;
+  }
 }
 
 // One 16-row block of a mode update on the matrix cores (f64 16x16x4):
@@ -1148,6 +1279,14 @@ hipError_t launch_inverse(const double* Gamma, double* Ginv, int R, DevStats* st
   } else {
     hipLaunchKernelGGL(k_inv<128>, dim3(1), dim3(512), 0, st, Gamma, Ginv, R, stats);
   }
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_pinv, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  const size_t lds = ((size_t)R * (R + 1) + R + 128) * sizeof(double) + 128 * sizeof(int);
+  hipLaunchKernelGGL(k_pinv, dim3(1), dim3(512), lds, st, Gamma, Ginv, R, stats);
   return hipGetLastError();
 }
 
@@ -1191,6 +1330,7 @@ template hipError_t launch_mttv<double, double>(const double*, const double*, do
 template hipError_t launch_convert<float>(const double*, float*, int64_t, hipStream_t);
 template hipError_t launch_convert<double>(const double*, double*, int64_t, hipStream_t);
 template hipError_t launch_norm2<float>(const float*, int64_t, double*, int, DevStats*, hipStream_t);
+template hipError_t launch_norm2<bf16>(const bf16*, int64_t, double*, int, DevStats*, hipStream_t);
 template hipError_t launch_norm2<double>(const double*, int64_t, double*, int, DevStats*,
                                          hipStream_t);
 template hipError_t launch_solve<float>(const SolveArgs<float>&, int, hipStream_t);

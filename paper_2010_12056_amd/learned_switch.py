@@ -147,8 +147,8 @@ def collect_seed(b, seed, steps, behavior_eps, log=print):
         try:
             b.side.als_sweep(Ae)
         except CpalsError as e:
-            # a regular sweep from this state breaks down (Gamma not positive definite):
-            # the trajectory has degenerated and ends here
+            # a regular sweep from this state breaks down (non-finite Gamma after a
+            # diverging approximated step): the trajectory ends here
             stop = f", stopped: regular sweep failed ({e.status})"
             break
         fe = b.audit(Ae)
@@ -311,10 +311,10 @@ def summarize(run, t_regular):
             "audited_fitness": run["audited"], "failed": run["failed"]}
 
 
-def evaluate_workload(b, model, sweeps=200, margin=1e-4):
+def evaluate_workload(b, model, sweeps=200, margin=1e-4, thresholds=None):
     """Time to reach the regular-only run's final (audited) fitness minus
     `margin`, for regular sweeps only, eps = 0.1, eps = 0.2 and the learned
-    switch."""
+    switch (at the model's threshold, or at each of `thresholds`)."""
     ref = run_policy(b, "exact", sweeps)
     target = ref["audited"] - margin
     t_regular = float(np.median(ref["times"][1:])) if len(ref["times"]) > 1 else ref["times"][0]
@@ -322,12 +322,27 @@ def evaluate_workload(b, model, sweeps=200, margin=1e-4):
            "regular": summarize(run_policy(b, "exact", sweeps, target=target), t_regular)}
     for name, eps in (("eps0.1", 0.1), ("eps0.2", 0.2)):
         out[name] = summarize(run_policy(b, "eps", sweeps, eps=eps, target=target), t_regular)
-    theta = attach(b.main, model)
-    try:
-        out["learned"] = summarize(run_policy(b, "learned", sweeps, target=target), t_regular)
-    finally:
-        b.main.set_switch(None, 0, None, None)
-        del theta
+    ths = thresholds if thresholds else [model.get("threshold", 0.5)]
+    for th in ths:
+        theta = attach(b.main, dict(model, threshold=th))
+        try:
+            name = "learned" if not thresholds else f"learned@{th:g}"
+            out[name] = summarize(run_policy(b, "learned", sweeps, target=target), t_regular)
+        finally:
+            b.main.set_switch(None, 0, None, None)
+            del theta
+    return out
+
+
+def aggregate(res):
+    """Per policy: runs that reached the target, and the geometric mean over
+    seeds of (time to target) / (regular-only time to target) on those runs."""
+    pols = [k for k, v in next(iter(res.values())).items() if isinstance(v, dict)]
+    out = {}
+    for pol in pols:
+        ratios = [r[pol]["time_s"] / r["regular"]["time_s"] for r in res.values() if r[pol]["reached"]]
+        out[pol] = {"reached": len(ratios), "runs": len(res),
+                    "time_ratio_geomean": float(np.exp(np.mean(np.log(ratios)))) if ratios else None}
     return out
 
 
@@ -343,16 +358,23 @@ def main(argv=None):
     t.add_argument("--traces", required=True)
     t.add_argument("--steps", type=int, default=3000)
     t.add_argument("--lr", type=float, default=3e-3)
+    t.add_argument("--exclude-seeds", default="", help="seed range kept out of training (threshold selection)")
     t.add_argument("--out", default=DEFAULT_MODEL)
+    sel = sub.add_parser("select", help="set the model threshold from an evaluation with --thresholds")
+    sel.add_argument("--eval", required=True)
+    sel.add_argument("--model", default=DEFAULT_MODEL)
     e = sub.add_parser("evaluate")
     e.add_argument("--seeds", default=f"{HELDOUT_SEEDS[0]}-{HELDOUT_SEEDS[-1]}")
     e.add_argument("--sweeps", type=int, default=200)
     e.add_argument("--model", default=DEFAULT_MODEL)
     e.add_argument("--small", action="store_true")
+    e.add_argument("--thresholds", default="", help="comma-separated switch thresholds to compare")
     e.add_argument("--out", required=True)
     args = ap.parse_args(argv)
 
     def seeds(spec):
+        if not spec:
+            return []
         a, b_ = spec.split("-")
         return list(range(int(a), int(b_) + 1))
 
@@ -376,27 +398,44 @@ def main(argv=None):
         log(f"[collect] wrote {args.out}")
     elif args.cmd == "train":
         d = np.load(args.traces)
-        model = train(d["X"], d["y"], steps=args.steps, lr=args.lr, log=log)
+        keep = ~np.isin(d["seed"], seeds(args.exclude_seeds))
+        model = train(d["X"][keep], d["y"][keep], steps=args.steps, lr=args.lr, log=log)
         fam = {k: (list(v) if isinstance(v, tuple) else v) for k, v in FAMILY.items()}
-        model["traces"] = {"seeds": sorted(set(int(s) for s in d["seed"])), "family": fam,
+        model["traces"] = {"seeds": sorted(set(int(s) for s in d["seed"][keep])), "family": fam,
                            "behavior_eps": list(BEHAVIOR_EPS), "gain_ratio": GAIN_RATIO}
         os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
         with open(args.out, "w") as f:
             json.dump(model, f)
         log(f"[train] wrote {args.out}")
+    elif args.cmd == "select":
+        with open(args.eval) as f:
+            agg = json.load(f)["aggregate"]
+        cands = [(v["reached"], -(v["time_ratio_geomean"] or math.inf), float(k.split("@")[1]))
+                 for k, v in agg.items() if k.startswith("learned@")]
+        best = max(cands)
+        model = load_model(args.model)
+        model["threshold"] = best[2]
+        model["threshold_selection"] = {"eval": os.path.basename(args.eval), "aggregate": agg}
+        with open(args.model, "w") as f:
+            json.dump(model, f)
+        log(f"[select] threshold {best[2]:g} (reached {best[0]}, time ratio {-best[1]:.3f})")
     else:
         model = load_model(args.model)
+        ths = [float(t) for t in args.thresholds.split(",")] if args.thresholds else None
         res = {}
         for sd, w in _prefetch(seeds(args.seeds), args.small, workers=2):
             b = Bench(w)
-            res[sd] = evaluate_workload(b, model, args.sweeps)
+            res[sd] = evaluate_workload(b, model, args.sweeps, thresholds=ths)
             b.close()
             del b, w
             log(f"[evaluate] seed {sd}: " + ", ".join(
                 f"{k} {v['time_s'] * 1e3:.1f} ms/{v['steps']} sweeps{'' if v['reached'] else ' (not reached)'}"
                 for k, v in res[sd].items() if isinstance(v, dict)))
             with open(args.out, "w") as f:
-                json.dump(res, f, indent=1)
+                json.dump({"seeds": res, "aggregate": aggregate(res)}, f, indent=1)
+        for k, v in aggregate(res).items():
+            log(f"[evaluate] {k}: reached {v['reached']}/{v['runs']}, time / regular-only time "
+                f"{v['time_ratio_geomean']}")
     return 0
 
 

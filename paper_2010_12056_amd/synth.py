@@ -131,3 +131,17 @@ def workload(name, **over):
     cfg = dict(WORKLOADS[name])
     cfg.update(over)
     return planted_tensor(name=name, **cfg)
+
+
+def bf16_bits(x):
+    """Round FP32 values to BF16 (nearest, ties to even); returns the raw
+    16-bit patterns (uint16).  Storage conversion of a generated tensor."""
+    u = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32)
+    r = (u + np.uint32(0x7FFF) + ((u >> np.uint32(16)) & np.uint32(1))) >> np.uint32(16)
+    return r.astype(np.uint16)
+
+
+def bf16_to_f32(bits):
+    """The FP32 values of raw BF16 patterns (exact)."""
+    return (np.asarray(bits, dtype=np.uint16).astype(np.uint32) << np.uint32(16)).view(np.float32)
+

@@ -179,19 +179,47 @@ def test_pp_auto_matches_oracle_schedule_fp64(dev):
     plan.close()
 
 
-def test_singular_gamma_reports_not_spd(dev):
+def test_singular_gamma_uses_pseudo_inverse(dev):
+    """Alg. 1 updates with the pseudo-inverse of Gamma^(n).  A zero column in
+    one factor makes every other Gamma^(n) exactly singular: the elimination
+    gives up and the eigendecomposition path must reproduce the oracle's
+    pseudo-inverse update, sweep after sweep."""
+    import oracle
+    from paper_2010_12056_amd import cpals, synth
+
+    say("case singular Gamma")
+    w = synth.workload("o3_small_f64")
+    init = [a.copy() for a in w.init]
+    init[1][:, 3] = 0.0
+    plan = cpals.Plan(w.dims, w.R, prec="f64", tree="dt", device=dev)
+    T = torch.from_numpy(w.T).to(dev)
+    plan.set_tensor(T)
+    A = to_dev(init, dev)
+    st = oracle.AlsState.start(w.T.astype(np.float64), init)
+    for sweep in range(3):
+        info = plan.als_sweep(A)
+        r_ref = oracle.als_sweep(st)
+        assert info["pinv_updates"] >= 2, info  # Gamma^(0) and Gamma^(2) at least
+        assert abs(info["r"] - r_ref) <= 1e-10, (sweep, info["r"], r_ref)
+        for n in range(3):
+            assert relerr(A[n].cpu().numpy(), st.A[n]) <= 1e-9, (sweep, n)
+        assert np.all(A[1].cpu().numpy()[:, 3] == 0.0)
+    plan.close()
+
+
+def test_nonfinite_gamma_reports_error(dev):
     from paper_2010_12056_amd import cpals, synth
 
     w = synth.workload("o3_small_f64")
     init = [a.copy() for a in w.init]
-    init[1][:, 3] = 0.0  # a zero column makes every Gamma^(n), n != 1, singular
+    init[2][0, 0] = np.inf
     plan = cpals.Plan(w.dims, w.R, prec="f64", tree="dt", device=dev)
     T = torch.from_numpy(w.T).to(dev)
     plan.set_tensor(T)
     A = to_dev(init, dev)
     with pytest.raises(cpals.CpalsError) as ei:
         plan.als_sweep(A)
-    assert ei.value.status == cpals.CP_ERR_NOT_SPD
+    assert ei.value.status in (cpals.CP_ERR_NOT_SPD, cpals.CP_ERR_NUMERIC)
     plan.reset()
     plan.close()
 

@@ -133,6 +133,22 @@ def test_spd_solve_pinv_fallback():
     np.testing.assert_allclose(A, M @ np.linalg.pinv(G, rcond=5 * np.finfo(float).eps, hermitian=True), rtol=1e-10, atol=1e-12)
 
 
+def test_spd_solve_drops_numerically_singular_directions():
+    """Alg. 1 writes the pseudo-inverse: a direction whose eigenvalue is below
+    the numerical-rank cutoff is dropped even where a Cholesky factorization
+    would still succeed (and return entries of order 1e19)."""
+    rng = np.random.default_rng(13)
+    B = rng.standard_normal((20, 5))
+    B[:, 4] = 1e-10 * rng.standard_normal(20)
+    G = B.T @ B
+    M = rng.standard_normal((6, 5))
+    A, used = core.spd_solve(G, M)
+    assert used
+    ref = np.zeros((6, 5))
+    ref[:, :4] = M[:, :4] @ np.linalg.inv(G[:4, :4])
+    np.testing.assert_allclose(A, ref, rtol=1e-7, atol=1e-8)
+
+
 def test_gamma_is_hadamard_of_others():
     rng = np.random.default_rng(5)
     S = [rng.random((4, 4)) for _ in range(4)]

@@ -144,6 +144,130 @@ def cpu_baseline(w, budget_s, dt_flops):
     }
 
 
+PRECISION_WORKLOAD = "o3_s1024_r128_bf16"
+
+
+def precision_bench(args):
+    """The precision path: order-3 1024^3 tensor stored in BF16 (planted
+    rank-128 N(0,1) factors with column norms spread log-uniformly over
+    [1e-2, 1], noise 1e-3 of the norm; the FP32 copy is the FP32 plan's
+    input), R = 128.  Times DT and MSDT sweeps for FP32, BF16 and BF16X2
+    plans, reports the first-contraction kernel against the HBM roofline, and
+    states the error of each BF16 path against the FP64 oracle run on the same
+    BF16 values: the oracle's exact fitness of the GPU's own factors after each
+    of the first sweeps (resynced), and sampled MTTKRP rows."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from oracle import core
+    from paper_2010_12056_amd import cpals, synth
+
+    dev = torch.device("cuda:0")
+    dims, R = (1024, 1024, 1024), 128
+    t_gen = time.perf_counter()
+    w = synth.planted_tensor(dims, R, 3001, kind="lognorm", noise_rel=1e-3, dtype=np.float32)
+    bits = synth.bf16_bits(w.T)
+    log(f"[bench] generated {PRECISION_WORKLOAD} in {time.perf_counter() - t_gen:.1f}s")
+    T32 = torch.from_numpy(w.T).to(dev)
+    Tb = torch.from_numpy(bits.view(np.int16)).to(dev).view(torch.bfloat16)
+    A0 = [torch.from_numpy(a).to(dev) for a in w.init]
+    numel = int(np.prod(dims))
+    stream = torch.cuda.current_stream(dev)
+    res = {}
+    for prec in ("f32", "bf16", "bf16x2"):
+        T = T32 if prec == "f32" else Tb
+        out = {}
+        for tree, nsw in (("dt", 3), ("msdt", 4)):
+            plan = cpals.Plan(dims, R, prec=prec, tree=tree, device=dev)
+            plan.set_tensor(T)
+            A = [a.clone() for a in A0]
+            for a, a0 in zip(A, A0):
+                a.copy_(a0)
+            plan.reset()
+            plan.als_sweep(A, info=False)  # warm
+            for a, a0 in zip(A, A0):
+                a.copy_(a0)
+            plan.reset()
+            plan.profile(True)
+            plan.profile_read()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            for _ in range(nsw):
+                plan.als_sweep(A, info=False)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ph = plan.profile_read()
+            plan.profile(False)
+            ttm_ms, ttm_n = ph["ttm"]
+            out[tree] = {"ms_per_sweep": round(e0.elapsed_time(e1) / nsw, 4),
+                         "ttm_avg_ms": round(ttm_ms / max(ttm_n, 1), 5), "ttm_launches": ttm_n}
+            plan.close()
+        res[prec] = out
+        log(f"[bench] {prec}: {out}")
+    # roofline of the BF16 first contraction: tensor read once, FP32 output written once
+    esz = 2
+    out_bytes = (numel // dims[0]) * R * 4
+    ttm_ms = res["bf16x2"]["dt"]["ttm_avg_ms"]
+    achieved = (numel * esz + out_bytes) / (ttm_ms * 1e-3) / 1e9
+    # error against the FP64 oracle on the BF16 values, resynced per sweep
+    log("[bench] oracle checks")
+    T64 = synth.bf16_to_f32(bits).astype(np.float64)
+    del bits
+    normT2 = float(np.sum(T64 * T64))
+    errs = {}
+    for prec in ("bf16", "bf16x2"):
+        plan = cpals.Plan(dims, R, prec=prec, tree="dt", device=dev)
+        plan.set_tensor(Tb)
+        A = [a.clone() for a in A0]
+        rows = np.random.default_rng(0).choice(dims[0], 4, replace=False)
+        M = plan.mttkrp(A, 0).cpu().numpy()[rows]
+        K = core.krp([w.init[1], w.init[2]])
+        X0 = T64.reshape(dims[0], -1)
+        ref = X0[rows] @ K
+        refabs = np.abs(X0[rows]) @ core.krp([np.abs(w.init[1]), np.abs(w.init[2])])
+        del K
+        unit = 2.0 ** -8 if prec == "bf16" else 2.0 ** -16
+        rec = {"mttkrp_rows_relerr": float(np.linalg.norm(M - ref) / np.linalg.norm(ref)),
+               "mttkrp_rows_err_over_bound": float(np.max(np.abs(M - ref) / (unit * refabs))),
+               "sweeps": []}
+        plan.reset()
+        for sweep in range(3):
+            info = plan.als_sweep(A)
+            Ah = [a.cpu().numpy() for a in A]
+            S = [core.gram(a) for a in Ah]
+            M0 = X0 @ core.krp([Ah[1], Ah[2]])
+            r_or = core.residual_fast(normT2, core.gamma(S, 0), S[0], M0, Ah[0])
+            rec["sweeps"].append({"gpu_fitness": info["fitness"], "oracle_fitness_same_factors": 1.0 - r_or,
+                                  "abs_err": abs(info["fitness"] - (1.0 - r_or))})
+            del M0
+        errs[prec] = rec
+        log(f"[bench] {prec} error vs oracle: {rec}")
+        plan.close()
+    line = {
+        "metric": "ALS sweep ms, order-3 1024^3 R=128: BF16 / split-BF16 first contraction vs FP32",
+        "value": res["bf16x2"]["msdt"]["ms_per_sweep"],
+        "unit": "ms per MSDT sweep (BF16X2)",
+        "n_gpus": 1,
+        "higher_is_better": False,
+        "vs_baseline": None,
+        "dtype": "bf16x2 (first contraction), f32 levels, f64 solve",
+        "data": "synthetic",
+        "config": {"workload": "order-3 dense 1024x1024x1024 stored BF16, planted rank-128 N(0,1) factors with "
+                               "log-uniform column norms in [1e-2, 1], noise 1e-3, CP rank 128",
+                   "dims": list(dims), "rank": R},
+        "by_precision": res,
+        "speedup_bf16x2_vs_f32_msdt": round(res["f32"]["msdt"]["ms_per_sweep"] / res["bf16x2"]["msdt"]["ms_per_sweep"], 3),
+        "roofline": {"kernel": "k_ttm_bf16 (BF16X2, first contraction)", "bound": "hbm",
+                     "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                     "bytes_per_launch": numel * esz + out_bytes, "avg_launch_ms": ttm_ms},
+        "error_vs_fp64_oracle": errs,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -170,6 +294,9 @@ def main():
         from paper_2010_12056_amd import build_lib
 
         build_lib.build()
+    if args.workload == PRECISION_WORKLOAD:
+        precision_bench(args)
+        return
     dev = torch.device("cuda:0")
     t_gen = time.perf_counter()
     w = synth.workload(args.workload)

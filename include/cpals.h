@@ -85,6 +85,11 @@ typedef struct {
   int pinv_updates;      /* factor updates since the last report whose Gamma^(n) was singular to
                             working precision, so that its pseudo-inverse (Alg. 1) came from the
                             eigendecomposition instead of the elimination */
+  int rolled_back;       /* CP_PP_LEARNED only: 1 when the switch's judge undid the PP phase that
+                            this call ended (the phase broke down, or the regular sweep closing it
+                            found a lower exact fitness than at its start); the factors are then
+                            back at their values when the phase began and `fitness` is theirs */
+  int pad;
 } cp_sweep_info;
 
 /* Create a plan for an order-`order` tensor of dims `dims` (host array of
@@ -153,7 +158,11 @@ cp_status cp_fitness(cp_plan plan, const double* const* A, double* fitness);
  *             fitness (a delta not yet available counts as 1),
  * normalizes (x - shift) / scale (host arrays of D), and runs a PP step when
  * the network's probability exceeds `threshold`, a regular sweep otherwise.
- * theta == NULL removes the switch. */
+ * The regular sweep is the judge: when a PP phase breaks down (non-finite
+ * state) or the regular sweep that closes it has a lower exact fitness than
+ * the one before the phase began, the factors are restored to their values at
+ * the phase start (A_p) and the next four outer steps are regular sweeps
+ * (cp_sweep_info.rolled_back).  theta == NULL removes the switch. */
 cp_status cp_pp_set_switch(cp_plan plan, const float* theta, int hidden, const double* shift,
                            const double* scale, double threshold);
 

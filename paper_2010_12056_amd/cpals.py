@@ -37,6 +37,8 @@ class SweepInfo(ctypes.Structure):
         ("dA_rel", ctypes.c_double * 8),
         ("ttm_count", ctypes.c_int),
         ("pinv_updates", ctypes.c_int),
+        ("rolled_back", ctypes.c_int),
+        ("pad", ctypes.c_int),
     ]
 
     def as_dict(self, order):
@@ -48,6 +50,7 @@ class SweepInfo(ctypes.Structure):
             "dA_rel": [self.dA_rel[i] for i in range(order)],
             "ttm_count": self.ttm_count,
             "pinv_updates": self.pinv_updates,
+            "rolled_back": bool(self.rolled_back),
         }
 
 

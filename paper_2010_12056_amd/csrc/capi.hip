@@ -107,6 +107,11 @@ struct cp_plan_s {
   double last_feat[16] = {};
   int last_feat_n = 0;
   double last_prob = -1.0;
+  // judge of the learned switch: exact fitness when the open PP phase began,
+  // regular sweeps still forced after a rollback
+  bool sw_phase_open = false;
+  double sw_entry_fit = 0.0;
+  int sw_cooldown = 0;
 
   // second stream: the Gamma / inverse kernel of a mode update runs there,
   // concurrently with that mode's MTTKRP on the plan stream (fork/join events)
@@ -269,6 +274,8 @@ void plan_carve(cp_plan p) {
 void drop_cache(cp_plan p) {
   p->n_hist = 0;
   p->pending_fit = false;
+  p->sw_phase_open = false;  // a PP phase cannot outlive the state it was judged against
+  p->sw_cooldown = 0;
   for (int d = 0; d < kMaxOrder; ++d) p->slot[d] = Slot();
   p->msdt_u = 0;
   p->phase = 0;
@@ -568,6 +575,7 @@ cp_status fill_info(cp_plan p, cp_sweep_info* info, int kind) {
       info->dA_rel[m] = m >= p->N ? 0.0 : (h.normA2[m] > 0 ? std::sqrt(h.normdA2[m] / h.normA2[m]) : 1.0);
     info->ttm_count = p->ttm_count;
     info->pinv_updates = h.pinv_count - pinv_seen;
+    info->rolled_back = 0;
   }
   if (h.status & 1) return fail(p, CP_ERR_NOT_SPD, "a Gamma matrix had non-finite entries");
   if (h.status & 2) return fail(p, CP_ERR_NUMERIC, "non-finite residual");
@@ -768,6 +776,25 @@ cp_status switch_decide(cp_plan p, bool* pp) {
   return CP_OK;
 }
 
+// Rollback of the learned switch's judge: the factors return to A_p, the
+// state at the start of the PP phase (pp_init copied A into A_p), the
+// plan's cached state is dropped, and the next kJudgeCooldown outer steps
+// are regular sweeps.
+constexpr int kJudgeCooldown = 4;
+
+cp_status judge_rollback(cp_plan p, double* const* A) {
+  for (int m = 0; m < p->N; ++m)
+    HIP_TRY(p, launch_copy_f64(p->Ap[m], A[m], p->dims[m] * p->R, p->st));
+  HIP_TRY(p, launch_zero_bytes(&p->stats->status, sizeof(int), p->st));
+  const double f = p->sw_entry_fit;
+  drop_cache(p);
+  p->sw_phase_open = false;
+  p->sw_cooldown = kJudgeCooldown;
+  p->fit_hist[0] = f;  // the exact fitness of the restored factors
+  p->n_hist = 1;
+  return CP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -911,8 +938,14 @@ cp_status cp_pp_sweep(cp_plan p, double* const* A, double pp_tol, cp_pp_mode mod
     kind = !ok ? CP_SWEEP_EXACT : (p->phase == 1 ? CP_SWEEP_PP_APPROX : CP_SWEEP_PP_INIT);
   } else if (mode == CP_PP_LEARNED) {
     bool pp = false;
-    if (!p->fresh) CP_TRY(switch_decide(p, &pp));
+    if (!p->fresh && p->sw_cooldown == 0) CP_TRY(switch_decide(p, &pp));
+    if (p->sw_cooldown > 0) --p->sw_cooldown;
     kind = !pp ? CP_SWEEP_EXACT : (p->phase == 1 ? CP_SWEEP_PP_APPROX : CP_SWEEP_PP_INIT);
+    if (kind == CP_SWEEP_PP_INIT) {
+      // the last sweep was regular: its fitness (noted above) is exact
+      p->sw_entry_fit = p->n_hist > 0 ? p->fit_hist[0] : -1e300;
+      p->sw_phase_open = true;
+    }
   } else if (mode == CP_PP_FORCE_EXACT) {
     kind = CP_SWEEP_EXACT;
   } else if (mode == CP_PP_FORCE_APPROX) {
@@ -930,6 +963,31 @@ cp_status cp_pp_sweep(cp_plan p, double* const* A, double pp_tol, cp_pp_mode mod
     CP_TRY(approx_sweep(p, A));
   }
   p->pending_fit = true;
+  if (mode == CP_PP_LEARNED && p->sw_phase_open) {
+    // the judge: a phase that broke down (non-finite state), or that the
+    // regular sweep closing it shows to have lost fitness, is undone
+    DevStats h;
+    CP_TRY(read_stats(p, &h));
+    const bool broke = (h.status & 3) != 0;
+    const bool closing = (kind == CP_SWEEP_EXACT);
+    if (broke || (closing && !(1.0 - h.r >= p->sw_entry_fit))) {
+      const int pinv_seen = p->pinv_seen;
+      p->pinv_seen = h.pinv_count;
+      CP_TRY(judge_rollback(p, A));
+      if (info) {
+        info->kind = kind;
+        info->fitness_is_exact = 1;
+        info->fitness = p->fit_hist[0];
+        info->r = 1.0 - info->fitness;
+        for (int m = 0; m < kMaxOrder; ++m) info->dA_rel[m] = 0.0;
+        info->ttm_count = p->ttm_count;
+        info->pinv_updates = h.pinv_count - pinv_seen;
+        info->rolled_back = 1;
+      }
+      return CP_OK;
+    }
+    if (closing) p->sw_phase_open = false;
+  }
   if (info) return fill_info(p, info, kind);
   return CP_OK;
 }

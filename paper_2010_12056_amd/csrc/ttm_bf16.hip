@@ -22,9 +22,11 @@
 //   KC (contraction index contiguous, Q == 1): X is P x K row-major; lane
 //      (i = lane % 16, g = lane / 16) of block u loads row 16 u + i, indices
 //      8 g .. 8 g + 7 of the step, as one 16-byte load.
-//   otherwise: X[p] is K x Q with q contiguous; the lane loads 4 consecutive
-//      q (8 bytes) for each of its eight indices and transposes the 8 x 4
-//      block in registers, so that block u gets row q0 + 4 i + u.
+//   otherwise: X[p] is K x Q with q contiguous; the lane needs 4 consecutive
+//      q for each of its eight indices (two lanes load eight q with one
+//      16-byte load per index and swap halves across the pair), then
+//      transposes the 8 x 4 block in registers, so that block u gets row
+//      q0 + 4 i + u.
 #include "kernels.h"
 
 namespace cpals {
@@ -143,6 +145,25 @@ __global__ __launch_bounds__(512) void k_ttm_bf16(const uint16_t* __restrict__ X
         }
       } else {
         u32x2 raw[8];
+        // 16-byte path: lanes 2m and 2m + 1 share eight consecutive q; lane
+        // h = l16 & 1 loads them at k = kb + 4h + j (j < 4) and swaps the half
+        // that belongs to its partner, so each lane ends with its own four q
+        // at all eight indices.  Uniform within a lane pair.
+        const int h = l16 & 1;
+        const int64_t qpair = row0 + 8 * (l16 >> 1);
+        if (vec == 2 && qpair + 8 <= Q && kb + 8 <= K) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const u32x4 v = *(const u32x4*)(Xb + (int64_t)(kb + 4 * h + j) * Q + qpair);
+            const uint32_t s0 = h ? v[0] : v[2], s1 = h ? v[1] : v[3];
+            const uint32_t r0 = (uint32_t)__builtin_amdgcn_mov_dpp((int)s0, 0xB1, 0xF, 0xF, false);
+            const uint32_t r1 = (uint32_t)__builtin_amdgcn_mov_dpp((int)s1, 0xB1, 0xF, 0xF, false);
+            const u32x2 own = h ? u32x2{v[2], v[3]} : u32x2{v[0], v[1]};
+            const u32x2 got = u32x2{r0, r1};
+            raw[j] = h ? got : own;
+            raw[4 + j] = h ? own : got;
+          }
+        } else {
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
           const int64_t k = kb + j;
@@ -150,11 +171,12 @@ __global__ __launch_bounds__(512) void k_ttm_bf16(const uint16_t* __restrict__ X
           if (k < K && qfull) {
             raw[j] = *(const u32x2*)src;
           } else {
-            uint32_t h[4];
+            uint32_t e[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) h[u] = (k < K && row0 + 4 * l16 + u < Q) ? (uint32_t)src[u] : 0u;
-            raw[j] = u32x2{h[0] | (h[1] << 16), h[2] | (h[3] << 16)};
+            for (int u = 0; u < 4; ++u) e[u] = (k < K && row0 + 4 * l16 + u < Q) ? (uint32_t)src[u] : 0u;
+            raw[j] = u32x2{e[0] | (e[1] << 16), e[2] | (e[3] << 16)};
           }
+        }
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -234,7 +256,9 @@ hipError_t launch_one(const uint16_t* X, const uint16_t* Bhi, const uint16_t* Bl
   const int64_t ntiles = KC ? (P + kTileRows - 1) / kTileRows : P * tilesQ;
   const unsigned nx = (unsigned)(ntiles < 256 ? ntiles : 256);  // one resident workgroup per CU
   const unsigned ny = (unsigned)((R + NC - 1) / NC);
-  const int vec = KC ? (K % 8 == 0 && ((uintptr_t)X % 16) == 0) : (Q % 4 == 0 && ((uintptr_t)X % 8) == 0);
+  // KC: 16-byte row loads; otherwise 2 = 16-byte loads shared by lane pairs, 1 = 8-byte loads
+  const int vec = KC ? (K % 8 == 0 && ((uintptr_t)X % 16) == 0)
+                     : ((Q % 8 == 0 && ((uintptr_t)X % 16) == 0) ? 2 : (Q % 4 == 0 && ((uintptr_t)X % 8) == 0));
   hipLaunchKernelGGL((k_ttm_bf16<KC, NCB, SPLIT>), dim3(nx, ny), dim3(kThreads), lds, st, X, Bhi, Blo, C, P, K, Q,
                      R, Kp, tilesQ, ntiles, vec);
   return hipGetLastError();

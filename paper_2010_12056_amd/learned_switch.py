@@ -19,8 +19,9 @@ forms on the plan).
   cross-entropy).  Parameters and the feature normalization are stored as JSON
   under paper_2010_12056_amd/models/.
 * The regular sweep stays the fallback and the judge: the first sweep of a run
-  is always regular, and the evaluation checks every claimed target with the
-  FP64 audit.
+  is always regular; the plan undoes a PP phase that breaks down or that the
+  regular sweep closing it shows to have lost fitness (cp_pp_set_switch); the
+  evaluation checks every claimed target with the FP64 audit.
 
 CLI (GPU):  python -m paper_2010_12056_amd.learned_switch collect|train|evaluate ...
 """
@@ -209,9 +210,16 @@ def init_params(D, H, seed):
                            glorot(H, 1).ravel(), [0.0]]).astype(np.float32)
 
 
-def train(X, y, hidden=HIDDEN, steps=3000, lr=3e-3, seed=0, device="cuda", log=print):
-    """Full-batch Adam on the GPU with the library's kernels.  Returns the
-    model dict (theta, feature normalization, loss curve)."""
+def _bce(p, y):
+    p = np.clip(np.asarray(p, dtype=np.float64), 1e-7, 1.0 - 1e-7)
+    return float(-np.mean(y * np.log(p) + (1.0 - y) * np.log(1.0 - p)))
+
+
+def train(X, y, hidden=HIDDEN, steps=3000, lr=3e-3, seed=0, device="cuda", X_val=None, y_val=None, log=print):
+    """Full-batch Adam on the GPU with the library's kernels.  With validation
+    traces, the parameters of the step with the lowest validation loss are
+    kept (early stopping).  Returns the model dict (theta, feature
+    normalization, loss curves)."""
     import torch
 
     from . import cpals
@@ -222,6 +230,9 @@ def train(X, y, hidden=HIDDEN, steps=3000, lr=3e-3, seed=0, device="cuda", log=p
     scale[scale < 1e-6] = 1.0
     Xn = torch.tensor((X - shift) / scale, dtype=torch.float32, device=dev)
     yt = torch.tensor(y, dtype=torch.float32, device=dev)
+    Xv = None
+    if X_val is not None and len(X_val):
+        Xv = torch.tensor((X_val - shift) / scale, dtype=torch.float32, device=dev)
     D = X.shape[1]
     theta = torch.tensor(init_params(D, hidden, seed), device=dev)
     m = torch.zeros_like(theta)
@@ -230,19 +241,34 @@ def train(X, y, hidden=HIDDEN, steps=3000, lr=3e-3, seed=0, device="cuda", log=p
     scratch = torch.empty(int(cpals.lib().cp_mlp_scratch_floats(Xn.shape[0], hidden)), dtype=torch.float32,
                           device=dev)
     out = torch.empty(n + 1, dtype=torch.float32, device=dev)
-    losses = []
+    losses, best = [], (math.inf, 0, theta.clone())
     for t in range(1, steps + 1):
         cpals.mlp_grad(Xn, yt, theta, hidden, scratch=scratch, out=out)
         cpals.mlp_adam(theta, out[:n], m, v, t, lr=lr)
-        if t == 1 or t % 100 == 0:
-            losses.append((t, float(out[n].item())))
+        if t == 1 or t % 25 == 0:
+            rec = [t, float(out[n].item())]
+            if Xv is not None:
+                vl = _bce(cpals.mlp_forward(Xv, theta, hidden).cpu().numpy(), y_val)
+                rec.append(vl)
+                if vl < best[0]:
+                    best = (vl, t, theta.clone())
+            losses.append(rec)
+    if Xv is not None:
+        theta = best[2]
+        log(f"[train] early stop at step {best[1]} (validation loss {best[0]:.4f})")
     p = cpals.mlp_forward(Xn, theta, hidden).cpu().numpy()
     acc = float(np.mean((p > 0.5) == (y > 0.5)))
-    log(f"[train] {X.shape[0]} samples, loss {losses[0][1]:.4f} -> {losses[-1][1]:.4f}, "
-        f"training accuracy {acc:.3f}")
-    return {"D": int(D), "H": int(hidden), "theta": [float(t) for t in theta.cpu().numpy()],
-            "shift": shift.tolist(), "scale": scale.tolist(), "threshold": 0.5, "loss_curve": losses,
-            "train_accuracy": acc, "n_samples": int(X.shape[0]), "n_positive": int(y.sum())}
+    res = {"D": int(D), "H": int(hidden), "theta": [float(t) for t in theta.cpu().numpy()],
+           "shift": shift.tolist(), "scale": scale.tolist(), "threshold": 0.5, "loss_curve": losses,
+           "train_accuracy": acc, "n_samples": int(X.shape[0]), "n_positive": int(y.sum()),
+           "steps_kept": best[1] if Xv is not None else steps}
+    if Xv is not None:
+        pv = cpals.mlp_forward(Xv, theta, hidden).cpu().numpy()
+        res["val_accuracy"] = float(np.mean((pv > 0.5) == (y_val > 0.5)))
+        res["val_loss"] = best[0]
+    log(f"[train] {X.shape[0]} samples, loss {losses[0][1]:.4f} -> {losses[-1][1]:.4f}, training accuracy {acc:.3f}"
+        + (f", validation accuracy {res['val_accuracy']:.3f}" if Xv is not None else ""))
+    return res
 
 
 def load_model(path=DEFAULT_MODEL):
@@ -358,7 +384,8 @@ def main(argv=None):
     t.add_argument("--traces", required=True)
     t.add_argument("--steps", type=int, default=3000)
     t.add_argument("--lr", type=float, default=3e-3)
-    t.add_argument("--exclude-seeds", default="", help="seed range kept out of training (threshold selection)")
+    t.add_argument("--exclude-seeds", default="",
+                   help="seed range kept out of training (early stopping and threshold selection)")
     t.add_argument("--out", default=DEFAULT_MODEL)
     sel = sub.add_parser("select", help="set the model threshold from an evaluation with --thresholds")
     sel.add_argument("--eval", required=True)
@@ -399,7 +426,8 @@ def main(argv=None):
     elif args.cmd == "train":
         d = np.load(args.traces)
         keep = ~np.isin(d["seed"], seeds(args.exclude_seeds))
-        model = train(d["X"][keep], d["y"][keep], steps=args.steps, lr=args.lr, log=log)
+        model = train(d["X"][keep], d["y"][keep], steps=args.steps, lr=args.lr, X_val=d["X"][~keep],
+                      y_val=d["y"][~keep], log=log)
         fam = {k: (list(v) if isinstance(v, tuple) else v) for k, v in FAMILY.items()}
         model["traces"] = {"seeds": sorted(set(int(s) for s in d["seed"][keep])), "family": fam,
                            "behavior_eps": list(BEHAVIOR_EPS), "gain_ratio": GAIN_RATIO}

@@ -226,3 +226,90 @@ def test_learned_switch_schedules_and_features(dev):
         pl.set_switch(None, 0, None, None)
         pl.close()
         ref.close()
+
+
+def test_learned_switch_judge_rolls_back_a_losing_phase(dev):
+    """The regular sweep judges each PP phase of the learned switch.  With a
+    constant network (probability 1/2) the threshold scripts the decisions.
+    From the uniform start of this workload, the FP64 oracle's Alg. 2 steps
+    show that one regular sweep, PP initialization and two approximated sweeps
+    lose 3e-2 of fitness by the closing regular sweep (the phase is undone:
+    factors bitwise back at the phase start, then four forced regular sweeps),
+    while two regular sweeps, initialization and one approximated sweep gain
+    3e-2 (the phase is kept)."""
+    from paper_2010_12056_amd import cpals, synth
+
+    say("case learned switch judge")
+    w = synth.workload("o4_small_f32")
+    N = len(w.dims)
+    D, H = N + 3, 8
+    T = torch.from_numpy(w.T).to(dev)
+    theta = torch.zeros(cpals.mlp_param_count(D, H), dtype=torch.float32, device=dev)
+
+    def run(warm, napprox):
+        pl = cpals.Plan(w.dims, w.R, prec="f32", tree="msdt", device=dev)
+        pl.set_tensor(T)
+        A = to_dev(w.init, dev)
+        pl.set_switch(theta, H, [0.0] * D, [1.0] * D, 0.6)  # regular
+        for _ in range(warm):
+            info = pl.pp_sweep(A, mode="learned")
+            assert info["kind"] == "exact"
+        entry = [a.clone() for a in A]
+        f_entry = info["fitness"]
+        pl.set_switch(theta, H, [0.0] * D, [1.0] * D, 0.4)  # PP
+        kinds = [pl.pp_sweep(A, mode="learned")["kind"] for _ in range(1 + napprox)]
+        assert kinds == ["init"] + ["approx"] * napprox
+        pl.set_switch(theta, H, [0.0] * D, [1.0] * D, 0.6)
+        close = pl.pp_sweep(A, mode="learned")
+        assert close["kind"] == "exact"
+        return pl, A, entry, f_entry, close
+
+    pl, A, entry, f_entry, close = run(1, 2)
+    say(f"  losing phase: entry {f_entry:.6f}, rolled back {close['rolled_back']}")
+    assert close["rolled_back"] and close["fitness"] == f_entry
+    for a, b in zip(A, entry):
+        assert torch.equal(a, b)
+    pl.set_switch(theta, H, [0.0] * D, [1.0] * D, 0.4)  # the switch asks for PP, the judge holds it off
+    kinds = [pl.pp_sweep(A, mode="learned")["kind"] for _ in range(5)]
+    assert kinds == ["exact"] * 4 + ["init"], kinds
+    pl.close()
+
+    pl, A, entry, f_entry, close = run(2, 1)
+    say(f"  gaining phase: entry {f_entry:.6f}, closing {close['fitness']:.6f}")
+    assert not close["rolled_back"] and close["fitness"] > f_entry + 1e-2
+    pl.close()
+
+
+def test_learned_switch_reset_closes_the_open_phase(dev):
+    """cp_reset ends an open PP phase: a run after the reset must not be
+    judged against the previous run's phase start (it would be 'restored' to
+    the previous run's factors).  The first regular sweeps after the reset
+    equal a fresh plan's, bit for bit."""
+    from paper_2010_12056_amd import cpals, synth
+
+    say("case learned switch reset")
+    w = synth.workload("o4_small_f32")
+    N = len(w.dims)
+    D, H = N + 3, 8
+    T = torch.from_numpy(w.T).to(dev)
+    theta = torch.zeros(cpals.mlp_param_count(D, H), dtype=torch.float32, device=dev)
+    pl = cpals.Plan(w.dims, w.R, prec="f32", tree="msdt", device=dev)
+    pl.set_tensor(T)
+    A = to_dev(w.init, dev)
+    pl.set_switch(theta, H, [0.0] * D, [1.0] * D, 0.4)  # PP whenever allowed
+    kinds = [pl.pp_sweep(A, mode="learned")["kind"] for _ in range(4)]
+    assert kinds == ["exact", "init", "approx", "approx"]
+    pl.reset()
+    pl.set_switch(theta, H, [0.0] * D, [1.0] * D, 0.6)  # regular
+    fresh = cpals.Plan(w.dims, w.R, prec="f32", tree="msdt", device=dev)
+    fresh.set_tensor(T)
+    A = to_dev(w.init, dev)
+    B = to_dev(w.init, dev)
+    for _ in range(3):
+        i1 = pl.pp_sweep(A, mode="learned")
+        i2 = fresh.als_sweep(B)
+        assert i1["kind"] == "exact" and not i1["rolled_back"]
+        assert i1["fitness"] == i2["fitness"]
+        assert all(torch.equal(a, b) for a, b in zip(A, B))
+    pl.close()
+    fresh.close()

@@ -219,6 +219,54 @@ cp_status cp_plan_destroy(cp_plan plan);
 const char* cp_status_str(cp_status s);
 const char* cp_last_error(cp_plan plan);
 
+/* ---------------------------------------------------------------------------
+ * Batched path (not from the paper): many small independent order-3 dense
+ * FP32 tensors, each with its own mode sizes (1 <= s <= 96) and rank
+ * (1 <= R <= 32), decomposed by CP-ALS (Alg. 1 with the standard dimension
+ * tree of Sec. II-C, residual by Eq. (3)) in ONE persistent kernel launch: a
+ * device work queue hands whole tensors, largest first, to free workgroups,
+ * which run every requested sweep of a tensor before taking the next.  The
+ * call enqueues two kernels (a counter reset and the persistent kernel),
+ * allocates nothing and does not synchronize, so it can be captured in a HIP
+ * graph and replayed.
+ * ------------------------------------------------------------------------- */
+typedef struct cp_batch_s* cp_batch;
+
+/* count tensors; dims: host array count x 3; ranks: host array of count.
+ * The queue order and the packed layout are fixed here. */
+cp_status cp_batch_create(cp_batch* out, int count, const int64_t* dims, const int* ranks, void* hip_stream);
+
+/* Packed layout the caller fills: tensor i (C order) starts at element
+ * t_offsets[i] of one FP32 array of t_total elements; its factor m (s_m x R,
+ * row-major, FP64) at element a_offsets[3 i + m] of one FP64 array of a_total
+ * elements.  Host output arrays (any may be NULL). */
+cp_status cp_batch_layout(cp_batch b, int64_t* t_offsets, int64_t* a_offsets, int64_t* t_total, int64_t* a_total);
+
+/* Launch shape: waves per workgroup (4 or 8) and resident workgroups per
+ * compute unit (1..4); before cp_batch_set_workspace (the scratch per
+ * workgroup is part of the workspace).  Chosen by the autotuner. */
+cp_status cp_batch_set_launch(cp_batch b, int waves_per_group, int groups_per_cu);
+
+/* Device workspace (256-byte aligned, caller-owned): queue, counter and one
+ * intermediate slot per workgroup. */
+cp_status cp_batch_workspace_size(cp_batch b, size_t* bytes);
+cp_status cp_batch_set_workspace(cp_batch b, void* dptr, size_t bytes);
+
+/* `sweeps` ALS sweeps on every tensor.  T: packed tensors (device FP32),
+ * A: packed factors (device FP64, read as the initial factors and
+ * overwritten), fitness: device FP64 count x sweeps (f = 1 - r after each
+ * sweep, Eq. (3)), status: device int count (0, or 1 when a Gamma^(n) was not
+ * numerically positive definite; that tensor's sweeps stop), ticks: device
+ * int64 count x 2 (wall-clock counter at the start and end of the tensor's
+ * sweeps; cp_batch_tick_rate gives the rate) or NULL. */
+cp_status cp_batch_sweeps(cp_batch b, const float* T, double* A, int sweeps, double* fitness, int* status,
+                          long long* ticks);
+
+/* Rate of the device wall clock used by `ticks`, in Hz. */
+cp_status cp_batch_tick_rate(cp_batch b, double* hz);
+
+void cp_batch_destroy(cp_batch b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcpals.so")
-SOURCES = ["kernels.hip", "ttm_bf16.hip", "capi.hip", "mlp.hip"]
+SOURCES = ["kernels.hip", "ttm_bf16.hip", "capi.hip", "mlp.hip", "batch.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

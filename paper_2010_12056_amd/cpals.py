@@ -94,6 +94,17 @@ EXPORTS = {
     "cp_mlp_adam": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                    ctypes.c_int, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                    ctypes.c_void_p]),
+    "cp_batch_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.POINTER(ctypes.c_int64),
+                                       ctypes.POINTER(ctypes.c_int), ctypes.c_void_p]),
+    "cp_batch_layout": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                       ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
+    "cp_batch_set_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
+    "cp_batch_workspace_size": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)]),
+    "cp_batch_set_workspace": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]),
+    "cp_batch_sweeps": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_void_p]),
+    "cp_batch_tick_rate": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
+    "cp_batch_destroy": (None, [ctypes.c_void_p]),
     "cp_status_str": (ctypes.c_char_p, [ctypes.c_int]),
     "cp_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
 }
@@ -296,3 +307,91 @@ def mlp_adam(theta, grad, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, st
     _mlp_check(lib().cp_mlp_adam(ctypes.c_void_p(theta.data_ptr()), ctypes.c_void_p(grad.data_ptr()),
                                  ctypes.c_void_p(m.data_ptr()), ctypes.c_void_p(v.data_ptr()), theta.numel(), int(t),
                                  float(lr), float(beta1), float(beta2), float(eps), ctypes.c_void_p(st)))
+
+
+class Batch:
+    """Many small order-3 FP32 tensors decomposed in one persistent launch
+    (cp_batch_* in include/cpals.h).  dims: list of (s0, s1, s2); ranks: list
+    of R.  Packs tensors and factors into the library's layout on the device."""
+
+    def __init__(self, dims, ranks, device="cuda", waves=4, groups_per_cu=2):
+        if not torch.cuda.is_available():
+            raise RuntimeError("cpals needs a GPU; none is visible")
+        self.L = lib()
+        self.count = len(dims)
+        self.dims = [tuple(int(x) for x in d) for d in dims]
+        self.ranks = [int(r) for r in ranks]
+        self.device = torch.device(device)
+        self.stream = torch.cuda.current_stream(self.device)
+        flat = (ctypes.c_int64 * (3 * self.count))(*[x for d in self.dims for x in d])
+        rk = (ctypes.c_int * self.count)(*self.ranks)
+        h = ctypes.c_void_p()
+        _mlp_check(self.L.cp_batch_create(ctypes.byref(h), self.count, flat, rk,
+                                          ctypes.c_void_p(self.stream.cuda_stream)))
+        self.h = h
+        _mlp_check(self.L.cp_batch_set_launch(self.h, int(waves), int(groups_per_cu)))
+        toff = (ctypes.c_int64 * self.count)()
+        aoff = (ctypes.c_int64 * (3 * self.count))()
+        tt, at = ctypes.c_int64(), ctypes.c_int64()
+        _mlp_check(self.L.cp_batch_layout(self.h, toff, aoff, ctypes.byref(tt), ctypes.byref(at)))
+        self.t_off = [toff[i] for i in range(self.count)]
+        self.a_off = [[aoff[3 * i + m] for m in range(3)] for i in range(self.count)]
+        self.t_total, self.a_total = tt.value, at.value
+        nbytes = ctypes.c_size_t()
+        _mlp_check(self.L.cp_batch_workspace_size(self.h, ctypes.byref(nbytes)))
+        self.ws = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=self.device)
+        aligned = (self.ws.data_ptr() + 255) // 256 * 256
+        _mlp_check(self.L.cp_batch_set_workspace(self.h, ctypes.c_void_p(aligned), int(nbytes.value)))
+
+    def pack_tensors(self, tensors):
+        """One FP32 device array holding every tensor at its offset."""
+        T = torch.zeros(self.t_total, dtype=torch.float32, device=self.device)
+        for i, t in enumerate(tensors):
+            src = torch.as_tensor(t, dtype=torch.float32).reshape(-1)
+            T[self.t_off[i]:self.t_off[i] + src.numel()].copy_(src)
+        return T
+
+    def pack_factors(self, factors):
+        """factors[i] = [A0, A1, A2] (FP64): one FP64 device array."""
+        A = torch.zeros(self.a_total, dtype=torch.float64, device=self.device)
+        for i, fs in enumerate(factors):
+            for m in range(3):
+                src = torch.as_tensor(fs[m], dtype=torch.float64).reshape(-1)
+                A[self.a_off[i][m]:self.a_off[i][m] + src.numel()].copy_(src)
+        return A
+
+    def unpack_factors(self, A, i):
+        out = []
+        for m in range(3):
+            n = self.dims[i][m] * self.ranks[i]
+            out.append(A[self.a_off[i][m]:self.a_off[i][m] + n].reshape(self.dims[i][m], self.ranks[i]))
+        return out
+
+    def sweeps(self, T, A, sweeps, fitness=None, status=None, ticks=None):
+        """Enqueue `sweeps` sweeps of every tensor (no synchronization)."""
+        if fitness is None:
+            fitness = torch.empty((self.count, sweeps), dtype=torch.float64, device=self.device)
+        if status is None:
+            status = torch.empty(self.count, dtype=torch.int32, device=self.device)
+        tp = ctypes.c_void_p(ticks.data_ptr()) if ticks is not None else None
+        _mlp_check(self.L.cp_batch_sweeps(self.h, ctypes.c_void_p(T.data_ptr()), ctypes.c_void_p(A.data_ptr()),
+                                          int(sweeps), ctypes.c_void_p(fitness.data_ptr()),
+                                          ctypes.c_void_p(status.data_ptr()), tp))
+        return fitness, status
+
+    def tick_rate(self):
+        hz = ctypes.c_double()
+        _mlp_check(self.L.cp_batch_tick_rate(self.h, ctypes.byref(hz)))
+        return hz.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.cp_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+

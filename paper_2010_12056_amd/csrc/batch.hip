@@ -1,0 +1,503 @@
+// Batched CP-ALS on many small independent order-3 tensors in one persistent
+// launch (not from the paper; the paper decomposes one large tensor).
+//
+// Work queue: a device counter hands whole tensors, largest first (the host
+// orders them by s0 s1 s2 R), to whichever workgroup is free; the workgroup
+// runs all requested sweeps of that tensor and takes the next.  Tensors are
+// independent, so no workgroup ever waits for another, and every workgroup
+// leaves the loop once the counter passes the last tensor.
+//
+// One sweep per tensor is the standard dimension tree for N = 3 (Sec. II-C,
+// Alg. 1): Y = T x_2 A2 (first-level contraction over the last mode) serves
+// modes 0 and 1, Z = T x_0 A0 (over the first mode) serves mode 2:
+//   M0[i][r] = sum_j Y[i][j][r] A1[j][r]      A0 <- M0 Gamma0^-1   (Eq. (1))
+//   M1[j][r] = sum_i Y[i][j][r] A0[i][r]      A1 <- M1 Gamma1^-1
+//   M2[k][r] = sum_j Z[j][k][r] A1[j][r]      A2 <- M2 Gamma2^-1
+// then the residual by Eq. (3).  Contractions with the tensor run on the
+// FP32 matrix cores (16x16x4), Y and Z are FP32 in a per-slot scratch, the
+// second level, the Gram matrices, Gamma, its inverse (Gauss-Jordan without
+// pivoting, SPD) and the update run in FP64.  Every reduction has a fixed
+// order: results do not depend on which workgroup took which tensor.
+#include "kernels.h"
+
+#include "../../include/cpals.h"
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+namespace cpals {
+namespace {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kMaxS = 96;    // largest mode size
+constexpr int kMaxR = 32;    // largest rank
+constexpr int kKP = kMaxS;   // staged factor pitch (floats)
+
+struct BatchTensor {
+  int64_t t_off;     // first element of the tensor in the packed tensor array
+  int idx;           // position in the caller's list (results are stored there)
+  int64_t a_off[3];  // first element of each factor in the packed factor array
+  int s[3];
+  int R;
+};
+
+struct BatchArgs {
+  const float* T;
+  double* A;
+  const BatchTensor* items;  // in queue order
+  int count;
+  int sweeps;
+  double* fitness;   // [count][sweeps], by the tensor's position in the caller's list
+  int* status;       // [count]: 0 ok, 1 Gamma not positive definite
+  long long* ticks;  // [count][2] wall-clock start / end, or null
+  int* counter;
+  float* scratch;    // gridDim.x slots of slot_floats
+  int64_t slot_floats;
+};
+
+// Shared state of one workgroup (FP64 R x R blocks and the staged factor).
+struct Lds {
+  double S[3][kMaxR * kMaxR];
+  double G[kMaxR * (kMaxR + 1)];   // Gamma, then its inverse in place (pitch R + 1)
+  double M[kMaxS * kMaxR];          // MTTKRP of the mode being updated
+  float Bt[kMaxR * kKP];            // FP32 factor transposed for the contraction, zero padded
+  double red[512];
+  int item;
+  int fail;
+};
+
+template <int NT>
+__device__ inline double block_sum(Lds& L, double v) {
+  const int t = threadIdx.x;
+  L.red[t] = v;
+  __syncthreads();
+  for (int h = NT / 2; h > 0; h >>= 1) {
+    if (t < h) L.red[t] += L.red[t + h];
+    __syncthreads();
+  }
+  const double s = L.red[0];
+  __syncthreads();
+  return s;
+}
+
+// Stage factor `a` (s x R, FP64 global) as Bt[c][k] (FP32), zero for k >= s or c >= R.
+template <int NT, int RP>
+__device__ inline void stage_factor(Lds& L, const double* a, int s, int R) {
+  const int KP = (s + 15) & ~15;
+  for (int e = threadIdx.x; e < RP * KP; e += NT) {
+    const int c = e / KP, k = e - c * KP;
+    L.Bt[c * kKP + k] = (k < s && c < R) ? (float)a[(int64_t)k * R + c] : 0.f;
+  }
+}
+
+// C[p][r] = sum_k X[p][k] B[k][r] (X is P x K row-major): 16-row tiles per wave.
+// Lane (i, g) feeds k = kb + 4 g + u at MFMA step u (one 16-byte load when
+// the row is aligned and complete), the staged factor the same k.
+template <int NT, int RP>
+__device__ inline void ttm_rows(Lds& L, const float* X, int64_t P, int K, int R, float* C) {
+  constexpr int NCB = RP / 16;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, l16 = lane & 15;
+  const bool vec = (K % 4 == 0) && (((uintptr_t)X & 15) == 0);
+  const int64_t ntiles = (P + 15) / 16;
+  for (int64_t tile = wave; tile < ntiles; tile += NT / 64) {
+    const int64_t p0 = tile * 16;
+    const int64_t row = (p0 + l16 < P) ? p0 + l16 : P - 1;
+    const float* xr = X + row * K;
+    f32x4 acc[NCB];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) acc[cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int kb = 0; kb < K; kb += 16) {
+      const int k0 = kb + 4 * g;
+      f32x4 a;
+      if (vec && k0 + 4 <= K) {
+        a = *(const f32x4*)(xr + k0);
+      } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) a[u] = (k0 + u < K) ? xr[k0 + u] : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb)
+          acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u], L.Bt[(cb * 16 + l16) * kKP + k0 + u], acc[cb], 0, 0, 0);
+    }
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t p = p0 + 4 * g + v;
+        const int c = cb * 16 + l16;
+        if (p < P && c < R) C[p * R + c] = acc[cb][v];
+      }
+  }
+}
+
+// C[q][r] = sum_k X[k][q] B[k][r] (X is K x Q, q contiguous): 16-row tiles of
+// q per wave; lane (i, g) feeds X[kb + g][q0 + i] (16 lanes read 64
+// contiguous bytes).
+template <int NT, int RP>
+__device__ inline void ttm_cols(Lds& L, const float* X, int K, int64_t Q, int R, float* C) {
+  constexpr int NCB = RP / 16;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int g = lane >> 4, l16 = lane & 15;
+  const int64_t ntiles = (Q + 15) / 16;
+  for (int64_t tile = wave; tile < ntiles; tile += NT / 64) {
+    const int64_t q0 = tile * 16;
+    const bool qok = q0 + l16 < Q;
+    f32x4 acc[NCB];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) acc[cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int kb = 0; kb < K; kb += 4) {
+      const int k = kb + g;
+      const float a = (k < K && qok) ? X[(int64_t)k * Q + q0 + l16] : 0.f;
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb)
+        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, L.Bt[(cb * 16 + l16) * kKP + k], acc[cb], 0, 0, 0);
+    }
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t q = q0 + 4 * g + v;
+        const int c = cb * 16 + l16;
+        if (q < Q && c < R) C[q * R + c] = acc[cb][v];
+      }
+  }
+}
+
+// Gamma = S[a] * S[b] (Hadamard), inverted in place by Gauss-Jordan without
+// pivoting (SPD: every pivot is a positive Schur-complement diagonal); a pivot
+// at or below R eps max(diag) flags L.fail.  Step k reads the old row and
+// column k (copied first), then every entry is replaced in one pass.
+template <int NT>
+__device__ inline void gamma_inverse(Lds& L, int a, int b, int R) {
+  const int P = R + 1;
+  for (int e = threadIdx.x; e < R * R; e += NT) {
+    const int i = e / R, j = e - i * R;
+    L.G[i * P + j] = L.S[a][e] * L.S[b][e];
+  }
+  __syncthreads();
+  double dmax = 0.0;
+  for (int i = 0; i < R; ++i) dmax = fmax(dmax, L.G[i * P + i]);
+  const double tol = dmax * (double)R * 2.220446049250313e-16;
+  double* rowk = L.red;
+  double* colk = L.red + kMaxR;
+  for (int k = 0; k < R; ++k) {
+    const double piv = L.G[k * P + k];
+    if (!(piv > tol)) {  // the same value in every thread
+      if (threadIdx.x == 0) L.fail = 1;
+      __syncthreads();
+      return;
+    }
+    if (threadIdx.x < R) {
+      rowk[threadIdx.x] = L.G[k * P + threadIdx.x];
+      colk[threadIdx.x] = L.G[threadIdx.x * P + k];
+    }
+    __syncthreads();
+    const double rinv = 1.0 / piv;
+    for (int e = threadIdx.x; e < R * R; e += NT) {
+      const int i = e / R, j = e - i * R;
+      double v;
+      if (i == k)
+        v = (j == k) ? rinv : rowk[j] * rinv;
+      else
+        v = (j == k) ? -colk[i] * rinv : L.G[i * P + j] - colk[i] * rowk[j] * rinv;
+      L.G[i * P + j] = v;
+    }
+    __syncthreads();
+  }
+}
+
+// A <- M Ginv (FP64, s x R, written to global) and S[m] <- A^T A.
+template <int NT>
+__device__ inline void update_factor(Lds& L, double* A, int s, int R, int m) {
+  const int P = R + 1;
+  for (int e = threadIdx.x; e < s * R; e += NT) {
+    const int i = e / R, r = e - i * R;
+    double acc = 0.0;
+    for (int c = 0; c < R; ++c) acc += L.M[i * R + c] * L.G[c * P + r];
+    A[e] = acc;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < R * R; e += NT) {
+    const int a = e / R, b = e - a * R;
+    double acc = 0.0;
+    for (int i = 0; i < s; ++i) acc += A[(int64_t)i * R + a] * A[(int64_t)i * R + b];
+    L.S[m][e] = acc;
+  }
+  __syncthreads();
+}
+
+template <int NT, int RP>
+__device__ void run_tensor(Lds& L, const BatchArgs& a, const BatchTensor& t, int idx, float* scratch) {
+  const int s0 = t.s[0], s1 = t.s[1], s2 = t.s[2], R = t.R;
+  const float* T = a.T + t.t_off;
+  double* A0 = a.A + t.a_off[0];
+  double* A1 = a.A + t.a_off[1];
+  double* A2 = a.A + t.a_off[2];
+  const int64_t numel = (int64_t)s0 * s1 * s2;
+  // ||T||^2 and the Gram matrices of the initial factors
+  double nt = 0.0;
+  for (int64_t e = threadIdx.x; e < numel; e += NT) nt += (double)T[e] * (double)T[e];
+  const double normT2 = block_sum<NT>(L, nt);
+  double* Af[3] = {A0, A1, A2};
+  const int sz[3] = {s0, s1, s2};
+  for (int m = 0; m < 3; ++m)
+    for (int e = threadIdx.x; e < R * R; e += NT) {
+      const int p = e / R, q = e - p * R;
+      double acc = 0.0;
+      for (int i = 0; i < sz[m]; ++i) acc += Af[m][(int64_t)i * R + p] * Af[m][(int64_t)i * R + q];
+      L.S[m][e] = acc;
+    }
+  if (threadIdx.x == 0) L.fail = 0;
+  __syncthreads();
+  float* Y = scratch;
+  for (int sw = 0; sw < a.sweeps; ++sw) {
+    // Y = T x_2 A2 over rows (i, j)
+    stage_factor<NT, RP>(L, A2, s2, R);
+    __syncthreads();
+    ttm_rows<NT, RP>(L, T, (int64_t)s0 * s1, s2, R, Y);
+    __syncthreads();
+    // mode 0: M0 = sum_j Y[i][j] * A1[j]
+    for (int e = threadIdx.x; e < s0 * R; e += NT) {
+      const int i = e / R, r = e - i * R;
+      double acc = 0.0;
+      for (int j = 0; j < s1; ++j) acc += (double)Y[((int64_t)i * s1 + j) * R + r] * A1[(int64_t)j * R + r];
+      L.M[e] = acc;
+    }
+    gamma_inverse<NT>(L, 1, 2, R);
+    if (L.fail) break;
+    update_factor<NT>(L, A0, s0, R, 0);
+    // mode 1: M1 = sum_i Y[i][j] * A0[i]
+    for (int e = threadIdx.x; e < s1 * R; e += NT) {
+      const int j = e / R, r = e - j * R;
+      double acc = 0.0;
+      for (int i = 0; i < s0; ++i) acc += (double)Y[((int64_t)i * s1 + j) * R + r] * A0[(int64_t)i * R + r];
+      L.M[e] = acc;
+    }
+    gamma_inverse<NT>(L, 0, 2, R);
+    if (L.fail) break;
+    update_factor<NT>(L, A1, s1, R, 1);
+    // Z = T x_0 A0 over columns (j, k)
+    stage_factor<NT, RP>(L, A0, s0, R);
+    __syncthreads();
+    ttm_cols<NT, RP>(L, T, s0, (int64_t)s1 * s2, R, Y);
+    __syncthreads();
+    // mode 2: M2 = sum_j Z[j][k] * A1[j]
+    for (int e = threadIdx.x; e < s2 * R; e += NT) {
+      const int k = e / R, r = e - k * R;
+      double acc = 0.0;
+      for (int j = 0; j < s1; ++j) acc += (double)Y[((int64_t)j * s2 + k) * R + r] * A1[(int64_t)j * R + r];
+      L.M[e] = acc;
+    }
+    gamma_inverse<NT>(L, 0, 1, R);
+    if (L.fail) break;
+    // <Gamma2, S2_old> is not needed: the residual uses the new S2 below
+    update_factor<NT>(L, A2, s2, R, 2);
+    // residual, Eq. (3): ||T||^2 + <Gamma2, S2> - 2 <M2, A2>, Gamma2 = S0 * S1
+    double part = 0.0;
+    for (int e = threadIdx.x; e < R * R; e += NT) part += L.S[0][e] * L.S[1][e] * L.S[2][e];
+    for (int e = threadIdx.x; e < s2 * R; e += NT) part -= 2.0 * L.M[e] * A2[e];
+    const double num = normT2 + block_sum<NT>(L, part);
+    if (threadIdx.x == 0) a.fitness[(int64_t)idx * a.sweeps + sw] = 1.0 - sqrt((num > 0.0 ? num : 0.0) / normT2);
+  }
+  if (threadIdx.x == 0) a.status[idx] = L.fail ? 1 : 0;
+  __syncthreads();
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_batch(BatchArgs a) {
+  __shared__ Lds L;
+  float* scratch = a.scratch + (int64_t)blockIdx.x * a.slot_floats;
+  for (;;) {
+    if (threadIdx.x == 0) L.item = atomicAdd(a.counter, 1);
+    __syncthreads();
+    const int q = L.item;
+    __syncthreads();
+    if (q >= a.count) break;  // uniform: every workgroup leaves once the queue is empty
+    const BatchTensor t = a.items[q];
+    const int idx = t.idx;
+    long long t0 = 0;
+    if (threadIdx.x == 0 && a.ticks) t0 = wall_clock64();
+    if (t.R <= 16)
+      run_tensor<NT, 16>(L, a, t, idx, scratch);
+    else
+      run_tensor<NT, 32>(L, a, t, idx, scratch);
+    if (threadIdx.x == 0 && a.ticks) {
+      a.ticks[2 * idx] = t0;
+      a.ticks[2 * idx + 1] = wall_clock64();
+    }
+  }
+}
+
+__global__ void k_reset_counter(int* c) {
+  if (threadIdx.x == 0) *c = 0;
+}
+
+}  // namespace
+}  // namespace cpals
+
+using namespace cpals;
+
+struct cp_batch_s {
+  int count = 0;
+  hipStream_t st = nullptr;
+  std::vector<BatchTensor> items;  // queue order
+  std::vector<int> order;          // queue position -> creation index
+  int64_t t_total = 0, a_total = 0;
+  int64_t slot_floats = 0;
+  int waves = 4, groups_per_cu = 2, cus = 256;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  std::string err;
+};
+
+namespace {
+constexpr size_t kAlign = 256;
+size_t up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+int grid_of(const cp_batch_s* b) { return b->cus * b->groups_per_cu; }
+size_t ws_need(const cp_batch_s* b) {
+  const size_t items = up(sizeof(BatchTensor) * (size_t)b->count);
+  const size_t counter = up(sizeof(int));
+  const size_t scratch = up((size_t)grid_of(b) * (size_t)b->slot_floats * sizeof(float));
+  return items + counter + scratch;
+}
+}  // namespace
+
+extern "C" {
+
+cp_status cp_batch_create(cp_batch* out, int count, const int64_t* dims, const int* ranks, void* hip_stream) {
+  if (!out || !dims || !ranks || count < 1) return CP_ERR_ARG;
+  *out = nullptr;
+  cp_batch_s* b = new cp_batch_s();
+  b->count = count;
+  b->st = (hipStream_t)hip_stream;
+  std::vector<BatchTensor> byidx(count);
+  int64_t toff = 0, aoff = 0;
+  for (int i = 0; i < count; ++i) {
+    BatchTensor t{};
+    t.R = ranks[i];
+    if (t.R < 1 || t.R > kMaxR) {
+      delete b;
+      return CP_ERR_UNSUPPORTED;
+    }
+    for (int m = 0; m < 3; ++m) {
+      const int64_t s = dims[3 * i + m];
+      if (s < 1 || s > kMaxS) {
+        delete b;
+        return CP_ERR_UNSUPPORTED;
+      }
+      t.s[m] = (int)s;
+    }
+    t.idx = i;
+    t.t_off = toff;
+    toff += ((int64_t)t.s[0] * t.s[1] * t.s[2] + 3) / 4 * 4;  // 16-byte aligned tensors
+    for (int m = 0; m < 3; ++m) {
+      t.a_off[m] = aoff;
+      aoff += (int64_t)t.s[m] * t.R;
+    }
+    const int64_t need = std::max((int64_t)t.s[0] * t.s[1], (int64_t)t.s[1] * t.s[2]) * t.R;
+    b->slot_floats = std::max(b->slot_floats, (need + 63) / 64 * 64);
+    byidx[i] = t;
+  }
+  b->t_total = toff;
+  b->a_total = aoff;
+  // queue: largest work first (longest-processing-time order)
+  b->order.resize(count);
+  for (int i = 0; i < count; ++i) b->order[i] = i;
+  std::stable_sort(b->order.begin(), b->order.end(), [&](int x, int y) {
+    const BatchTensor &u = byidx[x], &v = byidx[y];
+    return (double)u.s[0] * u.s[1] * u.s[2] * u.R > (double)v.s[0] * v.s[1] * v.s[2] * v.R;
+  });
+  for (int q = 0; q < count; ++q) b->items.push_back(byidx[b->order[q]]);
+  int dev = 0;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0) b->cus = cus;
+  }
+  *out = b;
+  return CP_OK;
+}
+
+cp_status cp_batch_layout(cp_batch b, int64_t* t_offsets, int64_t* a_offsets, int64_t* t_total, int64_t* a_total) {
+  if (!b) return CP_ERR_ARG;
+  for (int q = 0; q < b->count; ++q) {
+    const int i = b->order[q];
+    const BatchTensor& t = b->items[q];
+    if (t_offsets) t_offsets[i] = t.t_off;
+    if (a_offsets)
+      for (int m = 0; m < 3; ++m) a_offsets[3 * i + m] = t.a_off[m];
+  }
+  if (t_total) *t_total = b->t_total;
+  if (a_total) *a_total = b->a_total;
+  return CP_OK;
+}
+
+cp_status cp_batch_set_launch(cp_batch b, int waves_per_group, int groups_per_cu) {
+  if (!b) return CP_ERR_ARG;
+  if ((waves_per_group != 4 && waves_per_group != 8) || groups_per_cu < 1 || groups_per_cu > 4) return CP_ERR_UNSUPPORTED;
+  if (b->ws) return CP_ERR_STATE;  // the workspace size depends on the grid
+  b->waves = waves_per_group;
+  b->groups_per_cu = groups_per_cu;
+  return CP_OK;
+}
+
+cp_status cp_batch_workspace_size(cp_batch b, size_t* bytes) {
+  if (!b || !bytes) return CP_ERR_ARG;
+  *bytes = ws_need(b);
+  return CP_OK;
+}
+
+cp_status cp_batch_set_workspace(cp_batch b, void* dptr, size_t bytes) {
+  if (!b || !dptr) return CP_ERR_ARG;
+  if (((uintptr_t)dptr) % kAlign) return CP_ERR_ARG;
+  if (bytes < ws_need(b)) return CP_ERR_ARG;
+  b->ws = (char*)dptr;
+  b->ws_bytes = bytes;
+  // the queue order and offsets are static: upload them once
+  hipError_t e = hipMemcpyAsync(b->ws, b->items.data(), sizeof(BatchTensor) * b->items.size(), hipMemcpyHostToDevice,
+                                b->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->st);
+  return e == hipSuccess ? CP_OK : CP_ERR_HIP;
+}
+
+cp_status cp_batch_sweeps(cp_batch b, const float* T, double* A, int sweeps, double* fitness, int* status,
+                          long long* ticks) {
+  if (!b || !T || !A || !fitness || !status || sweeps < 1) return CP_ERR_ARG;
+  if (!b->ws) return CP_ERR_STATE;
+  BatchArgs a{};
+  a.T = T;
+  a.A = A;
+  a.items = (const BatchTensor*)b->ws;
+  a.count = b->count;
+  a.sweeps = sweeps;
+  a.fitness = fitness;
+  a.status = status;
+  a.ticks = ticks;
+  a.counter = (int*)(b->ws + up(sizeof(BatchTensor) * (size_t)b->count));
+  a.scratch = (float*)((char*)a.counter + up(sizeof(int)));
+  a.slot_floats = b->slot_floats;
+  hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, b->st, a.counter);
+  const unsigned grid = (unsigned)grid_of(b);
+  if (b->waves == 8)
+    hipLaunchKernelGGL(k_batch<512>, dim3(grid), dim3(512), 0, b->st, a);
+  else
+    hipLaunchKernelGGL(k_batch<256>, dim3(grid), dim3(256), 0, b->st, a);
+  return hipGetLastError() == hipSuccess ? CP_OK : CP_ERR_HIP;
+}
+
+cp_status cp_batch_tick_rate(cp_batch b, double* hz) {
+  if (!b || !hz) return CP_ERR_ARG;
+  int dev = 0, khz = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return CP_ERR_HIP;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess) return CP_ERR_HIP;
+  *hz = (double)khz * 1e3;
+  return CP_OK;
+}
+
+void cp_batch_destroy(cp_batch b) { delete b; }
+
+}  // extern "C"

@@ -145,3 +145,22 @@ def bf16_to_f32(bits):
     """The FP32 values of raw BF16 patterns (exact)."""
     return (np.asarray(bits, dtype=np.uint16).astype(np.uint32) << np.uint32(16)).view(np.float32)
 
+
+
+def batch_workload(count=512, seed=5001, smin=16, smax=96, ranks=(4, 8, 16, 32), noise_rel=1e-3):
+    """Many small independent order-3 FP32 tensors: each mode size iid
+    uniform on [smin, smax], rank uniform over `ranks`, planted iid
+    Uniform[0, 1) factors plus Gaussian noise at `noise_rel` of the norm,
+    initial factors iid Uniform[0, 1).  Tensor i uses seed
+    SeedSequence(seed).spawn(count + 1)[i + 1] through planted_tensor; the
+    first child draws the shapes."""
+    children = np.random.SeedSequence(seed).spawn(count + 1)
+    rng = np.random.default_rng(children[0])
+    dims = rng.integers(smin, smax + 1, size=(count, 3))
+    rs = rng.choice(np.asarray(ranks), size=count)
+    out = []
+    for i in range(count):
+        s = int(children[i + 1].generate_state(1)[0])
+        out.append(planted_tensor(tuple(int(x) for x in dims[i]), int(rs[i]), s, kind="uniform",
+                                  noise_rel=noise_rel, dtype=np.float32, name=f"batch{i}"))
+    return out

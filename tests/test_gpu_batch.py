@@ -1,0 +1,139 @@
+"""GPU parity of the batched path (many small order-3 tensors, one
+persistent launch) against the FP64 oracle's ALS sweeps, tensor by tensor,
+plus determinism, launch-shape independence and HIP-graph replay."""
+
+import numpy as np
+import pytest
+
+from gpu_util import relerr, say
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+def _edge_workloads():
+    """Shapes at the limits: unit and tiny modes, sizes not a multiple of 4
+    or 16, the largest mode (96), R = 1, R = 17 (padded to 32), R = 32."""
+    from paper_2010_12056_amd import synth
+
+    shapes = [((1, 5, 7), 1), ((3, 2, 9), 2), ((17, 33, 5), 17), ((96, 96, 96), 32), ((96, 16, 40), 4),
+              ((20, 21, 22), 8), ((50, 3, 61), 16), ((16, 96, 17), 32)]
+    return [synth.planted_tensor(d, R, 7000 + i, kind="uniform", noise_rel=1e-3, dtype=np.float32)
+            for i, (d, R) in enumerate(shapes)]
+
+
+def _run(dev, ws, sweeps, waves=4, groups=2, A_init=None):
+    from paper_2010_12056_amd import cpals
+
+    b = cpals.Batch([w.dims for w in ws], [w.R for w in ws], device=dev, waves=waves, groups_per_cu=groups)
+    T = b.pack_tensors([w.T for w in ws])
+    A = b.pack_factors([w.init for w in ws]) if A_init is None else A_init.clone()
+    fit, status = b.sweeps(T, A, sweeps)
+    torch.cuda.synchronize()
+    return b, T, A, fit.cpu().numpy(), status.cpu().numpy()
+
+
+def _fit_tol(r):
+    # The contractions with the tensor run in FP32 (the factor is rounded to
+    # FP32 for them: relative error ~6e-8 per entry), so <M, A> in Eq. (3)
+    # carries a relative error e of a few 1e-8; Eq. (3) subtracts terms of
+    # size ||T||^2, so r moves by about e / r.  A planted tensor that has
+    # converged to its 1e-3 noise level (r ~ 1e-3) therefore shows ~5e-5.
+    return 1e-6 + 2e-7 / max(r, 1e-12)
+
+
+def _oracle_check(ws, b, A, fit, sweeps, fac_tol):
+    import oracle
+
+    for i, w in enumerate(ws):
+        st = oracle.AlsState.start(w.T.astype(np.float64), w.init)
+        for s in range(sweeps):
+            r = oracle.als_sweep(st)
+            assert abs(fit[i, s] - (1.0 - r)) <= _fit_tol(r), (i, w.dims, w.R, s, fit[i, s], 1.0 - r)
+        got = [a.cpu().numpy() for a in b.unpack_factors(A, i)]
+        for m in range(3):
+            assert relerr(got[m], st.A[m]) <= fac_tol, (i, w.dims, w.R, m)
+
+
+def test_batch_edge_shapes_match_oracle(dev):
+    say("case batch edge shapes")
+    ws = _edge_workloads()
+    b, T, A, fit, status = _run(dev, ws, 5)
+    assert np.all(status == 0)
+    _oracle_check(ws, b, A, fit, 5, 2e-4)
+    b.close()
+
+
+def test_batch_mixed_workload_matches_oracle(dev):
+    """64 tensors of the benchmark's distribution (modes in [16, 96], R in
+    {4, 8, 16, 32}), 5 sweeps, every tensor checked."""
+    from paper_2010_12056_amd import synth
+
+    say("case batch mixed 64")
+    ws = synth.batch_workload(64, seed=5101)
+    b, T, A, fit, status = _run(dev, ws, 5)
+    assert np.all(status == 0)
+    _oracle_check(ws, b, A, fit, 5, 2e-4)
+    b.close()
+
+
+def test_batch_deterministic_and_independent_of_residency(dev):
+    """Same launch twice: bitwise equal.  One or two resident workgroups per
+    compute unit (a different assignment of tensors to workgroups): bitwise
+    equal, since each tensor is computed by one workgroup in a fixed order."""
+    from paper_2010_12056_amd import synth
+
+    say("case batch determinism")
+    ws = synth.batch_workload(40, seed=5202)
+    b1, _, A1, f1, _ = _run(dev, ws, 4, groups=2)
+    b2, _, A2, f2, _ = _run(dev, ws, 4, groups=2)
+    b3, _, A3, f3, _ = _run(dev, ws, 4, groups=1)
+    assert np.array_equal(f1, f2) and torch.equal(A1, A2)
+    assert np.array_equal(f1, f3) and torch.equal(A1, A3)
+    b4, _, A4, f4, _ = _run(dev, ws, 4, waves=8, groups=1)
+    assert np.max(np.abs(f4 - f1)) <= 1e-10  # eight waves: another reduction tree
+    for b in (b1, b2, b3, b4):
+        b.close()
+
+
+def test_batch_graph_replay(dev):
+    """The sweeps call enqueues kernels only (no allocation, no memset): it is
+    captured in a HIP graph and replayed; every replay, after the factors are
+    reset eagerly, reproduces the eager result bit for bit."""
+    from paper_2010_12056_amd import synth
+
+    say("case batch graph replay")
+    ws = synth.batch_workload(32, seed=5303)
+    b, T, A_eager, f_eager, _ = _run(dev, ws, 3)
+    A0 = b.pack_factors([w.init for w in ws])
+    A = A0.clone()
+    fit = torch.empty((len(ws), 3), dtype=torch.float64, device=dev)
+    status = torch.empty(len(ws), dtype=torch.int32, device=dev)
+    s = torch.cuda.Stream(dev)
+    s.wait_stream(torch.cuda.current_stream(dev))
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        from paper_2010_12056_amd import cpals
+
+        bg = cpals.Batch([w.dims for w in ws], [w.R for w in ws], device=dev)
+        with torch.cuda.graph(g, stream=s):
+            bg.sweeps(T, A, 3, fitness=fit, status=status)
+    torch.cuda.current_stream(dev).wait_stream(s)
+    for rep in range(3):
+        A.copy_(A0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(fit.cpu().numpy(), f_eager), rep
+        assert torch.equal(A, A_eager), rep
+        _ = torch.ones(8, device=dev).sum().item()  # eager work between replays
+    b.close()
+    bg.close()

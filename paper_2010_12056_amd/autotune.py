@@ -2,8 +2,9 @@
 
 The persistent batched kernel (cp_batch_sweeps) has two launch parameters:
 waves per workgroup (4 or 8: how many waves share one tensor's contractions
-and solves) and resident workgroups per compute unit (1 or 2: how many
-tensors a compute unit works on at once; the kernel's 74 KB of LDS allows two).
+and solves) and workgroups per compute unit in the grid (1 or 2; with the
+kernel's 145 KB of LDS only one is resident at a time, so 2 means a second
+round of workgroups that start as the first ones finish).
 The tuner times every candidate on the actual batch (a few sweeps, after a
 warm-up launch) and keeps the fastest; results are cached as JSON keyed by
 the device and a signature of the batch (size, mode-size range, rank set).

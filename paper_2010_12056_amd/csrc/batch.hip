@@ -16,7 +16,8 @@
 // then the residual by Eq. (3).  Contractions with the tensor run on the
 // FP32 matrix cores (16x16x4), Y and Z are FP32 in a per-slot scratch, the
 // second level, the Gram matrices, Gamma, its inverse (Gauss-Jordan without
-// pivoting, SPD) and the update run in FP64.  Every reduction has a fixed
+// pivoting, SPD) and the update run in FP64 on factors held in LDS for all the
+// tensor's sweeps.  Every reduction has a fixed
 // order: results do not depend on which workgroup took which tensor.
 #include "kernels.h"
 
@@ -57,11 +58,15 @@ struct BatchArgs {
   int64_t slot_floats;
 };
 
-// Shared state of one workgroup (FP64 R x R blocks and the staged factor).
+// Shared state of one workgroup: the three factors of the tensor in work
+// (FP64, resident for all its sweeps), their Gram matrices, Gamma and its
+// inverse, the MTTKRP of the mode being updated, the FP32 factor staged for
+// the contraction with the tensor.  About 145 KB: one workgroup per CU.
 struct Lds {
+  double F[3][kMaxS * kMaxR];
   double S[3][kMaxR * kMaxR];
   double G[kMaxR * (kMaxR + 1)];   // Gamma, then its inverse in place (pitch R + 1)
-  double M[kMaxS * kMaxR];          // MTTKRP of the mode being updated
+  double M[kMaxS * kMaxR];
   float Bt[kMaxR * kKP];            // FP32 factor transposed for the contraction, zero padded
   double red[512];
   int item;
@@ -82,13 +87,13 @@ __device__ inline double block_sum(Lds& L, double v) {
   return s;
 }
 
-// Stage factor `a` (s x R, FP64 global) as Bt[c][k] (FP32), zero for k >= s or c >= R.
+// Stage factor m (s x R, FP64 in LDS) as Bt[c][k] (FP32), zero for k >= s or c >= R.
 template <int NT, int RP>
-__device__ inline void stage_factor(Lds& L, const double* a, int s, int R) {
+__device__ inline void stage_factor(Lds& L, int m, int s, int R) {
   const int KP = (s + 15) & ~15;
   for (int e = threadIdx.x; e < RP * KP; e += NT) {
     const int c = e / KP, k = e - c * KP;
-    L.Bt[c * kKP + k] = (k < s && c < R) ? (float)a[(int64_t)k * R + c] : 0.f;
+    L.Bt[c * kKP + k] = (k < s && c < R) ? (float)L.F[m][k * R + c] : 0.f;
   }
 }
 
@@ -98,31 +103,40 @@ __device__ inline void stage_factor(Lds& L, const double* a, int s, int R) {
 template <int NT, int RP>
 __device__ inline void ttm_rows(Lds& L, const float* X, int64_t P, int K, int R, float* C) {
   constexpr int NCB = RP / 16;
+  constexpr int NKB = kMaxS / 16;  // 16-index steps of the longest row
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, l16 = lane & 15;
   const bool vec = (K % 4 == 0) && (((uintptr_t)X & 15) == 0);
+  const int nkb = (K + 15) / 16;
   const int64_t ntiles = (P + 15) / 16;
   for (int64_t tile = wave; tile < ntiles; tile += NT / 64) {
     const int64_t p0 = tile * 16;
     const int64_t row = (p0 + l16 < P) ? p0 + l16 : P - 1;
     const float* xr = X + row * K;
+    // every load of the tile in flight before the first product
+    f32x4 a[NKB];
+#pragma unroll
+    for (int t = 0; t < NKB; ++t) {
+      const int k0 = 16 * t + 4 * g;
+      if (t < nkb && vec && k0 + 4 <= K) {
+        a[t] = *(const f32x4*)(xr + k0);
+      } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) a[t][u] = (t < nkb && k0 + u < K) ? xr[k0 + u] : 0.f;
+      }
+    }
     f32x4 acc[NCB];
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) acc[cb] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int kb = 0; kb < K; kb += 16) {
-      const int k0 = kb + 4 * g;
-      f32x4 a;
-      if (vec && k0 + 4 <= K) {
-        a = *(const f32x4*)(xr + k0);
-      } else {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) a[u] = (k0 + u < K) ? xr[k0 + u] : 0.f;
-      }
+    for (int t = 0; t < NKB; ++t) {
+      if (t >= nkb) break;
+      const int k0 = 16 * t + 4 * g;
 #pragma unroll
       for (int u = 0; u < 4; ++u)
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb)
-          acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u], L.Bt[(cb * 16 + l16) * kKP + k0 + u], acc[cb], 0, 0, 0);
+          acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t][u], L.Bt[(cb * 16 + l16) * kKP + k0 + u], acc[cb], 0, 0, 0);
     }
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb)
@@ -141,21 +155,30 @@ __device__ inline void ttm_rows(Lds& L, const float* X, int64_t P, int K, int R,
 template <int NT, int RP>
 __device__ inline void ttm_cols(Lds& L, const float* X, int K, int64_t Q, int R, float* C) {
   constexpr int NCB = RP / 16;
+  constexpr int NKS = kMaxS / 4;  // 4-index steps of the longest contraction
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, l16 = lane & 15;
+  const int nks = (K + 3) / 4;
   const int64_t ntiles = (Q + 15) / 16;
   for (int64_t tile = wave; tile < ntiles; tile += NT / 64) {
     const int64_t q0 = tile * 16;
     const bool qok = q0 + l16 < Q;
+    float a[NKS];
+#pragma unroll
+    for (int t = 0; t < NKS; ++t) {
+      const int k = 4 * t + g;
+      a[t] = (t < nks && k < K && qok) ? X[(int64_t)k * Q + q0 + l16] : 0.f;
+    }
     f32x4 acc[NCB];
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) acc[cb] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int kb = 0; kb < K; kb += 4) {
-      const int k = kb + g;
-      const float a = (k < K && qok) ? X[(int64_t)k * Q + q0 + l16] : 0.f;
+#pragma unroll
+    for (int t = 0; t < NKS; ++t) {
+      if (t >= nks) break;
+      const int k = 4 * t + g;
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb)
-        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, L.Bt[(cb * 16 + l16) * kKP + k], acc[cb], 0, 0, 0);
+        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t], L.Bt[(cb * 16 + l16) * kKP + k], acc[cb], 0, 0, 0);
     }
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb)
@@ -211,45 +234,57 @@ __device__ inline void gamma_inverse(Lds& L, int a, int b, int R) {
   }
 }
 
-// A <- M Ginv (FP64, s x R, written to global) and S[m] <- A^T A.
+// F[m] <- M Ginv (FP64, s x R, in LDS) and S[m] <- F[m]^T F[m].
 template <int NT>
-__device__ inline void update_factor(Lds& L, double* A, int s, int R, int m) {
+__device__ inline void update_factor(Lds& L, int s, int R, int m) {
   const int P = R + 1;
   for (int e = threadIdx.x; e < s * R; e += NT) {
     const int i = e / R, r = e - i * R;
     double acc = 0.0;
     for (int c = 0; c < R; ++c) acc += L.M[i * R + c] * L.G[c * P + r];
-    A[e] = acc;
+    L.F[m][e] = acc;
   }
   __syncthreads();
   for (int e = threadIdx.x; e < R * R; e += NT) {
     const int a = e / R, b = e - a * R;
     double acc = 0.0;
-    for (int i = 0; i < s; ++i) acc += A[(int64_t)i * R + a] * A[(int64_t)i * R + b];
+    for (int i = 0; i < s; ++i) acc += L.F[m][i * R + a] * L.F[m][i * R + b];
     L.S[m][e] = acc;
   }
   __syncthreads();
 }
 
+// M[o][r] = sum_x Y[(o * so + x * sx) * R + r] * F[f][x][r] for o < n, x < nx
+// (the second level; eight loads in flight per thread).
+template <int NT>
+__device__ inline void second_level(Lds& L, const float* Y, int n, int nx, int64_t so, int64_t sx, int f, int R) {
+  for (int e = threadIdx.x; e < n * R; e += NT) {
+    const int o = e / R, r = e - o * R;
+    const float* y = Y + (int64_t)o * so * R + r;
+    double acc = 0.0;
+#pragma unroll 8
+    for (int x = 0; x < nx; ++x) acc += (double)y[(int64_t)x * sx * R] * L.F[f][x * R + r];
+    L.M[e] = acc;
+  }
+}
+
 template <int NT, int RP>
 __device__ void run_tensor(Lds& L, const BatchArgs& a, const BatchTensor& t, int idx, float* scratch) {
   const int s0 = t.s[0], s1 = t.s[1], s2 = t.s[2], R = t.R;
+  const int sz[3] = {s0, s1, s2};
   const float* T = a.T + t.t_off;
-  double* A0 = a.A + t.a_off[0];
-  double* A1 = a.A + t.a_off[1];
-  double* A2 = a.A + t.a_off[2];
   const int64_t numel = (int64_t)s0 * s1 * s2;
-  // ||T||^2 and the Gram matrices of the initial factors
+  // the factors into LDS, ||T||^2, the Gram matrices of the initial factors
+  for (int m = 0; m < 3; ++m)
+    for (int e = threadIdx.x; e < sz[m] * R; e += NT) L.F[m][e] = a.A[t.a_off[m] + e];
   double nt = 0.0;
   for (int64_t e = threadIdx.x; e < numel; e += NT) nt += (double)T[e] * (double)T[e];
-  const double normT2 = block_sum<NT>(L, nt);
-  double* Af[3] = {A0, A1, A2};
-  const int sz[3] = {s0, s1, s2};
+  const double normT2 = block_sum<NT>(L, nt);  // (its barriers also publish F)
   for (int m = 0; m < 3; ++m)
     for (int e = threadIdx.x; e < R * R; e += NT) {
       const int p = e / R, q = e - p * R;
       double acc = 0.0;
-      for (int i = 0; i < sz[m]; ++i) acc += Af[m][(int64_t)i * R + p] * Af[m][(int64_t)i * R + q];
+      for (int i = 0; i < sz[m]; ++i) acc += L.F[m][i * R + p] * L.F[m][i * R + q];
       L.S[m][e] = acc;
     }
   if (threadIdx.x == 0) L.fail = 0;
@@ -257,53 +292,40 @@ __device__ void run_tensor(Lds& L, const BatchArgs& a, const BatchTensor& t, int
   float* Y = scratch;
   for (int sw = 0; sw < a.sweeps; ++sw) {
     // Y = T x_2 A2 over rows (i, j)
-    stage_factor<NT, RP>(L, A2, s2, R);
+    stage_factor<NT, RP>(L, 2, s2, R);
     __syncthreads();
     ttm_rows<NT, RP>(L, T, (int64_t)s0 * s1, s2, R, Y);
     __syncthreads();
-    // mode 0: M0 = sum_j Y[i][j] * A1[j]
-    for (int e = threadIdx.x; e < s0 * R; e += NT) {
-      const int i = e / R, r = e - i * R;
-      double acc = 0.0;
-      for (int j = 0; j < s1; ++j) acc += (double)Y[((int64_t)i * s1 + j) * R + r] * A1[(int64_t)j * R + r];
-      L.M[e] = acc;
-    }
+    // mode 0: M0[i] = sum_j Y[i][j] * A1[j]
+    second_level<NT>(L, Y, s0, s1, s1, 1, 1, R);
     gamma_inverse<NT>(L, 1, 2, R);
     if (L.fail) break;
-    update_factor<NT>(L, A0, s0, R, 0);
-    // mode 1: M1 = sum_i Y[i][j] * A0[i]
-    for (int e = threadIdx.x; e < s1 * R; e += NT) {
-      const int j = e / R, r = e - j * R;
-      double acc = 0.0;
-      for (int i = 0; i < s0; ++i) acc += (double)Y[((int64_t)i * s1 + j) * R + r] * A0[(int64_t)i * R + r];
-      L.M[e] = acc;
-    }
+    update_factor<NT>(L, s0, R, 0);
+    // mode 1: M1[j] = sum_i Y[i][j] * A0[i]
+    second_level<NT>(L, Y, s1, s0, 1, s1, 0, R);
     gamma_inverse<NT>(L, 0, 2, R);
     if (L.fail) break;
-    update_factor<NT>(L, A1, s1, R, 1);
+    update_factor<NT>(L, s1, R, 1);
     // Z = T x_0 A0 over columns (j, k)
-    stage_factor<NT, RP>(L, A0, s0, R);
+    stage_factor<NT, RP>(L, 0, s0, R);
     __syncthreads();
     ttm_cols<NT, RP>(L, T, s0, (int64_t)s1 * s2, R, Y);
     __syncthreads();
-    // mode 2: M2 = sum_j Z[j][k] * A1[j]
-    for (int e = threadIdx.x; e < s2 * R; e += NT) {
-      const int k = e / R, r = e - k * R;
-      double acc = 0.0;
-      for (int j = 0; j < s1; ++j) acc += (double)Y[((int64_t)j * s2 + k) * R + r] * A1[(int64_t)j * R + r];
-      L.M[e] = acc;
-    }
+    // mode 2: M2[k] = sum_j Z[j][k] * A1[j]
+    second_level<NT>(L, Y, s2, s1, 1, s2, 1, R);
     gamma_inverse<NT>(L, 0, 1, R);
     if (L.fail) break;
-    // <Gamma2, S2_old> is not needed: the residual uses the new S2 below
-    update_factor<NT>(L, A2, s2, R, 2);
+    update_factor<NT>(L, s2, R, 2);
     // residual, Eq. (3): ||T||^2 + <Gamma2, S2> - 2 <M2, A2>, Gamma2 = S0 * S1
     double part = 0.0;
     for (int e = threadIdx.x; e < R * R; e += NT) part += L.S[0][e] * L.S[1][e] * L.S[2][e];
-    for (int e = threadIdx.x; e < s2 * R; e += NT) part -= 2.0 * L.M[e] * A2[e];
+    for (int e = threadIdx.x; e < s2 * R; e += NT) part -= 2.0 * L.M[e] * L.F[2][e];
     const double num = normT2 + block_sum<NT>(L, part);
     if (threadIdx.x == 0) a.fitness[(int64_t)idx * a.sweeps + sw] = 1.0 - sqrt((num > 0.0 ? num : 0.0) / normT2);
   }
+  // factors back to the caller's array
+  for (int m = 0; m < 3; ++m)
+    for (int e = threadIdx.x; e < sz[m] * R; e += NT) a.A[t.a_off[m] + e] = L.F[m][e];
   if (threadIdx.x == 0) a.status[idx] = L.fail ? 1 : 0;
   __syncthreads();
 }

@@ -268,7 +268,8 @@ __global__ __launch_bounds__(512) void k_ttm_rb(const T* __restrict__ X, const T
 
 // First-level contraction over the last mode for K <= 8 * 4V (one register
 // chunk): X is P x K row-major.  16-row output tiles per wave, eight waves
-// per workgroup, the factor transposed in LDS and re-read per tile.  Lane
+// per workgroup, the factor transposed in LDS and re-read per tile; each
+// wave loads its next tile while it multiplies the current one.  Lane
 // (row, g = lane / 16) feeds k = t*4V + g*V + u at MFMA step (t, u) from one
 // 16-byte load per t.  Rows beyond P are clamped for loads and masked for
 // stores; k beyond K meets zero rows of the staged factor.
@@ -292,33 +293,45 @@ __global__ __launch_bounds__(512) void k_ttm_kc(const T* __restrict__ X, const T
     Bt[col * pitch + k] = (k < K && c0 + col < R) ? B[(int64_t)k * R + c0 + col] : T(0);
   }
   __syncthreads();
-  for (int64_t tile = (int64_t)blockIdx.x * kTtmWaves + wave; tile < ntiles;
-       tile += (int64_t)gridDim.x * kTtmWaves) {
-    asm volatile("" ::: "memory");  // factor reads stay in the loop
-    const bool full_tile = (tile + 1) * 16 <= P;
-    // per-tile base pointers (uniform, 64-bit) and 32-bit lane offsets
-    const T* xt = X + tile * 16 * K;
-    T* ct = C + tile * 16 * R;
+  // the 16 rows of tile t, this lane's NTS 16-byte pieces (rows past P are clamped for the
+  // loads and masked at the store; indices past K read zero)
+  auto load_tile = [&](int64_t t, VT (&a)[NTS]) {
     int lrow = l16;
-    if (!full_tile) {
-      const int64_t last = P - 1 - tile * 16;
+    if ((t + 1) * 16 > P) {
+      const int64_t last = P - 1 - t * 16;
       lrow = lrow < last ? lrow : (int)last;
     }
-    const T* xr = xt + lrow * (int)K + g * V;
-    VT a[NTS];
+    const T* xr = X + t * 16 * K + lrow * (int)K + g * V;
 #pragma unroll
-    for (int t = 0; t < NTS; ++t) {
-      const int k = t * KT + g * V;
+    for (int s = 0; s < NTS; ++s) {
+      const int k = s * KT + g * V;
       if (FULLK) {
-        a[t] = *(const VT*)(xr + t * KT);
+        a[s] = *(const VT*)(xr + s * KT);
       } else if (vec) {
-        if (k + V <= K) a[t] = *(const VT*)(xr + t * KT);
-        else a[t] = VT{};
+        if (k + V <= K) a[s] = *(const VT*)(xr + s * KT);
+        else a[s] = VT{};
       } else {
 #pragma unroll
-        for (int u = 0; u < V; ++u) a[t][u] = (k + u < K) ? xr[t * KT + u] : T(0);
+        for (int u = 0; u < V; ++u) a[s][u] = (k + u < K) ? xr[s * KT + u] : T(0);
       }
     }
+  };
+  const int64_t stride = (int64_t)gridDim.x * kTtmWaves;
+  int64_t tile = (int64_t)blockIdx.x * kTtmWaves + wave;
+  VT a[NTS];
+  if (tile < ntiles) load_tile(tile, a);
+  for (; tile < ntiles; tile += stride) {
+    asm volatile("" ::: "memory");  // factor reads stay in the loop
+    // the next tile's rows are in flight while this one is multiplied
+    VT an[NTS];
+    if (tile + stride < ntiles) {
+      load_tile(tile + stride, an);
+    } else {
+#pragma unroll
+      for (int s = 0; s < NTS; ++s) an[s] = VT{};
+    }
+    const bool full_tile = (tile + 1) * 16 <= P;
+    T* ct = C + tile * 16 * R;
     typename Mma<T>::acc_t acc[NCB];
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) acc[cb] = Mma<T>::zero();
@@ -347,6 +360,8 @@ __global__ __launch_bounds__(512) void k_ttm_kc(const T* __restrict__ X, const T
           if (tile * 16 + r < P && c < R) ct[r * R + c] = acc[cb][v];
         }
     }
+#pragma unroll
+    for (int s = 0; s < NTS; ++s) a[s] = an[s];
   }
 }
 
@@ -359,8 +374,9 @@ __global__ __launch_bounds__(512) void k_ttm_kc(const T* __restrict__ X, const T
 // 16-lane group reads 256 contiguous bytes per load.  The factor is stored
 // transposed with k permuted inside each 32-wide chunk (k = kc + 4t + g at
 // position kc + 8g + t) so a lane reads its eight t-values with two 16-byte
-// LDS reads.
-template <int NCB>
+// LDS reads.  The next 32-index chunk (across tiles too) is loaded while the
+// current one is multiplied.
+template <int NCB, bool FULL>
 __global__ __launch_bounds__(512) void k_ttm_q(const float* __restrict__ X, const float* __restrict__ B,
                                                float* __restrict__ C, int64_t P, int64_t K, int64_t Q,
                                                int R, int64_t tilesQ, int64_t ntiles, int Kp, int vec) {
@@ -378,32 +394,52 @@ __global__ __launch_bounds__(512) void k_ttm_q(const float* __restrict__ X, cons
     Bt[col * pitch + pos] = (k < K && c0 + col < R) ? B[(int64_t)k * R + c0 + col] : 0.f;
   }
   __syncthreads();
-  for (int64_t tile = (int64_t)blockIdx.x * kTtmWaves + wave; tile < ntiles;
-       tile += (int64_t)gridDim.x * kTtmWaves) {
+  // this lane's eight 16-byte pieces of the 32-index chunk kc of tile t
+  auto load_chunk = [&](int64_t t, int kc, f32x4 (&a)[8]) {
+    const int64_t p = t / tilesQ;
+    const int64_t qa = (t - p * tilesQ) * 64 + 4 * l16;
+    const bool full = vec && qa + 4 <= Q;
+    const float* Xb = X + p * K * Q;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const int64_t k = kc + 4 * s + g;
+      const float* src = Xb + k * Q + qa;
+      if (FULL || (k < K && full)) {  // FULL: whole 64-q tiles and 32-index chunks, aligned
+        a[s] = *(const f32x4*)src;
+      } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) a[s][u] = (k < K && qa + u < Q) ? src[u] : 0.f;
+      }
+    }
+  };
+  // prefetching needs 32 more registers: kept for up to 64 factor columns per wave
+  constexpr bool PF = NCB <= 4;
+  const int64_t stride = (int64_t)gridDim.x * kTtmWaves;
+  int64_t tile = (int64_t)blockIdx.x * kTtmWaves + wave;
+  f32x4 a[8];
+  if (PF && tile < ntiles) load_chunk(tile, 0, a);
+  for (; tile < ntiles; tile += stride) {
     asm volatile("" ::: "memory");  // factor reads stay in the loop (see k_ttm_rb)
     const int64_t p = tile / tilesQ;
     const int64_t q0 = (tile - p * tilesQ) * 64;
-    const float* Xb = X + p * K * Q;
     float* Cb = C + p * Q * R;
-    const int64_t qa = q0 + 4 * l16;  // this lane's four rows qa .. qa + 3
-    const bool full = vec && qa + 4 <= Q;
     f32x4 acc[4][NCB];
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb) acc[u][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
     for (int kc = 0; kc < Kp; kc += 32) {
-      f32x4 a[8];
+      // the next chunk (or the next tile's first) is in flight while this one is multiplied
+      f32x4 an[8];
+      if (!PF) {
+        load_chunk(tile, kc, a);
+      } else if (kc + 32 < Kp) {
+        load_chunk(tile, kc + 32, an);
+      } else if (tile + stride < ntiles) {
+        load_chunk(tile + stride, 0, an);
+      } else {
 #pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        const int64_t k = kc + 4 * t + g;
-        const float* src = Xb + k * Q + qa;
-        if (k < K && full) {
-          a[t] = *(const f32x4*)src;
-        } else {
-#pragma unroll
-          for (int u = 0; u < 4; ++u) a[t][u] = (k < K && qa + u < Q) ? src[u] : 0.f;
-        }
+        for (int s = 0; s < 8; ++s) an[s] = f32x4{0.f, 0.f, 0.f, 0.f};
       }
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb) {
@@ -417,6 +453,10 @@ __global__ __launch_bounds__(512) void k_ttm_q(const float* __restrict__ X, cons
           for (int u = 0; u < 4; ++u)
             acc[u][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t][u], bv, acc[u][cb], 0, 0, 0);
         }
+      }
+      if (PF) {
+#pragma unroll
+        for (int s = 0; s < 8; ++s) a[s] = an[s];
       }
     }
 #pragma unroll
@@ -554,7 +594,8 @@ __global__ __launch_bounds__(256) void k_gram(const double* __restrict__ A, int6
   if (e >= R * R) return;
   const int a = e / R, b = e % R;
   double acc = 0.0;
-  for (int64_t r = 0; r < s; ++r) acc += A[r * R + a] * A[r * R + b];
+#pragma unroll 8
+  for (int64_t r = 0; r < s; ++r) acc += A[r * R + a] * A[r * R + b];  // eight rows in flight
   S[e] = acc;
 }
 
@@ -591,96 +632,133 @@ __global__ __launch_bounds__(256) void k_gamma(GammaArgs a) {
   if (a.pp) a.W[e] = w;
 }
 
-// Ginv = Gamma^-1 by Gauss-Jordan elimination without pivoting (Gamma is
-// SPD; each pivot is a positive Schur-complement diagonal).  Gamma is padded
-// to RP x RP with the identity.  Lane j of every wave owns column j (and
-// j + 64 when RP = 128); wave w owns rows 16 w .. 16 w + 15, in registers.
-// Step k: the wave holding row k publishes it through double-buffered LDS
-// (one barrier per step); each wave reads the column-k entries of its own
-// rows from lane k with readlane.
+// Ginv = Gamma^-1 by blocked Gauss-Jordan elimination without pivoting
+// (Gamma SPD), 16 x 16 blocks on the f64 matrix cores.  Gamma is padded to
+// RP x RP with the identity and kept in LDS.  Block step k, with D the
+// diagonal block, row panel A_kj, column panel A_ik, rest A_ij:
+//   D <- D^-1 (scalar elimination of the 16 pivots, one wave),
+//   A_kj <- D^-1 A_kj,  A_ij <- A_ij - A_ik A_kj (new A_kj),  A_ik <- -A_ik D^-1,
+// which is the in-place scalar elimination grouped by 16 pivots: the pivots
+// met are the same Schur-complement diagonals.  A pivot at or below
+// R eps max(diag) hands over to k_pinv (stats->pinv_pending).  The sequential
+// depth is RP / 16 block steps instead of RP pivots.
 template <int RP>
-__global__ __launch_bounds__(RP > 64 ? 512 : (RP / 16) * 64) void k_inv(const double* __restrict__ Gm,
-                                                                        double* __restrict__ Gi, int R,
-                                                                        DevStats* stats) {
-  constexpr int NW = RP / 16;
-  constexpr int NC = RP > 64 ? 2 : 1;
-  __shared__ double rowbuf[2][RP];
-  __shared__ double diag[RP];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  double g[NC][16];
+__global__ __launch_bounds__(256) void k_inv_blk(const double* __restrict__ Gm, double* __restrict__ Gi, int R,
+                                                 DevStats* stats) {
+  constexpr int NB = RP / 16;
+  constexpr int P = RP + 1;
+  __shared__ double A[RP * P];
+  __shared__ double red[256];
+  __shared__ int fail;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l16 = lane & 15, g = lane >> 4;
+  // every load in flight before the first store (the matrix was just written
+  // by another kernel: each load is a trip to the shared cache)
+  constexpr int PER = RP * RP / 256;
+  double vals[PER];
 #pragma unroll
-  for (int c = 0; c < NC; ++c)
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int i = 16 * w + r, j = lane + 64 * c;
-      double v = (i == j) ? 1.0 : 0.0;
-      if (i < R && j < R) v = Gm[i * R + j];
-      g[c][r] = v;
-      if (i == j && j < RP) diag[i] = v;
-    }
-  __syncthreads();
-  double dmax = 0.0;
-  for (int d = 0; d < R; ++d) dmax = fmax(dmax, diag[d]);
-  const double tol = dmax * (double)R * 2.220446049250313e-16;
-  bool failed = false;
-  for (int kw = 0; kw < NW && !failed; ++kw) {
-#pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
-      const int k = 16 * kw + kk;
-      const int b = kk & 1;
-      if (w == kw) {
-#pragma unroll
-        for (int c = 0; c < NC; ++c)
-          if (lane + 64 * c < RP) rowbuf[b][lane + 64 * c] = g[c][kk];
-      }
-      __syncthreads();
-      const double piv = rowbuf[b][k];
-      if (!(piv > tol)) {  // same value in every thread: uniform exit
-        failed = true;
-        break;
-      }
-      double rinv = __builtin_amdgcn_rcp(piv);  // refined by two Newton steps
-      rinv = fma(rinv, fma(-piv, rinv, 1.0), rinv);
-      rinv = fma(rinv, fma(-piv, rinv, 1.0), rinv);
-      double rk[NC];
-#pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        const int jc = lane + 64 * c;
-        rk[c] = (jc == k) ? rinv : ((jc < RP) ? rowbuf[b][jc] : 0.0) * rinv;
-      }
-      // column k of this wave's rows, from lane k % 64 of column set k / 64
-      const int kc = k >> 6, kl = k & 63;
-      double ck[16];
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        double src = g[0][r];
-        if (NC == 2 && kc == 1) src = g[NC - 1][r];
-        const int lo = __builtin_amdgcn_readlane(__double2loint(src), kl);
-        const int hi = __builtin_amdgcn_readlane(__double2hiint(src), kl);
-        ck[r] = __hiloint2double(hi, lo);
-      }
-#pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        const int jc = lane + 64 * c;
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          if (r == kk && w == kw) {
-            g[c][r] = rk[c];
-          } else {
-            g[c][r] = ((jc == k) ? 0.0 : g[c][r]) - ck[r] * rk[c];
-          }
-        }
-      }
-    }
+  for (int q = 0; q < PER; ++q) {
+    const int e = tid + 256 * q, i = e / RP, j = e - i * RP;
+    vals[q] = (i < R && j < R) ? Gm[i * R + j] : (i == j ? 1.0 : 0.0);
   }
+  double dm = 0.0;
 #pragma unroll
-  for (int c = 0; c < NC; ++c)
+  for (int q = 0; q < PER; ++q) {
+    const int e = tid + 256 * q, i = e / RP, j = e - i * RP;
+    A[i * P + j] = vals[q];
+    if (i == j && i < R) dm = fmax(dm, vals[q]);
+  }
+  red[tid] = dm;
+  if (tid == 0) fail = 0;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (tid < h) red[tid] = fmax(red[tid], red[tid + h]);
+    __syncthreads();
+  }
+  const double tol = red[0] * (double)R * 2.220446049250313e-16;
+  for (int kb = 0; kb < NB; ++kb) {
+    const int k0 = 16 * kb;
+    // (1) D <- D^-1 by wave 0: lane owns entries e = lane + 64 q of the 16 x 16 block
+    if (wave == 0) {
+      for (int s = 0; s < 16; ++s) {
+        const double piv = A[(k0 + s) * P + k0 + s];
+        if (!(piv > tol)) {  // uniform in the wave
+          if (lane == 0) fail = 1;
+          break;
+        }
+        const double rinv = 1.0 / piv;
+        double nv[4];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int i = 16 * w + r, j = lane + 64 * c;
-      if (i < R && j < R) Gi[i * R + j] = failed ? 0.0 : g[c][r];
+        for (int q = 0; q < 4; ++q) {
+          const int e = lane + 64 * q, i = e >> 4, j = e & 15;
+          const double rk = A[(k0 + s) * P + k0 + j], ck = A[(k0 + i) * P + k0 + s], a = A[(k0 + i) * P + k0 + j];
+          if (i == s)
+            nv[q] = (j == s) ? rinv : rk * rinv;
+          else
+            nv[q] = (j == s) ? -ck * rinv : a - ck * rk * rinv;
+        }
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int e = lane + 64 * q, i = e >> 4, j = e & 15;
+          A[(k0 + i) * P + k0 + j] = nv[q];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      }
     }
-  if (failed && threadIdx.x == 0) stats->pinv_pending = 1;
+    __syncthreads();
+    if (fail) break;  // uniform
+    // (2) row panel A_kj <- D^-1 A_kj, one 16 x 16 tile per wave at a time
+    for (int jb = wave; jb < NB; jb += 4) {
+      if (jb == kb) continue;
+      const int j0 = 16 * jb;
+      f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(A[(k0 + l16) * P + k0 + 4 * t + g],
+                                                   A[(k0 + 4 * t + g) * P + j0 + l16], acc, 0, 0, 0);
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int v = 0; v < 4; ++v) A[(k0 + g + 4 * v) * P + j0 + l16] = acc[v];
+    }
+    __syncthreads();
+    // (3) A_ij <- A_ij - A_ik A_kj for every block i, j != k
+    for (int tt = wave; tt < NB * NB; tt += 4) {
+      const int ib = tt / NB, jb = tt - ib * NB;
+      if (ib == kb || jb == kb) continue;
+      const int i0 = 16 * ib, j0 = 16 * jb;
+      f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(A[(i0 + l16) * P + k0 + 4 * t + g],
+                                                   A[(k0 + 4 * t + g) * P + j0 + l16], acc, 0, 0, 0);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) A[(i0 + g + 4 * v) * P + j0 + l16] -= acc[v];
+    }
+    __syncthreads();
+    // (4) column panel A_ik <- -A_ik D^-1
+    for (int ib = wave; ib < NB; ib += 4) {
+      if (ib == kb) continue;
+      const int i0 = 16 * ib;
+      f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(A[(i0 + l16) * P + k0 + 4 * t + g],
+                                                   A[(k0 + 4 * t + g) * P + k0 + l16], acc, 0, 0, 0);
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int v = 0; v < 4; ++v) A[(i0 + g + 4 * v) * P + k0 + l16] = -acc[v];
+    }
+    __syncthreads();
+  }
+  const bool failed = fail != 0;
+  for (int e = tid; e < R * R; e += 256) {
+    const int i = e / R, j = e - i * R;
+    Gi[e] = failed ? 0.0 : A[i * P + j];
+  }
+  if (failed && tid == 0) stats->pinv_pending = 1;
 }
 
 // Gamma^dagger when k_inv gave up (stats->pinv_pending): the cyclic Jacobi
@@ -1113,7 +1191,7 @@ hipError_t launch_ttm_kc(const T* X, const T* B, T* C, int64_t P, int64_t K, int
   constexpr int V = 16 / sizeof(T);
   const int64_t ntiles = (P + 15) / 16;
   const int64_t want = (ntiles + kTtmWaves - 1) / kTtmWaves;
-  const unsigned nx = (unsigned)(want < 1024 ? want : 1024);
+  const unsigned nx = (unsigned)(want < 256 ? want : 256);  // one workgroup per CU, each wave two tiles deep
   const unsigned ny = (unsigned)((R + NCB * 16 - 1) / (NCB * 16));
   const int vec = (K % V == 0 && ((uintptr_t)X % 16) == 0) ? 1 : 0;
   // NTS t-steps of 4V contraction indices: the padded depth follows K
@@ -1144,19 +1222,26 @@ hipError_t launch_ttm_q(const float* X, const float* B, float* C, int64_t P, int
   const size_t lds = (size_t)NCB * 16 * (Kp + 4) * sizeof(float);
   static bool attr = false;
   if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_ttm_q<NCB>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    hipError_t e = hipFuncSetAttribute((const void*)k_ttm_q<NCB, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        160 * 1024);
+    if (e == hipSuccess)
+      e = hipFuncSetAttribute((const void*)k_ttm_q<NCB, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              160 * 1024);
     if (e != hipSuccess) return e;
     attr = true;
   }
   const int64_t tilesQ = (Q + 63) / 64;
   const int64_t ntiles = P * tilesQ;
   const int64_t want = (ntiles + kTtmWaves - 1) / kTtmWaves;
-  const unsigned nx = (unsigned)(want < 2048 ? want : 2048);
+  const unsigned nx = (unsigned)(want < 512 ? want : 512);
   const unsigned ny = (unsigned)((R + NCB * 16 - 1) / (NCB * 16));
   const int vec = (Q % 4 == 0 && ((uintptr_t)X % 16) == 0) ? 1 : 0;
-  hipLaunchKernelGGL((k_ttm_q<NCB>), dim3(nx, ny), dim3(kTtmThreads), lds, st, X, B, C, P, K, Q, R, tilesQ, ntiles, Kp,
-                     vec);
+  if (vec && Q % 64 == 0 && K % 32 == 0)
+    hipLaunchKernelGGL((k_ttm_q<NCB, true>), dim3(nx, ny), dim3(kTtmThreads), lds, st, X, B, C, P, K, Q, R, tilesQ,
+                       ntiles, Kp, vec);
+  else
+    hipLaunchKernelGGL((k_ttm_q<NCB, false>), dim3(nx, ny), dim3(kTtmThreads), lds, st, X, B, C, P, K, Q, R, tilesQ,
+                       ntiles, Kp, vec);
   return hipGetLastError();
 }
 
@@ -1272,12 +1357,14 @@ hipError_t launch_gamma(const GammaArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_inverse(const double* Gamma, double* Ginv, int R, DevStats* stats, hipStream_t st) {
-  if (R <= 32) {
-    hipLaunchKernelGGL(k_inv<32>, dim3(1), dim3(128), 0, st, Gamma, Ginv, R, stats);
+  if (R <= 16) {
+    hipLaunchKernelGGL(k_inv_blk<16>, dim3(1), dim3(256), 0, st, Gamma, Ginv, R, stats);
+  } else if (R <= 32) {
+    hipLaunchKernelGGL(k_inv_blk<32>, dim3(1), dim3(256), 0, st, Gamma, Ginv, R, stats);
   } else if (R <= 64) {
-    hipLaunchKernelGGL(k_inv<64>, dim3(1), dim3(256), 0, st, Gamma, Ginv, R, stats);
+    hipLaunchKernelGGL(k_inv_blk<64>, dim3(1), dim3(256), 0, st, Gamma, Ginv, R, stats);
   } else {
-    hipLaunchKernelGGL(k_inv<128>, dim3(1), dim3(512), 0, st, Gamma, Ginv, R, stats);
+    hipLaunchKernelGGL(k_inv_blk<128>, dim3(1), dim3(256), 0, st, Gamma, Ginv, R, stats);
   }
   static bool attr = false;
   if (!attr) {

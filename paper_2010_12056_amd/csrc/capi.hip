@@ -89,6 +89,8 @@ struct cp_plan_s {
   bool have_ops = false;
   bool fresh = true;  // no sweep since the state was (re)initialized: dA = A
   int ttm_count = 0;
+  int ginv_ready = -1;        // mode whose Gamma^dagger the last update left in Ginv
+  bool join_pending = false;  // an inverse runs on the second stream
 
   // learned PP switch (set by cp_pp_set_switch)
   const float* sw_theta = nullptr;
@@ -206,7 +208,7 @@ void plan_layout(cp_plan p) {
   };
   int64_t smax = 0;
   for (int m = 0; m < N; ++m) smax = std::max(smax, p->dims[m]);
-  p->nblk_max = (int)((smax + solve_rows(R) - 1) / solve_rows(R));
+  p->nblk_max = update_groups(smax, R, false);  // workgroups of a mode update
   // fixed order of regions; set_workspace replays it
   for (int m = 0; m < N; ++m) take((size_t)p->dims[m] * R * p->esz);      // Ash
   for (int m = 0; m < N; ++m) take((size_t)p->dims[m] * R * p->esz);      // dAsh
@@ -272,6 +274,7 @@ void plan_carve(cp_plan p) {
 }
 
 void drop_cache(cp_plan p) {
+  p->ginv_ready = -1;
   p->n_hist = 0;
   p->pending_fit = false;
   p->sw_phase_open = false;  // a PP phase cannot outlive the state it was judged against
@@ -349,12 +352,12 @@ cp_status contract_any(cp_plan p, const void* in, uint32_t in_set, int c, void* 
 }
 
 // Walk a root-to-leaf contraction sequence; M (FP64, s_leaf x R) receives the leaf.
-cp_status run_path(cp_plan p, const std::vector<int>& seq, double* M) {
-  const int N = p->N;
+// Depth of the deepest cached node on a path (0: the path starts from the
+// tensor).
+int path_start(cp_plan p, const std::vector<int>& seq, std::vector<uint32_t>* sets_out = nullptr) {
   const int len = (int)seq.size();
-  if (len != N - 1) return fail(p, CP_ERR_STATE, "internal: path of length %d", len);
   std::vector<uint32_t> sets(len + 1);
-  sets[0] = full_set(N);
+  sets[0] = full_set(p->N);
   for (int d = 1; d <= len; ++d) sets[d] = sets[d - 1] & ~(1u << seq[d - 1]);
   int start = 0;
   for (int d = len - 1; d >= 1; --d)
@@ -362,6 +365,16 @@ cp_status run_path(cp_plan p, const std::vector<int>& seq, double* M) {
       start = d;
       break;
     }
+  if (sets_out) *sets_out = sets;
+  return start;
+}
+
+cp_status run_path(cp_plan p, const std::vector<int>& seq, double* M) {
+  const int N = p->N;
+  const int len = (int)seq.size();
+  if (len != N - 1) return fail(p, CP_ERR_STATE, "internal: path of length %d", len);
+  std::vector<uint32_t> sets;
+  const int start = path_start(p, seq, &sets);
   for (int d = start + 1; d <= len; ++d) {
     const void* in = (d == 1) ? p->T : p->slot_buf[d - 1];
     if (d == len) {
@@ -432,11 +445,17 @@ cp_status ensure_aux(cp_plan p) {
 }
 
 // Gamma^(n)^-1 on the second stream.  Gamma^(n) (and W^(n)) were formed by
-// the previous update's finalize (or at state setup), so the inverse depends
-// only on the Gram matrices and overlaps the MTTKRP of the same mode.
+// the previous update (or at state setup), so the inverse depends only on
+// the Gram matrices and overlaps the MTTKRP of the same mode.  Nothing to do
+// when the previous update already inverted Gamma^(n) itself.
 cp_status launch_prep_forked(cp_plan p, int n, bool pp) {
-  (void)n;
   (void)pp;
+  if (p->ginv_ready == n) {
+    p->ginv_ready = -1;
+    return CP_OK;
+  }
+  p->ginv_ready = -1;
+  p->join_pending = true;
   CP_TRY(ensure_aux(p));
   HIP_TRY(p, hipEventRecord(p->ev_fork, p->st));
   HIP_TRY(p, hipStreamWaitEvent(p->aux, p->ev_fork, 0));
@@ -450,6 +469,7 @@ cp_status launch_prep_forked(cp_plan p, int n, bool pp) {
 
 // Gamma^(n) and W^(n) from the current Gram matrices (state setup).
 cp_status form_gamma(cp_plan p, int n, bool pp) {
+  p->ginv_ready = -1;
   GammaArgs ga{};
   for (int m = 0; m < p->N; ++m) {
     ga.S[m] = p->S[m];
@@ -465,49 +485,61 @@ cp_status form_gamma(cp_plan p, int n, bool pp) {
   return CP_OK;
 }
 
+// Whether the update of mode n also inverts the next mode's Gamma (inside
+// its last workgroup) instead of leaving it to the second stream: worth it
+// when the next MTTKRP is short, so that nothing would hide the inverse:
+// in PP sweeps (the first-order correction) and in exact sweeps when the
+// next path starts from a cached node.  Called after ver[n] moved on.
+bool inline_next_inverse(cp_plan p, int n, bool pp) {
+  if (pp) return true;
+  if (n == p->N - 1) return false;
+  const std::vector<int> seq =
+      (p->tree == CP_TREE_MSDT) ? msdt_path(p->N, p->msdt_u) : dt_path(p->N, n + 1);
+  return path_start(p, seq) >= 1;
+}
+
 // Rest of a mode update on the plan stream once the prep has joined:
-// A^(n) <- M Gamma^-1 (with V^(n) in PP), shadows, Gram, norms, residual.
+// A^(n) <- M Gamma^-1 (with V^(n) in PP), shadows, Gram, norms, residual,
+// Gamma^(nx) (and its inverse when the next MTTKRP is short).
 template <typename TT>
 cp_status finish_update_t(cp_plan p, int n, double* A, bool pp) {
   const int R = p->R;
-  HIP_TRY(p, hipStreamWaitEvent(p->st, p->ev_join, 0));
-  ProfScope ps(p, CP_PHASE_UPDATE);
-  const int nblk = (int)((p->dims[n] + solve_rows(R) - 1) / solve_rows(R));
-  SolveArgs<TT> sa{};
-  sa.M = p->Mbuf;
-  sa.A = A;
-  sa.Ash = (TT*)p->Ash[n];
-  sa.Ap = pp ? p->Ap[n] : nullptr;
-  sa.dAsh = pp ? (TT*)p->dAsh[n] : nullptr;
-  sa.W = pp ? p->W : nullptr;
-  sa.Ginv = p->Ginv;
-  sa.Gamma = p->Gamma;
-  sa.partS = p->partS;
-  sa.partdS = p->partdS;
-  sa.partSc = p->partSc;
-  sa.s = p->dims[n];
-  sa.R = R;
-  sa.pp = pp ? 1 : 0;
-  HIP_TRY(p, launch_solve<TT>(sa, nblk, p->st));
-  FinalArgs fa{};
-  fa.partS = p->partS;
-  fa.partdS = p->partdS;
-  fa.partSc = p->partSc;
-  for (int m = 0; m < p->N; ++m) {
-    fa.S[m] = p->S[m];
-    fa.dS[m] = p->dS[m];
+  if (p->join_pending) {
+    HIP_TRY(p, hipStreamWaitEvent(p->st, p->ev_join, 0));
+    p->join_pending = false;
   }
-  fa.Gamma = p->Gamma;
-  fa.W = p->W;
-  fa.stats = p->stats;
-  fa.nblk = nblk;
-  fa.R = R;
-  fa.n = n;
-  fa.N = p->N;
-  fa.last = (n == p->N - 1) ? 1 : 0;
-  fa.pp = sa.pp;
-  HIP_TRY(p, launch_finalize(fa, p->st));
+  ProfScope ps(p, CP_PHASE_UPDATE);
   ++p->ver[n];
+  const bool inv_next = inline_next_inverse(p, n, pp);
+  UpdateArgs<TT> ua{};
+  ua.M = p->Mbuf;
+  ua.A = A;
+  ua.Ash = (TT*)p->Ash[n];
+  ua.Ap = pp ? p->Ap[n] : nullptr;
+  ua.dAsh = pp ? (TT*)p->dAsh[n] : nullptr;
+  ua.Ginv = p->Ginv;
+  ua.partS = p->partS;
+  ua.partdS = p->partdS;
+  ua.partSc = p->partSc;
+  for (int m = 0; m < p->N; ++m) {
+    ua.S[m] = p->S[m];
+    ua.dS[m] = p->dS[m];
+  }
+  ua.Gamma = p->Gamma;
+  ua.W = p->W;
+  ua.stats = p->stats;
+  ua.ticket = &p->stats->ticket;
+  ua.s = p->dims[n];
+  ua.nrb = (int)((p->dims[n] + 15) / 16);
+  ua.R = R;
+  ua.n = n;
+  ua.N = p->N;
+  ua.last = (n == p->N - 1) ? 1 : 0;
+  ua.pp = pp ? 1 : 0;
+  ua.inv_next = inv_next ? 1 : 0;
+  const int groups = std::min(update_groups(p->dims[n], R, pp), p->nblk_max);
+  HIP_TRY(p, launch_update<TT>(ua, groups, p->st));
+  p->ginv_ready = inv_next ? (n + 1) % p->N : -1;
   return CP_OK;
 }
 

@@ -15,7 +15,7 @@ struct DevStats {
   int status;         // bit 0: a Gamma had non-finite entries; bit 1: non-finite residual
   int pinv_pending;   // set by the elimination when a pivot fell below its tolerance
   int pinv_count;     // updates that used the pseudo-inverse (cumulative)
-  int pad;
+  unsigned ticket;    // arrival counter of k_update (0 between launches)
 };
 
 // A BF16 tensor element: the upper 16 bits of an FP32 value.
@@ -26,8 +26,6 @@ struct bf16 {
 
 constexpr int kMaxOrder = 8;
 constexpr int kMaxRank = 128;
-// factor rows per workgroup in the solve/Gram kernel (one 16-row MFMA block)
-__host__ __device__ inline int solve_rows(int) { return 16; }
 
 // C[p][q][r] = sum_k X[p][k][q] * B[k][r]  (Q == 1: X is [P][K] row-major).
 template <typename T>
@@ -81,41 +79,35 @@ hipError_t launch_gamma(const GammaArgs& a, hipStream_t st);
 // stats->status and zero Ginv.
 hipError_t launch_inverse(const double* Gamma, double* Ginv, int R, DevStats* stats, hipStream_t st);
 
-// Row-block solve and partial reductions for one mode update.
+// One mode update (Alg. 1 inner body; Alg. 2 with Eq. (7) in PP) in one
+// launch of `groups` workgroups (update_groups): A^(n) <- M~ Ginv with the
+// shadows, the Gram S^(n) (and dS^(n)), the norms, after the last mode the
+// residual of Eq. (3), Gamma^(nx) and W^(nx) of the next mode
+// nx = (n + 1) mod N, and with inv_next also Ginv <- Gamma^(nx)^dagger.
 template <typename T>
-struct SolveArgs {
+struct UpdateArgs {
   const double* M;    // s x R right-hand side (exact or first-order PP MTTKRP)
   double* A;          // s x R FP64 factor, read (old) and overwritten (new)
   T* Ash;             // s x R shadow of the new factor in tensor precision
   const double* Ap;   // PP: A_p of this mode (else null)
   T* dAsh;            // PP: shadow of dA = A - A_p (else null)
-  const double* W;    // PP: bracket of Eq. (7) (else null)
-  const double* Ginv;
-  const double* Gamma;  // for this block's <Gamma, S_part>
-  double* partS;      // [nblk][R][R]
-  double* partdS;     // PP: [nblk][R][R]
-  double* partSc;     // [nblk][4]: ||A||^2, ||dA||^2, <M, A>, <Gamma, S_part>
-  int64_t s;
-  int R, pp;
-};
-template <typename T>
-hipError_t launch_solve(const SolveArgs<T>& a, int nblk, hipStream_t st);
-
-// Sums the row-block partials of mode n into S^(n) (and dS^(n)), the
-// norms and (after the last mode) the residual; then forms Gamma and W of the
-// next mode, nx = (n + 1) mod N, from the updated Gram matrices.
-struct FinalArgs {
-  const double* partS;
-  const double* partdS;
-  const double* partSc;
+  double* Ginv;       // in: Gamma^(n)^dagger; out (inv_next): Gamma^(nx)^dagger
+  double* partS;      // [groups][R][R] partial Gram matrices
+  double* partdS;     // PP: [groups][R][R]
+  double* partSc;     // [groups][4]: ||A||^2, ||dA||^2, <M~, A>
   double* S[kMaxOrder];   // S^(m); S[n] is written
-  double* dS[kMaxOrder];  // dS^(m); dS[n] is written when pp
-  double* Gamma;          // out: Gamma^(nx)
-  double* W;              // out: W^(nx) (from the current dS, meaningful in PP sweeps)
-  DevStats* stats;
-  int nblk, R, n, N, last, pp;
+  double* dS[kMaxOrder];  // dS^(m); dS[n] is written in PP
+  double* Gamma;      // in: Gamma^(n); out: Gamma^(nx)
+  double* W;          // in (PP): W^(n); out: W^(nx) from the current dS
+  DevStats* stats;    // norms, residual, status
+  unsigned* ticket;   // arrival counter: 0 at launch, left at 0
+  int64_t s;          // rows of A^(n)
+  int nrb;            // 16-row blocks, ceil(s / 16)
+  int R, n, N, last, pp, inv_next;
 };
-hipError_t launch_finalize(const FinalArgs& a, hipStream_t st);
+int update_groups(int64_t s, int R, bool pp);
+template <typename T>
+hipError_t launch_update(const UpdateArgs<T>& a, int groups, hipStream_t st);
 
 // r of Eq. (3) for given factors into stats->r: M is the exact MTTKRP of the
 // last mode, A its factor (s x R), Gamma / S of that mode.

@@ -6,8 +6,8 @@
 //  k_mttv       batched tensor-times-vector down the tree, HBM streaming,
 //               lanes over the contiguous (q, r) block.       Sec. II-C
 //  k_prep       Gamma^(n) (Eq. (1)), its inverse, and the bracket of Eq. (7)
-//  k_solve      A^(n) <- M Gamma^-1 (plus V^(n) in PP), partial Gram, dS, norms
-//  k_finalize   fixed-order reduction of the partials, residual by Eq. (3)
+//  k_update     A^(n) <- M Gamma^-1 (plus V^(n) in PP), Gram, dS, norms, the
+//               residual by Eq. (3), Gamma of the next mode and its inverse
 //  k_pp_mttkrp  first-order PP correction, Eqs. (5)-(6)
 //
 // Every floating-point reduction runs in a fixed order (no atomics), so two
@@ -565,6 +565,26 @@ __device__ inline double block_sum(double v, double* sh) {
   return out;
 }
 
+// Sums of K doubles per thread over 256 threads in a fixed order: an xor
+// butterfly inside each wave, then the four wave totals in wave order.  Every
+// thread gets the totals (sh: at least 4 K doubles of LDS).
+template <int K>
+__device__ inline void block_sums(double (&v)[K], double* sh) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) sh[wave * K + k] = v[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = ((sh[k] + sh[K + k]) + sh[2 * K + k]) + sh[3 * K + k];
+  __syncthreads();
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_norm2_part(const T* __restrict__ X, int64_t n,
                                                     double* __restrict__ part) {
@@ -632,84 +652,75 @@ __global__ __launch_bounds__(256) void k_gamma(GammaArgs a) {
   if (a.pp) a.W[e] = w;
 }
 
-// Ginv = Gamma^-1 by blocked Gauss-Jordan elimination without pivoting
-// (Gamma SPD), 16 x 16 blocks on the f64 matrix cores.  Gamma is padded to
-// RP x RP with the identity and kept in LDS.  Block step k, with D the
+// In-place inverse of an SPD matrix by blocked Gauss-Jordan elimination
+// without pivoting, 16 x 16 blocks, 256 threads.  A is RP x RP in LDS with
+// pitch RP + 1 (padded with the identity).  Block step k, with D the
 // diagonal block, row panel A_kj, column panel A_ik, rest A_ij:
-//   D <- D^-1 (scalar elimination of the 16 pivots, one wave),
+//   D <- D^-1 (scalar elimination of the 16 pivots by one wave),
 //   A_kj <- D^-1 A_kj,  A_ij <- A_ij - A_ik A_kj (new A_kj),  A_ik <- -A_ik D^-1,
 // which is the in-place scalar elimination grouped by 16 pivots: the pivots
-// met are the same Schur-complement diagonals.  A pivot at or below
-// R eps max(diag) hands over to k_pinv (stats->pinv_pending).  The sequential
-// depth is RP / 16 block steps instead of RP pivots.
+// met are the same Schur-complement diagonals.  The panels and the trailing
+// update run on the f64 matrix cores.  Returns false (uniformly, A then
+// undefined) when a pivot is at or below tol.  xb: 64 doubles of LDS,
+// fail: an LDS flag.
 template <int RP>
-__global__ __launch_bounds__(256) void k_inv_blk(const double* __restrict__ Gm, double* __restrict__ Gi, int R,
-                                                 DevStats* stats) {
+__device__ bool gj_inverse_lds(double* A, double tol, double* xb, int* fail) {
   constexpr int NB = RP / 16;
   constexpr int P = RP + 1;
-  __shared__ double A[RP * P];
-  __shared__ double red[256];
-  __shared__ int fail;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int l16 = lane & 15, g = lane >> 4;
-  // every load in flight before the first store (the matrix was just written
-  // by another kernel: each load is a trip to the shared cache)
-  constexpr int PER = RP * RP / 256;
-  double vals[PER];
-#pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    const int e = tid + 256 * q, i = e / RP, j = e - i * RP;
-    vals[q] = (i < R && j < R) ? Gm[i * R + j] : (i == j ? 1.0 : 0.0);
-  }
-  double dm = 0.0;
-#pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    const int e = tid + 256 * q, i = e / RP, j = e - i * RP;
-    A[i * P + j] = vals[q];
-    if (i == j && i < R) dm = fmax(dm, vals[q]);
-  }
-  red[tid] = dm;
-  if (tid == 0) fail = 0;
+  if (tid == 0) *fail = 0;
   __syncthreads();
-  for (int h = 128; h > 0; h >>= 1) {
-    if (tid < h) red[tid] = fmax(red[tid], red[tid + h]);
-    __syncthreads();
-  }
-  const double tol = red[0] * (double)R * 2.220446049250313e-16;
   for (int kb = 0; kb < NB; ++kb) {
     const int k0 = 16 * kb;
-    // (1) D <- D^-1 by wave 0: lane owns entries e = lane + 64 q of the 16 x 16 block
+    // (1) D <- D^-1 by wave 0.  Lane (g, l16) keeps D[g + 4q][l16], q < 4, in
+    // registers; per pivot s the lanes holding row s and column s publish
+    // them in LDS (two alternating buffers, so one wave-level fence per pivot
+    // suffices) and every lane reads the pivot, its row entry and its four
+    // column entries back.
     if (wave == 0) {
+      double x[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) x[q] = A[(k0 + g + 4 * q) * P + k0 + l16];
+      bool ok = true;
+#pragma unroll 1
       for (int s = 0; s < 16; ++s) {
-        const double piv = A[(k0 + s) * P + k0 + s];
-        if (!(piv > tol)) {  // uniform in the wave
-          if (lane == 0) fail = 1;
-          break;
-        }
-        const double rinv = 1.0 / piv;
-        double nv[4];
+        double* rowb = xb + 32 * (s & 1);
+        double* colb = rowb + 16;
+        const int qs = s >> 2;
+        const double xs = qs == 0 ? x[0] : qs == 1 ? x[1] : qs == 2 ? x[2] : x[3];
+        if (g == (s & 3)) rowb[l16] = xs;
+        if (l16 == s) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int e = lane + 64 * q, i = e >> 4, j = e & 15;
-          const double rk = A[(k0 + s) * P + k0 + j], ck = A[(k0 + i) * P + k0 + s], a = A[(k0 + i) * P + k0 + j];
-          if (i == s)
-            nv[q] = (j == s) ? rinv : rk * rinv;
-          else
-            nv[q] = (j == s) ? -ck * rinv : a - ck * rk * rinv;
-        }
-        __builtin_amdgcn_wave_barrier();
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int e = lane + 64 * q, i = e >> 4, j = e & 15;
-          A[(k0 + i) * P + k0 + j] = nv[q];
+          for (int q = 0; q < 4; ++q) colb[g + 4 * q] = x[q];
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const double piv = rowb[s];
+        const double rk = rowb[l16];
+        double ck[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) ck[q] = colb[g + 4 * q];
+        ok = ok && (piv > tol);  // uniform in the wave; after a failure the rest is discarded
+        const double rinv = 1.0 / piv;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (g + 4 * q == s)
+            x[q] = (l16 == s) ? rinv : rk * rinv;
+          else
+            x[q] = (l16 == s) ? -ck[q] * rinv : x[q] - ck[q] * rk * rinv;
+        }
+      }
+      if (ok) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) A[(k0 + g + 4 * q) * P + k0 + l16] = x[q];
+      } else if (lane == 0) {
+        *fail = 1;
       }
     }
     __syncthreads();
-    if (fail) break;  // uniform
+    if (*fail) return false;  // uniform
     // (2) row panel A_kj <- D^-1 A_kj, one 16 x 16 tile per wave at a time
     for (int jb = wave; jb < NB; jb += 4) {
       if (jb == kb) continue;
@@ -753,39 +764,88 @@ __global__ __launch_bounds__(256) void k_inv_blk(const double* __restrict__ Gm, 
     }
     __syncthreads();
   }
-  const bool failed = fail != 0;
-  for (int e = tid; e < R * R; e += 256) {
-    const int i = e / R, j = e - i * R;
-    Gi[e] = failed ? 0.0 : A[i * P + j];
-  }
-  if (failed && tid == 0) stats->pinv_pending = 1;
+  return true;
 }
 
-// Gamma^dagger when k_inv gave up (stats->pinv_pending): the cyclic Jacobi
-// eigenvalue method (Golub and Van Loan, Matrix Computations, Sec. 8.5) in
-// parallel round-robin order.  Each round rotates R/2 disjoint index pairs
-// (p, q), chosen by the circle method (with a bye for odd R), with the
-// rotation that zeroes A[p][q]; rows, then columns of the working matrix A
-// (LDS, pitch R + 1) and the columns of V (kept in Ginv's memory) are
-// updated.  A pair with |A[p][q]| <= eps sqrt(|A[p][p] A[q][q]|) is not
-// rotated (its entry is set to zero); the sweeps stop when none rotates.
-// Then Ginv = V diag(w+) V^T with w+ = 1 / w for w > R eps max(w), else 0.
-__global__ __launch_bounds__(512) void k_pinv(const double* __restrict__ Gm, double* __restrict__ Gi, int R,
-                                              DevStats* stats) {
-  if (stats->pinv_pending == 0) return;  // uniform
+// Largest of one double per thread over 256 threads (red: 256 doubles of LDS).
+__device__ inline double block_max(double v, double* red) {
+  const int tid = threadIdx.x;
+  red[tid] = v;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (tid < h) red[tid] = fmax(red[tid], red[tid + h]);
+    __syncthreads();
+  }
+  const double out = red[0];
+  __syncthreads();
+  return out;
+}
+
+// Ginv = Gamma^-1 (gj_inverse_lds) in one workgroup.  A pivot at or below
+// R eps max(diag) hands over to k_pinv (stats->pinv_pending).
+template <int RP>
+__global__ __launch_bounds__(256) void k_inv_blk(const double* __restrict__ Gm, double* __restrict__ Gi, int R,
+                                                 DevStats* stats) {
+  constexpr int P = RP + 1;
+  __shared__ double A[RP * P];
+  __shared__ double red[256];
+  __shared__ int fail;
+  const int tid = threadIdx.x;
+  // every load in flight before the first store (the matrix was just written
+  // by another kernel: each load is a trip to the shared cache)
+  constexpr int PER = RP * RP / 256;
+  double vals[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int e = tid + 256 * q, i = e / RP, j = e - i * RP;
+    vals[q] = (i < R && j < R) ? Gm[i * R + j] : (i == j ? 1.0 : 0.0);
+  }
+  double dm = 0.0;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int e = tid + 256 * q, i = e / RP, j = e - i * RP;
+    A[i * P + j] = vals[q];
+    if (i == j && i < R) dm = fmax(dm, vals[q]);
+  }
+  const double tol = block_max(dm, red) * (double)R * 2.220446049250313e-16;
+  const bool ok = gj_inverse_lds<RP>(A, tol, red, &fail);
+  for (int e = tid; e < R * R; e += 256) {
+    const int i = e / R, j = e - i * R;
+    Gi[e] = ok ? A[i * P + j] : 0.0;
+  }
+  if (!ok && tid == 0) stats->pinv_pending = 1;
+}
+
+// LDS doubles used by pinv_lds for rank R.
+__host__ __device__ inline size_t pinv_lds_doubles(int R) { return (size_t)R * (R + 1) + R + 128 + 64 + 2; }
+
+// Gamma^dagger by the cyclic Jacobi eigenvalue method (Golub and Van Loan,
+// Matrix Computations, Sec. 8.5) in parallel round-robin order, NT threads.
+// Each round rotates R/2 disjoint index pairs (p, q), chosen by the circle
+// method (with a bye for odd R), with the rotation that zeroes A[p][q]; rows,
+// then columns of the working matrix A (LDS, pitch R + 1) and the columns of
+// V (kept in Gi's memory) are updated.  A pair with
+// |A[p][q]| <= eps sqrt(|A[p][p] A[q][q]|) is not rotated (its entry is set
+// to zero); the sweeps stop when none rotates.  Then
+// Gi = V diag(w+) V^T with w+ = 1 / w for w > R eps max(w), else 0.
+// Non-finite entries of Gm zero Gi and set bit 0 of stats->status.
+template <int NT>
+__device__ void pinv_lds(const double* __restrict__ Gm, double* __restrict__ Gi, int R, DevStats* stats,
+                         double* lds) {
   constexpr double eps = 2.220446049250313e-16;
-  extern __shared__ double lds_d[];
   const int pitch = R + 1;
-  double* A = lds_d;                     // R x pitch
-  double* w = A + (size_t)R * pitch;     // R eigenvalues
-  double* cs = w + R;                    // 2 x 64 rotation (c, s)
-  int* pq = (int*)(cs + 128);            // 2 x 64 pair indices
-  __shared__ int bad, rot;
+  double* A = lds;                     // R x pitch
+  double* w = A + (size_t)R * pitch;   // R eigenvalues
+  double* cs = w + R;                  // 2 x 64 rotation (c, s)
+  int* pq = (int*)(cs + 128);          // 2 x 64 pair indices
+  int* flags = pq + 128;               // bad, rot
+  int& bad = flags[0];
+  int& rot = flags[1];
   const int tid = threadIdx.x;
   const int RR = R * R;
   if (tid == 0) bad = 0;
   __syncthreads();
-  for (int e = tid; e < RR; e += 512) {
+  for (int e = tid; e < RR; e += NT) {
     const int i = e / R, j = e - i * R;
     const double v = Gm[e];
     if (!isfinite(v)) bad = 1;
@@ -794,7 +854,7 @@ __global__ __launch_bounds__(512) void k_pinv(const double* __restrict__ Gm, dou
   }
   __syncthreads();
   if (bad) {
-    for (int e = tid; e < RR; e += 512) Gi[e] = 0.0;
+    for (int e = tid; e < RR; e += NT) Gi[e] = 0.0;
     if (tid == 0) {
       stats->status |= 1;
       stats->pinv_pending = 0;
@@ -830,7 +890,7 @@ __global__ __launch_bounds__(512) void k_pinv(const double* __restrict__ Gm, dou
       }
       __syncthreads();
       // rows p, q of A
-      for (int e = tid; e < npair * R; e += 512) {
+      for (int e = tid; e < npair * R; e += NT) {
         const int k = e / R, j = e - k * R;
         const int p = pq[2 * k], q = pq[2 * k + 1];
         if (p == q) continue;
@@ -841,7 +901,7 @@ __global__ __launch_bounds__(512) void k_pinv(const double* __restrict__ Gm, dou
       }
       __syncthreads();
       // columns p, q of A and of V
-      for (int e = tid; e < npair * R; e += 512) {
+      for (int e = tid; e < npair * R; e += NT) {
         const int k = e / R, i = e - k * R;
         const int p = pq[2 * k], q = pq[2 * k + 1];
         if (p == q) continue;
@@ -867,22 +927,22 @@ __global__ __launch_bounds__(512) void k_pinv(const double* __restrict__ Gm, dou
     __syncthreads();
     if (done) break;
   }
-  for (int i = tid; i < R; i += 512) w[i] = A[i * pitch + i];
+  for (int i = tid; i < R; i += NT) w[i] = A[i * pitch + i];
   __syncthreads();
   double wmax = 0.0;
   for (int i = 0; i < R; ++i) wmax = fmax(wmax, w[i]);
   const double cut = (double)R * eps * wmax;
   __syncthreads();
-  for (int i = tid; i < R; i += 512) w[i] = (w[i] > cut) ? 1.0 / w[i] : 0.0;
+  for (int i = tid; i < R; i += NT) w[i] = (w[i] > cut) ? 1.0 / w[i] : 0.0;
   __syncthreads();
-  for (int e = tid; e < RR; e += 512) {
+  for (int e = tid; e < RR; e += NT) {
     const int i = e / R, j = e - i * R;
     double acc = 0.0;
     for (int k = 0; k < R; ++k) acc += Gi[i * R + k] * w[k] * Gi[j * R + k];
     A[i * pitch + j] = acc;
   }
   __syncthreads();
-  for (int e = tid; e < RR; e += 512) {
+  for (int e = tid; e < RR; e += NT) {
     const int i = e / R, j = e - i * R;
     Gi[e] = A[i * pitch + j];
   }
@@ -892,177 +952,363 @@ __global__ __launch_bounds__(512) void k_pinv(const double* __restrict__ Gm, dou
   }
 }
 
-// One 16-row block of a mode update on the matrix cores (f64 16x16x4):
+// Gamma^dagger when k_inv_blk gave up (stats->pinv_pending; otherwise the
+// kernel returns at once).
+__global__ __launch_bounds__(512) void k_pinv(const double* __restrict__ Gm, double* __restrict__ Gi, int R,
+                                              DevStats* stats) {
+  if (stats->pinv_pending == 0) return;  // uniform
+  extern __shared__ double lds_d[];
+  pinv_lds<512>(Gm, Gi, R, stats, lds_d);
+}
+
+// LDS doubles of k_update's solve phase for padded rank RP: the R x R
+// operand chunk(s) (Ginv, and W in PP, whole when RP <= 64) and four 16 x RP
+// row buffers (M~, new A, dA, reference A).
+__host__ __device__ inline size_t update_solve_lds_doubles(int RP) {
+  const int CH = RP < 64 ? RP : 64;
+  const int nbuf = (RP <= 64) ? 2 : 1;
+  return (size_t)nbuf * RP * (CH + 1) + 4 * 16 * (size_t)(RP + 1);
+}
+
+// One mode update in one launch (Alg. 1 inner body; Alg. 2 with Eq. (7) in
+// PP).  Workgroup b takes the 16-row blocks b, b + G, ... of mode n:
 //   M~ = M (+ A_old W in PP),  A_new = M~ Ginv,
-// then the shadows, dA and this block's partial Gram A^T A, dS = A^T dA,
-// ||A||^2, ||dA||^2, <M~, A_new> and <Gamma, S_part>.  R is padded to RP, a
-// multiple of 16, with zeros; the R x R operand (W, Ginv, Gamma) is staged in
-// LDS in column chunks of at most 64.  Wave w handles column blocks
-// w, w + 4, ... of each chunk.
-template <typename T>
-__global__ __launch_bounds__(256) void k_solve(SolveArgs<T> a) {
+// the shadows, dA (A_new - A_old, or A_new - A_p in PP), ||A||^2, ||dA||^2
+// and <M~, A_new> over its rows, and its partial Gram A^T A (and dS = A^T dA)
+// accumulated on the f64 matrix cores across its row blocks.  The last
+// workgroup to finish (a ticket counter, which it resets) sums the partials
+// in workgroup order into S^(n), dS^(n) and the norms, forms the residual
+// of Eq. (3) after the last mode (with <Gamma^(n), S^(n)>), writes Gamma and
+// W of the next mode nx = (n + 1) mod N, and, when inv_next is set, inverts
+// Gamma^(nx) into Ginv in place (gj_inverse_lds; the Jacobi
+// pseudo-inverse when a pivot is too small), so that the next mode needs no
+// separate inverse.  All workgroups read Ginv, W and Gamma before taking
+// their ticket, so the last one may overwrite them.
+template <typename T, int RP, bool PP>
+__global__ __launch_bounds__(256) void k_update(UpdateArgs<T> a) {
+  constexpr int CH = RP < 64 ? RP : 64, NCH = RP / CH;
+  constexpr int PG = CH + 1, PM = RP + 1, NB = RP / 16;
+  constexpr int NGW = (NB * NB + 3) / 4;  // Gram blocks per wave
+  // Gram accumulators live in registers across row blocks, except where
+  // they would not fit (RP = 128 with dS)
+  constexpr bool kGramInRegs = !(RP == 128 && PP);
   extern __shared__ double lds[];
   __shared__ double sh[256];
+  __shared__ double xb[64];
+  __shared__ int flag;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int l16 = lane & 15, lg = lane >> 4;
-  const int R = a.R, RP = (R + 15) & ~15, CH = RP < 64 ? RP : 64;
-  const int PG = CH + 1, PM = RP + 1;
-  double* Gs = lds;              // RP x CH chunk of an R x R operand, pitch PG
-  double* Mt = Gs + RP * PG;     // 16 x RP, pitch PM
-  double* An = Mt + 16 * PM;     // 16 x RP
-  double* dAn = An + 16 * PM;    // 16 x RP
-  const int64_t r0 = (int64_t)blockIdx.x * 16;
-  const int rows = (int)((a.s - r0) < 16 ? (a.s - r0) : 16);
-  for (int e = tid; e < 16 * RP; e += 256) {
-    const int r = e / RP, c = e - r * RP;
-    const bool in = r < rows && c < R;
-    Mt[r * PM + c] = in ? a.M[(r0 + r) * R + c] : 0.0;
-    An[r * PM + c] = (in && a.pp) ? a.A[(r0 + r) * R + c] : 0.0;
-  }
-  auto stage = [&](const double* src, int c0) {
-    for (int e = tid; e < RP * CH; e += 256) {
-      const int k = e / CH, c = e - k * CH;
-      Gs[k * PG + c] = (k < R && c0 + c < R) ? src[k * R + c0 + c] : 0.0;
+  const int R = a.R;
+  constexpr bool pp = PP;
+  double* Gi = lds;                                // RP x PG: Ginv (chunk)
+  double* Gw = (NCH == 1) ? Gi + RP * PG : Gi;     // RP x PG: W (PP)
+  double* Mt = Gi + (NCH == 1 ? 2 : 1) * RP * PG;  // 16 x PM
+  double* An = Mt + 16 * PM;
+  double* dAn = An + 16 * PM;
+  double* Ao = dAn + 16 * PM;
+  auto stage = [&](double* dst, const double* src, int c0) {
+    constexpr int PER = RP * CH / 256;
+    double v[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = tid + 256 * q, k = e / CH, c = e - k * CH;
+      v[q] = (k < R && c0 + c < R) ? src[k * R + c0 + c] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = tid + 256 * q, k = e / CH, c = e - k * CH;
+      dst[k * PG + c] = v[q];
     }
   };
-  // X (16 x RP, pitch PM) times the staged chunk -> 16 x 16 block at column cb
-  auto block_mm = [&](const double* X, int cbl) {
-    Mma<double>::acc_t acc = Mma<double>::zero();
-    for (int ks = 0; ks < RP / 4; ++ks) {
-      const int k = ks * 4 + lg;
-      acc = Mma<double>::mma(X[l16 * PM + k], Gs[k * PG + cbl * 16 + l16], acc);
+  // X (16 x RP, pitch PM) times the staged chunk B -> 16 x 16 block at column block cbl
+  auto block_mm = [&](const double* X, const double* B, int cbl) {
+    constexpr int KU = RP <= 64 ? RP / 4 : 8;  // k-steps unrolled (register pressure at RP = 128)
+    f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 1
+    for (int k0 = 0; k0 < RP / 4; k0 += KU) {
+#pragma unroll
+      for (int ks = k0; ks < k0 + KU; ++ks) {
+        const int k = ks * 4 + lg;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(X[l16 * PM + k], B[k * PG + cbl * 16 + l16], acc, 0, 0, 0);
+      }
     }
     return acc;
   };
-  if (a.pp) {
-    // M~ = M + V^(n), V^(n) = A^(n) W with the current (old) A^(n)  (Eq. (7))
-    for (int c0 = 0; c0 < RP; c0 += CH) {
-      stage(a.W, c0);
-      __syncthreads();
-      for (int cbl = wave; cbl < CH / 16; cbl += 4) {
-        const Mma<double>::acc_t acc = block_mm(An, cbl);
+  if (NCH == 1) {
+    stage(Gi, a.Ginv, 0);
+    if (pp) stage(Gw, a.W, 0);
+  }
+  f64x4 accS[kGramInRegs ? NGW : 1], accD[kGramInRegs ? NGW : 1];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) Mt[(lg + 4 * v) * PM + c0 + cbl * 16 + l16] += acc[v];
-      }
-      __syncthreads();
-    }
+  for (int t = 0; t < (kGramInRegs ? NGW : 1); ++t) {
+    accS[t] = f64x4{0.0, 0.0, 0.0, 0.0};
+    accD[t] = f64x4{0.0, 0.0, 0.0, 0.0};
   }
   double nA2 = 0.0, nd2 = 0.0, ma = 0.0;
-  for (int c0 = 0; c0 < RP; c0 += CH) {
-    stage(a.Ginv, c0);
-    __syncthreads();
-    for (int cbl = wave; cbl < CH / 16; cbl += 4) {
-      const Mma<double>::acc_t acc = block_mm(Mt, cbl);
+  for (int rb = blockIdx.x; rb < a.nrb; rb += gridDim.x) {
+    const int64_t r0 = (int64_t)rb * 16;
+    const int rows = (int)((a.s - r0) < 16 ? (a.s - r0) : 16);
+    {
+      constexpr int PR = RP / 16;
+      double m[PR], an[PR], ao[PR];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int r = lg + 4 * v, c = c0 + cbl * 16 + l16;
-        double val = 0.0, d = 0.0;
-        if (r < rows && c < R) {
-          val = acc[v];
-          const int64_t gi = (r0 + r) * R + c;
-          if (a.pp) {
-            d = val - a.Ap[gi];
-            a.dAsh[gi] = (T)d;
-          } else {
-            d = val - a.A[gi];
-          }
-          a.A[gi] = val;
-          a.Ash[gi] = (T)val;
-          nA2 += val * val;
-          nd2 += d * d;
-          ma += Mt[r * PM + c] * val;
-        }
-        An[r * PM + c] = val;
-        dAn[r * PM + c] = d;
+      for (int q = 0; q < PR; ++q) {
+        const int e = tid + 256 * q, r = e / RP, c = e - r * RP;
+        const bool in = r < rows && c < R;
+        const int64_t gi = (r0 + r) * R + c;
+        m[q] = in ? a.M[gi] : 0.0;
+        an[q] = in ? a.A[gi] : 0.0;
+        ao[q] = (in && pp) ? a.Ap[gi] : an[q];
+      }
+#pragma unroll
+      for (int q = 0; q < PR; ++q) {
+        const int e = tid + 256 * q, r = e / RP, c = e - r * RP;
+        Mt[r * PM + c] = m[q];
+        An[r * PM + c] = an[q];
+        Ao[r * PM + c] = ao[q];
       }
     }
     __syncthreads();
-  }
-  // partial Gram (and dS) over this block's rows, with <Gamma, S_part>
-  const int ncb = RP / 16;
-  double* pS = a.partS + (int64_t)blockIdx.x * R * R;
-  double* pdS = a.pp ? a.partdS + (int64_t)blockIdx.x * R * R : nullptr;
-  double gs = 0.0;
-  for (int c0 = 0; c0 < RP; c0 += CH) {
-    stage(a.Gamma, c0);
-    __syncthreads();
-    const int nbl = CH / 16;
-    for (int blk = wave; blk < ncb * nbl; blk += 4) {
-      const int ab = blk / nbl, bbl = blk - ab * nbl;
-      const int bcol = c0 + bbl * 16 + l16;
-      Mma<double>::acc_t s = Mma<double>::zero(), ds = Mma<double>::zero();
+    if (pp) {
+      // M~ = M + V^(n), V^(n) = A^(n) W with the current (old) A^(n)  (Eq. (7))
+      for (int c0 = 0; c0 < RP; c0 += CH) {
+        if (NCH > 1) {
+          stage(Gw, a.W, c0);
+          __syncthreads();
+        }
+        for (int cbl = wave; cbl < CH / 16; cbl += 4) {
+          const f64x4 acc = block_mm(An, Gw, cbl);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) Mt[(lg + 4 * v) * PM + c0 + cbl * 16 + l16] += acc[v];
+        }
+        __syncthreads();
+      }
+    }
+    for (int c0 = 0; c0 < RP; c0 += CH) {
+      if (NCH > 1) {
+        stage(Gi, a.Ginv, c0);
+        __syncthreads();
+      }
+      for (int cbl = wave; cbl < CH / 16; cbl += 4) {
+        const f64x4 acc = block_mm(Mt, Gi, cbl);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = lg + 4 * v, c = c0 + cbl * 16 + l16;
+          double val = 0.0, d = 0.0;
+          if (r < rows && c < R) {
+            val = acc[v];
+            d = val - Ao[r * PM + c];
+            const int64_t gi = (r0 + r) * R + c;
+            a.A[gi] = val;
+            a.Ash[gi] = (T)val;
+            if (pp) a.dAsh[gi] = (T)d;
+            nA2 += val * val;
+            nd2 += d * d;
+            ma += Mt[r * PM + c] * val;
+          }
+          An[r * PM + c] = val;
+          dAn[r * PM + c] = d;
+        }
+      }
+      __syncthreads();
+    }
+    // partial Gram (and dS) of these rows
+    auto gram_block = [&](int ab, int bb, f64x4& sacc, f64x4& dacc) {
 #pragma unroll
       for (int ks = 0; ks < 4; ++ks) {
         const int r = ks * 4 + lg;
         const double x = An[r * PM + ab * 16 + l16];
-        s = Mma<double>::mma(x, An[r * PM + bcol], s);
-        if (a.pp) ds = Mma<double>::mma(x, dAn[r * PM + bcol], ds);
+        sacc = __builtin_amdgcn_mfma_f64_16x16x4f64(x, An[r * PM + bb * 16 + l16], sacc, 0, 0, 0);
+        if (pp) dacc = __builtin_amdgcn_mfma_f64_16x16x4f64(x, dAn[r * PM + bb * 16 + l16], dacc, 0, 0, 0);
       }
+    };
+    if constexpr (kGramInRegs) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int ar = ab * 16 + lg + 4 * v;
-        if (ar < R && bcol < R) {
-          pS[ar * R + bcol] = s[v];
-          if (a.pp) pdS[ar * R + bcol] = ds[v];
-          gs += Gs[ar * PG + bbl * 16 + l16] * s[v];
+      for (int t = 0; t < NGW; ++t) {
+        const int blk = wave + 4 * t;
+        if (blk < NB * NB) gram_block(blk / NB, blk % NB, accS[t], accD[t]);
+      }
+    } else {
+      // too many accumulators to keep: add into this workgroup's partials
+      const bool first = rb == (int)blockIdx.x;
+#pragma unroll 1
+      for (int t = 0; t < NGW; ++t) {
+        const int blk = wave + 4 * t;
+        if (blk < NB * NB) {
+          const int ab = blk / NB, bb = blk - ab * NB;
+          f64x4 sacc = {0.0, 0.0, 0.0, 0.0}, dacc = {0.0, 0.0, 0.0, 0.0};
+          gram_block(ab, bb, sacc, dacc);
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int ar = ab * 16 + lg + 4 * v, bc = bb * 16 + l16;
+            if (ar < R && bc < R) {
+              const int64_t idx = (int64_t)blockIdx.x * R * R + ar * R + bc;
+              a.partS[idx] = first ? sacc[v] : a.partS[idx] + sacc[v];
+              if (pp) a.partdS[idx] = first ? dacc[v] : a.partdS[idx] + dacc[v];
+            }
+          }
         }
       }
     }
     __syncthreads();
   }
-  const double t0 = block_sum(nA2, sh);
-  const double t1 = block_sum(nd2, sh);
-  const double t2 = block_sum(ma, sh);
-  const double t3 = block_sum(gs, sh);
+  const int RR = R * R;
+  if constexpr (kGramInRegs) {
+    double* pS = a.partS + (int64_t)blockIdx.x * RR;
+    double* pdS = a.partdS + (int64_t)blockIdx.x * RR;
+#pragma unroll
+    for (int t = 0; t < NGW; ++t) {
+      const int blk = wave + 4 * t;
+      if (blk < NB * NB) {
+        const int ab = blk / NB, bb = blk - ab * NB;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int ar = ab * 16 + lg + 4 * v, bc = bb * 16 + l16;
+          if (ar < R && bc < R) {
+            pS[ar * R + bc] = accS[t][v];
+            if (pp) pdS[ar * R + bc] = accD[t][v];
+          }
+        }
+      }
+    }
+  }
+  {
+    double v3[3] = {nA2, nd2, ma};
+    block_sums<3>(v3, sh);
+    if (tid == 0) {
+      a.partSc[blockIdx.x * 4 + 0] = v3[0];
+      a.partSc[blockIdx.x * 4 + 1] = v3[1];
+      a.partSc[blockIdx.x * 4 + 2] = v3[2];
+    }
+  }
+  // ticket: the last workgroup to arrive does the reductions
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) flag = (atomicAdd(a.ticket, 1u) == gridDim.x - 1) ? 1 : 0;
+  __syncthreads();
+  if (!flag) return;  // uniform
+  __threadfence();
+  if (tid == 0) atomicExch(a.ticket, 0u);
+  const int n = a.n, N = a.N, nx = (n + 1) % N, G = gridDim.x;
+  constexpr int P = RP + 1;
+  double* Aj = lds;  // RP x P: Gamma^(nx) for the inverse (solve buffers are done)
+  // (1) S^(n) (and dS^(n)) = the partials summed in workgroup order; thread
+  // t owns entries t + 256 j.  Batches of entries with every partial load in
+  // flight: the sums are a chain of round trips to the shared cache.
+  constexpr int EB = PP ? 4 : 8;
+  double gsum = 0.0;
+  for (int j0 = 0; j0 * 256 < RR; j0 += EB) {
+    double sv[EB], dv[EB], gm[EB];
+#pragma unroll
+    for (int u = 0; u < EB; ++u) {
+      const int e = tid + 256 * (j0 + u);
+      sv[u] = 0.0;
+      dv[u] = 0.0;
+      gm[u] = (e < RR) ? a.Gamma[e] : 0.0;
+    }
+    for (int b0 = 0; b0 < G; b0 += 8) {
+      double pv[8][EB], pd[8][EB];
+#pragma unroll
+      for (int bb = 0; bb < 8; ++bb)
+#pragma unroll
+        for (int u = 0; u < EB; ++u) {
+          const int e = tid + 256 * (j0 + u);
+          const bool in = (b0 + bb < G) && e < RR;
+          pv[bb][u] = in ? a.partS[(int64_t)(b0 + bb) * RR + e] : 0.0;
+          pd[bb][u] = (in && pp) ? a.partdS[(int64_t)(b0 + bb) * RR + e] : 0.0;
+        }
+#pragma unroll
+      for (int bb = 0; bb < 8; ++bb)
+#pragma unroll
+        for (int u = 0; u < EB; ++u) {
+          sv[u] += pv[bb][u];
+          if (pp) dv[u] += pd[bb][u];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < EB; ++u) {
+      const int e = tid + 256 * (j0 + u);
+      if (e < RR) {
+        a.S[n][e] = sv[u];
+        if (pp) a.dS[n][e] = dv[u];
+        gsum += gm[u] * sv[u];
+      }
+    }
+  }
+  // (2) entries of Gamma^(nx) (Eq. (1)) and, in PP, W^(nx) (the bracket of
+  // Eq. (7)) from the Gram matrices, S^(n) and dS^(n) as just written by
+  // this thread; W is only read by PP updates, which follow a PP
+  // initialization (W = 0) or another PP update.
+  double dmax = 0.0;
+  for (int j0 = 0; j0 * 256 < RR; j0 += EB) {
+    double sm[kMaxOrder][EB], dm[kMaxOrder][EB];
+#pragma unroll
+    for (int m = 0; m < kMaxOrder; ++m)
+#pragma unroll
+      for (int u = 0; u < EB; ++u) {
+        const int e = tid + 256 * (j0 + u);
+        const bool in = m < N && m != nx && e < RR;
+        sm[m][u] = in ? a.S[m][e] : 1.0;
+        dm[m][u] = (in && pp) ? a.dS[m][e] : 0.0;
+      }
+#pragma unroll
+    for (int u = 0; u < EB; ++u) {
+      const int e = tid + 256 * (j0 + u);
+      if (e >= RR) continue;
+      double v = 1.0, f0 = 1.0, f1 = 0.0, f2 = 0.0;
+#pragma unroll
+      for (int m = 0; m < kMaxOrder; ++m) {
+        v *= sm[m][u];
+        if (pp) {
+          f2 = f2 * sm[m][u] + f1 * dm[m][u];
+          f1 = f1 * sm[m][u] + f0 * dm[m][u];
+          f0 = f0 * sm[m][u];
+        }
+      }
+      a.Gamma[e] = v;
+      if (pp) a.W[e] = f2;
+      if (a.inv_next) {
+        const int i = e / R, j = e - i * R;
+        Aj[i * P + j] = v;
+        if (i == j) dmax = fmax(dmax, v);
+      }
+    }
+  }
+  double v4[4] = {0.0, 0.0, 0.0, gsum};
+  for (int b = tid; b < G; b += 256) {
+    v4[0] += a.partSc[b * 4 + 0];
+    v4[1] += a.partSc[b * 4 + 1];
+    v4[2] += a.partSc[b * 4 + 2];
+  }
+  block_sums<4>(v4, sh);
   if (tid == 0) {
-    a.partSc[blockIdx.x * 4 + 0] = t0;
-    a.partSc[blockIdx.x * 4 + 1] = t1;
-    a.partSc[blockIdx.x * 4 + 2] = t2;
-    a.partSc[blockIdx.x * 4 + 3] = t3;
-  }
-}
-
-// S^(n) (and dS^(n)) = sum of the block partials in block order, one thread
-// per entry, which then forms entry e of Gamma and W of the next mode;
-// block 0 also sums the scalars and, after the last mode, forms the
-// residual of Eq. (3).
-__global__ __launch_bounds__(256) void k_finalize(FinalArgs a) {
-  const int RR = a.R * a.R;
-  const int e = blockIdx.x * 256 + threadIdx.x;
-  if (e < RR) {
-    double sv = 0.0, ds = 0.0;
-#pragma unroll 8
-    for (int b = 0; b < a.nblk; ++b) sv += a.partS[(int64_t)b * RR + e];
-    if (a.pp) {
-#pragma unroll 8
-      for (int b = 0; b < a.nblk; ++b) ds += a.partdS[(int64_t)b * RR + e];
-    }
-    a.S[a.n][e] = sv;
-    if (a.pp) a.dS[a.n][e] = ds;
-    const int nx = (a.n + 1) % a.N;
-    double g, w;
-    gamma_entry(a.S, a.dS, a.N, nx, e, true, &g, &w);
-    a.Gamma[e] = g;
-    a.W[e] = w;
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    double nA2 = 0.0, nd2 = 0.0, ma = 0.0, gs = 0.0;
-    for (int b = 0; b < a.nblk; ++b) {
-      nA2 += a.partSc[b * 4 + 0];
-      nd2 += a.partSc[b * 4 + 1];
-      ma += a.partSc[b * 4 + 2];
-      gs += a.partSc[b * 4 + 3];
-    }
-    a.stats->normA2[a.n] = nA2;
-    a.stats->normdA2[a.n] = nd2;
+    a.stats->normA2[n] = v4[0];
+    a.stats->normdA2[n] = v4[1];
     if (a.last) {
-      const double t2 = a.stats->normT2;
-      const double num = t2 + gs - 2.0 * ma;
+      const double tn = a.stats->normT2;
+      const double num = tn + v4[3] - 2.0 * v4[2];
       a.stats->fit_num = num;
-      const double r = sqrt((num > 0.0 ? num : 0.0) / t2);
+      const double r = sqrt((num > 0.0 ? num : 0.0) / tn);
       a.stats->r = r;
       if (!isfinite(r)) a.stats->status |= 2;
     }
+  }
+  if (!a.inv_next) return;  // uniform
+  for (int e = tid; e < RP * RP; e += 256) {
+    const int i = e / RP, j = e - i * RP;
+    if (i >= R || j >= R) Aj[i * P + j] = (i == j) ? 1.0 : 0.0;
+  }
+  const double tol = block_max(dmax, sh) * (double)R * 2.220446049250313e-16;
+  if (gj_inverse_lds<RP>(Aj, tol, xb, &flag)) {
+    for (int e = tid; e < RR; e += 256) {
+      const int i = e / R, j = e - i * R;
+      a.Ginv[e] = Aj[i * P + j];
+    }
+  } else {
+    // Gamma^(nx) as written above (this workgroup's own stores)
+    __threadfence_block();
+    __syncthreads();
+    pinv_lds<256>(a.Gamma, a.Ginv, R, a.stats, lds);
   }
 }
 
@@ -1250,7 +1496,9 @@ hipError_t launch_ttm_rb_ncb(const T* X, const T* B, T* C, int64_t P, int64_t K,
                              hipStream_t st) {
   if (R <= 16) return launch_ttm_rb<T, KC, 1>(X, B, C, P, K, Q, R, st);
   if (R <= 32) return launch_ttm_rb<T, KC, 2>(X, B, C, P, K, Q, R, st);
-  if (R <= 64) return launch_ttm_rb<T, KC, 4>(X, B, C, P, K, Q, R, st);
+  // eight column blocks of an FP64 factor with K > 128 exceed the LDS: two
+  // passes of four instead
+  if (R <= 64 || (sizeof(T) == 8 && K > 128)) return launch_ttm_rb<T, KC, 4>(X, B, C, P, K, Q, R, st);
   return launch_ttm_rb<T, KC, 8>(X, B, C, P, K, Q, R, st);
 }
 
@@ -1372,29 +1620,48 @@ hipError_t launch_inverse(const double* Gamma, double* Ginv, int R, DevStats* st
     if (e != hipSuccess) return e;
     attr = true;
   }
-  const size_t lds = ((size_t)R * (R + 1) + R + 128) * sizeof(double) + 128 * sizeof(int);
+  const size_t lds = pinv_lds_doubles(R) * sizeof(double);
   hipLaunchKernelGGL(k_pinv, dim3(1), dim3(512), lds, st, Gamma, Ginv, R, stats);
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_solve(const SolveArgs<T>& a, int nblk, hipStream_t st) {
+template <typename T, int RP, bool PP>
+hipError_t launch_update_rp(const UpdateArgs<T>& a, int groups, hipStream_t st) {
   static bool attr = false;
   if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_solve<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       150 * 1024);
+    hipError_t e = hipFuncSetAttribute((const void*)k_update<T, RP, PP>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
     if (e != hipSuccess) return e;
     attr = true;
   }
-  const int RP = (a.R + 15) & ~15, CH = RP < 64 ? RP : 64;
-  const size_t lds = ((size_t)RP * (CH + 1) + 3 * 16 * (size_t)(RP + 1)) * sizeof(double);
-  hipLaunchKernelGGL((k_solve<T>), dim3(nblk), dim3(256), lds, st, a);
+  size_t dbl = update_solve_lds_doubles(RP);
+  if (a.inv_next) {
+    const size_t gj = (size_t)RP * (RP + 1), pv = pinv_lds_doubles(a.R);
+    dbl = std::max(dbl, std::max(gj, pv));
+  }
+  hipLaunchKernelGGL((k_update<T, RP, PP>), dim3(groups), dim3(256), dbl * sizeof(double), st, a);
   return hipGetLastError();
 }
 
-hipError_t launch_finalize(const FinalArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(k_finalize, dim3(nblocks((int64_t)a.R * a.R)), dim3(256), 0, st, a);
-  return hipGetLastError();
+template <typename T, bool PP>
+hipError_t launch_update_pp(const UpdateArgs<T>& a, int groups, hipStream_t st) {
+  if (a.R <= 16) return launch_update_rp<T, 16, PP>(a, groups, st);
+  if (a.R <= 32) return launch_update_rp<T, 32, PP>(a, groups, st);
+  if (a.R <= 64) return launch_update_rp<T, 64, PP>(a, groups, st);
+  return launch_update_rp<T, 128, PP>(a, groups, st);
+}
+
+int update_groups(int64_t s, int R, bool pp) {
+  const int64_t nrb = (s + 15) / 16;
+  // the last workgroup reads every partial Gram: keep them to about 1 MiB
+  const int64_t cap = std::max<int64_t>(1, (int64_t)(1 << 20) / ((int64_t)R * R * 8 * (pp ? 2 : 1)));
+  return (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(nrb, cap), 256));
+}
+
+template <typename T>
+hipError_t launch_update(const UpdateArgs<T>& a, int groups, hipStream_t st) {
+  if (a.R < 1 || a.R > kMaxRank || groups < 1) return hipErrorInvalidValue;
+  return a.pp ? launch_update_pp<T, true>(a, groups, st) : launch_update_pp<T, false>(a, groups, st);
 }
 
 template <typename T>
@@ -1420,8 +1687,8 @@ template hipError_t launch_norm2<float>(const float*, int64_t, double*, int, Dev
 template hipError_t launch_norm2<bf16>(const bf16*, int64_t, double*, int, DevStats*, hipStream_t);
 template hipError_t launch_norm2<double>(const double*, int64_t, double*, int, DevStats*,
                                          hipStream_t);
-template hipError_t launch_solve<float>(const SolveArgs<float>&, int, hipStream_t);
-template hipError_t launch_solve<double>(const SolveArgs<double>&, int, hipStream_t);
+template hipError_t launch_update<float>(const UpdateArgs<float>&, int, hipStream_t);
+template hipError_t launch_update<double>(const UpdateArgs<double>&, int, hipStream_t);
 template hipError_t launch_pp_mttkrp<float>(const PPArgs<float>&, hipStream_t);
 template hipError_t launch_pp_mttkrp<double>(const PPArgs<double>&, hipStream_t);
 

@@ -124,6 +124,12 @@ WORKLOADS = {
                          dtype=np.float32),
     "o3_small_f64": dict(dims=(37, 45, 29), R=12, seed=1002, kind="uniform", noise_rel=1e-3,
                          dtype=np.float64),
+    # rank above 64 (the R x R operands split into two 64-column chunks) and a
+    # long mode (several 16-row blocks per workgroup of a mode update)
+    "o3_r80_f64": dict(dims=(200, 40, 36), R=80, seed=1003, kind="normal", noise_rel=1e-3,
+                       dtype=np.float64),
+    "o3_r40_long_f64": dict(dims=(1400, 12, 10), R=40, seed=1004, kind="normal", noise_rel=1e-3,
+                            dtype=np.float64),
 }
 
 

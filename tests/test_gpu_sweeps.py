@@ -30,6 +30,8 @@ def _plan(w, prec, tree, dev):
 SWEEP_CASES = [
     ("o3_small_f64", "f64", 1e-10, 1e-9),
     ("o4_small_f32", "f32", 1e-6, 1e-4),
+    ("o3_r80_f64", "f64", 1e-10, 1e-9),
+    ("o3_r40_long_f64", "f64", 1e-10, 1e-9),
 ]
 
 
@@ -111,16 +113,17 @@ def test_determinism_bitwise(dev):
 SCHED = ["exact"] * 3 + ["init"] + ["approx"] * 4 + ["exact", "init", "approx"]
 
 
+@pytest.mark.parametrize("name", ["o3_small_f64", "o3_r80_f64", "o3_r40_long_f64"])
 @pytest.mark.parametrize("tree", ["dt", "msdt"])
-def test_pp_forced_schedule_fp64_free_running(dev, tree):
+def test_pp_forced_schedule_fp64_free_running(dev, tree, name):
     """FP64: replay exact x3 -> init -> approx x4 -> exact -> init -> approx on
     both sides from the same init; fitness after every step and the final
     factors agree to FP64 rounding."""
     from oracle import pp
     from paper_2010_12056_amd import synth
 
-    say(f"case pp forced o3_small_f64 {tree}")
-    w = synth.workload("o3_small_f64")
+    say(f"case pp forced {name} {tree}")
+    w = synth.workload(name)
     plan, T, A = _plan(w, "f64", tree, dev)
     st = pp.PPState.start(w.T.astype(np.float64), w.init)
     for step, kind in enumerate(SCHED):
@@ -205,6 +208,36 @@ def test_singular_gamma_uses_pseudo_inverse(dev):
             assert relerr(A[n].cpu().numpy(), st.A[n]) <= 1e-9, (sweep, n)
         assert np.all(A[1].cpu().numpy()[:, 3] == 0.0)
     plan.close()
+
+
+def test_singular_gamma_every_update(dev):
+    """A zero column in the last factor: Gamma^(0) and Gamma^(1) are singular
+    at the first sweep, the pseudo-inverse update keeps the column of every
+    factor at zero, so every later Gamma^(n) is singular too.  Covers the
+    pseudo-inverse both on the second stream and inside the update that
+    inverts the next mode's Gamma itself."""
+    import oracle
+    from paper_2010_12056_amd import cpals, synth
+
+    say("case singular Gamma every update")
+    w = synth.workload("o3_small_f64")
+    init = [a.copy() for a in w.init]
+    init[2][:, 3] = 0.0
+    for tree in ("dt", "msdt"):
+        plan = cpals.Plan(w.dims, w.R, prec="f64", tree=tree, device=dev)
+        T = torch.from_numpy(w.T).to(dev)
+        plan.set_tensor(T)
+        A = to_dev(init, dev)
+        st = oracle.AlsState.start(w.T.astype(np.float64), init)
+        for sweep in range(3):
+            info = plan.als_sweep(A)
+            r_ref = oracle.als_sweep(st)
+            assert info["pinv_updates"] == 3, (tree, sweep, info)
+            assert abs(info["r"] - r_ref) <= 1e-10, (tree, sweep, info["r"], r_ref)
+            for n in range(3):
+                assert relerr(A[n].cpu().numpy(), st.A[n]) <= 1e-9, (tree, sweep, n)
+                assert np.all(A[n].cpu().numpy()[:, 3] == 0.0), (tree, sweep, n)
+        plan.close()
 
 
 def test_nonfinite_gamma_reports_error(dev):

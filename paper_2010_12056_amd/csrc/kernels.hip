@@ -661,7 +661,7 @@ __global__ __launch_bounds__(256) void k_gamma(GammaArgs a) {
 // which is the in-place scalar elimination grouped by 16 pivots: the pivots
 // met are the same Schur-complement diagonals.  The panels and the trailing
 // update run on the f64 matrix cores.  Returns false (uniformly, A then
-// undefined) when a pivot is at or below tol.  xb: 64 doubles of LDS,
+// undefined) when a pivot is at or below tol.  xb: 144 doubles of LDS,
 // fail: an LDS flag.
 template <int RP>
 __device__ bool gj_inverse_lds(double* A, double tol, double* xb, int* fail) {
@@ -676,8 +676,11 @@ __device__ bool gj_inverse_lds(double* A, double tol, double* xb, int* fail) {
     // (1) D <- D^-1 by wave 0.  Lane (g, l16) keeps D[g + 4q][l16], q < 4, in
     // registers; per pivot s the lanes holding row s and column s publish
     // them in LDS (two alternating buffers, so one wave-level fence per pivot
-    // suffices) and every lane reads the pivot, its row entry and its four
-    // column entries back.
+    // suffices; the other lanes write a dummy slot, so no lane branches) and
+    // every lane reads the pivot, its row entry and its four column entries
+    // back.  1 / pivot: the hardware reciprocal refined by two Newton steps
+    // y <- y + y (1 - p y) (error a few units in the last place; pivots are
+    // positive, far from the exponent limits).
     if (wave == 0) {
       double x[4];
 #pragma unroll
@@ -685,15 +688,15 @@ __device__ bool gj_inverse_lds(double* A, double tol, double* xb, int* fail) {
       bool ok = true;
 #pragma unroll 1
       for (int s = 0; s < 16; ++s) {
-        double* rowb = xb + 32 * (s & 1);
+        double* rowb = xb + 32 * (s & 1);  // [0, 16): row s, [16, 32): column s
         double* colb = rowb + 16;
+        double* dummy = xb + 64;           // 80 slots nobody reads
+        double* rw = (g == (s & 3)) ? rowb + l16 : dummy + lane;
+        double* cw = (l16 == s) ? colb + g : dummy + lane;
         const int qs = s >> 2;
-        const double xs = qs == 0 ? x[0] : qs == 1 ? x[1] : qs == 2 ? x[2] : x[3];
-        if (g == (s & 3)) rowb[l16] = xs;
-        if (l16 == s) {
+        *rw = qs == 0 ? x[0] : qs == 1 ? x[1] : qs == 2 ? x[2] : x[3];
 #pragma unroll
-          for (int q = 0; q < 4; ++q) colb[g + 4 * q] = x[q];
-        }
+        for (int q = 0; q < 4; ++q) cw[4 * q] = x[q];
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -703,7 +706,9 @@ __device__ bool gj_inverse_lds(double* A, double tol, double* xb, int* fail) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) ck[q] = colb[g + 4 * q];
         ok = ok && (piv > tol);  // uniform in the wave; after a failure the rest is discarded
-        const double rinv = 1.0 / piv;
+        double rinv = __builtin_amdgcn_rcp(piv);
+        rinv = fma(rinv, fma(-piv, rinv, 1.0), rinv);
+        rinv = fma(rinv, fma(-piv, rinv, 1.0), rinv);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           if (g + 4 * q == s)
@@ -994,7 +999,7 @@ __global__ __launch_bounds__(256) void k_update(UpdateArgs<T> a) {
   constexpr bool kGramInRegs = !(RP == 128 && PP);
   extern __shared__ double lds[];
   __shared__ double sh[256];
-  __shared__ double xb[64];
+  __shared__ double xb[144];
   __shared__ int flag;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int l16 = lane & 15, lg = lane >> 4;
@@ -1195,42 +1200,52 @@ __global__ __launch_bounds__(256) void k_update(UpdateArgs<T> a) {
   // (1) S^(n) (and dS^(n)) = the partials summed in workgroup order; thread
   // t owns entries t + 256 j.  Batches of entries with every partial load in
   // flight: the sums are a chain of round trips to the shared cache.
+  // Loads are unconditional (indices clamped into range, out-of-range values
+  // masked afterwards) so that a batch issues them all before any wait.
   constexpr int EB = PP ? 4 : 8;
+  double* const Sn = a.S[n];
+  double* const dSn = a.dS[n];
+  const double* __restrict__ const pS = a.partS;
+  const double* __restrict__ const pdS = a.partdS;
   double gsum = 0.0;
   for (int j0 = 0; j0 * 256 < RR; j0 += EB) {
+    int ei[EB];
     double sv[EB], dv[EB], gm[EB];
 #pragma unroll
     for (int u = 0; u < EB; ++u) {
       const int e = tid + 256 * (j0 + u);
+      ei[u] = e < RR ? e : 0;
       sv[u] = 0.0;
       dv[u] = 0.0;
-      gm[u] = (e < RR) ? a.Gamma[e] : 0.0;
+      gm[u] = a.Gamma[ei[u]];
     }
     for (int b0 = 0; b0 < G; b0 += 8) {
       double pv[8][EB], pd[8][EB];
 #pragma unroll
-      for (int bb = 0; bb < 8; ++bb)
+      for (int bb = 0; bb < 8; ++bb) {
+        const int64_t off = (int64_t)(b0 + bb < G ? b0 + bb : G - 1) * RR;
 #pragma unroll
         for (int u = 0; u < EB; ++u) {
-          const int e = tid + 256 * (j0 + u);
-          const bool in = (b0 + bb < G) && e < RR;
-          pv[bb][u] = in ? a.partS[(int64_t)(b0 + bb) * RR + e] : 0.0;
-          pd[bb][u] = (in && pp) ? a.partdS[(int64_t)(b0 + bb) * RR + e] : 0.0;
+          pv[bb][u] = pS[off + ei[u]];
+          if (pp) pd[bb][u] = pdS[off + ei[u]];
         }
+      }
 #pragma unroll
-      for (int bb = 0; bb < 8; ++bb)
+      for (int bb = 0; bb < 8; ++bb) {
+        const bool in = b0 + bb < G;
 #pragma unroll
         for (int u = 0; u < EB; ++u) {
-          sv[u] += pv[bb][u];
-          if (pp) dv[u] += pd[bb][u];
+          sv[u] += in ? pv[bb][u] : 0.0;
+          if (pp) dv[u] += in ? pd[bb][u] : 0.0;
         }
+      }
     }
 #pragma unroll
     for (int u = 0; u < EB; ++u) {
       const int e = tid + 256 * (j0 + u);
       if (e < RR) {
-        a.S[n][e] = sv[u];
-        if (pp) a.dS[n][e] = dv[u];
+        Sn[e] = sv[u];
+        if (pp) dSn[e] = dv[u];
         gsum += gm[u] * sv[u];
       }
     }
@@ -1239,22 +1254,33 @@ __global__ __launch_bounds__(256) void k_update(UpdateArgs<T> a) {
   // Eq. (7)) from the Gram matrices, S^(n) and dS^(n) as just written by
   // this thread; W is only read by PP updates, which follow a PP
   // initialization (W = 0) or another PP update.
+  const double* Sm[kMaxOrder];
+  const double* dSm[kMaxOrder];
+#pragma unroll
+  for (int m = 0; m < kMaxOrder; ++m) {
+    const bool use = m < N && m != nx;
+    Sm[m] = use ? a.S[m] : nullptr;
+    dSm[m] = use ? a.dS[m] : nullptr;
+  }
   double dmax = 0.0;
   for (int j0 = 0; j0 * 256 < RR; j0 += EB) {
+    int ei[EB];
+#pragma unroll
+    for (int u = 0; u < EB; ++u) {
+      const int e = tid + 256 * (j0 + u);
+      ei[u] = e < RR ? e : 0;
+    }
     double sm[kMaxOrder][EB], dm[kMaxOrder][EB];
 #pragma unroll
     for (int m = 0; m < kMaxOrder; ++m)
 #pragma unroll
       for (int u = 0; u < EB; ++u) {
-        const int e = tid + 256 * (j0 + u);
-        const bool in = m < N && m != nx && e < RR;
-        sm[m][u] = in ? a.S[m][e] : 1.0;
-        dm[m][u] = (in && pp) ? a.dS[m][e] : 0.0;
+        sm[m][u] = Sm[m] ? Sm[m][ei[u]] : 1.0;
+        dm[m][u] = (pp && dSm[m]) ? dSm[m][ei[u]] : 0.0;
       }
 #pragma unroll
     for (int u = 0; u < EB; ++u) {
       const int e = tid + 256 * (j0 + u);
-      if (e >= RR) continue;
       double v = 1.0, f0 = 1.0, f1 = 0.0, f2 = 0.0;
 #pragma unroll
       for (int m = 0; m < kMaxOrder; ++m) {
@@ -1265,12 +1291,14 @@ __global__ __launch_bounds__(256) void k_update(UpdateArgs<T> a) {
           f0 = f0 * sm[m][u];
         }
       }
-      a.Gamma[e] = v;
-      if (pp) a.W[e] = f2;
-      if (a.inv_next) {
-        const int i = e / R, j = e - i * R;
-        Aj[i * P + j] = v;
-        if (i == j) dmax = fmax(dmax, v);
+      if (e < RR) {
+        a.Gamma[e] = v;
+        if (pp) a.W[e] = f2;
+        if (a.inv_next) {
+          const int i = e / R, j = e - i * R;
+          Aj[i * P + j] = v;
+          if (i == j) dmax = fmax(dmax, v);
+        }
       }
     }
   }

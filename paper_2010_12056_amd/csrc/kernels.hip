@@ -318,18 +318,22 @@ __global__ __launch_bounds__(512) void k_ttm_kc(const T* __restrict__ X, const T
   };
   const int64_t stride = (int64_t)gridDim.x * kTtmWaves;
   int64_t tile = (int64_t)blockIdx.x * kTtmWaves + wave;
-  VT a[NTS];
-  if (tile < ntiles) load_tile(tile, a);
+  // the next tile's rows are in flight while this one is multiplied.  The
+  // loaded registers are copied at the top of the iteration, before the next
+  // loads are issued, so the products read registers with no load pending
+  // (the wait falls on the copy, for loads issued a whole tile earlier).
+  VT an[NTS];
+  if (tile < ntiles) load_tile(tile, an);
   for (; tile < ntiles; tile += stride) {
     asm volatile("" ::: "memory");  // factor reads stay in the loop
-    // the next tile's rows are in flight while this one is multiplied
-    VT an[NTS];
-    if (tile + stride < ntiles) {
-      load_tile(tile + stride, an);
-    } else {
+    VT a[NTS];
 #pragma unroll
-      for (int s = 0; s < NTS; ++s) an[s] = VT{};
-    }
+    for (int s = 0; s < NTS; ++s) a[s] = an[s];
+    // unconditional (past the last tile it reloads this one, unused): no
+    // branch around the loads; the scheduling barrier keeps them ahead of
+    // the products
+    load_tile(tile + stride < ntiles ? tile + stride : tile, an);
+    __builtin_amdgcn_sched_barrier(0);
     const bool full_tile = (tile + 1) * 16 <= P;
     T* ct = C + tile * 16 * R;
     typename Mma<T>::acc_t acc[NCB];
@@ -360,8 +364,6 @@ __global__ __launch_bounds__(512) void k_ttm_kc(const T* __restrict__ X, const T
           if (tile * 16 + r < P && c < R) ct[r * R + c] = acc[cb][v];
         }
     }
-#pragma unroll
-    for (int s = 0; s < NTS; ++s) a[s] = an[s];
   }
 }
 
@@ -416,8 +418,10 @@ __global__ __launch_bounds__(512) void k_ttm_q(const float* __restrict__ X, cons
   constexpr bool PF = NCB <= 4;
   const int64_t stride = (int64_t)gridDim.x * kTtmWaves;
   int64_t tile = (int64_t)blockIdx.x * kTtmWaves + wave;
-  f32x4 a[8];
-  if (PF && tile < ntiles) load_chunk(tile, 0, a);
+  // as in k_ttm_kc, the prefetched registers are copied before the next
+  // chunk's loads are issued, so the products wait on nothing in flight
+  f32x4 an[8];
+  if (PF && tile < ntiles) load_chunk(tile, 0, an);
   for (; tile < ntiles; tile += stride) {
     asm volatile("" ::: "memory");  // factor reads stay in the loop (see k_ttm_rb)
     const int64_t p = tile / tilesQ;
@@ -430,16 +434,21 @@ __global__ __launch_bounds__(512) void k_ttm_q(const float* __restrict__ X, cons
       for (int cb = 0; cb < NCB; ++cb) acc[u][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
     for (int kc = 0; kc < Kp; kc += 32) {
       // the next chunk (or the next tile's first) is in flight while this one is multiplied
-      f32x4 an[8];
+      f32x4 a[8];
+      if (PF) {
+#pragma unroll
+        for (int s = 0; s < 8; ++s) a[s] = an[s];
+      }
       if (!PF) {
         load_chunk(tile, kc, a);
-      } else if (kc + 32 < Kp) {
-        load_chunk(tile, kc + 32, an);
-      } else if (tile + stride < ntiles) {
-        load_chunk(tile + stride, 0, an);
       } else {
-#pragma unroll
-        for (int s = 0; s < 8; ++s) an[s] = f32x4{0.f, 0.f, 0.f, 0.f};
+        // unconditional (after the last chunk of the last tile it reloads
+        // this tile's first, unused): no branch around the loads, and the
+        // scheduling barrier keeps them ahead of the products
+        const bool more = kc + 32 < Kp;
+        const int64_t tn = more ? tile : (tile + stride < ntiles ? tile + stride : tile);
+        load_chunk(tn, more ? kc + 32 : 0, an);
+        __builtin_amdgcn_sched_barrier(0);
       }
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb) {
@@ -453,10 +462,6 @@ __global__ __launch_bounds__(512) void k_ttm_q(const float* __restrict__ X, cons
           for (int u = 0; u < 4; ++u)
             acc[u][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t][u], bv, acc[u][cb], 0, 0, 0);
         }
-      }
-      if (PF) {
-#pragma unroll
-        for (int s = 0; s < 8; ++s) a[s] = an[s];
       }
     }
 #pragma unroll

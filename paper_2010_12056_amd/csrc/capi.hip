@@ -73,7 +73,7 @@ struct cp_plan_s {
   double* Mp[kMaxOrder] = {};  // PP: M_p^(n), FP64
   void* pair[kMaxOrder][kMaxOrder] = {};  // PP: M_p^(i,j), i < j, axes (s_i, s_j, R)
   double *Gamma = nullptr, *Ginv = nullptr, *W = nullptr, *Mbuf = nullptr;
-  double *partS = nullptr, *partdS = nullptr, *partSc = nullptr, *normParts = nullptr;
+  double *partS = nullptr, *partdS = nullptr, *partSc = nullptr, *partG = nullptr, *normParts = nullptr;
   DevStats* stats = nullptr;
   void* slot_buf[kMaxOrder] = {};
   size_t slot_cap[kMaxOrder] = {};
@@ -208,7 +208,7 @@ void plan_layout(cp_plan p) {
   };
   int64_t smax = 0;
   for (int m = 0; m < N; ++m) smax = std::max(smax, p->dims[m]);
-  p->nblk_max = update_groups(smax, R, false);  // workgroups of a mode update
+  p->nblk_max = update_groups_max(smax, R);  // workgroups of a mode update
   // fixed order of regions; set_workspace replays it
   for (int m = 0; m < N; ++m) take((size_t)p->dims[m] * R * p->esz);      // Ash
   for (int m = 0; m < N; ++m) take((size_t)p->dims[m] * R * p->esz);      // dAsh
@@ -225,6 +225,7 @@ void plan_layout(cp_plan p) {
   take((size_t)p->nblk_max * R * R * 8);         // partS
   take((size_t)p->nblk_max * R * R * 8);         // partdS
   take((size_t)p->nblk_max * 4 * 8);             // partSc
+  take((size_t)(R * R + 31) / 32 * 8);           // partG
   take((size_t)kNormParts * 8);                  // normParts
   take(sizeof(DevStats));                        // stats
   take(16 * sizeof(float));                      // sw_in
@@ -263,6 +264,7 @@ void plan_carve(cp_plan p) {
   p->partS = (double*)next();
   p->partdS = (double*)next();
   p->partSc = (double*)next();
+  p->partG = (double*)next();
   p->normParts = (double*)next();
   p->stats = (DevStats*)next();
   p->sw_in = (float*)next();
@@ -529,6 +531,7 @@ cp_status finish_update_t(cp_plan p, int n, double* A, bool pp) {
   ua.W = p->W;
   ua.stats = p->stats;
   ua.ticket = &p->stats->ticket;
+  ua.partG = p->partG;
   ua.s = p->dims[n];
   ua.nrb = (int)((p->dims[n] + 15) / 16);
   ua.R = R;
@@ -537,7 +540,11 @@ cp_status finish_update_t(cp_plan p, int n, double* A, bool pp) {
   ua.last = (n == p->N - 1) ? 1 : 0;
   ua.pp = pp ? 1 : 0;
   ua.inv_next = inv_next ? 1 : 0;
-  const int groups = std::min(update_groups(p->dims[n], R, pp), p->nblk_max);
+  int groups = 1;
+  bool fused = true;
+  update_shape(p->dims[n], R, pp, &groups, &fused);
+  groups = std::min(groups, p->nblk_max);
+  ua.fused = fused ? 1 : 0;
   HIP_TRY(p, launch_update<TT>(ua, groups, p->st));
   p->ginv_ready = inv_next ? (n + 1) % p->N : -1;
   return CP_OK;

@@ -101,11 +101,19 @@ struct UpdateArgs {
   double* W;          // in (PP): W^(n); out: W^(nx) from the current dS
   DevStats* stats;    // norms, residual, status
   unsigned* ticket;   // arrival counter: 0 at launch, left at 0
+  double* partG;      // split path: [ceil(R * R / 32)] shares of <Gamma^(n), S^(n)>
   int64_t s;          // rows of A^(n)
   int nrb;            // 16-row blocks, ceil(s / 16)
   int R, n, N, last, pp, inv_next;
+  int fused;          // 1: the last workgroup reduces (update_shape); 0: launch_update reduces
 };
-int update_groups(int64_t s, int R, bool pp);
+// Launch shape of a mode update: `groups` workgroups and whether the last of
+// them does the reductions (few, small partials) or a second, parallel
+// kernel does (launch_update then also inverts Gamma^(nx) itself with
+// launch_inverse when inv_next is set).
+void update_shape(int64_t s, int R, bool pp, int* groups, bool* fused);
+// Upper bound of `groups` over all mode sizes up to smax.
+int update_groups_max(int64_t smax, int R);
 template <typename T>
 hipError_t launch_update(const UpdateArgs<T>& a, int groups, hipStream_t st);
 

@@ -1191,6 +1191,7 @@ __global__ __launch_bounds__(256) void k_update(UpdateArgs<T> a) {
       a.partSc[blockIdx.x * 4 + 2] = v3[2];
     }
   }
+  if (!a.fused) return;  // k_update_reduce sums the partials
   // ticket: the last workgroup to arrive does the reductions
   __threadfence();
   __syncthreads();
@@ -1658,6 +1659,103 @@ hipError_t launch_inverse(const double* Gamma, double* Ginv, int R, DevStats* st
   return hipGetLastError();
 }
 
+// The reductions of a mode update when the partials are too many for one
+// workgroup (the split path of k_update): workgroup w takes the 32 entries
+// 32 w .. 32 w + 31 of the R x R matrices; thread (l, i), l = tid / 32, sums
+// the partials l, l + 8, l + 16, ... of entry i and the eight sums are added
+// in l order.  Each entry then gets S^(n), dS^(n), Gamma^(nx) and (PP)
+// W^(nx) as in k_update; the workgroup's share of <Gamma^(n), S^(n)> goes to
+// partG, and the last workgroup to finish (ticket) adds the shares and the
+// norm partials in order and forms the residual of Eq. (3).
+template <typename T, bool PP>
+__global__ __launch_bounds__(256) void k_update_reduce(UpdateArgs<T> a, int G) {
+  __shared__ double ls[8][33], ld[8][33];
+  __shared__ double sh[256];
+  __shared__ int flag;
+  const int tid = threadIdx.x, es = tid & 31, bl = tid >> 5;
+  const int R = a.R, RR = R * R, n = a.n, N = a.N, nx = (n + 1) % N;
+  const int e = blockIdx.x * 32 + es;
+  const int ei = e < RR ? e : 0;
+  double sv = 0.0, dv = 0.0;
+  for (int b0 = bl; b0 < G; b0 += 64) {
+    double pv[8], pd[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int b = b0 + 8 * k < G ? b0 + 8 * k : b0;
+      pv[k] = a.partS[(int64_t)b * RR + ei];
+      pd[k] = PP ? a.partdS[(int64_t)b * RR + ei] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const bool in = b0 + 8 * k < G;
+      sv += in ? pv[k] : 0.0;
+      if (PP) dv += in ? pd[k] : 0.0;
+    }
+  }
+  ls[bl][es] = sv;
+  ld[bl][es] = dv;
+  __syncthreads();
+  double gpart = 0.0;
+  if (bl == 0 && e < RR) {
+    double st = ls[0][es], dt = ld[0][es];
+#pragma unroll
+    for (int q = 1; q < 8; ++q) {
+      st += ls[q][es];
+      dt += ld[q][es];
+    }
+    a.S[n][e] = st;
+    if (PP) a.dS[n][e] = dt;
+    gpart = a.Gamma[e] * st;
+    double v = 1.0, f0 = 1.0, f1 = 0.0, f2 = 0.0;
+#pragma unroll
+    for (int m = 0; m < kMaxOrder; ++m) {
+      if (m >= N || m == nx) continue;
+      const double smv = (m == n) ? st : a.S[m][e];
+      const double dmv = PP ? ((m == n) ? dt : a.dS[m][e]) : 0.0;
+      v *= smv;
+      if (PP) {
+        f2 = f2 * smv + f1 * dmv;
+        f1 = f1 * smv + f0 * dmv;
+        f0 = f0 * smv;
+      }
+    }
+    a.Gamma[e] = v;
+    if (PP) a.W[e] = f2;
+  }
+  {
+    double v1[1] = {gpart};
+    block_sums<1>(v1, sh);
+    if (tid == 0) a.partG[blockIdx.x] = v1[0];
+  }
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) flag = (atomicAdd(a.ticket, 1u) == gridDim.x - 1) ? 1 : 0;
+  __syncthreads();
+  if (!flag) return;  // uniform
+  __threadfence();
+  if (tid == 0) atomicExch(a.ticket, 0u);
+  double v4[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int b = tid; b < G; b += 256) {
+    v4[0] += a.partSc[b * 4 + 0];
+    v4[1] += a.partSc[b * 4 + 1];
+    v4[2] += a.partSc[b * 4 + 2];
+  }
+  for (int b = tid; b < (int)gridDim.x; b += 256) v4[3] += a.partG[b];
+  block_sums<4>(v4, sh);
+  if (tid == 0) {
+    a.stats->normA2[n] = v4[0];
+    a.stats->normdA2[n] = v4[1];
+    if (a.last) {
+      const double tn = a.stats->normT2;
+      const double num = tn + v4[3] - 2.0 * v4[2];
+      a.stats->fit_num = num;
+      const double r = sqrt((num > 0.0 ? num : 0.0) / tn);
+      a.stats->r = r;
+      if (!isfinite(r)) a.stats->status |= 2;
+    }
+  }
+}
+
 template <typename T, int RP, bool PP>
 hipError_t launch_update_rp(const UpdateArgs<T>& a, int groups, hipStream_t st) {
   static bool attr = false;
@@ -1668,7 +1766,7 @@ hipError_t launch_update_rp(const UpdateArgs<T>& a, int groups, hipStream_t st) 
     attr = true;
   }
   size_t dbl = update_solve_lds_doubles(RP);
-  if (a.inv_next) {
+  if (a.inv_next && a.fused) {
     const size_t gj = (size_t)RP * (RP + 1), pv = pinv_lds_doubles(a.R);
     dbl = std::max(dbl, std::max(gj, pv));
   }
@@ -1684,17 +1782,35 @@ hipError_t launch_update_pp(const UpdateArgs<T>& a, int groups, hipStream_t st) 
   return launch_update_rp<T, 128, PP>(a, groups, st);
 }
 
-int update_groups(int64_t s, int R, bool pp) {
-  const int64_t nrb = (s + 15) / 16;
-  // the last workgroup reads every partial Gram: keep them to about 1 MiB
-  const int64_t cap = std::max<int64_t>(1, (int64_t)(1 << 20) / ((int64_t)R * R * 8 * (pp ? 2 : 1)));
-  return (int)std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(nrb, cap), 256));
+// Fused (the last workgroup reduces) while the partials are few and small:
+// at most 16 row blocks and about 1 MiB of partials; otherwise up to 64
+// workgroups, several row blocks each, and k_update_reduce.
+void update_shape(int64_t s, int R, bool pp, int* groups, bool* fused) {
+  const int64_t nrb = std::max<int64_t>(1, (s + 15) / 16);
+  const int64_t bytes = nrb * (int64_t)R * R * 8 * (pp ? 2 : 1);
+  *fused = nrb <= 16 && bytes <= (1 << 20);
+  *groups = (int)std::min<int64_t>(nrb, 64);
+}
+
+int update_groups_max(int64_t smax, int R) {
+  (void)R;
+  return (int)std::max<int64_t>(1, std::min<int64_t>((smax + 15) / 16, 64));
 }
 
 template <typename T>
 hipError_t launch_update(const UpdateArgs<T>& a, int groups, hipStream_t st) {
   if (a.R < 1 || a.R > kMaxRank || groups < 1) return hipErrorInvalidValue;
-  return a.pp ? launch_update_pp<T, true>(a, groups, st) : launch_update_pp<T, false>(a, groups, st);
+  hipError_t e = a.pp ? launch_update_pp<T, true>(a, groups, st) : launch_update_pp<T, false>(a, groups, st);
+  if (e != hipSuccess || a.fused) return e;
+  const unsigned nb = (unsigned)((a.R * a.R + 31) / 32);
+  if (a.pp) {
+    hipLaunchKernelGGL((k_update_reduce<T, true>), dim3(nb), dim3(256), 0, st, a, groups);
+  } else {
+    hipLaunchKernelGGL((k_update_reduce<T, false>), dim3(nb), dim3(256), 0, st, a, groups);
+  }
+  e = hipGetLastError();
+  if (e != hipSuccess || !a.inv_next) return e;
+  return launch_inverse(a.Gamma, a.Ginv, a.R, a.stats, st);
 }
 
 template <typename T>

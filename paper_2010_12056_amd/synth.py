@@ -14,7 +14,8 @@ Recipe (every workload):
   * Noise is iid Gaussian with sigma = rel * ||T0||_F / sqrt(numel), drawn in
     the same row blocks (one standard_normal call per block, in order), so
     that ||E||_F is close to rel * ||T0||_F.
-  * The stored tensor is (T0 + sigma * E) cast to the storage dtype.
+  * The stored tensor is (T0 + sigma * E) cast to the storage dtype; with
+    nonneg=True it is clipped at zero first (non-negative data).
   * Initial factors are iid Uniform[0, 1) (the paper's initialization).
 
 Factor distributions:
@@ -73,7 +74,7 @@ def _outer_rows(factors, rows):
 
 
 def planted_tensor(dims, R, seed, kind="uniform", noise_rel=1e-2, dtype=np.float32,
-                   collinearity=0.9, block_elems=1 << 24, name="custom"):
+                   collinearity=0.9, block_elems=1 << 24, name="custom", nonneg=False):
     dims = tuple(int(d) for d in dims)
     rng_p, rng_e, rng_i = [np.random.default_rng(s) for s in np.random.SeedSequence(seed).spawn(3)]
     planted = _factors(rng_p, dims, R, kind, collinearity)
@@ -99,6 +100,8 @@ def planted_tensor(dims, R, seed, kind="uniform", noise_rel=1e-2, dtype=np.float
         blk = T0[r0:r0 + rows_per_block]
         if sigma > 0:
             blk = blk + sigma * rng_e.standard_normal(blk.shape)
+        if nonneg:
+            blk = np.maximum(blk, 0.0)
         out[r0:r0 + rows_per_block] = blk.astype(dtype)
     del T0
     return Workload(name=name, dims=dims, R=R, T=out.reshape(dims), planted=planted, init=init,
@@ -130,6 +133,24 @@ WORKLOADS = {
                        dtype=np.float64),
     "o3_r40_long_f64": dict(dims=(1400, 12, 10), R=40, seed=1004, kind="normal", noise_rel=1e-3,
                             dtype=np.float64),
+    # Shape-only stand-ins for the paper's real tensors (the data themselves
+    # are not available): the shapes and CP ranks of its experiments, planted
+    # non-negative rank-R factors (Uniform[0, 1)), noise 1e-2, clipped at zero.
+    # The density-fitting tensor is run at R = 128, the largest rank this
+    # implementation supports (the paper uses 300, 600 and 1000).
+    "coil_standin": dict(dims=(128, 128, 3, 7200), R=20, seed=6001, kind="uniform", noise_rel=1e-2,
+                         dtype=np.float32, nonneg=True),
+    "timelapse_standin": dict(dims=(1024, 1344, 33, 9), R=50, seed=6002, kind="uniform",
+                              noise_rel=1e-2, dtype=np.float32, nonneg=True),
+    "chem_standin": dict(dims=(4520, 280, 280), R=128, seed=6003, kind="uniform", noise_rel=1e-2,
+                         dtype=np.float32, nonneg=True),
+    # the same mode-size structure at oracle-sized shapes
+    "coil_small": dict(dims=(32, 32, 3, 450), R=20, seed=6101, kind="uniform", noise_rel=1e-2,
+                       dtype=np.float64, nonneg=True),
+    "timelapse_small": dict(dims=(64, 84, 33, 9), R=50, seed=6102, kind="uniform", noise_rel=1e-2,
+                            dtype=np.float64, nonneg=True),
+    "chem_small": dict(dims=(565, 35, 35), R=64, seed=6103, kind="uniform", noise_rel=1e-2,
+                       dtype=np.float64, nonneg=True),
 }
 
 

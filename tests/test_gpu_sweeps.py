@@ -32,6 +32,10 @@ SWEEP_CASES = [
     ("o4_small_f32", "f32", 1e-6, 1e-4),
     ("o3_r80_f64", "f64", 1e-10, 1e-9),
     ("o3_r40_long_f64", "f64", 1e-10, 1e-9),
+    # the paper's real-tensor shapes (mode sizes 3 and 9 next to long modes), reduced
+    ("coil_small", "f64", 1e-10, 1e-9),
+    ("timelapse_small", "f64", 1e-10, 1e-9),
+    ("chem_small", "f64", 1e-10, 1e-9),
 ]
 
 
@@ -111,14 +115,23 @@ def test_determinism_bitwise(dev):
 
 
 SCHED = ["exact"] * 3 + ["init"] + ["approx"] * 4 + ["exact", "init", "approx"]
+# On the real-tensor shapes the forced approximated sweeps, far from
+# convergence, break the approximation down after the first one (the
+# estimated residual reaches zero) and leave Gamma with condition numbers near
+# 1e10: the oracle's own fitness then moves by 3e-9 when its initial factors
+# are perturbed by 1e-15 (relative).  Their schedule keeps one approximated
+# sweep per PP phase, where the trajectory stays well conditioned.
+SCHED_SHORT = ["exact"] * 3 + ["init", "approx", "exact", "init", "approx"]
 
 
-@pytest.mark.parametrize("name", ["o3_small_f64", "o3_r80_f64", "o3_r40_long_f64"])
+@pytest.mark.parametrize("name,sched", [("o3_small_f64", SCHED), ("o3_r80_f64", SCHED),
+                                        ("o3_r40_long_f64", SCHED), ("coil_small", SCHED_SHORT),
+                                        ("timelapse_small", SCHED_SHORT), ("chem_small", SCHED_SHORT)])
 @pytest.mark.parametrize("tree", ["dt", "msdt"])
-def test_pp_forced_schedule_fp64_free_running(dev, tree, name):
-    """FP64: replay exact x3 -> init -> approx x4 -> exact -> init -> approx on
-    both sides from the same init; fitness after every step and the final
-    factors agree to FP64 rounding."""
+def test_pp_forced_schedule_fp64_free_running(dev, tree, name, sched):
+    """FP64: replay a forced schedule (exact x3 -> init -> approx ... -> exact
+    -> init -> approx) on both sides from the same init; fitness after every
+    step and the final factors agree to FP64 rounding."""
     from oracle import pp
     from paper_2010_12056_amd import synth
 
@@ -126,7 +139,7 @@ def test_pp_forced_schedule_fp64_free_running(dev, tree, name):
     w = synth.workload(name)
     plan, T, A = _plan(w, "f64", tree, dev)
     st = pp.PPState.start(w.T.astype(np.float64), w.init)
-    for step, kind in enumerate(SCHED):
+    for step, kind in enumerate(sched):
         info = plan.pp_sweep(A, mode=kind)
         pp.pp_als_step(st, force=kind)
         assert info["kind"] == kind

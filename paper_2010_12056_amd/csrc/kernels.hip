@@ -367,6 +367,130 @@ __global__ __launch_bounds__(512) void k_ttm_kc(const T* __restrict__ X, const T
   }
 }
 
+// First-level contraction over the last mode (Q == 1) when K is larger than
+// one register tile: the k_ttm_kc layout (a wave owns 16 rows, lane (i, g)
+// loads 16 bytes of row i per 4V-index step) with K in chunks of KP = 8 * 4V
+// indices.  The factor chunk sits transposed in LDS, double-buffered: while
+// chunk c is multiplied out of one buffer, chunk c + 1 is loaded (before the
+// rows' prefetch, so the wait for it does not wait on the rows) and written
+// into the other; one barrier per chunk.  The waves of a workgroup step
+// through the same (tile, chunk) sequence, a wave past the last tile
+// recomputing the last one without storing it.  The rows of the next chunk
+// (or of the next tile's first) are in flight while a chunk is multiplied.
+template <typename T, int NCB>
+__global__ __launch_bounds__(512) void k_ttm_kcx(const T* __restrict__ X, const T* __restrict__ B,
+                                                 T* __restrict__ C, int64_t P, int64_t K, int R,
+                                                 int64_t ntiles, int vec) {
+  constexpr int V = 16 / sizeof(T);
+  constexpr int KT = 4 * V;
+  constexpr int NTS = 8;
+  constexpr int KP = NTS * KT;
+  constexpr int pitch = KP + V;
+  constexpr int NC = NCB * 16;
+  constexpr int BPER = KP * NC / kTtmThreads;  // factor elements per thread and chunk
+  typedef typename Vec16<T>::type VT;
+  __shared__ __align__(16) T Bt[2][NC * pitch];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, l16 = lane & 15;
+  const int c0 = blockIdx.y * NC;
+  const int nch = (int)((K + KP - 1) / KP);
+  auto load_b = [&](int c, T (&bv)[BPER]) {
+#pragma unroll
+    for (int q = 0; q < BPER; ++q) {
+      const int idx = tid + kTtmThreads * q, k = idx / NC, col = idx - k * NC;
+      const int64_t gk = (int64_t)c * KP + k;
+      bv[q] = (gk < K && c0 + col < R) ? B[gk * R + c0 + col] : T(0);
+    }
+  };
+  auto store_b = [&](int buf, const T (&bv)[BPER]) {
+#pragma unroll
+    for (int q = 0; q < BPER; ++q) {
+      const int idx = tid + kTtmThreads * q, k = idx / NC, col = idx - k * NC;
+      Bt[buf][col * pitch + k] = bv[q];
+    }
+  };
+  // rows of tile t, chunk c: this lane's NTS 16-byte pieces (rows past P
+  // clamped, indices past K read as zero)
+  auto load_rows = [&](int64_t t, int c, VT (&a)[NTS]) {
+    int lrow = l16;
+    if ((t + 1) * 16 > P) {
+      const int64_t last = P - 1 - t * 16;
+      lrow = lrow < last ? lrow : (int)last;
+    }
+    const T* xr = X + (t * 16 + lrow) * K + (int64_t)c * KP + g * V;
+#pragma unroll
+    for (int s2 = 0; s2 < NTS; ++s2) {
+      const int64_t k = (int64_t)c * KP + s2 * KT + g * V;
+      if (vec && k + V <= K) {
+        a[s2] = *(const VT*)(xr + s2 * KT);
+      } else {
+#pragma unroll
+        for (int u = 0; u < V; ++u) a[s2][u] = (k + u < K) ? xr[s2 * KT + u] : T(0);
+      }
+    }
+  };
+  const int64_t stride = (int64_t)gridDim.x * kTtmWaves;
+  int64_t tb = (int64_t)blockIdx.x * kTtmWaves;
+  if (tb >= ntiles) return;  // uniform: the whole workgroup
+  {
+    T bv[BPER];
+    load_b(0, bv);
+    store_b(0, bv);
+  }
+  VT an[NTS];
+  load_rows(tb + wave < ntiles ? tb + wave : ntiles - 1, 0, an);
+  __syncthreads();
+  int buf = 0;
+  for (; tb < ntiles; tb += stride) {
+    asm volatile("" ::: "memory");
+    const int64_t tile = tb + wave < ntiles ? tb + wave : ntiles - 1;
+    const bool own = tb + wave < ntiles;
+    const int64_t tnext = tb + stride + wave < ntiles ? tb + stride + wave : (tb + stride < ntiles ? ntiles - 1 : tile);
+    typename Mma<T>::acc_t acc[NCB];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) acc[cb] = Mma<T>::zero();
+    for (int c = 0; c < nch; ++c) {
+      VT a[NTS];
+#pragma unroll
+      for (int s2 = 0; s2 < NTS; ++s2) a[s2] = an[s2];
+      // the factor's next chunk first, then the next rows
+      const bool more = c + 1 < nch;
+      const int cn = more ? c + 1 : 0;
+      T bv[BPER];
+      load_b(cn, bv);
+      load_rows(more ? tile : tnext, cn, an);
+      __builtin_amdgcn_sched_barrier(0);
+      const T* bb = Bt[buf];
+#pragma unroll
+      for (int t = 0; t < NTS; ++t) {
+        VT b[NCB];
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) b[cb] = *(const VT*)(bb + (cb * 16 + l16) * pitch + t * KT + g * V);
+#pragma unroll
+        for (int u = 0; u < V; ++u)
+#pragma unroll
+          for (int cb = 0; cb < NCB; ++cb) acc[cb] = Mma<T>::mma(a[t][u], b[cb][u], acc[cb]);
+      }
+      if (nch > 1 || tb + stride < ntiles) {
+        store_b(buf ^ 1, bv);
+        buf ^= 1;
+      }
+      __syncthreads();
+    }
+    if (own) {
+      T* ct = C + tile * 16 * R;
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = Mma<T>::row(lane, v);
+          const int col = c0 + cb * 16 + l16;
+          if (tile * 16 + r < P && col < R) ct[r * R + col] = acc[cb][v];
+        }
+    }
+  }
+}
+
 // First-level contraction when the contracted mode is not the last one
 // (X[p] is K x Q with q contiguous), FP32, factor resident in LDS (K <= 256).
 // A wave owns 64 consecutive q and 16*NCB rank columns.  Lane (i = lane % 16,
@@ -474,6 +598,133 @@ __global__ __launch_bounds__(512) void k_ttm_q(const float* __restrict__ X, cons
           const int c = c0 + cb * 16 + l16;
           if (q < Q && c < R) Cb[q * R + c] = acc[u][cb][v];
         }
+  }
+}
+
+// First-level contraction over a mode other than the last (the k_ttm_q
+// layout: a wave owns 64 consecutive q, lane (i, g) loads X[k][q0 + 4i ..
+// 4i + 3] for k = kc + 4t + g) when K is too long for the whole factor in
+// LDS: the factor in chunks of 128 indices, double-buffered in LDS with the
+// k_ttm_q permutation inside each 32-index piece; the next chunk is loaded
+// at the first piece of the current one (ahead of the rows' prefetch) and
+// written into the other buffer after its last piece, one barrier per
+// chunk.  Waves of a workgroup step through the same (tile, piece)
+// sequence; a wave past the last tile recomputes it without storing.
+template <int NCB>
+__global__ __launch_bounds__(512) void k_ttm_qx(const float* __restrict__ X, const float* __restrict__ B,
+                                                float* __restrict__ C, int64_t P, int64_t K, int64_t Q,
+                                                int R, int64_t tilesQ, int64_t ntiles, int vec) {
+  constexpr int KCH = 128;
+  constexpr int pitch = KCH + 4;
+  constexpr int NC = NCB * 16;
+  constexpr int BPER = KCH * NC / kTtmThreads;
+  __shared__ __align__(16) float Bt[2][NC * pitch];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, l16 = lane & 15;
+  const int c0 = blockIdx.y * NC;
+  const int nch = (int)((K + KCH - 1) / KCH);
+  auto load_b = [&](int c, float (&bv)[BPER]) {
+#pragma unroll
+    for (int q = 0; q < BPER; ++q) {
+      const int idx = tid + kTtmThreads * q, k = idx / NC, col = idx - k * NC;
+      const int64_t gk = (int64_t)c * KCH + k;
+      bv[q] = (gk < K && c0 + col < R) ? B[gk * R + c0 + col] : 0.f;
+    }
+  };
+  auto store_b = [&](int buf, const float (&bv)[BPER]) {
+#pragma unroll
+    for (int q = 0; q < BPER; ++q) {
+      const int idx = tid + kTtmThreads * q, k = idx / NC, col = idx - k * NC;
+      const int kc = k & ~31, kr = k & 31;
+      Bt[buf][col * pitch + kc + 8 * (kr & 3) + (kr >> 2)] = bv[q];
+    }
+  };
+  auto load_piece = [&](int64_t t, int64_t kc, f32x4 (&a)[8]) {
+    const int64_t p = t / tilesQ;
+    const int64_t qa = (t - p * tilesQ) * 64 + 4 * l16;
+    const bool full = vec && qa + 4 <= Q;
+    const float* Xb = X + p * K * Q;
+#pragma unroll
+    for (int s2 = 0; s2 < 8; ++s2) {
+      const int64_t k = kc + 4 * s2 + g;
+      const float* src = Xb + k * Q + qa;
+      if (k < K && full) {
+        a[s2] = *(const f32x4*)src;
+      } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) a[s2][u] = (k < K && qa + u < Q) ? src[u] : 0.f;
+      }
+    }
+  };
+  const int64_t stride = (int64_t)gridDim.x * kTtmWaves;
+  int64_t tb = (int64_t)blockIdx.x * kTtmWaves;
+  if (tb >= ntiles) return;  // uniform: the whole workgroup
+  {
+    float bv[BPER];
+    load_b(0, bv);
+    store_b(0, bv);
+  }
+  const int npc = (int)((K + 31) / 32);  // 32-index pieces
+  f32x4 an[8];
+  load_piece(tb + wave < ntiles ? tb + wave : ntiles - 1, 0, an);
+  __syncthreads();
+  int buf = 0;
+  for (; tb < ntiles; tb += stride) {
+    asm volatile("" ::: "memory");
+    const int64_t tile = tb + wave < ntiles ? tb + wave : ntiles - 1;
+    const bool own = tb + wave < ntiles;
+    const int64_t tnext = tb + stride + wave < ntiles ? tb + stride + wave : (tb + stride < ntiles ? ntiles - 1 : tile);
+    f32x4 acc[4][NCB];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) acc[u][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int c = 0; c < nch; ++c) {
+      float bv[BPER];
+      const int cn = c + 1 < nch ? c + 1 : 0;
+      const int pend = (c + 1) * 4 < npc ? (c + 1) * 4 : npc;  // pieces of this chunk
+      for (int pc = c * 4; pc < pend; ++pc) {
+        f32x4 a[8];
+#pragma unroll
+        for (int s2 = 0; s2 < 8; ++s2) a[s2] = an[s2];
+        if (pc == c * 4) load_b(cn, bv);
+        const bool more = pc + 1 < npc;
+        load_piece(more ? tile : tnext, more ? (int64_t)(pc + 1) * 32 : 0, an);
+        __builtin_amdgcn_sched_barrier(0);
+        const int kl = (pc - c * 4) * 32;
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+          const float* bp = Bt[buf] + (cb * 16 + l16) * pitch + kl + 8 * g;
+          const f32x4 b0 = *(const f32x4*)bp;
+          const f32x4 b1 = *(const f32x4*)(bp + 4);
+#pragma unroll
+          for (int t = 0; t < 8; ++t) {
+            const float bval = t < 4 ? b0[t & 3] : b1[t & 3];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+              acc[u][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t][u], bval, acc[u][cb], 0, 0, 0);
+          }
+        }
+      }
+      store_b(buf ^ 1, bv);
+      buf ^= 1;
+      __syncthreads();
+    }
+    if (own) {
+      const int64_t p = tile / tilesQ;
+      const int64_t q0 = (tile - p * tilesQ) * 64;
+      float* Cb = C + p * Q * R;
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int64_t q = q0 + 16 * g + 4 * v + u;
+            const int col = c0 + cb * 16 + l16;
+            if (q < Q && col < R) Cb[q * R + col] = acc[u][cb][v];
+          }
+    }
   }
 }
 
@@ -1495,6 +1746,32 @@ hipError_t launch_ttm_kc(const T* X, const T* B, T* C, int64_t P, int64_t K, int
   return hipGetLastError();
 }
 
+template <typename T, int NCB>
+hipError_t launch_ttm_kcx(const T* X, const T* B, T* C, int64_t P, int64_t K, int R, hipStream_t st) {
+  constexpr int V = 16 / sizeof(T);
+  const int64_t ntiles = (P + 15) / 16;
+  const int64_t want = (ntiles + kTtmWaves - 1) / kTtmWaves;
+  const unsigned nx = (unsigned)(want < 256 ? want : 256);
+  const unsigned ny = (unsigned)((R + NCB * 16 - 1) / (NCB * 16));
+  const int vec = (K % V == 0 && ((uintptr_t)X % 16) == 0) ? 1 : 0;
+  hipLaunchKernelGGL((k_ttm_kcx<T, NCB>), dim3(nx, ny), dim3(kTtmThreads), 0, st, X, B, C, P, K, R, ntiles, vec);
+  return hipGetLastError();
+}
+
+template <int NCB>
+hipError_t launch_ttm_qx(const float* X, const float* B, float* C, int64_t P, int64_t K, int64_t Q, int R,
+                         hipStream_t st) {
+  const int64_t tilesQ = (Q + 63) / 64;
+  const int64_t ntiles = P * tilesQ;
+  const int64_t want = (ntiles + kTtmWaves - 1) / kTtmWaves;
+  const unsigned nx = (unsigned)(want < 256 ? want : 256);
+  const unsigned ny = (unsigned)((R + NCB * 16 - 1) / (NCB * 16));
+  const int vec = (Q % 4 == 0 && ((uintptr_t)X % 16) == 0) ? 1 : 0;
+  hipLaunchKernelGGL((k_ttm_qx<NCB>), dim3(nx, ny), dim3(kTtmThreads), 0, st, X, B, C, P, K, Q, R, tilesQ, ntiles,
+                     vec);
+  return hipGetLastError();
+}
+
 template <int NCB>
 hipError_t launch_ttm_q(const float* X, const float* B, float* C, int64_t P, int64_t K, int64_t Q, int R,
                         hipStream_t st) {
@@ -1543,6 +1820,22 @@ hipError_t launch_ttm(const T* X, const T* B, T* C, int64_t P, int64_t K, int64_
     if (R <= 16) return launch_ttm_kc<T, 1>(X, B, C, P, K, R, st);
     if (R <= 32) return launch_ttm_kc<T, 2>(X, B, C, P, K, R, st);
     return launch_ttm_kc<T, 4>(X, B, C, P, K, R, st);
+  }
+  if (Q == 1 && K > 32 * (int64_t)(16 / sizeof(T))) {
+    // chunked factor, any K (f32: chunks of 128, f64: 64)
+    if (R <= 16) return launch_ttm_kcx<T, 1>(X, B, C, P, K, R, st);
+    if (R <= 32) return launch_ttm_kcx<T, 2>(X, B, C, P, K, R, st);
+    if (R <= 64) return launch_ttm_kcx<T, 4>(X, B, C, P, K, R, st);
+    return launch_ttm_kcx<T, 8>(X, B, C, P, K, R, st);
+  }
+  if (sizeof(T) == 4 && Q >= 64 && K > 256) {
+    // FP32, a mode other than the last, factor too long for LDS: chunked
+    const float* Xf = (const float*)X;
+    const float* Bf = (const float*)B;
+    float* Cf = (float*)C;
+    if (R <= 16) return launch_ttm_qx<1>(Xf, Bf, Cf, P, K, Q, R, st);
+    if (R <= 32) return launch_ttm_qx<2>(Xf, Bf, Cf, P, K, Q, R, st);
+    return launch_ttm_qx<4>(Xf, Bf, Cf, P, K, Q, R, st);  // R > 64: 64-column passes
   }
   if (K <= 256) {
     if (Q == 1) return launch_ttm_rb_ncb<T, true>(X, B, C, P, K, Q, R, st);

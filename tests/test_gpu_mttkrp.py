@@ -34,6 +34,17 @@ CASES = [
     ((1, 9, 1), 3, "f64"),
     ((16, 17, 15, 3, 5, 4), 33, "f32"),
     ((64, 64, 64), 128, "f32"),
+    # long contracted last modes: the factor in chunks (ragged last chunk; K not a
+    # multiple of 4 takes the element-wise loads)
+    ((20, 9, 700), 40, "f32"),
+    ((20, 9, 701), 20, "f32"),
+    ((17, 5, 1000), 16, "f32"),
+    ((30, 11, 300), 70, "f64"),
+    # long contracted modes that are not the last (FP32): chunked factor, one and two
+    # 64-column passes, q rows not a multiple of 4
+    ((700, 9, 8), 40, "f32"),
+    ((300, 10, 8), 70, "f32"),
+    ((520, 65, 3), 20, "f32"),
 ]
 
 

@@ -20,6 +20,7 @@
 // tensor's sweeps.  Every reduction has a fixed
 // order: results do not depend on which workgroup took which tensor.
 #include "kernels.h"
+#include "blocked_inverse.h"
 
 #include "../../include/cpals.h"
 
@@ -65,7 +66,7 @@ struct BatchArgs {
 struct Lds {
   double F[3][kMaxS * kMaxR];
   double S[3][kMaxR * kMaxR];
-  double G[kMaxR * (kMaxR + 1)];   // Gamma, then its inverse in place (pitch R + 1)
+  double G[kMaxR * (kMaxR + 1)];   // Gamma, then its inverse in place (RP x RP, pitch RP + 1)
   double M[kMaxS * kMaxR];
   float Bt[kMaxR * kKP];            // FP32 factor transposed for the contraction, zero padded
   double red[512];
@@ -191,53 +192,44 @@ __device__ inline void ttm_cols(Lds& L, const float* X, int K, int64_t Q, int R,
   }
 }
 
-// Gamma = S[a] * S[b] (Hadamard), inverted in place by Gauss-Jordan without
-// pivoting (SPD: every pivot is a positive Schur-complement diagonal); a pivot
-// at or below R eps max(diag) flags L.fail.  Step k reads the old row and
-// column k (copied first), then every entry is replaced in one pass.
-template <int NT>
+// Gamma = S[a] * S[b] (Hadamard), padded to RP x RP with the identity and
+// inverted in place by the blocked Gauss-Jordan elimination without pivoting
+// (SPD: every pivot is a positive Schur-complement diagonal); a pivot at or
+// below R eps max(diag) flags L.fail.
+template <int NT, int RP>
 __device__ inline void gamma_inverse(Lds& L, int a, int b, int R) {
-  const int P = R + 1;
-  for (int e = threadIdx.x; e < R * R; e += NT) {
-    const int i = e / R, j = e - i * R;
-    L.G[i * P + j] = L.S[a][e] * L.S[b][e];
+  constexpr int P = RP + 1;
+  double dm = 0.0;
+  for (int e = threadIdx.x; e < RP * RP; e += NT) {
+    const int i = e / RP, j = e - i * RP;
+    double v;
+    if (i < R && j < R) {
+      v = L.S[a][i * R + j] * L.S[b][i * R + j];
+      if (i == j) dm = fmax(dm, v);
+    } else {
+      v = (i == j) ? 1.0 : 0.0;
+    }
+    L.G[i * P + j] = v;
   }
+  // largest diagonal entry (fixed tree, every thread gets it)
+  L.red[threadIdx.x] = dm;
   __syncthreads();
-  double dmax = 0.0;
-  for (int i = 0; i < R; ++i) dmax = fmax(dmax, L.G[i * P + i]);
-  const double tol = dmax * (double)R * 2.220446049250313e-16;
-  double* rowk = L.red;
-  double* colk = L.red + kMaxR;
-  for (int k = 0; k < R; ++k) {
-    const double piv = L.G[k * P + k];
-    if (!(piv > tol)) {  // the same value in every thread
-      if (threadIdx.x == 0) L.fail = 1;
-      __syncthreads();
-      return;
-    }
-    if (threadIdx.x < R) {
-      rowk[threadIdx.x] = L.G[k * P + threadIdx.x];
-      colk[threadIdx.x] = L.G[threadIdx.x * P + k];
-    }
+  for (int h = NT / 2; h > 0; h >>= 1) {
+    if (threadIdx.x < h) L.red[threadIdx.x] = fmax(L.red[threadIdx.x], L.red[threadIdx.x + h]);
     __syncthreads();
-    const double rinv = 1.0 / piv;
-    for (int e = threadIdx.x; e < R * R; e += NT) {
-      const int i = e / R, j = e - i * R;
-      double v;
-      if (i == k)
-        v = (j == k) ? rinv : rowk[j] * rinv;
-      else
-        v = (j == k) ? -colk[i] * rinv : L.G[i * P + j] - colk[i] * rowk[j] * rinv;
-      L.G[i * P + j] = v;
-    }
+  }
+  const double tol = L.red[0] * (double)R * 2.220446049250313e-16;
+  __syncthreads();
+  if (!gj_inverse_lds<RP, NT / 64>(L.G, tol, L.red, &L.fail)) {
+    if (threadIdx.x == 0) L.fail = 1;
     __syncthreads();
   }
 }
 
-// F[m] <- M Ginv (FP64, s x R, in LDS) and S[m] <- F[m]^T F[m].
-template <int NT>
+// F[m] <- M Ginv (FP64, s x R, in LDS; Ginv with pitch RP + 1) and S[m] <- F[m]^T F[m].
+template <int NT, int RP>
 __device__ inline void update_factor(Lds& L, int s, int R, int m) {
-  const int P = R + 1;
+  constexpr int P = RP + 1;
   for (int e = threadIdx.x; e < s * R; e += NT) {
     const int i = e / R, r = e - i * R;
     double acc = 0.0;
@@ -255,16 +247,47 @@ __device__ inline void update_factor(Lds& L, int s, int R, int m) {
 }
 
 // M[o][r] = sum_x Y[(o * so + x * sx) * R + r] * F[f][x][r] for o < n, x < nx
-// (the second level; eight loads in flight per thread).
+// (the second level).  Thread t owns the outputs t, t + NT, ... and takes
+// them three at a time: eight x of the three are loaded at once (clamped
+// indices, masked terms), 24 loads in flight; each sum runs in x order.
 template <int NT>
 __device__ inline void second_level(Lds& L, const float* Y, int n, int nx, int64_t so, int64_t sx, int f, int R) {
-  for (int e = threadIdx.x; e < n * R; e += NT) {
-    const int o = e / R, r = e - o * R;
-    const float* y = Y + (int64_t)o * so * R + r;
-    double acc = 0.0;
-#pragma unroll 8
-    for (int x = 0; x < nx; ++x) acc += (double)y[(int64_t)x * sx * R] * L.F[f][x * R + r];
-    L.M[e] = acc;
+  constexpr int J = 3;
+  const int nout = n * R;
+  const int64_t step = sx * R;
+  for (int e0 = threadIdx.x; e0 < nout; e0 += NT * J) {
+    const float* yp[J];
+    int rr[J];
+    double acc[J];
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int e = e0 + NT * j;
+      const int ee = e < nout ? e : e0;
+      const int o = ee / R;
+      rr[j] = ee - o * R;
+      yp[j] = Y + (int64_t)o * so * R + rr[j];
+      acc[j] = 0.0;
+    }
+#pragma unroll 1
+    for (int x0 = 0; x0 < nx; x0 += 8) {
+      float yv[J][8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int64_t off = (int64_t)(x0 + u < nx ? x0 + u : nx - 1) * step;
+#pragma unroll
+        for (int j = 0; j < J; ++j) yv[j][u] = yp[j][off];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (x0 + u < nx) {
+#pragma unroll
+          for (int j = 0; j < J; ++j) acc[j] += (double)yv[j][u] * L.F[f][(x0 + u) * R + rr[j]];
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < J; ++j)
+      if (e0 + NT * j < nout) L.M[e0 + NT * j] = acc[j];
   }
 }
 
@@ -298,14 +321,14 @@ __device__ void run_tensor(Lds& L, const BatchArgs& a, const BatchTensor& t, int
     __syncthreads();
     // mode 0: M0[i] = sum_j Y[i][j] * A1[j]
     second_level<NT>(L, Y, s0, s1, s1, 1, 1, R);
-    gamma_inverse<NT>(L, 1, 2, R);
+    gamma_inverse<NT, RP>(L, 1, 2, R);
     if (L.fail) break;
-    update_factor<NT>(L, s0, R, 0);
+    update_factor<NT, RP>(L, s0, R, 0);
     // mode 1: M1[j] = sum_i Y[i][j] * A0[i]
     second_level<NT>(L, Y, s1, s0, 1, s1, 0, R);
-    gamma_inverse<NT>(L, 0, 2, R);
+    gamma_inverse<NT, RP>(L, 0, 2, R);
     if (L.fail) break;
-    update_factor<NT>(L, s1, R, 1);
+    update_factor<NT, RP>(L, s1, R, 1);
     // Z = T x_0 A0 over columns (j, k)
     stage_factor<NT, RP>(L, 0, s0, R);
     __syncthreads();
@@ -313,9 +336,9 @@ __device__ void run_tensor(Lds& L, const BatchArgs& a, const BatchTensor& t, int
     __syncthreads();
     // mode 2: M2[k] = sum_j Z[j][k] * A1[j]
     second_level<NT>(L, Y, s2, s1, 1, s2, 1, R);
-    gamma_inverse<NT>(L, 0, 1, R);
+    gamma_inverse<NT, RP>(L, 0, 1, R);
     if (L.fail) break;
-    update_factor<NT>(L, s2, R, 2);
+    update_factor<NT, RP>(L, s2, R, 2);
     // residual, Eq. (3): ||T||^2 + <Gamma2, S2> - 2 <M2, A2>, Gamma2 = S0 * S1
     double part = 0.0;
     for (int e = threadIdx.x; e < R * R; e += NT) part += L.S[0][e] * L.S[1][e] * L.S[2][e];

@@ -35,7 +35,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kMaxS = 96;    // largest mode size
 constexpr int kMaxR = 32;    // largest rank
-constexpr int kKP = kMaxS;   // staged factor pitch (floats)
+constexpr int kKP = kMaxS + 4;  // staged factor pitch (floats): 16 lanes' rows fall in different banks
 
 struct BatchTensor {
   int64_t t_off;     // first element of the tensor in the packed tensor array
@@ -90,7 +90,7 @@ __device__ inline double block_sum(Lds& L, double v) {
 
 // Stage factor m (s x R, FP64 in LDS) as Bt[c][k] (FP32), zero for k >= s or c >= R.
 template <int NT, int RP>
-__device__ inline void stage_factor(Lds& L, int m, int s, int R) {
+__device__ __forceinline__ void stage_factor(Lds& L, int m, int s, int R) {
   const int KP = (s + 15) & ~15;
   for (int e = threadIdx.x; e < RP * KP; e += NT) {
     const int c = e / KP, k = e - c * KP;
@@ -100,9 +100,13 @@ __device__ inline void stage_factor(Lds& L, int m, int s, int R) {
 
 // C[p][r] = sum_k X[p][k] B[k][r] (X is P x K row-major): 16-row tiles per wave.
 // Lane (i, g) feeds k = kb + 4 g + u at MFMA step u (one 16-byte load when
-// the row is aligned and complete), the staged factor the same k.
+// the row is aligned and complete), the staged factor the same k (one
+// 16-byte LDS read).  The next tile's rows are in flight while a tile is
+// multiplied (loaded unconditionally: past the last tile it reloads the
+// last, unused), and a scheduling barrier keeps those loads ahead of the
+// products.
 template <int NT, int RP>
-__device__ inline void ttm_rows(Lds& L, const float* X, int64_t P, int K, int R, float* C) {
+__device__ __forceinline__ void ttm_rows(Lds& L, const float* X, int64_t P, int K, int R, float* C) {
   constexpr int NCB = RP / 16;
   constexpr int NKB = kMaxS / 16;  // 16-index steps of the longest row
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -110,12 +114,10 @@ __device__ inline void ttm_rows(Lds& L, const float* X, int64_t P, int K, int R,
   const bool vec = (K % 4 == 0) && (((uintptr_t)X & 15) == 0);
   const int nkb = (K + 15) / 16;
   const int64_t ntiles = (P + 15) / 16;
-  for (int64_t tile = wave; tile < ntiles; tile += NT / 64) {
+  auto load_tile = [&](int64_t tile, f32x4 (&a)[NKB]) {
     const int64_t p0 = tile * 16;
     const int64_t row = (p0 + l16 < P) ? p0 + l16 : P - 1;
     const float* xr = X + row * K;
-    // every load of the tile in flight before the first product
-    f32x4 a[NKB];
 #pragma unroll
     for (int t = 0; t < NKB; ++t) {
       const int k0 = 16 * t + 4 * g;
@@ -126,6 +128,18 @@ __device__ inline void ttm_rows(Lds& L, const float* X, int64_t P, int K, int R,
         for (int u = 0; u < 4; ++u) a[t][u] = (t < nkb && k0 + u < K) ? xr[k0 + u] : 0.f;
       }
     }
+  };
+  constexpr int NW = NT / 64;
+  if (wave >= ntiles) return;
+  f32x4 an[NKB];
+  load_tile(wave, an);
+  for (int64_t tile = wave; tile < ntiles; tile += NW) {
+    f32x4 a[NKB];
+#pragma unroll
+    for (int t = 0; t < NKB; ++t) a[t] = an[t];
+    load_tile(tile + NW < ntiles ? tile + NW : tile, an);
+    __builtin_amdgcn_sched_barrier(0);
+    const int64_t p0 = tile * 16;
     f32x4 acc[NCB];
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) acc[cb] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -133,11 +147,14 @@ __device__ inline void ttm_rows(Lds& L, const float* X, int64_t P, int K, int R,
     for (int t = 0; t < NKB; ++t) {
       if (t >= nkb) break;
       const int k0 = 16 * t + 4 * g;
+      f32x4 b[NCB];
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) b[cb] = *(const f32x4*)&L.Bt[(cb * 16 + l16) * kKP + k0];
 #pragma unroll
       for (int u = 0; u < 4; ++u)
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb)
-          acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t][u], L.Bt[(cb * 16 + l16) * kKP + k0 + u], acc[cb], 0, 0, 0);
+          acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t][u], b[cb][u], acc[cb], 0, 0, 0);
     }
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb)
@@ -152,24 +169,36 @@ __device__ inline void ttm_rows(Lds& L, const float* X, int64_t P, int K, int R,
 
 // C[q][r] = sum_k X[k][q] B[k][r] (X is K x Q, q contiguous): 16-row tiles of
 // q per wave; lane (i, g) feeds X[kb + g][q0 + i] (16 lanes read 64
-// contiguous bytes).
+// contiguous bytes).  The next tile is in flight while a tile is multiplied,
+// as in ttm_rows.
 template <int NT, int RP>
-__device__ inline void ttm_cols(Lds& L, const float* X, int K, int64_t Q, int R, float* C) {
+__device__ __forceinline__ void ttm_cols(Lds& L, const float* X, int K, int64_t Q, int R, float* C) {
   constexpr int NCB = RP / 16;
   constexpr int NKS = kMaxS / 4;  // 4-index steps of the longest contraction
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, l16 = lane & 15;
   const int nks = (K + 3) / 4;
   const int64_t ntiles = (Q + 15) / 16;
-  for (int64_t tile = wave; tile < ntiles; tile += NT / 64) {
+  auto load_tile = [&](int64_t tile, float (&a)[NKS]) {
     const int64_t q0 = tile * 16;
     const bool qok = q0 + l16 < Q;
-    float a[NKS];
 #pragma unroll
     for (int t = 0; t < NKS; ++t) {
       const int k = 4 * t + g;
       a[t] = (t < nks && k < K && qok) ? X[(int64_t)k * Q + q0 + l16] : 0.f;
     }
+  };
+  constexpr int NW = NT / 64;
+  if (wave >= ntiles) return;
+  float an[NKS];
+  load_tile(wave, an);
+  for (int64_t tile = wave; tile < ntiles; tile += NW) {
+    float a[NKS];
+#pragma unroll
+    for (int t = 0; t < NKS; ++t) a[t] = an[t];
+    load_tile(tile + NW < ntiles ? tile + NW : tile, an);
+    __builtin_amdgcn_sched_barrier(0);
+    const int64_t q0 = tile * 16;
     f32x4 acc[NCB];
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) acc[cb] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -197,7 +226,7 @@ __device__ inline void ttm_cols(Lds& L, const float* X, int K, int64_t Q, int R,
 // (SPD: every pivot is a positive Schur-complement diagonal); a pivot at or
 // below R eps max(diag) flags L.fail.
 template <int NT, int RP>
-__device__ inline void gamma_inverse(Lds& L, int a, int b, int R) {
+__device__ __forceinline__ void gamma_inverse(Lds& L, int a, int b, int R) {
   constexpr int P = RP + 1;
   double dm = 0.0;
   for (int e = threadIdx.x; e < RP * RP; e += NT) {
@@ -228,7 +257,7 @@ __device__ inline void gamma_inverse(Lds& L, int a, int b, int R) {
 
 // F[m] <- M Ginv (FP64, s x R, in LDS; Ginv with pitch RP + 1) and S[m] <- F[m]^T F[m].
 template <int NT, int RP>
-__device__ inline void update_factor(Lds& L, int s, int R, int m) {
+__device__ __forceinline__ void update_factor(Lds& L, int s, int R, int m) {
   constexpr int P = RP + 1;
   for (int e = threadIdx.x; e < s * R; e += NT) {
     const int i = e / R, r = e - i * R;
@@ -251,7 +280,7 @@ __device__ inline void update_factor(Lds& L, int s, int R, int m) {
 // them three at a time: eight x of the three are loaded at once (clamped
 // indices, masked terms), 24 loads in flight; each sum runs in x order.
 template <int NT>
-__device__ inline void second_level(Lds& L, const float* Y, int n, int nx, int64_t so, int64_t sx, int f, int R) {
+__device__ __forceinline__ void second_level(Lds& L, const float* Y, int n, int nx, int64_t so, int64_t sx, int f, int R) {
   constexpr int J = 3;
   const int nout = n * R;
   const int64_t step = sx * R;
@@ -292,7 +321,7 @@ __device__ inline void second_level(Lds& L, const float* Y, int n, int nx, int64
 }
 
 template <int NT, int RP>
-__device__ void run_tensor(Lds& L, const BatchArgs& a, const BatchTensor& t, int idx, float* scratch) {
+__device__ __forceinline__ void run_tensor(Lds& L, const BatchArgs& a, const BatchTensor& t, int idx, float* scratch) {
   const int s0 = t.s[0], s1 = t.s[1], s2 = t.s[2], R = t.R;
   const int sz[3] = {s0, s1, s2};
   const float* T = a.T + t.t_off;

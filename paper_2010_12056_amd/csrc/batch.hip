@@ -329,8 +329,27 @@ __device__ __forceinline__ void run_tensor(Lds& L, const BatchArgs& a, const Bat
   // the factors into LDS, ||T||^2, the Gram matrices of the initial factors
   for (int m = 0; m < 3; ++m)
     for (int e = threadIdx.x; e < sz[m] * R; e += NT) L.F[m][e] = a.A[t.a_off[m] + e];
+  // ||T||^2: thread t takes the 16-byte pieces t, t + NT, ... (the packed
+  // tensors start 16-byte aligned), eight pieces in flight, then the tail
   double nt = 0.0;
-  for (int64_t e = threadIdx.x; e < numel; e += NT) nt += (double)T[e] * (double)T[e];
+  {
+    const int64_t nv = (((uintptr_t)T & 15) == 0) ? numel / 4 : 0;  // else element by element
+    const f32x4* T4 = (const f32x4*)T;
+    for (int64_t v0 = threadIdx.x; v0 < nv; v0 += 8 * (int64_t)NT) {
+      f32x4 x[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int64_t v = v0 + (int64_t)u * NT;
+        x[u] = T4[v < nv ? v : 0];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (v0 + (int64_t)u * NT < nv)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) nt += (double)x[u][c] * (double)x[u][c];
+    }
+    for (int64_t e = nv * 4 + threadIdx.x; e < numel; e += NT) nt += (double)T[e] * (double)T[e];
+  }
   const double normT2 = block_sum<NT>(L, nt);  // (its barriers also publish F)
   for (int m = 0; m < 3; ++m)
     for (int e = threadIdx.x; e < R * R; e += NT) {

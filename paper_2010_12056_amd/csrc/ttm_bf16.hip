@@ -16,9 +16,10 @@
 //
 // Workgroup: eight waves, a tile of 512 output rows; each wave owns 64 rows
 // (four 16-row MFMA blocks u) by 16 * NCB factor columns.  The factor is kept
-// transposed (Bt[c][k], k contiguous) and staged through LDS 256 indices at a
-// time; the tensor goes from HBM straight to registers, one contraction step
-// (32 indices) ahead of the matrix cores.
+// transposed (Bt[c][k], k contiguous) and staged through LDS in chunks of 64
+// indices, double-buffered (the next chunk is loaded while the current one is
+// used; one barrier per chunk); the tensor goes from HBM straight to
+// registers, one contraction step (32 indices) ahead of the matrix cores.
 //   KC (contraction index contiguous, Q == 1): X is P x K row-major; lane
 //      (i = lane % 16, g = lane / 16) of block u loads row 16 u + i, indices
 //      8 g .. 8 g + 7 of the step, as one 16-byte load.
@@ -40,8 +41,8 @@ typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 constexpr int kWaves = 8;
 constexpr int kThreads = kWaves * 64;
 constexpr int kTileRows = kWaves * 64;  // output rows per workgroup tile
-constexpr int KB = 256;                 // contraction indices per LDS stage
-constexpr int KPITCH = KB + 8;          // staged column pitch (bf16 elements)
+constexpr int KB = 64;                  // contraction indices per LDS chunk (two steps)
+constexpr int KPITCH = KB + 8;          // chunk column pitch (bf16 elements)
 
 // Round to nearest, ties to even (finite inputs).
 __device__ inline uint32_t bf16_bits(float f) {
@@ -66,44 +67,59 @@ __global__ __launch_bounds__(256) void k_split_factor(const float* __restrict__ 
 
 __device__ inline bf16x8 as_bf16x8(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
 
-template <bool KC, int NCB, bool SPLIT>
+// Lane source of one workgroup tile in the unguarded layout: KC, the four
+// row pointers (rows row0 + 16 u + l16, clamped to P - 1) at index 8 g;
+// otherwise p[0] points at k = 8 g + 4 h, q = qpair (clamped to Q - 8).
+struct LaneSrc {
+  const uint16_t* p[4];
+};
+
+template <bool KC, int NCB, bool SPLIT, bool FAST>
 __global__ __launch_bounds__(512) void k_ttm_bf16(const uint16_t* __restrict__ X, const uint16_t* __restrict__ Bhi,
                                                   const uint16_t* __restrict__ Blo, float* __restrict__ C,
                                                   int64_t P, int64_t K, int64_t Q, int R, int Kp, int64_t tilesQ,
                                                   int64_t ntiles, int vec) {
   constexpr int NC = NCB * 16;
   constexpr int NPART = SPLIT ? 2 : 1;
-  extern __shared__ __align__(16) unsigned char lds_raw[];
-  uint16_t* Bs = (uint16_t*)lds_raw;  // [NPART][NC][KPITCH]
+  constexpr int BITEMS = NPART * NC * (KB / 8);  // 16-byte pieces of one factor chunk
+  constexpr int BPER = (BITEMS + kThreads - 1) / kThreads;
+  __shared__ __align__(16) uint16_t Bs[2][NPART * NC * KPITCH];  // [buffer][part][column][index]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, l16 = lane & 15;
   const int c0 = blockIdx.y * NC;
-  const bool one_stage = Kp <= KB;
+  const int nch = Kp / KB;
 
-  // columns c0 .. c0 + NC - 1 of Bt, indices k0 .. k0 + KB - 1 (Kp is a multiple of 32)
-  auto stage = [&](int k0) {
-    const int per_col = (Kp - k0 < KB ? Kp - k0 : KB) / 8;
-    const int items = NPART * NC * per_col;
-    for (int idx = tid; idx < items; idx += kThreads) {
-      const int part = idx / (NC * per_col);
-      const int rem = idx - part * NC * per_col;
-      const int c = rem / per_col, j = rem - c * per_col;
-      u32x4 v = {0u, 0u, 0u, 0u};
-      if (c0 + c < R) v = *(const u32x4*)((part ? Blo : Bhi) + (int64_t)(c0 + c) * Kp + k0 + 8 * j);
-      *(u32x4*)(Bs + (part * NC + c) * KPITCH + 8 * j) = v;
+  // ---- factor chunks: columns c0 .. c0 + NC - 1 (past R clamped to R - 1;
+  // their products are never stored), indices ch KB .. ch KB + KB - 1 (the
+  // padding up to Kp holds zeros) ----
+  auto b_piece = [&](int q, int& part, int& c, int& j) {
+    int idx = tid + kThreads * q;
+    if (BITEMS % kThreads != 0) idx = idx < BITEMS ? idx : BITEMS - 1;
+    part = idx / (NC * (KB / 8));
+    const int rem = idx - part * NC * (KB / 8);
+    c = rem / (KB / 8);
+    j = rem - c * (KB / 8);
+  };
+  auto load_b = [&](int ch, u32x4 (&bv)[BPER]) {
+#pragma unroll
+    for (int q = 0; q < BPER; ++q) {
+      int part, c, j;
+      b_piece(q, part, c, j);
+      const int col = c0 + c < R ? c0 + c : R - 1;
+      bv[q] = *(const u32x4*)((part ? Blo : Bhi) + (int64_t)col * Kp + ch * KB + 8 * j);
+    }
+  };
+  auto store_b = [&](int buf, const u32x4 (&bv)[BPER]) {
+#pragma unroll
+    for (int q = 0; q < BPER; ++q) {
+      int part, c, j;
+      b_piece(q, part, c, j);
+      *(u32x4*)(Bs[buf] + (part * NC + c) * KPITCH + 8 * j) = bv[q];
     }
   };
 
-  if (one_stage) {
-    stage(0);
-    __syncthreads();
-  }
-  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    // ---- rows of this lane and the load addressing ----
-    int64_t row0;      // KC: first row (p) of the wave's 64; else first q of the wave's 64
-    const uint16_t* Xb;  // base of the batch (p) in the non-KC layout
-    float* Cb;
-    int64_t nrows;     // valid extent of the row index (P or Q)
+  // ---- tile addressing ----
+  auto tile_rows = [&](int64_t tile, int64_t& row0, const uint16_t*& Xb, float*& Cb, int64_t& nrows) {
     if (KC) {
       row0 = tile * kTileRows + wave * 64;
       Xb = X;
@@ -116,116 +132,195 @@ __global__ __launch_bounds__(512) void k_ttm_bf16(const uint16_t* __restrict__ X
       Cb = C + p * Q * R;
       nrows = Q;
     }
-    // KC: lane rows row0 + 16u + l16 (clamped for loads); else rows row0 + 4 l16 + u
-    int64_t lrow[4];
+  };
+  auto lane_src = [&](int64_t tile) {
+    LaneSrc s;
+    int64_t row0, nrows;
+    const uint16_t* Xb;
+    float* Cb;
+    tile_rows(tile, row0, Xb, Cb, nrows);
+    if (KC) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int64_t r = KC ? row0 + 16 * u + l16 : row0 + 4 * l16 + u;
-      lrow[u] = r < nrows ? r : nrows - 1;
+      for (int u = 0; u < 4; ++u) {
+        const int64_t r = row0 + 16 * u + l16;
+        s.p[u] = Xb + (r < nrows ? r : nrows - 1) * K + 8 * g;
+      }
+    } else {
+      const int64_t qp = row0 + 8 * (l16 >> 1);
+      s.p[0] = Xb + (int64_t)(8 * g + 4 * (l16 & 1)) * Q + (qp < Q - 8 ? qp : Q - 8);
+      s.p[1] = s.p[2] = s.p[3] = s.p[0];
     }
-    const bool qfull = !KC && vec && row0 + 4 * l16 + 4 <= Q;
+    return s;
+  };
 
-    auto load_a = [&](int ks, bf16x8 (&a)[4]) {
-      const int kb = ks + 8 * g;  // this lane's eight indices kb .. kb + 7
+  // ---- tensor step (32 indices from ks) into registers ----
+  // Unguarded layout (FAST: K a multiple of KB, 16-byte aligned rows, KC or
+  // Q a multiple of 8): plain 16-byte loads, converted to MFMA operands only
+  // when used, so the loads of the next step stay in flight meanwhile.
+  // Guarded layout: the operands are formed at load time with every index
+  // checked (indices past K read as zero).
+  auto issue = [&](const LaneSrc& s, int64_t tile, int ks, u32x4 (&r)[4]) {
+    if (FAST) {
       if (KC) {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const uint16_t* src = Xb + lrow[u] * K + kb;
-          if (vec && kb + 8 <= K) {
-            a[u] = as_bf16x8(*(const u32x4*)src);
-          } else {
-            u32x4 v = {0u, 0u, 0u, 0u};
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-              const uint32_t h = (kb + j < K) ? (uint32_t)src[j] : 0u;
-              v[j >> 1] |= (j & 1) ? (h << 16) : h;
-            }
-            a[u] = as_bf16x8(v);
-          }
-        }
+        for (int u = 0; u < 4; ++u) r[u] = *(const u32x4*)(s.p[u] + ks);
       } else {
-        u32x2 raw[8];
-        // 16-byte path: lanes 2m and 2m + 1 share eight consecutive q; lane
-        // h = l16 & 1 loads them at k = kb + 4h + j (j < 4) and swaps the half
-        // that belongs to its partner, so each lane ends with its own four q
-        // at all eight indices.  Uniform within a lane pair.
-        const int h = l16 & 1;
-        const int64_t qpair = row0 + 8 * (l16 >> 1);
-        if (vec == 2 && qpair + 8 <= Q && kb + 8 <= K) {
+        const uint16_t* src = s.p[0] + (int64_t)ks * Q;
 #pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const u32x4 v = *(const u32x4*)(Xb + (int64_t)(kb + 4 * h + j) * Q + qpair);
-            const uint32_t s0 = h ? v[0] : v[2], s1 = h ? v[1] : v[3];
-            const uint32_t r0 = (uint32_t)__builtin_amdgcn_mov_dpp((int)s0, 0xB1, 0xF, 0xF, false);
-            const uint32_t r1 = (uint32_t)__builtin_amdgcn_mov_dpp((int)s1, 0xB1, 0xF, 0xF, false);
-            const u32x2 own = h ? u32x2{v[2], v[3]} : u32x2{v[0], v[1]};
-            const u32x2 got = u32x2{r0, r1};
-            raw[j] = h ? got : own;
-            raw[4 + j] = h ? own : got;
-          }
+        for (int j = 0; j < 4; ++j) r[j] = *(const u32x4*)(src + (int64_t)j * Q);
+      }
+      return;
+    }
+    int64_t row0, nrows;
+    const uint16_t* Xb;
+    float* Cb;
+    tile_rows(tile, row0, Xb, Cb, nrows);
+    const int kb = ks + 8 * g;  // this lane's eight indices kb .. kb + 7
+    if (KC) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        int64_t rr = row0 + 16 * u + l16;
+        rr = rr < nrows ? rr : nrows - 1;
+        const uint16_t* src = Xb + rr * K + kb;
+        if (vec && kb + 8 <= K) {
+          r[u] = *(const u32x4*)src;
         } else {
+          u32x4 v = {0u, 0u, 0u, 0u};
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const int64_t k = kb + j;
-          const uint16_t* src = Xb + k * Q + (row0 + 4 * l16);
-          if (k < K && qfull) {
-            raw[j] = *(const u32x2*)src;
-          } else {
-            uint32_t e[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) e[u] = (k < K && row0 + 4 * l16 + u < Q) ? (uint32_t)src[u] : 0u;
-            raw[j] = u32x2{e[0] | (e[1] << 16), e[2] | (e[3] << 16)};
+          for (int j = 0; j < 8; ++j) {
+            const uint32_t h = (kb + j < K) ? (uint32_t)src[j] : 0u;
+            v[j >> 1] |= (j & 1) ? (h << 16) : h;
           }
-        }
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          u32x4 v;
-#pragma unroll
-          for (int m = 0; m < 4; ++m) {
-            const uint32_t x0 = raw[2 * m][u >> 1], x1 = raw[2 * m + 1][u >> 1];
-            v[m] = (u & 1) ? ((x0 >> 16) | (x1 & 0xffff0000u)) : ((x0 & 0xffffu) | (x1 << 16));
-          }
-          a[u] = as_bf16x8(v);
+          r[u] = v;
         }
       }
-    };
+      return;
+    }
+    const bool qfull = vec && row0 + 4 * l16 + 4 <= Q;
+    u32x2 raw[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int64_t k = kb + j;
+      const uint16_t* src = Xb + k * Q + (row0 + 4 * l16);
+      if (k < K && qfull) {
+        raw[j] = *(const u32x2*)src;
+      } else {
+        uint32_t e[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) e[u] = (k < K && row0 + 4 * l16 + u < Q) ? (uint32_t)src[u] : 0u;
+        raw[j] = u32x2{e[0] | (e[1] << 16), e[2] | (e[3] << 16)};
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const uint32_t x0 = raw[2 * m][u >> 1], x1 = raw[2 * m + 1][u >> 1];
+        r[u][m] = (u & 1) ? ((x0 >> 16) | (x1 & 0xffff0000u)) : ((x0 & 0xffffu) | (x1 << 16));
+      }
+    }
+  };
+  // Operands of one step.  Unguarded q-contiguous layout: lanes 2m and 2m + 1
+  // loaded the same eight q at k = kb + 4h + j (h = l16 & 1, j < 4); each
+  // swaps the half that belongs to its partner, so it holds its own four q
+  // at all eight indices, and transposes that 8 x 4 block.
+  auto operands = [&](const u32x4 (&r)[4], bf16x8 (&a)[4]) {
+    if (!FAST || KC) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a[u] = as_bf16x8(r[u]);
+      return;
+    }
+    const int h = l16 & 1;
+    u32x2 raw[8];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const u32x4 v = r[j];
+      const uint32_t s0 = h ? v[0] : v[2], s1 = h ? v[1] : v[3];
+      const uint32_t r0 = (uint32_t)__builtin_amdgcn_mov_dpp((int)s0, 0xB1, 0xF, 0xF, false);
+      const uint32_t r1 = (uint32_t)__builtin_amdgcn_mov_dpp((int)s1, 0xB1, 0xF, 0xF, false);
+      const u32x2 own = h ? u32x2{v[2], v[3]} : u32x2{v[0], v[1]};
+      const u32x2 got = u32x2{r0, r1};
+      raw[j] = h ? got : own;
+      raw[4 + j] = h ? own : got;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      u32x4 v;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const uint32_t x0 = raw[2 * m][u >> 1], x1 = raw[2 * m + 1][u >> 1];
+        v[m] = (u & 1) ? ((x0 >> 16) | (x1 & 0xffff0000u)) : ((x0 & 0xffffu) | (x1 << 16));
+      }
+      a[u] = as_bf16x8(v);
+    }
+  };
 
-    f32x4 acc[4][NCB];
+  f32x4 acc[4][NCB];
+  auto multiply = [&](const u32x4 (&r)[4], const uint16_t* bs, int kl) {
+    bf16x8 a[4];
+    operands(r, a);
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+      const uint16_t* bp = bs + (cb * 16 + l16) * KPITCH + kl + 8 * g;
+      const bf16x8 bh = as_bf16x8(*(const u32x4*)bp);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[u], bh, acc[u][cb], 0, 0, 0);
+      if (SPLIT) {
+        const bf16x8 bl = as_bf16x8(*(const u32x4*)(bp + NC * KPITCH));
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          acc[u][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[u], bl, acc[u][cb], 0, 0, 0);
+      }
+    }
+  };
+
+  // ---- main loop: the workgroup's waves step through the same (tile, chunk)
+  // sequence; the factor's next chunk and the tensor's next step are loaded
+  // while the current step is multiplied ----
+  int64_t tile = blockIdx.x;
+  if (tile >= ntiles) return;  // uniform: the whole workgroup
+  {
+    u32x4 bv[BPER];
+    load_b(0, bv);
+    store_b(0, bv);
+  }
+  LaneSrc cur = FAST ? lane_src(tile) : LaneSrc{};
+  u32x4 ra[4], rb[4];
+  issue(cur, tile, 0, ra);
+  __syncthreads();
+  int buf = 0;
+  for (; tile < ntiles; tile += gridDim.x) {
+    const int64_t tn = tile + gridDim.x < ntiles ? tile + gridDim.x : tile;
+    const LaneSrc nxt = FAST ? lane_src(tn) : LaneSrc{};
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb) acc[u][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
-
-    bf16x8 an[4];
-    load_a(0, an);
-    for (int ks = 0; ks < Kp; ks += 32) {
-      const int kl = ks % KB;
-      if (!one_stage && kl == 0) {
-        __syncthreads();  // every wave is done with the previous stage
-        stage(ks);
-        __syncthreads();
+    for (int ch = 0; ch < nch; ++ch) {
+      const bool more = ch + 1 < nch;
+      u32x4 bv[BPER];
+      load_b(more ? ch + 1 : 0, bv);  // before the tensor loads: waiting for it leaves them in flight
+      issue(cur, tile, ch * KB + 32, rb);
+      __builtin_amdgcn_sched_barrier(0);
+      multiply(ra, Bs[buf], 0);
+      {
+        LaneSrc sn;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) sn.p[u] = more ? cur.p[u] : nxt.p[u];
+        issue(sn, more ? tile : tn, more ? (ch + 1) * KB : 0, ra);
       }
-      bf16x8 a[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) a[u] = an[u];
-      if (ks + 32 < Kp) load_a(ks + 32, an);
-#pragma unroll
-      for (int cb = 0; cb < NCB; ++cb) {
-        const uint16_t* bp = Bs + (cb * 16 + l16) * KPITCH + kl + 8 * g;
-        const bf16x8 bh = as_bf16x8(*(const u32x4*)bp);
-#pragma unroll
-        for (int u = 0; u < 4; ++u) acc[u][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[u], bh, acc[u][cb], 0, 0, 0);
-        if (SPLIT) {
-          const bf16x8 bl = as_bf16x8(*(const u32x4*)(bp + NC * KPITCH));
-#pragma unroll
-          for (int u = 0; u < 4; ++u)
-            acc[u][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[u], bl, acc[u][cb], 0, 0, 0);
-        }
-      }
+      __builtin_amdgcn_sched_barrier(0);
+      multiply(rb, Bs[buf], 32);
+      store_b(buf ^ 1, bv);
+      buf ^= 1;
+      __syncthreads();
     }
 
     // ---- store: register v of block u is output row 4 g + v of the block ----
+    int64_t row0, nrows;
+    const uint16_t* Xb;
+    float* Cb;
+    tile_rows(tile, row0, Xb, Cb, nrows);
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
@@ -237,45 +332,43 @@ __global__ __launch_bounds__(512) void k_ttm_bf16(const uint16_t* __restrict__ X
           const int c = c0 + cb * 16 + l16;
           if (r < nrows && c < R) Cb[r * R + c] = acc[u][cb][v];
         }
+    cur = nxt;
   }
 }
 
-template <bool KC, int NCB, bool SPLIT>
+template <bool KC, int NCB, bool SPLIT, bool FAST>
 hipError_t launch_one(const uint16_t* X, const uint16_t* Bhi, const uint16_t* Blo, float* C, int64_t P, int64_t K,
-                      int64_t Q, int R, int Kp, hipStream_t st) {
+                      int64_t Q, int R, int Kp, int vec, hipStream_t st) {
   constexpr int NC = NCB * 16;
-  constexpr size_t lds = (size_t)(SPLIT ? 2 : 1) * NC * KPITCH * sizeof(uint16_t);
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_ttm_bf16<KC, NCB, SPLIT>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
   const int64_t tilesQ = KC ? 1 : (Q + kTileRows - 1) / kTileRows;
   const int64_t ntiles = KC ? (P + kTileRows - 1) / kTileRows : P * tilesQ;
   const unsigned nx = (unsigned)(ntiles < 256 ? ntiles : 256);  // one resident workgroup per CU
   const unsigned ny = (unsigned)((R + NC - 1) / NC);
-  // KC: 16-byte row loads; otherwise 2 = 16-byte loads shared by lane pairs, 1 = 8-byte loads
-  const int vec = KC ? (K % 8 == 0 && ((uintptr_t)X % 16) == 0)
-                     : ((Q % 8 == 0 && ((uintptr_t)X % 16) == 0) ? 2 : (Q % 4 == 0 && ((uintptr_t)X % 8) == 0));
-  hipLaunchKernelGGL((k_ttm_bf16<KC, NCB, SPLIT>), dim3(nx, ny), dim3(kThreads), lds, st, X, Bhi, Blo, C, P, K, Q,
-                     R, Kp, tilesQ, ntiles, vec);
+  hipLaunchKernelGGL((k_ttm_bf16<KC, NCB, SPLIT, FAST>), dim3(nx, ny), dim3(kThreads), 0, st, X, Bhi, Blo, C, P, K,
+                     Q, R, Kp, tilesQ, ntiles, vec);
   return hipGetLastError();
 }
 
 template <bool KC, bool SPLIT>
 hipError_t launch_ncb(const uint16_t* X, const uint16_t* Bhi, const uint16_t* Blo, float* C, int64_t P, int64_t K,
                       int64_t Q, int R, int Kp, hipStream_t st) {
-  if (R <= 16) return launch_one<KC, 1, SPLIT>(X, Bhi, Blo, C, P, K, Q, R, Kp, st);
-  if (R <= 32) return launch_one<KC, 2, SPLIT>(X, Bhi, Blo, C, P, K, Q, R, Kp, st);
-  if (R <= 64) return launch_one<KC, 4, SPLIT>(X, Bhi, Blo, C, P, K, Q, R, Kp, st);
-  return launch_one<KC, 8, SPLIT>(X, Bhi, Blo, C, P, K, Q, R, Kp, st);
+  // KC: 16-byte row loads; otherwise 2 = 16-byte loads shared by lane pairs, 1 = 8-byte loads
+  const int vec = KC ? (K % 8 == 0 && ((uintptr_t)X % 16) == 0)
+                     : ((Q % 8 == 0 && ((uintptr_t)X % 16) == 0) ? 2 : (Q % 4 == 0 && ((uintptr_t)X % 8) == 0));
+  const bool fast = K % KB == 0 && (KC ? vec == 1 : vec == 2);
+#define CPALS_BF16_NCB(NCB)                                                                     \
+  return fast ? launch_one<KC, NCB, SPLIT, true>(X, Bhi, Blo, C, P, K, Q, R, Kp, vec, st)      \
+              : launch_one<KC, NCB, SPLIT, false>(X, Bhi, Blo, C, P, K, Q, R, Kp, vec, st)
+  if (R <= 16) CPALS_BF16_NCB(1);
+  if (R <= 32) CPALS_BF16_NCB(2);
+  if (R <= 64) CPALS_BF16_NCB(4);
+  CPALS_BF16_NCB(8);
+#undef CPALS_BF16_NCB
 }
 
 }  // namespace
 
-int bf16_factor_pitch(int64_t K) { return (int)((K + 31) / 32 * 32); }
+int bf16_factor_pitch(int64_t K) { return (int)((K + KB - 1) / KB * KB); }
 
 hipError_t launch_split_factor(const float* A, int64_t K, int R, uint16_t* hi, uint16_t* lo, hipStream_t st) {
   const int Kp = bf16_factor_pitch(K);

@@ -52,14 +52,18 @@ def _dev_bf16(bits, dev):
 
 
 CASES = [
-    # KC and q-contiguous layouts, ragged K (K % 8 != 0), Q % 4 != 0, several LDS stages
-    # (K > 256, with a partial last stage), R beyond one column block and not a multiple of 16
+    # KC and q-contiguous layouts, ragged K (K % 8 != 0, K not a multiple of the 128-index
+    # pass), Q % 4 != 0, many factor chunks, R beyond one column block and not a multiple of 16;
+    # the unguarded loads (K % 128 == 0) in both layouts with ragged row tails, several tiles
+    # per workgroup, and Q below one wave's 64 rows (clamped lane pairs)
     ((40, 37, 33, 29), 20),
     ((24, 17, 512), 128),
     ((8, 520, 12), 33),
     ((64, 64, 64), 16),
     ((300, 7, 9), 64),
     ((3, 1, 5, 2, 4), 1),
+    ((128, 41, 256), 48),
+    ((24, 256, 40), 20),
 ]
 
 

@@ -100,6 +100,7 @@ struct cp_plan_s {
   bool sw_set = false;
   float* sw_in = nullptr;   // workspace: normalized features
   float* sw_out = nullptr;  // workspace: probability
+  void* krp = nullptr;        // CP_TREE_DT_COMBINED (order >= 4): Khatri-Rao product of the last two factors
   uint16_t* Bt_hi = nullptr;  // BF16 plans: transposed BF16 factor of the first contraction
   uint16_t* Bt_lo = nullptr;  // BF16X2 plans: its remainder part
   int pinv_seen = 0;         // stats->pinv_count at the last report
@@ -196,6 +197,18 @@ int64_t node_numel(cp_plan p, uint32_t set) {
   return n;
 }
 
+// CP_TREE_DT_COMBINED: the half of the dimension tree that keeps the leading
+// modes starts by contracting the last two modes, N-1 then N-2, and nothing
+// but its next level reads the node in between.  Done as one contraction of
+// the tensor, viewed as (s_0 ... s_{N-3}) x (s_{N-2} s_{N-1}), with the
+// Khatri-Rao product of the two factors: the upper two levels combined (the
+// memory / computation trade-off of Sec. IV).  The intermediate of order N-1
+// is never formed.  Orders 4 and up (at order 3 that half has one contraction).
+int64_t combined_k(cp_plan p) {
+  if (p->tree != CP_TREE_DT_COMBINED || p->N < 4) return 0;
+  return p->dims[p->N - 2] * p->dims[p->N - 1];
+}
+
 void plan_layout(cp_plan p) {
   const int N = p->N, R = p->R;
   p->regions.clear();
@@ -231,8 +244,11 @@ void plan_layout(cp_plan p) {
   take(16 * sizeof(float));                      // sw_in
   take(16 * sizeof(float));                      // sw_out
   const bool bf = (p->prec == CP_BF16 || p->prec == CP_BF16X2);
-  take(bf ? (size_t)R * bf16_factor_pitch(smax) * 2 : 0);                               // Bt_hi
-  take(p->prec == CP_BF16X2 ? (size_t)R * bf16_factor_pitch(smax) * 2 : 0);             // Bt_lo
+  const int64_t kc = combined_k(p);  // contraction length of the combined first level (0: none)
+  take((size_t)kc * R * p->esz);     // krp
+  const int64_t kb = std::max(smax, kc);
+  take(bf ? (size_t)R * bf16_factor_pitch(kb) * 2 : 0);                                 // Bt_hi
+  take(p->prec == CP_BF16X2 ? (size_t)R * bf16_factor_pitch(kb) * 2 : 0);               // Bt_lo
   // slots for depths 1..N-2 (depth d keeps N - d modes)
   std::vector<int64_t> sorted(p->dims, p->dims + N);
   std::sort(sorted.begin(), sorted.end(), std::greater<int64_t>());
@@ -269,6 +285,7 @@ void plan_carve(cp_plan p) {
   p->stats = (DevStats*)next();
   p->sw_in = (float*)next();
   p->sw_out = (float*)next();
+  p->krp = next();
   p->Bt_hi = (uint16_t*)next();
   void* lo = next();
   p->Bt_lo = (p->prec == CP_BF16X2) ? (uint16_t*)lo : nullptr;
@@ -353,6 +370,34 @@ cp_status contract_any(cp_plan p, const void* in, uint32_t in_set, int c, void* 
   return contract<float>(p, in, in_set, c, out, out_f64);
 }
 
+// The combined first level: node (modes 0 .. N-3, R) = T viewed as
+// (s_0 ... s_{N-3}) x (s_{N-2} s_{N-1}) times the Khatri-Rao product of the
+// shadows of A^(N-2) and A^(N-1).
+template <typename TT>
+cp_status contract_combined(cp_plan p, void* out) {
+  const int N = p->N;
+  int64_t P = 1;
+  for (int m = 0; m < N - 2; ++m) P *= p->dims[m];
+  const int64_t K = combined_k(p);
+  ++p->ttm_count;
+  ProfScope ps(p, CP_PHASE_TTM);
+  HIP_TRY(p, launch_krp2<TT>((const TT*)p->Ash[N - 2], p->dims[N - 2], (const TT*)p->Ash[N - 1], p->dims[N - 1],
+                             p->R, (TT*)p->krp, p->st));
+  if (p->prec == CP_BF16 || p->prec == CP_BF16X2) {
+    HIP_TRY(p, launch_split_factor((const float*)p->krp, K, p->R, p->Bt_hi, p->Bt_lo, p->st));
+    HIP_TRY(p, launch_ttm_bf16((const uint16_t*)p->T, p->Bt_hi, p->Bt_lo, (float*)out, P, K, 1, p->R, p->st));
+  } else {
+    HIP_TRY(p, launch_ttm<TT>((const TT*)p->T, (const TT*)p->krp, (TT*)out, P, K, 1, p->R, p->st));
+  }
+  return CP_OK;
+}
+
+// Whether a path from the tensor takes the combined first level: it starts
+// with the contractions of modes N-1 and N-2 and goes on below that node.
+bool path_combines(cp_plan p, const std::vector<int>& seq) {
+  return combined_k(p) > 0 && seq.size() >= 3 && seq[0] == p->N - 1 && seq[1] == p->N - 2;
+}
+
 // Walk a root-to-leaf contraction sequence; M (FP64, s_leaf x R) receives the leaf.
 // Depth of the deepest cached node on a path (0: the path starts from the
 // tensor).
@@ -377,7 +422,15 @@ cp_status run_path(cp_plan p, const std::vector<int>& seq, double* M) {
   if (len != N - 1) return fail(p, CP_ERR_STATE, "internal: path of length %d", len);
   std::vector<uint32_t> sets;
   const int start = path_start(p, seq, &sets);
-  for (int d = start + 1; d <= len; ++d) {
+  int d = start + 1;
+  if (d == 1 && path_combines(p, seq)) {
+    if ((size_t)node_numel(p, sets[2]) * p->esz > p->slot_cap[2])
+      return fail(p, CP_ERR_STATE, "internal: slot 2 too small");
+    CP_TRY(p->prec == CP_F64 ? contract_combined<double>(p, p->slot_buf[2]) : contract_combined<float>(p, p->slot_buf[2]));
+    slot_record(p, 2, sets[2]);
+    d = 3;
+  }
+  for (; d <= len; ++d) {
     const void* in = (d == 1) ? p->T : p->slot_buf[d - 1];
     if (d == len) {
       CP_TRY(contract_any(p, in, sets[d - 1], seq[d - 1], M, true));
@@ -845,7 +898,7 @@ cp_status cp_plan_create(cp_plan* out, int order, const int64_t* dims, int rank,
   if (order < 3 || order > kMaxOrder) return CP_ERR_UNSUPPORTED;
   if (rank < 1 || rank > kMaxRank) return CP_ERR_UNSUPPORTED;
   if (prec != CP_F64 && prec != CP_F32 && prec != CP_BF16 && prec != CP_BF16X2) return CP_ERR_UNSUPPORTED;
-  if (tree != CP_TREE_DT && tree != CP_TREE_MSDT) return CP_ERR_UNSUPPORTED;
+  if (tree != CP_TREE_DT && tree != CP_TREE_DT_COMBINED && tree != CP_TREE_MSDT) return CP_ERR_UNSUPPORTED;
   double numel = 1.0;
   for (int m = 0; m < order; ++m) {
     if (dims[m] < 1) return CP_ERR_ARG;

@@ -48,6 +48,9 @@ hipError_t launch_mttv(const TI* X, const TI* A, TO* Y, int64_t P, int64_t I, in
 // dst[i] = (T) src[i] for n elements.
 template <typename T>
 hipError_t launch_convert(const double* src, T* dst, int64_t n, hipStream_t st);
+// B (sa sb x R) = Khatri-Rao product of Aa (sa x R) and Ab (sb x R), row i sb + j.
+template <typename T>
+hipError_t launch_krp2(const T* Aa, int64_t sa, const T* Ab, int64_t sb, int R, T* B, hipStream_t st);
 
 // FP64 copy, dst[i] = src[i] (n elements).
 hipError_t launch_copy_f64(const double* src, double* dst, int64_t n, hipStream_t st);

@@ -793,6 +793,20 @@ __global__ void k_convert(const double* __restrict__ s, T* __restrict__ d, int64
   if (g < n) d[g] = (T)s[g];
 }
 
+// Khatri-Rao product of two factors as the contraction operand of two
+// adjacent modes a, b (b contiguous): B[i sb + j][r] = Aa[i][r] Ab[j][r]
+// (Sec. II-A), the product of the two values rounded once.
+template <typename T>
+__global__ void k_krp2(const T* __restrict__ Aa, const T* __restrict__ Ab, int64_t sb, int R, int64_t n,
+                       T* __restrict__ B) {
+  const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (g >= n) return;
+  const int64_t k = g / R;
+  const int r = (int)(g - k * R);
+  const int64_t i = k / sb, j = k - i * sb;
+  B[g] = (T)((double)Aa[i * R + r] * (double)Ab[j * R + r]);
+}
+
 __global__ void k_copy_f64(const double* __restrict__ s, double* __restrict__ d, int64_t n) {
   const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (g < n) d[g] = s[g];
@@ -1765,6 +1779,14 @@ hipError_t launch_mttv(const TI* X, const TI* A, TO* Y, int64_t P, int64_t I, in
 }
 
 template <typename T>
+hipError_t launch_krp2(const T* Aa, int64_t sa, const T* Ab, int64_t sb, int R, T* B, hipStream_t st) {
+  const int64_t n = sa * sb * R;
+  if (n <= 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_krp2<T>), dim3(nblocks(n)), dim3(256), 0, st, Aa, Ab, sb, R, n, B);
+  return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_convert(const double* src, T* dst, int64_t n, hipStream_t st) {
   hipLaunchKernelGGL((k_convert<T>), dim3(nblocks(n)), dim3(256), 0, st, src, dst, n);
   return hipGetLastError();
@@ -2004,6 +2026,8 @@ template hipError_t launch_mttv<float, double>(const float*, const float*, doubl
                                                int64_t, int64_t, int, hipStream_t);
 template hipError_t launch_mttv<double, double>(const double*, const double*, double*, int64_t,
                                                 int64_t, int64_t, int, hipStream_t);
+template hipError_t launch_krp2<float>(const float*, int64_t, const float*, int64_t, int, float*, hipStream_t);
+template hipError_t launch_krp2<double>(const double*, int64_t, const double*, int64_t, int, double*, hipStream_t);
 template hipError_t launch_convert<float>(const double*, float*, int64_t, hipStream_t);
 template hipError_t launch_convert<double>(const double*, double*, int64_t, hipStream_t);
 template hipError_t launch_norm2<float>(const float*, int64_t, double*, int, DevStats*, hipStream_t);

@@ -61,6 +61,28 @@ def test_plan_create_argument_checks():
     bad = (ctypes.c_int64 * 4)(8, 0, 8, 8)
     assert L.cp_plan_create(ctypes.byref(h), 4, bad, 4, cpals.CP_F32, cpals.CP_TREE_DT, None) == cpals.CP_ERR_ARG
     assert L.cp_plan_create(None, 4, dims, 4, cpals.CP_F32, cpals.CP_TREE_DT, None) == cpals.CP_ERR_ARG
+    assert L.cp_plan_create(ctypes.byref(h), 4, dims, 4, cpals.CP_F32, 3, None) == cpals.CP_ERR_UNSUPPORTED
+
+
+def test_combined_tree_accepted_at_every_order():
+    """CP_TREE_DT_COMBINED is a valid tree at orders 3 (where it is the
+    standard tree) and up; the workspace also holds the Khatri-Rao operand of
+    the last two modes (s_{N-2} s_{N-1} x R)."""
+    from paper_2010_12056_amd import cpals
+
+    L = _lib()
+    for dims_t in ((40, 30, 20), (256, 256, 33, 3), (12, 10, 9, 8, 7)):
+        dims = (ctypes.c_int64 * len(dims_t))(*dims_t)
+        sizes = {}
+        for tree in (cpals.CP_TREE_DT, cpals.CP_TREE_DT_COMBINED):
+            h = ctypes.c_void_p()
+            assert L.cp_plan_create(ctypes.byref(h), len(dims_t), dims, 50, cpals.CP_F32, tree, None) == cpals.CP_OK
+            n = ctypes.c_size_t()
+            assert L.cp_plan_workspace_size(h, ctypes.byref(n)) == cpals.CP_OK
+            sizes[tree] = n.value
+            assert L.cp_plan_destroy(h) == cpals.CP_OK
+        krp = dims_t[-2] * dims_t[-1] * 50 * 4 if len(dims_t) >= 4 else 0
+        assert sizes[cpals.CP_TREE_DT_COMBINED] >= sizes[cpals.CP_TREE_DT] + krp - 256  # regions are 256-aligned
 
 
 def test_workspace_size_and_state_errors():

@@ -99,44 +99,50 @@ __device__ __forceinline__ void stage_factor(Lds& L, int m, int s, int R) {
 }
 
 // C[p][r] = sum_k X[p][k] B[k][r] (X is P x K row-major): 16-row tiles per wave.
-// Lane (i, g) feeds k = kb + 4 g + u at MFMA step u (one 16-byte load when
-// the row is aligned and complete), the staged factor the same k (one
-// 16-byte LDS read).  The next tile's rows are in flight while a tile is
-// multiplied (loaded unconditionally: past the last tile it reloads the
-// last, unused), and a scheduling barrier keeps those loads ahead of the
-// products.
-template <int NT, int RP>
+// NB = ceil(K / 16) is a template parameter so that every loop over the
+// contraction is unrolled (the staged factor is zero up to 16 NB).  Lane
+// (i, g) feeds k = 16 t + 4 g + u at MFMA step (t, u) (one 16-byte load when
+// the row is 16-byte aligned, VEC: K % 4 == 0); its factor operands are the
+// same for every tile and stay in registers.  Every load is unconditional:
+// rows past P read row P - 1 (never stored) and indices past K read index
+// K - 1 (or K - 4), which the factor's zero padding cancels.  The next tile's
+// rows are in flight while a tile is multiplied (past the last tile it
+// reloads the last, unused), and a scheduling barrier keeps those loads
+// ahead of the products.
+template <int NT, int RP, int NB, bool VEC>
 __device__ __forceinline__ void ttm_rows(Lds& L, const float* X, int64_t P, int K, int R, float* C) {
   constexpr int NCB = RP / 16;
-  constexpr int NKB = kMaxS / 16;  // 16-index steps of the longest row
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, l16 = lane & 15;
-  const bool vec = (K % 4 == 0) && (((uintptr_t)X & 15) == 0);
-  const int nkb = (K + 15) / 16;
   const int64_t ntiles = (P + 15) / 16;
-  auto load_tile = [&](int64_t tile, f32x4 (&a)[NKB]) {
+  auto load_tile = [&](int64_t tile, f32x4 (&a)[NB]) {
     const int64_t p0 = tile * 16;
     const int64_t row = (p0 + l16 < P) ? p0 + l16 : P - 1;
     const float* xr = X + row * K;
 #pragma unroll
-    for (int t = 0; t < NKB; ++t) {
+    for (int t = 0; t < NB; ++t) {
       const int k0 = 16 * t + 4 * g;
-      if (t < nkb && vec && k0 + 4 <= K) {
-        a[t] = *(const f32x4*)(xr + k0);
+      if (VEC) {
+        a[t] = *(const f32x4*)(xr + (k0 + 4 <= K ? k0 : K - 4));
       } else {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) a[t][u] = (t < nkb && k0 + u < K) ? xr[k0 + u] : 0.f;
+        for (int u = 0; u < 4; ++u) a[t][u] = xr[k0 + u < K ? k0 + u : K - 1];
       }
     }
   };
   constexpr int NW = NT / 64;
   if (wave >= ntiles) return;
-  f32x4 an[NKB];
+  f32x4 b[NB][NCB];
+#pragma unroll
+  for (int t = 0; t < NB; ++t)
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) b[t][cb] = *(const f32x4*)&L.Bt[(cb * 16 + l16) * kKP + 16 * t + 4 * g];
+  f32x4 an[NB];
   load_tile(wave, an);
   for (int64_t tile = wave; tile < ntiles; tile += NW) {
-    f32x4 a[NKB];
+    f32x4 a[NB];
 #pragma unroll
-    for (int t = 0; t < NKB; ++t) a[t] = an[t];
+    for (int t = 0; t < NB; ++t) a[t] = an[t];
     load_tile(tile + NW < ntiles ? tile + NW : tile, an);
     __builtin_amdgcn_sched_barrier(0);
     const int64_t p0 = tile * 16;
@@ -144,18 +150,12 @@ __device__ __forceinline__ void ttm_rows(Lds& L, const float* X, int64_t P, int 
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) acc[cb] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int t = 0; t < NKB; ++t) {
-      if (t >= nkb) break;
-      const int k0 = 16 * t + 4 * g;
-      f32x4 b[NCB];
-#pragma unroll
-      for (int cb = 0; cb < NCB; ++cb) b[cb] = *(const f32x4*)&L.Bt[(cb * 16 + l16) * kKP + k0];
+    for (int t = 0; t < NB; ++t)
 #pragma unroll
       for (int u = 0; u < 4; ++u)
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb)
-          acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t][u], b[cb][u], acc[cb], 0, 0, 0);
-    }
+          acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t][u], b[t][cb][u], acc[cb], 0, 0, 0);
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
@@ -168,24 +168,25 @@ __device__ __forceinline__ void ttm_rows(Lds& L, const float* X, int64_t P, int 
 }
 
 // C[q][r] = sum_k X[k][q] B[k][r] (X is K x Q, q contiguous): 16-row tiles of
-// q per wave; lane (i, g) feeds X[kb + g][q0 + i] (16 lanes read 64
-// contiguous bytes).  The next tile is in flight while a tile is multiplied,
-// as in ttm_rows.
-template <int NT, int RP>
+// q per wave; lane (i, g) feeds X[4 t + g][q0 + i] (16 lanes read 64
+// contiguous bytes), NB = ceil(K / 16) as in ttm_rows, the factor operands
+// read from LDS at each step, unconditional clamped loads (q past Q read column Q - 1, never
+// stored; k past K read row K - 1, cancelled by the factor's zero padding),
+// the next tile in flight while a tile is multiplied.
+template <int NT, int RP, int NB>
 __device__ __forceinline__ void ttm_cols(Lds& L, const float* X, int K, int64_t Q, int R, float* C) {
   constexpr int NCB = RP / 16;
-  constexpr int NKS = kMaxS / 4;  // 4-index steps of the longest contraction
+  constexpr int NKS = 4 * NB;  // 4-index steps
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, l16 = lane & 15;
-  const int nks = (K + 3) / 4;
   const int64_t ntiles = (Q + 15) / 16;
   auto load_tile = [&](int64_t tile, float (&a)[NKS]) {
-    const int64_t q0 = tile * 16;
-    const bool qok = q0 + l16 < Q;
+    const int64_t q = tile * 16 + l16 < Q ? tile * 16 + l16 : Q - 1;
+    const float* xq = X + q;
 #pragma unroll
     for (int t = 0; t < NKS; ++t) {
       const int k = 4 * t + g;
-      a[t] = (t < nks && k < K && qok) ? X[(int64_t)k * Q + q0 + l16] : 0.f;
+      a[t] = xq[(int64_t)(k < K ? k : K - 1) * Q];
     }
   };
   constexpr int NW = NT / 64;
@@ -203,13 +204,10 @@ __device__ __forceinline__ void ttm_cols(Lds& L, const float* X, int K, int64_t 
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) acc[cb] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int t = 0; t < NKS; ++t) {
-      if (t >= nks) break;
-      const int k = 4 * t + g;
+    for (int t = 0; t < NKS; ++t)
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb)
-        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t], L.Bt[(cb * 16 + l16) * kKP + k], acc[cb], 0, 0, 0);
-    }
+        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t], L.Bt[(cb * 16 + l16) * kKP + 4 * t + g], acc[cb], 0, 0, 0);
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
@@ -220,6 +218,38 @@ __device__ __forceinline__ void ttm_cols(Lds& L, const float* X, int K, int64_t 
       }
   }
 }
+
+// The contractions for K <= kMaxS, with the block count as a compile-time constant.
+template <int NT, int RP, bool VEC>
+__device__ __forceinline__ void ttm_rows_kv(Lds& L, const float* X, int64_t P, int K, int R, float* C) {
+  switch ((K + 15) / 16) {
+    case 1: ttm_rows<NT, RP, 1, VEC>(L, X, P, K, R, C); break;
+    case 2: ttm_rows<NT, RP, 2, VEC>(L, X, P, K, R, C); break;
+    case 3: ttm_rows<NT, RP, 3, VEC>(L, X, P, K, R, C); break;
+    case 4: ttm_rows<NT, RP, 4, VEC>(L, X, P, K, R, C); break;
+    case 5: ttm_rows<NT, RP, 5, VEC>(L, X, P, K, R, C); break;
+    default: ttm_rows<NT, RP, 6, VEC>(L, X, P, K, R, C); break;
+  }
+}
+template <int NT, int RP>
+__device__ __forceinline__ void ttm_rows_k(Lds& L, const float* X, int64_t P, int K, int R, float* C) {
+  if (K % 4 == 0 && ((uintptr_t)X & 15) == 0)
+    ttm_rows_kv<NT, RP, true>(L, X, P, K, R, C);
+  else
+    ttm_rows_kv<NT, RP, false>(L, X, P, K, R, C);
+}
+template <int NT, int RP>
+__device__ __forceinline__ void ttm_cols_k(Lds& L, const float* X, int K, int64_t Q, int R, float* C) {
+  switch ((K + 15) / 16) {
+    case 1: ttm_cols<NT, RP, 1>(L, X, K, Q, R, C); break;
+    case 2: ttm_cols<NT, RP, 2>(L, X, K, Q, R, C); break;
+    case 3: ttm_cols<NT, RP, 3>(L, X, K, Q, R, C); break;
+    case 4: ttm_cols<NT, RP, 4>(L, X, K, Q, R, C); break;
+    case 5: ttm_cols<NT, RP, 5>(L, X, K, Q, R, C); break;
+    default: ttm_cols<NT, RP, 6>(L, X, K, Q, R, C); break;
+  }
+}
+static_assert(kMaxS <= 6 * 16, "contraction block dispatch covers kMaxS");
 
 // Gamma = S[a] * S[b] (Hadamard), padded to RP x RP with the identity and
 // inverted in place by the blocked Gauss-Jordan elimination without pivoting
@@ -365,7 +395,7 @@ __device__ __forceinline__ void run_tensor(Lds& L, const BatchArgs& a, const Bat
     // Y = T x_2 A2 over rows (i, j)
     stage_factor<NT, RP>(L, 2, s2, R);
     __syncthreads();
-    ttm_rows<NT, RP>(L, T, (int64_t)s0 * s1, s2, R, Y);
+    ttm_rows_k<NT, RP>(L, T, (int64_t)s0 * s1, s2, R, Y);
     __syncthreads();
     // mode 0: M0[i] = sum_j Y[i][j] * A1[j]
     second_level<NT>(L, Y, s0, s1, s1, 1, 1, R);
@@ -380,7 +410,7 @@ __device__ __forceinline__ void run_tensor(Lds& L, const BatchArgs& a, const Bat
     // Z = T x_0 A0 over columns (j, k)
     stage_factor<NT, RP>(L, 0, s0, R);
     __syncthreads();
-    ttm_cols<NT, RP>(L, T, s0, (int64_t)s1 * s2, R, Y);
+    ttm_cols_k<NT, RP>(L, T, s0, (int64_t)s1 * s2, R, Y);
     __syncthreads();
     // mode 2: M2[k] = sum_j Z[j][k] * A1[j]
     second_level<NT>(L, Y, s2, s1, 1, s2, 1, R);

@@ -212,9 +212,14 @@ typedef enum {
   CP_PHASE_COUNT = 5
 } cp_phase;
 
-/* on != 0: from now on, record a HIP event pair on the plan's stream around
- * every group of launches, by category.  Costs two event records per group. */
-cp_status cp_profile_enable(cp_plan plan, int on);
+/* mask: the categories to time from now on, bit (1 << cp_phase) for each
+ * (CP_PROFILE_ALL: every one; 0: none).  A HIP event pair is recorded on the
+ * plan's stream around every group of launches of a timed category: two
+ * event records per group, which on a short sweep cost measurable time (all
+ * categories: about a tenth of a 128^4 R = 64 step), so time only what is
+ * needed.  CP_ERR_ARG for bits past CP_PHASE_COUNT. */
+#define CP_PROFILE_ALL ((1 << CP_PHASE_COUNT) - 1)
+cp_status cp_profile_enable(cp_plan plan, int mask);
 
 /* Wait for the plan's stream, then write the summed device time in
  * milliseconds (ms[CP_PHASE_COUNT], host array) and the number of recorded

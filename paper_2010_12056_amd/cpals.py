@@ -242,8 +242,13 @@ class Plan:
         self._check(self.L.cp_pp_last_decision(self.h, f, ctypes.byref(pr)))
         return [f[i] for i in range(D)], pr.value
 
-    def profile(self, on=True):
-        self._check(self.L.cp_profile_enable(self.h, 1 if on else 0))
+    def profile(self, on=True, phases=None):
+        """Time the given phases (names from PHASES; all when None) from now on,
+        or none when `on` is false."""
+        mask = 0
+        if on:
+            mask = (1 << len(PHASES)) - 1 if phases is None else sum(1 << PHASES.index(ph) for ph in phases)
+        self._check(self.L.cp_profile_enable(self.h, mask))
 
     def profile_read(self):
         ms = (ctypes.c_double * 5)()

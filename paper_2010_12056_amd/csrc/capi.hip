@@ -122,7 +122,7 @@ struct cp_plan_s {
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 
   // phase timers: a HIP event pair around every launch group, by category
-  bool prof = false;
+  unsigned prof = 0;  // phase categories recorded (bit 1 << cp_phase)
   struct Mark {
     hipEvent_t a, b;
     int cat;
@@ -178,7 +178,7 @@ struct ProfScope {
   hipEvent_t a = nullptr;
   ProfScope(cp_plan p_, int cat_) : ProfScope(p_, cat_, p_->st) {}
   ProfScope(cp_plan p_, int cat_, hipStream_t st_) : p(p_), cat(cat_), st(st_) {
-    if (p->prof) {
+    if ((p->prof >> cat) & 1u) {
       a = get_event(p);
       if (a && hipEventRecord(a, st) != hipSuccess) a = nullptr;
     }
@@ -1158,7 +1158,8 @@ cp_status cp_sync(cp_plan p) {
 
 cp_status cp_profile_enable(cp_plan p, int on) {
   if (!p) return CP_ERR_ARG;
-  p->prof = (on != 0);
+  if (on < 0 || on >= (1 << CP_PHASE_COUNT)) return fail(p, CP_ERR_ARG, "bad phase mask %d", on);
+  p->prof = (unsigned)on;
   return CP_OK;
 }
 

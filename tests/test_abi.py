@@ -85,6 +85,20 @@ def test_combined_tree_accepted_at_every_order():
         assert sizes[cpals.CP_TREE_DT_COMBINED] >= sizes[cpals.CP_TREE_DT] + krp - 256  # regions are 256-aligned
 
 
+def test_profile_mask_checked():
+    from paper_2010_12056_amd import cpals
+
+    L = _lib()
+    h = ctypes.c_void_p()
+    dims = (ctypes.c_int64 * 3)(8, 8, 8)
+    assert L.cp_plan_create(ctypes.byref(h), 3, dims, 4, cpals.CP_F32, cpals.CP_TREE_DT, None) == cpals.CP_OK
+    for mask in (0, 1, 0b10101, 31):
+        assert L.cp_profile_enable(h, mask) == cpals.CP_OK
+    for mask in (-1, 32, 1 << 20):
+        assert L.cp_profile_enable(h, mask) == cpals.CP_ERR_ARG
+    assert L.cp_plan_destroy(h) == cpals.CP_OK
+
+
 def test_workspace_size_and_state_errors():
     from paper_2010_12056_amd import cpals
 

@@ -11,9 +11,11 @@
  *     the caller and borrowed for the duration of the call (the tensor is
  *     borrowed from cp_set_tensor until the next cp_set_tensor or destroy).
  *   - Factor matrices are always FP64 (the ALS state).  The tensor is stored
- *     in the plan's precision (FP64 or FP32); contractions with it run in that
- *     precision, every R x R operation (Gram matrices, their Hadamard
- *     products, the SPD solve, norms, the residual) runs in FP64.
+ *     in the plan's precision (FP64, FP32, or BF16 for the precision path);
+ *     contractions with it run in that precision (BF16: on the BF16 matrix
+ *     cores with FP32 accumulation), every R x R operation (Gram matrices,
+ *     their Hadamard products, the inverse or pseudo-inverse of Gamma, norms,
+ *     the residual) runs in FP64.
  *   - All work is enqueued on the plan's HIP stream and the call returns
  *     without waiting, unless it has to read a device result: a non-null
  *     `info`, or cp_pp_sweep in CP_PP_AUTO mode (one small device-to-host

@@ -93,8 +93,10 @@ def dt_sweep_flops(dims, R):
 # kernels and their launchers (text from each marker to the end of that function)
 TTM_SOURCE_MARKERS = (
     "__global__ __launch_bounds__(512) void k_ttm_kc(",
+    "__global__ __launch_bounds__(512) void k_ttm_kc32(",
     "__global__ __launch_bounds__(512) void k_ttm_q(",
     "hipError_t launch_ttm_kc(",
+    "hipError_t launch_ttm_kc32(",
     "hipError_t launch_ttm_q(",
     "hipError_t launch_ttm(const T* X",
 )

@@ -21,6 +21,7 @@ namespace cpals {
 namespace {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 // ---------------------------------------------------------------------------
@@ -365,6 +366,77 @@ __global__ __launch_bounds__(512) void k_ttm_kc(const T* __restrict__ X, const T
           if (tile * 16 + r < P && c < R) ct[r * R + c] = acc[cb][v];
         }
     }
+  }
+}
+
+// First-level contraction over the last mode for FP32 and K == 128 (16-byte
+// aligned rows) on v_mfma_f32_32x32x2f32: 32-row output tiles per wave,
+// 32-column blocks.  In step s, lane (i = lane % 32, h = lane / 32) loads
+// X[row i][8 s + 4 h .. + 3] with one 16-byte load and feeds element j to
+// instruction j, whose contraction slot h then holds index 8 s + 4 h + j; the
+// factor lane of the same slot reads the same indices from the transposed
+// factor in LDS.  Register v of lane l holds output row 8 (v / 4) + 4 h +
+// v % 4, column l % 32.  Otherwise as k_ttm_kc (factor staged once, the next
+// tile in flight, prefetched registers copied before the next loads).
+template <int NCB>
+__global__ __launch_bounds__(512) void k_ttm_kc32(const float* __restrict__ X, const float* __restrict__ B,
+                                                  float* __restrict__ C, int64_t P, int R, int64_t ntiles) {
+  constexpr int K = 128;
+  constexpr int NS = K / 8;
+  constexpr int pitch = K + 4;
+  constexpr int NC = NCB * 32;
+  __shared__ __align__(16) float Bt[NC * pitch];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int h = lane >> 5, l32 = lane & 31;
+  const int c0 = blockIdx.y * NC;
+  for (int idx = tid; idx < K * NC; idx += kTtmThreads) {
+    const int k = idx / NC, col = idx - k * NC;
+    Bt[col * pitch + k] = (c0 + col < R) ? B[(int64_t)k * R + c0 + col] : 0.f;
+  }
+  __syncthreads();
+  auto load_tile = [&](int64_t t, f32x4 (&a)[NS]) {
+    int64_t row = t * 32 + l32;
+    row = row < P ? row : P - 1;
+    const float* xr = X + row * K + 4 * h;
+#pragma unroll
+    for (int st = 0; st < NS; ++st) a[st] = *(const f32x4*)(xr + 8 * st);
+  };
+  const int64_t stride = (int64_t)gridDim.x * kTtmWaves;
+  int64_t tile = (int64_t)blockIdx.x * kTtmWaves + wave;
+  f32x4 an[NS];
+  if (tile < ntiles) load_tile(tile, an);
+  for (; tile < ntiles; tile += stride) {
+    asm volatile("" ::: "memory");  // factor reads stay in the loop
+    f32x4 a[NS];
+#pragma unroll
+    for (int st = 0; st < NS; ++st) a[st] = an[st];
+    load_tile(tile + stride < ntiles ? tile + stride : tile, an);
+    __builtin_amdgcn_sched_barrier(0);
+    f32x16 acc[NCB];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[cb][v] = 0.f;
+#pragma unroll
+    for (int st = 0; st < NS; ++st) {
+      f32x4 b[NCB];
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) b[cb] = *(const f32x4*)(Bt + (cb * 32 + l32) * pitch + 8 * st + 4 * h);
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb)
+          acc[cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[st][j], b[cb][j], acc[cb], 0, 0, 0);
+    }
+    const int64_t r0 = tile * 32;
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int64_t row = r0 + 8 * (v >> 2) + 4 * h + (v & 3);
+        const int c = c0 + cb * 32 + l32;
+        if (row < P && c < R) C[row * R + c] = acc[cb][v];
+      }
   }
 }
 
@@ -1641,6 +1713,16 @@ hipError_t launch_ttm_kc(const T* X, const T* B, T* C, int64_t P, int64_t K, int
   return hipGetLastError();
 }
 
+template <int NCB>
+hipError_t launch_ttm_kc32(const float* X, const float* B, float* C, int64_t P, int R, hipStream_t st) {
+  const int64_t ntiles = (P + 31) / 32;
+  const int64_t want = (ntiles + kTtmWaves - 1) / kTtmWaves;
+  const unsigned nx = (unsigned)(want < 256 ? want : 256);
+  const unsigned ny = (unsigned)((R + NCB * 32 - 1) / (NCB * 32));
+  hipLaunchKernelGGL((k_ttm_kc32<NCB>), dim3(nx, ny), dim3(kTtmThreads), 0, st, X, B, C, P, R, ntiles);
+  return hipGetLastError();
+}
+
 template <typename T, int NCB>
 hipError_t launch_ttm_kcx(const T* X, const T* B, T* C, int64_t P, int64_t K, int R, hipStream_t st) {
   constexpr int V = 16 / sizeof(T);
@@ -1711,6 +1793,13 @@ hipError_t launch_ttm_rb_ncb(const T* X, const T* B, T* C, int64_t P, int64_t K,
 template <typename T>
 hipError_t launch_ttm(const T* X, const T* B, T* C, int64_t P, int64_t K, int64_t Q, int R,
                       hipStream_t st) {
+  if (sizeof(T) == 4 && Q == 1 && K == 128 && R > 16 && R <= 64 && ((uintptr_t)X % 16) == 0) {
+    const float* Xf = (const float*)X;
+    const float* Bf = (const float*)B;
+    float* Cf = (float*)C;
+    if (R <= 32) return launch_ttm_kc32<1>(Xf, Bf, Cf, P, R, st);
+    return launch_ttm_kc32<2>(Xf, Bf, Cf, P, R, st);
+  }
   if (Q == 1 && K <= 32 * (int64_t)(16 / sizeof(T)) && R <= 64) {
     if (R <= 16) return launch_ttm_kc<T, 1>(X, B, C, P, K, R, st);
     if (R <= 32) return launch_ttm_kc<T, 2>(X, B, C, P, K, R, st);

@@ -45,6 +45,11 @@ CASES = [
     ((700, 9, 8), 40, "f32"),
     ((300, 10, 8), 70, "f32"),
     ((520, 65, 3), 20, "f32"),
+    # FP32 last mode of exactly 128 (the 32x32x2 kernel): one and two 32-column blocks, ragged
+    # 32-row tiles, R not a multiple of 32
+    ((37, 5, 128), 24, "f32"),
+    ((21, 9, 128), 64, "f32"),
+    ((7, 3, 2, 128), 50, "f32"),
 ]
 
 

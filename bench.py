@@ -493,17 +493,21 @@ def main():
     torch.cuda.synchronize()
     # per-kind timing of single sweeps (reported breakdown, separate from the timed steps)
     log("[bench] timed region")
-    # inside the timed region only the first-level contractions carry event
-    # pairs (their average launch time feeds the roofline); the other phases
-    # are timed on one more step afterwards
+    # inside the timed region only the first-level contractions of the last
+    # timed step carry event pairs (their average launch time feeds the
+    # roofline; each pair costs device time); the other phases are timed on
+    # one more step afterwards
     for k in ("dt", "msdt"):
-        plans[k].profile(True, phases=("ttm",))
+        plans[k].profile(False)
         plans[k].profile_read()
     evs = [{k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
             for k in ("dt", "msdt", "pp")} for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(args.steps):
+        if s == args.steps - 1:
+            for k in ("dt", "msdt"):
+                plans[k].profile(True, phases=("ttm",))
         one_step(evs[s])
     torch.cuda.synchronize()
     t1 = time.perf_counter()

@@ -22,6 +22,8 @@ namespace {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 // ---------------------------------------------------------------------------
@@ -928,16 +930,57 @@ __device__ inline void block_sums(double (&v)[K], double* sh) {
   __syncthreads();
 }
 
+// Sum of squares of the 16-byte piece v (E elements of type T), in element order.
+template <typename T>
+__device__ inline double piece_norm2(u32x4 v) {
+  double s = 0.0;
+  if constexpr (sizeof(T) == 8) {
+    const f64x2 d = __builtin_bit_cast(f64x2, v);
+    s = d[0] * d[0] + d[1] * d[1];
+  } else if constexpr (sizeof(T) == 4) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const double x = (double)__uint_as_float(v[u]);
+      s += x * x;
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const uint32_t w = v[u >> 1];
+      const double x = (double)__uint_as_float((u & 1) ? (w & 0xffff0000u) : (w << 16));
+      s += x * x;
+    }
+  }
+  return s;
+}
+
+// Partial sums of squares: thread t of workgroup b takes the 16-byte pieces
+// g, g + G, ... (g = 256 b + t, G = 256 gridDim.x), four in flight, each into
+// its own FP64 sum; the elements after the last whole piece (or all of them
+// when X is not 16-byte aligned) one by one.  Fixed order: deterministic.
 template <typename T>
 __global__ __launch_bounds__(256) void k_norm2_part(const T* __restrict__ X, int64_t n,
                                                     double* __restrict__ part) {
   __shared__ double sh[256];
-  double s = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-    const double v = (double)X[i];
-    s += v * v;
+  constexpr int E = 16 / (int)sizeof(T);
+  const int64_t nv = (((uintptr_t)X & 15) == 0) ? n / E : 0;
+  const u32x4* __restrict__ V = (const u32x4*)X;
+  const int64_t G = (int64_t)gridDim.x * 256;
+  int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  for (; i + 3 * G < nv; i += 4 * G) {
+    u32x4 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = V[i + u * G];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) s[u] += piece_norm2<T>(v[u]);
   }
-  const double t = block_sum(s, sh);
+  for (; i < nv; i += G) s[0] += piece_norm2<T>(V[i]);
+  for (int64_t e = nv * E + (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += G) {
+    const double v = (double)X[e];
+    s[1] += v * v;
+  }
+  const double t = block_sum((s[0] + s[1]) + (s[2] + s[3]), sh);
   if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 

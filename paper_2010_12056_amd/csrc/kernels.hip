@@ -14,6 +14,8 @@
 // runs give bitwise-identical results.
 #include <math.h>
 
+#include <atomic>
+
 #include "kernels.h"
 #include "blocked_inverse.h"
 
@@ -1698,6 +1700,20 @@ __global__ __launch_bounds__(256) void k_fitness(const double* __restrict__ M, c
 
 inline unsigned nblocks(int64_t n) { return (unsigned)((n + 255) / 256); }
 
+// Raise a kernel's dynamic LDS limit on the current device, once per device
+// (the attribute belongs to the device; two first calls at once both set it,
+// harmlessly).  `done` holds one bit per device index below 64.
+inline hipError_t lds_limit_once(std::atomic<uint64_t>& done, const void* fn, int bytes) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  const uint64_t bit = (dev >= 0 && dev < 64) ? (1ull << dev) : 0;
+  if (bit && (done.load(std::memory_order_acquire) & bit)) return hipSuccess;
+  e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e == hipSuccess && bit) done.fetch_or(bit, std::memory_order_release);
+  return e;
+}
+
 
 
 }  // namespace
@@ -1709,12 +1725,10 @@ hipError_t launch_ttm_rb(const T* X, const T* B, T* C, int64_t P, int64_t K, int
   constexpr int CH = 8 * 4 * V;
   const int Kp = (int)((K + CH - 1) / CH * CH);
   const size_t lds = (size_t)NCB * 16 * (Kp + V) * sizeof(T);
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_ttm_rb<T, KC, NCB>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  static std::atomic<uint64_t> attr{0};
+  {
+    hipError_t e = lds_limit_once(attr, (const void*)k_ttm_rb<T, KC, NCB>, 160 * 1024);
     if (e != hipSuccess) return e;
-    attr = true;
   }
   const int64_t tilesQ = KC ? 1 : (Q + 31) / 32;
   const int64_t ntiles = KC ? (P + 31) / 32 : P * tilesQ;
@@ -1797,15 +1811,11 @@ hipError_t launch_ttm_q(const float* X, const float* B, float* C, int64_t P, int
                         hipStream_t st) {
   const int Kp = (int)((K + 31) / 32 * 32);
   const size_t lds = (size_t)NCB * 16 * (Kp + 4) * sizeof(float);
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_ttm_q<NCB, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       160 * 1024);
-    if (e == hipSuccess)
-      e = hipFuncSetAttribute((const void*)k_ttm_q<NCB, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              160 * 1024);
+  static std::atomic<uint64_t> attr_g{0}, attr_f{0};
+  {
+    hipError_t e = lds_limit_once(attr_g, (const void*)k_ttm_q<NCB, false>, 160 * 1024);
+    if (e == hipSuccess) e = lds_limit_once(attr_f, (const void*)k_ttm_q<NCB, true>, 160 * 1024);
     if (e != hipSuccess) return e;
-    attr = true;
   }
   const int64_t tilesQ = (Q + 63) / 64;
   const int64_t ntiles = P * tilesQ;
@@ -1976,11 +1986,10 @@ hipError_t launch_inverse(const double* Gamma, double* Ginv, int R, DevStats* st
   } else {
     hipLaunchKernelGGL(k_inv_blk<128>, dim3(1), dim3(256), 0, st, Gamma, Ginv, R, stats);
   }
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_pinv, hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+  static std::atomic<uint64_t> attr{0};
+  {
+    hipError_t e = lds_limit_once(attr, (const void*)k_pinv, 150 * 1024);
     if (e != hipSuccess) return e;
-    attr = true;
   }
   const size_t lds = pinv_lds_doubles(R) * sizeof(double);
   hipLaunchKernelGGL(k_pinv, dim3(1), dim3(512), lds, st, Gamma, Ginv, R, stats);
@@ -2086,12 +2095,10 @@ __global__ __launch_bounds__(256) void k_update_reduce(UpdateArgs<T> a, int G) {
 
 template <typename T, int RP, bool PP>
 hipError_t launch_update_rp(const UpdateArgs<T>& a, int groups, hipStream_t st) {
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_update<T, RP, PP>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+  static std::atomic<uint64_t> attr{0};
+  {
+    hipError_t e = lds_limit_once(attr, (const void*)k_update<T, RP, PP>, 150 * 1024);
     if (e != hipSuccess) return e;
-    attr = true;
   }
   size_t dbl = update_solve_lds_doubles(RP);
   if (a.inv_next && a.fused) {

@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <atomic>
 #include <cmath>
 
 #include "../../include/cpals.h"
@@ -160,14 +161,20 @@ bool dims_ok(int B, int D, int H) {
 
 // The largest parameter vector (D = 16, H = 128) takes 75 KB of LDS, above
 // the default dynamic limit of 64 KB.
+// The attribute belongs to the device: set once per device index (one bit
+// each below 64; two first calls at once both set it, harmlessly).
 hipError_t allow_large_lds() {
-  static bool done = false;
-  if (done) return hipSuccess;
+  static std::atomic<uint64_t> done{0};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  const uint64_t bit = (dev >= 0 && dev < 64) ? (1ull << dev) : 0;
+  if (bit && (done.load(std::memory_order_acquire) & bit)) return hipSuccess;
   const int bytes = (int)(offsets(kMaxInput, kMaxHidden).n * sizeof(float));
-  hipError_t e = hipFuncSetAttribute((const void*)k_mlp_forward, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  e = hipFuncSetAttribute((const void*)k_mlp_forward, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void*)k_mlp_back_rows, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  if (e == hipSuccess) done = true;
+  if (e == hipSuccess && bit) done.fetch_or(bit, std::memory_order_release);
   return e;
 }
 

@@ -272,6 +272,84 @@ __global__ __launch_bounds__(512) void k_ttm_rb(const T* __restrict__ X, const T
   }
 }
 
+// First-level contraction over a mode followed by a short run of q
+// (1 < Q < 64), K <= 8 * 4V: the output rows (p, q) are numbered
+// rho = p Q + q, as C[p][q][r] is stored, and tiled 16 at a time as in
+// k_ttm_kc, so no row of a tile is wasted on a short q.  Element k of row
+// rho is X[p][k][q] at (rho / Q) K Q + rho % Q + k Q: lane (row, g = lane /
+// 16) loads the four elements k = t*4V + g*V + u, u < V, of its row with
+// four single loads per t (runs of Q elements; the tensor is still read
+// about once, from the caches).  Rows beyond P Q are clamped for loads and
+// masked for stores; k beyond K is clamped to K - 1 and meets zero rows of
+// the staged factor.
+template <typename T, int NCB, int NTS>
+__global__ __launch_bounds__(512) void k_ttm_sq(const T* __restrict__ X, const T* __restrict__ B,
+                                                T* __restrict__ C, int64_t rows, int64_t K, int64_t Q, int R,
+                                                int64_t ntiles) {
+  constexpr int V = 16 / sizeof(T);
+  constexpr int KT = 4 * V;
+  constexpr int KP = NTS * KT;
+  constexpr int pitch = KP + V;
+  constexpr int NC = NCB * 16;
+  typedef typename Vec16<T>::type VT;
+  __shared__ __align__(16) T Bt[NC * pitch];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane >> 4, l16 = lane & 15;
+  const int c0 = blockIdx.y * NC;
+  for (int idx = tid; idx < KP * NC; idx += kTtmThreads) {
+    const int k = idx / NC, col = idx - k * NC;
+    Bt[col * pitch + k] = (k < K && c0 + col < R) ? B[(int64_t)k * R + c0 + col] : T(0);
+  }
+  __syncthreads();
+  auto load_tile = [&](int64_t t, VT (&a)[NTS]) {
+    int64_t rho = t * 16 + l16;
+    rho = rho < rows ? rho : rows - 1;
+    const int64_t p = rho / Q;
+    const T* xr = X + p * K * Q + (rho - p * Q);
+#pragma unroll
+    for (int st = 0; st < NTS; ++st)
+#pragma unroll
+      for (int u = 0; u < V; ++u) {
+        const int64_t k = st * KT + g * V + u;
+        a[st][u] = xr[(k < K ? k : K - 1) * Q];
+      }
+  };
+  const int64_t stride = (int64_t)gridDim.x * kTtmWaves;
+  int64_t tile = (int64_t)blockIdx.x * kTtmWaves + wave;
+  VT an[NTS];
+  if (tile < ntiles) load_tile(tile, an);
+  for (; tile < ntiles; tile += stride) {
+    asm volatile("" ::: "memory");  // factor reads stay in the loop
+    VT a[NTS];
+#pragma unroll
+    for (int st = 0; st < NTS; ++st) a[st] = an[st];
+    load_tile(tile + stride < ntiles ? tile + stride : tile, an);
+    __builtin_amdgcn_sched_barrier(0);
+    typename Mma<T>::acc_t acc[NCB];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) acc[cb] = Mma<T>::zero();
+#pragma unroll
+    for (int st = 0; st < NTS; ++st) {
+      VT b[NCB];
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) b[cb] = *(const VT*)(Bt + (cb * 16 + l16) * pitch + st * KT + g * V);
+#pragma unroll
+      for (int u = 0; u < V; ++u)
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) acc[cb] = Mma<T>::mma(a[st][u], b[cb][u], acc[cb]);
+    }
+    T* ct = C + tile * 16 * R;
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = Mma<T>::row(lane, v);
+        const int c = c0 + cb * 16 + l16;
+        if (tile * 16 + r < rows && c < R) ct[r * R + c] = acc[cb][v];
+      }
+  }
+}
+
 // First-level contraction over the last mode for K <= 8 * 4V (one register
 // chunk): X is P x K row-major.  16-row output tiles per wave, eight waves
 // per workgroup, the factor transposed in LDS and re-read per tile; each
@@ -1781,6 +1859,23 @@ hipError_t launch_ttm_kc32(const float* X, const float* B, float* C, int64_t P, 
 }
 
 template <typename T, int NCB>
+hipError_t launch_ttm_sq(const T* X, const T* B, T* C, int64_t P, int64_t K, int64_t Q, int R, hipStream_t st) {
+  constexpr int KT = 4 * (16 / sizeof(T));
+  const int64_t rows = P * Q;
+  const int64_t ntiles = (rows + 15) / 16;
+  const int64_t want = (ntiles + kTtmWaves - 1) / kTtmWaves;
+  const unsigned nx = (unsigned)(want < 256 ? want : 256);
+  const unsigned ny = (unsigned)((R + NCB * 16 - 1) / (NCB * 16));
+  if (K <= 2 * KT)
+    hipLaunchKernelGGL((k_ttm_sq<T, NCB, 2>), dim3(nx, ny), dim3(kTtmThreads), 0, st, X, B, C, rows, K, Q, R, ntiles);
+  else if (K <= 4 * KT)
+    hipLaunchKernelGGL((k_ttm_sq<T, NCB, 4>), dim3(nx, ny), dim3(kTtmThreads), 0, st, X, B, C, rows, K, Q, R, ntiles);
+  else
+    hipLaunchKernelGGL((k_ttm_sq<T, NCB, 8>), dim3(nx, ny), dim3(kTtmThreads), 0, st, X, B, C, rows, K, Q, R, ntiles);
+  return hipGetLastError();
+}
+
+template <typename T, int NCB>
 hipError_t launch_ttm_kcx(const T* X, const T* B, T* C, int64_t P, int64_t K, int R, hipStream_t st) {
   constexpr int V = 16 / sizeof(T);
   const int64_t ntiles = (P + 15) / 16;
@@ -1857,6 +1952,12 @@ hipError_t launch_ttm(const T* X, const T* B, T* C, int64_t P, int64_t K, int64_
     if (R <= 16) return launch_ttm_kc<T, 1>(X, B, C, P, K, R, st);
     if (R <= 32) return launch_ttm_kc<T, 2>(X, B, C, P, K, R, st);
     return launch_ttm_kc<T, 4>(X, B, C, P, K, R, st);
+  }
+  if (Q > 1 && Q < 64 && K <= 32 * (int64_t)(16 / sizeof(T)) && R <= 64) {
+    // a short run of q after the contracted mode: rows (p, q) tiled without waste
+    if (R <= 16) return launch_ttm_sq<T, 1>(X, B, C, P, K, Q, R, st);
+    if (R <= 32) return launch_ttm_sq<T, 2>(X, B, C, P, K, Q, R, st);
+    return launch_ttm_sq<T, 4>(X, B, C, P, K, Q, R, st);
   }
   if (Q == 1 && K > 32 * (int64_t)(16 / sizeof(T))) {
     // chunked factor, any K (f32: chunks of 128, f64: 64)

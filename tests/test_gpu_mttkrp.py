@@ -50,6 +50,11 @@ CASES = [
     ((37, 5, 128), 24, "f32"),
     ((21, 9, 128), 64, "f32"),
     ((7, 3, 2, 128), 50, "f32"),
+    # a short run of q after the contracted mode (1 < Q < 64: rows (p, q) tiled as one index),
+    # ragged row tiles, one to four column blocks
+    ((30, 41, 33, 9), 50, "f32"),
+    ((30, 41, 33, 9), 50, "f64"),
+    ((50, 100, 3, 2), 17, "f32"),
 ]
 
 

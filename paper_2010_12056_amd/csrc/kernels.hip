@@ -773,25 +773,29 @@ __global__ __launch_bounds__(512) void k_ttm_qx(const float* __restrict__ X, con
   constexpr int pitch = KCH + 4;
   constexpr int NC = NCB * 16;
   constexpr int BPER = KCH * NC / kTtmThreads;
+  constexpr int BQ = BPER / 4;  // factor elements per thread and quarter chunk
   __shared__ __align__(16) float Bt[2][NC * pitch];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, l16 = lane & 15;
   const int c0 = blockIdx.y * NC;
   const int nch = (int)((K + KCH - 1) / KCH);
-  auto load_b = [&](int c, float (&bv)[BPER]) {
+  // quarter j of factor chunk c: the thread's elements q = j BQ .. j BQ + BQ - 1
+  auto load_b = [&](int c, int j, float (&bv)[BQ]) {
 #pragma unroll
-    for (int q = 0; q < BPER; ++q) {
+    for (int i = 0; i < BQ; ++i) {
+      const int q = j * BQ + i;
       const int idx = tid + kTtmThreads * q, k = idx / NC, col = idx - k * NC;
       const int64_t gk = (int64_t)c * KCH + k;
-      bv[q] = (gk < K && c0 + col < R) ? B[gk * R + c0 + col] : 0.f;
+      bv[i] = (gk < K && c0 + col < R) ? B[gk * R + c0 + col] : 0.f;
     }
   };
-  auto store_b = [&](int buf, const float (&bv)[BPER]) {
+  auto store_b = [&](int buf, int j, const float (&bv)[BQ]) {
 #pragma unroll
-    for (int q = 0; q < BPER; ++q) {
+    for (int i = 0; i < BQ; ++i) {
+      const int q = j * BQ + i;
       const int idx = tid + kTtmThreads * q, k = idx / NC, col = idx - k * NC;
       const int kc = k & ~31, kr = k & 31;
-      Bt[buf][col * pitch + kc + 8 * (kr & 3) + (kr >> 2)] = bv[q];
+      Bt[buf][col * pitch + kc + 8 * (kr & 3) + (kr >> 2)] = bv[i];
     }
   };
   auto load_piece = [&](int64_t t, int64_t kc, f32x4 (&a)[8]) {
@@ -814,10 +818,10 @@ __global__ __launch_bounds__(512) void k_ttm_qx(const float* __restrict__ X, con
   const int64_t stride = (int64_t)gridDim.x * kTtmWaves;
   int64_t tb = (int64_t)blockIdx.x * kTtmWaves;
   if (tb >= ntiles) return;  // uniform: the whole workgroup
-  {
-    float bv[BPER];
-    load_b(0, bv);
-    store_b(0, bv);
+  for (int j = 0; j < 4; ++j) {
+    float bv[BQ];
+    load_b(0, j, bv);
+    store_b(0, j, bv);
   }
   const int npc = (int)((K + 31) / 32);  // 32-index pieces
   f32x4 an[8];
@@ -835,14 +839,18 @@ __global__ __launch_bounds__(512) void k_ttm_qx(const float* __restrict__ X, con
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb) acc[u][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
     for (int c = 0; c < nch; ++c) {
-      float bv[BPER];
       const int cn = c + 1 < nch ? c + 1 : 0;
       const int pend = (c + 1) * 4 < npc ? (c + 1) * 4 : npc;  // pieces of this chunk
+      // piece j of the chunk loads quarter j of the next chunk's factor and
+      // writes it into the other buffer after its products (that buffer was
+      // last read before the previous barrier); a chunk of fewer than four
+      // pieces (the last, K % 128 != 0) writes the remaining quarters at its end
       for (int pc = c * 4; pc < pend; ++pc) {
         f32x4 a[8];
 #pragma unroll
         for (int s2 = 0; s2 < 8; ++s2) a[s2] = an[s2];
-        if (pc == c * 4) load_b(cn, bv);
+        float bv[BQ];
+        load_b(cn, pc - c * 4, bv);
         const bool more = pc + 1 < npc;
         load_piece(more ? tile : tnext, more ? (int64_t)(pc + 1) * 32 : 0, an);
         __builtin_amdgcn_sched_barrier(0);
@@ -860,8 +868,14 @@ __global__ __launch_bounds__(512) void k_ttm_qx(const float* __restrict__ X, con
               acc[u][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t][u], bval, acc[u][cb], 0, 0, 0);
           }
         }
+        __builtin_amdgcn_sched_barrier(0);
+        store_b(buf ^ 1, pc - c * 4, bv);
       }
-      store_b(buf ^ 1, bv);
+      for (int j = pend - c * 4; j < 4; ++j) {
+        float bv[BQ];
+        load_b(cn, j, bv);
+        store_b(buf ^ 1, j, bv);
+      }
       buf ^= 1;
       __syncthreads();
     }
@@ -1973,7 +1987,8 @@ hipError_t launch_ttm(const T* X, const T* B, T* C, int64_t P, int64_t K, int64_
     float* Cf = (float*)C;
     if (R <= 16) return launch_ttm_qx<1>(Xf, Bf, Cf, P, K, Q, R, st);
     if (R <= 32) return launch_ttm_qx<2>(Xf, Bf, Cf, P, K, Q, R, st);
-    return launch_ttm_qx<4>(Xf, Bf, Cf, P, K, Q, R, st);  // R > 64: 64-column passes
+    if (R <= 64) return launch_ttm_qx<4>(Xf, Bf, Cf, P, K, Q, R, st);
+    return launch_ttm_qx<8>(Xf, Bf, Cf, P, K, Q, R, st);
   }
   if (K <= 256) {
     if (Q == 1) return launch_ttm_rb_ncb<T, true>(X, B, C, P, K, Q, R, st);

@@ -45,6 +45,7 @@ CASES = [
     ((700, 9, 8), 40, "f32"),
     ((300, 10, 8), 70, "f32"),
     ((520, 65, 3), 20, "f32"),
+    ((260, 7, 10), 128, "f32"),  # 128 columns in one pass, a last factor chunk of one 32-index piece
     # FP32 last mode of exactly 128 (the 32x32x2 kernel): one and two 32-column blocks, ragged
     # 32-row tiles, R not a multiple of 32
     ((37, 5, 128), 24, "f32"),

@@ -646,6 +646,132 @@ __global__ __launch_bounds__(512) void k_ttm_kcx(const T* __restrict__ X, const 
   }
 }
 
+// First-level contraction over the last mode for FP32 when K is longer than
+// 128, on v_mfma_f32_32x32x2f32: the k_ttm_kc32 layout (a wave owns 32 rows;
+// lane (i = lane % 32, h = lane / 32) loads X[row i][8 s + 4 h .. + 3] of
+// each 8-index step s and feeds element j to instruction j) with K in chunks
+// of 128 indices, as in k_ttm_kcx: the factor chunk transposed in LDS,
+// double-buffered, the waves of a workgroup in lockstep over (tile, chunk),
+// one barrier per chunk, a wave past the last tile recomputing the last one
+// without storing.  The next chunk's factor is staged a quarter per four
+// steps (written into the other buffer after their products), and the
+// rows of the next chunk (or of the next tile's first) are in flight while a
+// chunk is multiplied.  Loads are unconditional: rows past P read row P - 1;
+// indices past K read within the row (clamped) and meet zero factor rows.
+template <int NCB, bool VEC>
+__global__ __launch_bounds__(512) void k_ttm_kcx32(const float* __restrict__ X, const float* __restrict__ B,
+                                                   float* __restrict__ C, int64_t P, int64_t K, int R,
+                                                   int64_t ntiles) {
+  constexpr int KP = 128;
+  constexpr int NS = KP / 8;
+  constexpr int pitch = KP + 4;
+  constexpr int NC = NCB * 32;
+  constexpr int BPER = KP * NC / kTtmThreads;
+  constexpr int BQ = BPER / 4;
+  __shared__ __align__(16) float Bt[2][NC * pitch];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int h = lane >> 5, l32 = lane & 31;
+  const int c0 = blockIdx.y * NC;
+  const int nch = (int)((K + KP - 1) / KP);
+  // factor loads are unconditional (index and column clamped); indices past
+  // K are zeroed when written to LDS, columns past R are never stored
+  auto load_b = [&](int c, int j, float (&bv)[BQ]) {
+#pragma unroll
+    for (int i = 0; i < BQ; ++i) {
+      const int idx = tid + kTtmThreads * (j * BQ + i), k = idx / NC, col = idx - k * NC;
+      const int64_t gk = (int64_t)c * KP + k;
+      bv[i] = B[(gk < K ? gk : K - 1) * R + (c0 + col < R ? c0 + col : R - 1)];
+    }
+  };
+  auto store_b = [&](int buf, int c, int j, const float (&bv)[BQ]) {
+#pragma unroll
+    for (int i = 0; i < BQ; ++i) {
+      const int idx = tid + kTtmThreads * (j * BQ + i), k = idx / NC, col = idx - k * NC;
+      Bt[buf][col * pitch + k] = (int64_t)c * KP + k < K ? bv[i] : 0.f;
+    }
+  };
+  auto load_rows = [&](int64_t t, int c, f32x4 (&a)[NS]) {
+    int64_t row = t * 32 + l32;
+    row = row < P ? row : P - 1;
+    const float* xr = X + row * K;
+#pragma unroll
+    for (int st = 0; st < NS; ++st) {
+      const int64_t k = (int64_t)c * KP + 8 * st + 4 * h;
+      if (VEC) {
+        a[st] = *(const f32x4*)(xr + (k + 4 <= K ? k : K - 4));
+      } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) a[st][u] = xr[k + u < K ? k + u : K - 1];
+      }
+    }
+  };
+  const int64_t stride = (int64_t)gridDim.x * kTtmWaves;
+  int64_t tb = (int64_t)blockIdx.x * kTtmWaves;
+  if (tb >= ntiles) return;  // uniform: the whole workgroup
+  for (int j = 0; j < 4; ++j) {
+    float bv[BQ];
+    load_b(0, j, bv);
+    store_b(0, 0, j, bv);
+  }
+  f32x4 an[NS];
+  load_rows(tb + wave < ntiles ? tb + wave : ntiles - 1, 0, an);
+  __syncthreads();
+  int buf = 0;
+  for (; tb < ntiles; tb += stride) {
+    asm volatile("" ::: "memory");
+    const int64_t tile = tb + wave < ntiles ? tb + wave : ntiles - 1;
+    const bool own = tb + wave < ntiles;
+    const int64_t tnext = tb + stride + wave < ntiles ? tb + stride + wave : (tb + stride < ntiles ? ntiles - 1 : tile);
+    f32x16 acc[NCB];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[cb][v] = 0.f;
+    for (int c = 0; c < nch; ++c) {
+      f32x4 a[NS];
+#pragma unroll
+      for (int st = 0; st < NS; ++st) a[st] = an[st];
+      const bool more = c + 1 < nch;
+      const int cn = more ? c + 1 : 0;
+      float bv[BQ];
+      load_b(cn, 0, bv);
+      load_rows(more ? tile : tnext, cn, an);
+      __builtin_amdgcn_sched_barrier(0);
+      const float* bb = Bt[buf];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+#pragma unroll
+        for (int st = 4 * j; st < 4 * j + 4; ++st) {
+          f32x4 b[NCB];
+#pragma unroll
+          for (int cb = 0; cb < NCB; ++cb) b[cb] = *(const f32x4*)(bb + (cb * 32 + l32) * pitch + 8 * st + 4 * h);
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb)
+              acc[cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[st][q], b[cb][q], acc[cb], 0, 0, 0);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        store_b(buf ^ 1, cn, j, bv);
+        if (j < 3) load_b(cn, j + 1, bv);
+      }
+      buf ^= 1;
+      __syncthreads();
+    }
+    if (own) {
+      const int64_t r0 = tile * 32;
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int64_t row = r0 + 8 * (v >> 2) + 4 * h + (v & 3);
+          const int col = c0 + cb * 32 + l32;
+          if (row < P && col < R) C[row * R + col] = acc[cb][v];
+        }
+    }
+  }
+}
+
 // First-level contraction when the contracted mode is not the last one
 // (X[p] is K x Q with q contiguous), FP32, factor resident in LDS (K <= 256).
 // A wave owns 64 consecutive q and 16*NCB rank columns.  Lane (i = lane % 16,
@@ -1902,6 +2028,19 @@ hipError_t launch_ttm_kcx(const T* X, const T* B, T* C, int64_t P, int64_t K, in
 }
 
 template <int NCB>
+hipError_t launch_ttm_kcx32(const float* X, const float* B, float* C, int64_t P, int64_t K, int R, hipStream_t st) {
+  const int64_t ntiles = (P + 31) / 32;
+  const int64_t want = (ntiles + kTtmWaves - 1) / kTtmWaves;
+  const unsigned nx = (unsigned)(want < 256 ? want : 256);
+  const unsigned ny = (unsigned)((R + NCB * 32 - 1) / (NCB * 32));
+  if (K % 4 == 0 && ((uintptr_t)X % 16) == 0)
+    hipLaunchKernelGGL((k_ttm_kcx32<NCB, true>), dim3(nx, ny), dim3(kTtmThreads), 0, st, X, B, C, P, K, R, ntiles);
+  else
+    hipLaunchKernelGGL((k_ttm_kcx32<NCB, false>), dim3(nx, ny), dim3(kTtmThreads), 0, st, X, B, C, P, K, R, ntiles);
+  return hipGetLastError();
+}
+
+template <int NCB>
 hipError_t launch_ttm_qx(const float* X, const float* B, float* C, int64_t P, int64_t K, int64_t Q, int R,
                          hipStream_t st) {
   const int64_t tilesQ = (Q + 63) / 64;
@@ -1972,6 +2111,16 @@ hipError_t launch_ttm(const T* X, const T* B, T* C, int64_t P, int64_t K, int64_
     if (R <= 16) return launch_ttm_sq<T, 1>(X, B, C, P, K, Q, R, st);
     if (R <= 32) return launch_ttm_sq<T, 2>(X, B, C, P, K, Q, R, st);
     return launch_ttm_sq<T, 4>(X, B, C, P, K, Q, R, st);
+  }
+  if (sizeof(T) == 4 && Q == 1 && K > 128 && R > 16 && R <= 64 && P >= 131072) {
+    // FP32, chunked factor on the 32x32x2 instruction, when there are rows enough for 32-row
+    // tiles to keep every wave busy (with fewer, the 16-row tiles of k_ttm_kcx are faster;
+    // R > 64 spills here)
+    const float* Xf = (const float*)X;
+    const float* Bf = (const float*)B;
+    float* Cf = (float*)C;
+    if (R <= 32) return launch_ttm_kcx32<1>(Xf, Bf, Cf, P, K, R, st);
+    return launch_ttm_kcx32<2>(Xf, Bf, Cf, P, K, R, st);
   }
   if (Q == 1 && K > 32 * (int64_t)(16 / sizeof(T))) {
     // chunked factor, any K (f32: chunks of 128, f64: 64)

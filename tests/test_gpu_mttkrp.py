@@ -116,3 +116,27 @@ def test_mttkrp_config_o4_s128_r64_sampled(dev):
         del K
     plan.close()
     del oracle
+
+
+@pytest.mark.parametrize("dims,R", [((1024, 129, 133), 40), ((1024, 128, 260), 24)])
+def test_mttkrp_long_last_mode_many_rows(dev, dims, R):
+    """FP32 first-level contraction over a long last mode with many rows (the
+    32x32x2 chunked kernel takes over from 131072 rows): a ragged last chunk
+    with K % 4 != 0, and an aligned one; modes 0 and 1 rooted at the last."""
+    import oracle
+    from paper_2010_12056_amd import cpals
+
+    say(f"case long last mode dims={dims} R={R}")
+    w = _case(dims, R, 900 + R, np.float32)
+    plan = cpals.Plan(dims, R, prec="f32", tree="dt", device=dev)
+    T = torch.from_numpy(w.T).to(dev)
+    plan.set_tensor(T)
+    A = to_dev(w.init, dev)
+    T64 = w.T.astype(np.float64)
+    for n in (0, 1):
+        ref = oracle.mttkrp_naive(T64, w.init, n)
+        M = plan.mttkrp(A, n, root=2).cpu().numpy()
+        e = relerr(M, ref)
+        say(f"  mode {n}: relerr {e:.2e}")
+        assert e <= 1e-5, (n, e)
+    plan.close()

@@ -48,3 +48,37 @@ def test_o4_s128_r64_dt_msdt_against_oracle(dev):
         plan.close()
         del T
         torch.cuda.empty_cache()
+
+
+def test_o4_s128_r64_pp_schedule_resynced_against_oracle(dev):
+    """Full-size order-4 128^4 FP32 workload, R = 64, on the MSDT plan the
+    benchmark times for its PP schedule (exact, init, approximated x 2): the
+    oracle is restarted from the GPU's factors before every step (A_p taken
+    from them at the initialization), so each comparison measures one step's
+    rounding.  The approximated steps run far from convergence here, where
+    both sides clamp the estimated residual at zero (Eq. (3) goes negative);
+    their factors are compared."""
+    from oracle import core, pp
+    from paper_2010_12056_amd import synth
+
+    say("case full-size o4_s128_r64_f32 PP schedule")
+    w = synth.workload("o4_s128_r64_f32")
+    T64 = w.T.astype(np.float64)
+    plan, T, A = _plan(w, "f32", "msdt", dev)
+    st = pp.PPState.start(T64, w.init)
+    for step, kind in enumerate(["exact", "init", "approx", "approx"]):
+        st.A = [a.cpu().numpy().copy() for a in A]
+        st.S = [core.gram(a) for a in st.A]
+        if st.phase == "pp":
+            st.dA = [st.A[i] - st.Ap[i] for i in range(len(st.A))]
+        info = plan.pp_sweep(A, mode=kind)
+        pp.pp_als_step(st, force=kind)
+        say(f"  step {step} {kind}: fitness {info['fitness']:.8f} oracle {st.last_fit_est:.8f}")
+        assert info["kind"] == kind
+        assert abs(info["fitness"] - st.last_fit_est) <= 1e-6, (step, kind)
+        for n in range(4):
+            e = relerr(A[n].cpu().numpy(), st.A[n])
+            assert e <= 1e-4, (step, kind, n, e)
+    plan.close()
+    del T
+    torch.cuda.empty_cache()

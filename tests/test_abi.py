@@ -116,3 +116,51 @@ def test_workspace_size_and_state_errors():
     assert b"workspace" in L.cp_last_error(h)
     assert L.cp_plan_set_workspace(h, ctypes.c_void_p(256), 16) == cpals.CP_ERR_ARG
     assert L.cp_plan_destroy(h) == cpals.CP_OK
+
+
+def test_batch_create_layout_and_argument_checks():
+    """Batched path, host side: limits (1 <= s <= 96, 1 <= R <= 32), the
+    packed layout (tensors 16-byte aligned, factors back to back, offsets by
+    the caller's order) and the launch / workspace argument checks."""
+    from paper_2010_12056_amd import cpals
+
+    L = _lib()
+    L.cp_batch_destroy.restype = None
+    b = ctypes.c_void_p()
+
+    def dims_of(lst):
+        return (ctypes.c_int64 * (3 * len(lst)))(*[x for d in lst for x in d])
+
+    def ranks_of(lst):
+        return (ctypes.c_int * len(lst))(*lst)
+
+    assert L.cp_batch_create(ctypes.byref(b), 0, dims_of([(4, 4, 4)]), ranks_of([2]), None) == cpals.CP_ERR_ARG
+    assert L.cp_batch_create(None, 1, dims_of([(4, 4, 4)]), ranks_of([2]), None) == cpals.CP_ERR_ARG
+    for bad_dims, bad_r in (((97, 4, 4), 2), ((4, 0, 4), 2), ((4, 4, 4), 33), ((4, 4, 4), 0)):
+        assert L.cp_batch_create(ctypes.byref(b), 1, dims_of([bad_dims]), ranks_of([bad_r]), None) == \
+            cpals.CP_ERR_UNSUPPORTED
+    shapes = [(3, 5, 7), (16, 16, 16), (1, 1, 1), (96, 2, 9)]
+    ranks = [3, 32, 1, 8]
+    assert L.cp_batch_create(ctypes.byref(b), 4, dims_of(shapes), ranks_of(ranks), None) == cpals.CP_OK
+    toff = (ctypes.c_int64 * 4)()
+    aoff = (ctypes.c_int64 * 12)()
+    ttot, atot = ctypes.c_int64(), ctypes.c_int64()
+    assert L.cp_batch_layout(b, toff, aoff, ctypes.byref(ttot), ctypes.byref(atot)) == cpals.CP_OK
+    padded = [-(-(x * y * z) // 4) * 4 for x, y, z in shapes]
+    assert ttot.value == sum(padded)
+    assert atot.value == sum(sum(d) * r for d, r in zip(shapes, ranks))
+    # tensors: disjoint, 16-byte aligned, covering [0, t_total)
+    spans = sorted((toff[i], padded[i]) for i in range(4))
+    assert all(o % 4 == 0 for o, _ in spans)
+    assert spans[0][0] == 0 and all(spans[i][0] + spans[i][1] == spans[i + 1][0] for i in range(3))
+    # factors: each of s_m x R, disjoint, covering [0, a_total)
+    fac = sorted((aoff[3 * i + m], shapes[i][m] * ranks[i]) for i in range(4) for m in range(3))
+    assert fac[0][0] == 0 and all(fac[j][0] + fac[j][1] == fac[j + 1][0] for j in range(11))
+    assert L.cp_batch_set_launch(b, 3, 1) == cpals.CP_ERR_UNSUPPORTED
+    assert L.cp_batch_set_launch(b, 8, 0) == cpals.CP_ERR_UNSUPPORTED
+    assert L.cp_batch_set_launch(b, 8, 1) == cpals.CP_OK
+    n = ctypes.c_size_t()
+    assert L.cp_batch_workspace_size(b, ctypes.byref(n)) == cpals.CP_OK and n.value > 0
+    assert L.cp_batch_set_workspace(b, ctypes.c_void_p(256 + 8), n.value) == cpals.CP_ERR_ARG  # misaligned
+    assert L.cp_batch_set_workspace(b, ctypes.c_void_p(256), n.value - 1) == cpals.CP_ERR_ARG  # too small
+    L.cp_batch_destroy(b)

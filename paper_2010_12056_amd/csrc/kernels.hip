@@ -1884,14 +1884,22 @@ __global__ __launch_bounds__(256) void k_mttv_split(const TI* __restrict__ X, co
   if (j < QR) {
     const int r = (int)(j % R);
     const TI* x = X + p * I * QR + j;
-    TO s0 = 0, s1 = 0;
+    // group ig takes i = ig, ig + 4, ...: eight of them per pass, each into
+    // its own partial sum (eight loads in flight), then the remainder
+    TO sp[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     int64_t i = ig;
-    for (; i + 4 < I; i += 8) {
-      s0 += (TO)x[i * QR] * (TO)A[i * R + r];
-      s1 += (TO)x[(i + 4) * QR] * (TO)A[(i + 4) * R + r];
+    for (; i + 28 < I; i += 32) {
+      TI xv[8], av[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        xv[u] = x[(i + 4 * u) * QR];
+        av[u] = A[(i + 4 * u) * R + r];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) sp[u] += (TO)xv[u] * (TO)av[u];
     }
-    if (i < I) s0 += (TO)x[i * QR] * (TO)A[i * R + r];
-    s = s0 + s1;
+    for (; i < I; i += 4) sp[0] += (TO)x[i * QR] * (TO)A[i * R + r];
+    s = ((sp[0] + sp[1]) + (sp[2] + sp[3])) + ((sp[4] + sp[5]) + (sp[6] + sp[7]));
   }
   red[ig][jj] = s;
   __syncthreads();

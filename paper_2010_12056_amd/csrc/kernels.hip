@@ -1213,16 +1213,34 @@ __global__ __launch_bounds__(256) void k_norm2_final(const double* __restrict__ 
   if (threadIdx.x == 0) stats->normT2 = t;
 }
 
-// S[a][b] = sum_r A[r][a] A[r][b], one thread per entry, rows in order.
+// S[a][b] = sum_r A[r][a] A[r][b]: a workgroup takes 64 entries; thread
+// group g (of four) the rows r = g, g + 4, ..., four of them per pass into
+// four partial sums (eight loads in flight); the groups' sums are added in a
+// fixed order.
 __global__ __launch_bounds__(256) void k_gram(const double* __restrict__ A, int64_t s, int R,
                                               double* __restrict__ S) {
-  const int e = blockIdx.x * 256 + threadIdx.x;
-  if (e >= R * R) return;
-  const int a = e / R, b = e % R;
-  double acc = 0.0;
-#pragma unroll 8
-  for (int64_t r = 0; r < s; ++r) acc += A[r * R + a] * A[r * R + b];  // eight rows in flight
-  S[e] = acc;
+  __shared__ double red[4][64];
+  const int jj = threadIdx.x & 63, ig = threadIdx.x >> 6;
+  const int e = blockIdx.x * 64 + jj;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  if (e < R * R) {
+    const int a = e / R, b = e - (e / R) * R;
+    int64_t r = ig;
+    for (; r + 12 < s; r += 16) {
+      double x[4], y[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        x[u] = A[(r + 4 * u) * R + a];
+        y[u] = A[(r + 4 * u) * R + b];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] += x[u] * y[u];
+    }
+    for (; r < s; r += 4) acc[0] += A[r * R + a] * A[r * R + b];
+  }
+  red[ig][jj] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+  __syncthreads();
+  if (ig == 0 && e < R * R) S[e] = (red[0][jj] + red[1][jj]) + (red[2][jj] + red[3][jj]);
 }
 
 // Entry e of Gamma^(n) and of W^(n): the product over m != n of S[m][e]
@@ -2240,7 +2258,7 @@ hipError_t launch_norm2(const T* X, int64_t n, double* partials, int nparts, Dev
 }
 
 hipError_t launch_gram(const double* A, int64_t s, int R, double* S, hipStream_t st) {
-  hipLaunchKernelGGL(k_gram, dim3(nblocks((int64_t)R * R)), dim3(256), 0, st, A, s, R, S);
+  hipLaunchKernelGGL(k_gram, dim3((unsigned)(((int64_t)R * R + 63) / 64)), dim3(256), 0, st, A, s, R, S);
   return hipGetLastError();
 }
 

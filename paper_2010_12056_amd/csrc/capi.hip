@@ -624,16 +624,20 @@ cp_status check_ready(cp_plan p) {
   return CP_OK;
 }
 
-// Shadows and Gram matrices from the caller's factors.
+// Shadows and Gram matrices from the caller's factors (one setup launch for
+// every mode's conversion, Gram matrix and zero dS, and W), then Gamma^(0).
 cp_status init_state(cp_plan p, double* const* A) {
+  SetupBatch sb;
+  const int64_t RR = (int64_t)p->R * p->R;
   for (int m = 0; m < p->N; ++m) {
-    CP_TRY(convert_factor(p, A[m], p->Ash[m], p->dims[m] * p->R));
-    HIP_TRY(p, launch_gram(A[m], p->dims[m], p->R, p->S[m], p->st));
-    HIP_TRY(p, launch_zero_f64(p->dS[m], (int64_t)p->R * p->R, p->st));
+    sb.op[sb.nops++] = {A[m], p->Ash[m], p->dims[m] * p->R, p->prec == CP_F64 ? kSetupToF64 : kSetupToF32, 0};
+    sb.op[sb.nops++] = {A[m], p->S[m], p->dims[m], kSetupGram, p->R};
+    sb.op[sb.nops++] = {nullptr, p->dS[m], 2 * RR, kSetupZero32, 0};
     ++p->ver[m];
   }
+  sb.op[sb.nops++] = {nullptr, p->W, 2 * RR, kSetupZero32, 0};
+  HIP_TRY(p, launch_setup(sb, p->st));
   CP_TRY(form_gamma(p, 0, false));
-  HIP_TRY(p, launch_zero_f64(p->W, (int64_t)p->R * p->R, p->st));
   p->state_ready = true;
   p->fresh = true;
   return CP_OK;
@@ -762,12 +766,18 @@ cp_status pp_node(cp_plan p, const std::vector<std::vector<PPNode>>& lv, int l, 
 
 cp_status pp_init(cp_plan p, double* const* A) {
   const int N = p->N;
+  // A_p <- A; dA = 0, so dS = 0, W^(0) = 0 and the shadow of dA (read only by
+  // the first-order corrections) is zero; Gamma^(0) is current (S unchanged).
+  // One setup launch.
+  SetupBatch sb;
+  const int64_t RR = (int64_t)p->R * p->R;
   for (int m = 0; m < N; ++m) {
-    HIP_TRY(p, launch_copy_f64(A[m], p->Ap[m], p->dims[m] * p->R, p->st));
-    HIP_TRY(p, launch_zero_f64(p->dS[m], (int64_t)p->R * p->R, p->st));
+    sb.op[sb.nops++] = {A[m], p->Ap[m], p->dims[m] * p->R, kSetupToF64, 0};
+    sb.op[sb.nops++] = {nullptr, p->dS[m], 2 * RR, kSetupZero32, 0};
+    sb.op[sb.nops++] = {nullptr, p->dAsh[m], p->dims[m] * p->R * (int64_t)(p->esz / 4), kSetupZero32, 0};
   }
-  // dA = 0, so dS = 0 and W^(0) = 0; Gamma^(0) is current (S unchanged)
-  HIP_TRY(p, launch_zero_f64(p->W, (int64_t)p->R * p->R, p->st));
+  sb.op[sb.nops++] = {nullptr, p->W, 2 * RR, kSetupZero32, 0};
+  HIP_TRY(p, launch_setup(sb, p->st));
   // relabel so that the first root is the live first-level node, if any
   int live = -1;
   for (int m = 0; m < N; ++m)
@@ -784,9 +794,6 @@ cp_status pp_init(cp_plan p, double* const* A) {
     const uint32_t set = (1u << a) | (1u << b);
     CP_TRY(contract_any(p, p->pair[a][b], set, x, p->Mp[n], true));
   }
-  // dA <- 0 (its shadow feeds the first-order corrections)
-  for (int m = 0; m < N; ++m)
-    HIP_TRY(p, launch_zero_bytes(p->dAsh[m], (size_t)p->dims[m] * p->R * p->esz, p->st));
   p->have_ops = true;
   p->phase = 1;
   return CP_OK;

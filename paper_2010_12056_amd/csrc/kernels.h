@@ -129,6 +129,24 @@ hipError_t launch_fitness(const double* M, const double* A, int64_t s, int R, co
 hipError_t launch_zero_f64(double* p, int64_t n, hipStream_t st);
 hipError_t launch_zero_bytes(void* p, size_t bytes, hipStream_t st);
 
+// Independent small setup operations run by one launch (each takes its own
+// range of workgroups): FP64 -> FP32 or FP64 conversion (a copy for FP64),
+// zero fill of 32-bit words, Gram matrix S = A^T A of an s x R FP64 factor.
+enum SetupKind { kSetupToF32 = 0, kSetupToF64 = 1, kSetupZero32 = 2, kSetupGram = 3 };
+struct SetupOp {
+  const double* src;  // conversions: source; Gram: A (s x R)
+  void* dst;          // destination (S for Gram)
+  int64_t n;          // elements (conversions), 32-bit words (zero); Gram: s
+  int kind;
+  int R;              // Gram only
+};
+constexpr int kMaxSetupOps = 40;
+struct SetupBatch {
+  SetupOp op[kMaxSetupOps];
+  int nops = 0;
+};
+hipError_t launch_setup(const SetupBatch& b, hipStream_t st);
+
 // First-order PP MTTKRP, Eqs. (5)-(6) without V:
 // M[x][r] = Mp[x][r] + sum_{i != n} sum_y P_(n,i)[x][y][r] dA_i[y][r]
 template <typename T>

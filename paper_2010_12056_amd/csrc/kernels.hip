@@ -1243,6 +1243,54 @@ __global__ __launch_bounds__(256) void k_gram(const double* __restrict__ A, int6
   if (ig == 0 && e < R * R) S[e] = (red[0][jj] + red[1][jj]) + (red[2][jj] + red[3][jj]);
 }
 
+// One launch of independent setup operations; workgroup b runs operation
+// i for first[i] <= b < first[i + 1] (256 threads: 256 elements per
+// workgroup for conversions and fills; 64 Gram entries, as k_gram).
+struct SetupArgs {
+  SetupOp op[kMaxSetupOps];
+  int first[kMaxSetupOps + 1];
+  int nops;
+};
+__global__ __launch_bounds__(256) void k_setup(SetupArgs a) {
+  __shared__ double red[4][64];
+  int i = 0;
+  while (i + 1 < a.nops && (int)blockIdx.x >= a.first[i + 1]) ++i;  // uniform
+  const SetupOp o = a.op[i];
+  const int64_t lb = (int64_t)blockIdx.x - a.first[i];
+  if (o.kind == kSetupGram) {
+    const int R = o.R;
+    const int64_t s = o.n;
+    const double* A = o.src;
+    const int jj = threadIdx.x & 63, ig = threadIdx.x >> 6;
+    const int e = (int)lb * 64 + jj;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    if (e < R * R) {
+      const int ea = e / R, eb = e - (e / R) * R;
+      int64_t r = ig;
+      for (; r + 12 < s; r += 16) {
+        double x[4], y[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          x[u] = A[(r + 4 * u) * R + ea];
+          y[u] = A[(r + 4 * u) * R + eb];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[u] += x[u] * y[u];
+      }
+      for (; r < s; r += 4) acc[0] += A[r * R + ea] * A[r * R + eb];
+    }
+    red[ig][jj] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    __syncthreads();
+    if (ig == 0 && e < R * R) ((double*)o.dst)[e] = (red[0][jj] + red[1][jj]) + (red[2][jj] + red[3][jj]);
+    return;
+  }
+  const int64_t g = lb * 256 + threadIdx.x;
+  if (g >= o.n) return;
+  if (o.kind == kSetupToF32) ((float*)o.dst)[g] = (float)o.src[g];
+  else if (o.kind == kSetupToF64) ((double*)o.dst)[g] = o.src[g];
+  else ((uint32_t*)o.dst)[g] = 0u;
+}
+
 // Entry e of Gamma^(n) and of W^(n): the product over m != n of S[m][e]
 // (Eq. (1)) and the coefficient of t^2 in the product over m != n of
 // (S[m][e] + t dS[m][e]), which is the bracket of Eq. (7).
@@ -2239,6 +2287,24 @@ hipError_t launch_zero_f64(double* p, int64_t n, hipStream_t st) {
 hipError_t launch_fitness(const double* M, const double* A, int64_t s, int R, const double* Gamma,
                           const double* S, DevStats* stats, hipStream_t st) {
   hipLaunchKernelGGL(k_fitness, dim3(1), dim3(256), 0, st, M, A, s * R, Gamma, S, R * R, stats);
+  return hipGetLastError();
+}
+
+hipError_t launch_setup(const SetupBatch& b, hipStream_t st) {
+  if (b.nops < 1) return hipSuccess;
+  if (b.nops > kMaxSetupOps) return hipErrorInvalidValue;
+  SetupArgs a;
+  int blocks = 0;
+  for (int i = 0; i < b.nops; ++i) {
+    a.op[i] = b.op[i];
+    a.first[i] = blocks;
+    const SetupOp& o = b.op[i];
+    const int64_t nb = (o.kind == kSetupGram) ? ((int64_t)o.R * o.R + 63) / 64 : (o.n + 255) / 256;
+    blocks += (int)(nb > 0 ? nb : 1);  // an empty operation keeps one (idle) workgroup
+  }
+  a.first[b.nops] = blocks;
+  a.nops = b.nops;
+  hipLaunchKernelGGL(k_setup, dim3((unsigned)blocks), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 

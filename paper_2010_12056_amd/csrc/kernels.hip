@@ -1916,14 +1916,22 @@ __global__ __launch_bounds__(256) void k_pp_mttkrp(PPArgs<T> a) {
         p = a.pair[i] + x * R + r;  // P[y][x][r]
         ys = sn * R;
       }
+      // y = yg, yg + G, ...: eight per pass into eight partial sums (sixteen
+      // loads in flight), then the remainder; fixed order
       int64_t y = yg;
-      double u0 = 0.0, u1 = 0.0;
-      for (; y + G < si; y += 2 * G) {
-        u0 += (double)p[y * ys] * (double)d[y * R];
-        u1 += (double)p[(y + G) * ys] * (double)d[(y + G) * R];
+      double up[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      for (; y + 7 * G < si; y += 8 * G) {
+        double pv[8], dv[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          pv[k] = (double)p[(y + k * G) * ys];
+          dv[k] = (double)d[(y + k * G) * R];
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) up[k] += pv[k] * dv[k];
       }
-      if (y < si) u0 += (double)p[y * ys] * (double)d[y * R];
-      u += u0 + u1;
+      for (; y < si; y += G) up[0] += (double)p[y * ys] * (double)d[y * R];
+      u += ((up[0] + up[1]) + (up[2] + up[3])) + ((up[4] + up[5]) + (up[6] + up[7]));
     }
   }
   red[tid] = u;

@@ -414,8 +414,8 @@ def main():
                          "on the workload, then a plain 512 MiB device copy as the calibration kernel")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU; runs on more than one GPU are not part of this build "
-              "(--gpus must be 1)", file=sys.stderr)
+        print("bench.py measures one GPU: the multi-GPU decomposition (a processor grid with "
+              "collectives) is not implemented, so --gpus must be 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -154,20 +154,28 @@ __global__ __launch_bounds__(512) void k_ttm_bf16(const uint16_t* __restrict__ X
   };
 
   // ---- tensor step (32 indices from ks) into registers ----
-  // Unguarded layout (FAST: K a multiple of KB, 16-byte aligned rows, KC or
-  // Q a multiple of 8): plain 16-byte loads, converted to MFMA operands only
-  // when used, so the loads of the next step stay in flight meanwhile.
+  // Unguarded layout (FAST: 16-byte aligned rows, K a multiple of 8 for KC,
+  // Q a multiple of 8 otherwise): plain 16-byte loads, converted to MFMA
+  // operands only when used, so the loads of the next step stay in flight
+  // meanwhile.
   // Guarded layout: the operands are formed at load time with every index
   // checked (indices past K read as zero).
   auto issue = [&](const LaneSrc& s, int64_t tile, int ks, u32x4 (&r)[4]) {
     if (FAST) {
+      // indices past K: KC reads the row's last eight (K % 8 == 0, so a
+      // piece is wholly inside or wholly past), otherwise row K - 1; the
+      // factor's zero padding cancels either
       if (KC) {
+        const int kc = ks < K - 8 - 8 * g ? ks : (int)K - 8 - 8 * g;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) r[u] = *(const u32x4*)(s.p[u] + ks);
+        for (int u = 0; u < 4; ++u) r[u] = *(const u32x4*)(s.p[u] + kc);
       } else {
-        const uint16_t* src = s.p[0] + (int64_t)ks * Q;
+        const int kb = 8 * g + 4 * (l16 & 1);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) r[j] = *(const u32x4*)(src + (int64_t)j * Q);
+        for (int j = 0; j < 4; ++j) {
+          const int64_t k = kb + ks + j < K ? kb + ks + j : K - 1;
+          r[j] = *(const u32x4*)(s.p[0] + (k - kb) * Q);
+        }
       }
       return;
     }
@@ -355,7 +363,7 @@ hipError_t launch_ncb(const uint16_t* X, const uint16_t* Bhi, const uint16_t* Bl
   // KC: 16-byte row loads; otherwise 2 = 16-byte loads shared by lane pairs, 1 = 8-byte loads
   const int vec = KC ? (K % 8 == 0 && ((uintptr_t)X % 16) == 0)
                      : ((Q % 8 == 0 && ((uintptr_t)X % 16) == 0) ? 2 : (Q % 4 == 0 && ((uintptr_t)X % 8) == 0));
-  const bool fast = K % KB == 0 && (KC ? vec == 1 : vec == 2);
+  const bool fast = KC ? vec == 1 : vec == 2;
 #define CPALS_BF16_NCB(NCB)                                                                     \
   return fast ? launch_one<KC, NCB, SPLIT, true>(X, Bhi, Blo, C, P, K, Q, R, Kp, vec, st)      \
               : launch_one<KC, NCB, SPLIT, false>(X, Bhi, Blo, C, P, K, Q, R, Kp, vec, st)

@@ -64,6 +64,9 @@ CASES = [
     ((3, 1, 5, 2, 4), 1),
     ((128, 41, 256), 48),
     ((24, 256, 40), 20),
+    # the unguarded loads with K not a multiple of the 64-index chunk (clamped loads meet the
+    # factor's zero padding): K = 40 contiguous, K = 48 and 72 over q
+    ((48, 72, 40), 24),
 ]
 
 

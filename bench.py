@@ -190,15 +190,19 @@ def precision_bench(args):
     t_gen = time.perf_counter()
     w = synth.planted_tensor(dims, R, 3001, kind="lognorm", noise_rel=1e-3, dtype=np.float32)
     bits = synth.bf16_bits(w.T)
+    fp8_scale = synth.fp8_scale(w.T)  # the FP8 copy is the tensor times this power of two
+    bits8 = synth.fp8_bits(w.T, scale=fp8_scale)
     log(f"[bench] generated {PRECISION_WORKLOAD} in {time.perf_counter() - t_gen:.1f}s")
     T32 = torch.from_numpy(w.T).to(dev)
     Tb = torch.from_numpy(bits.view(np.int16)).to(dev).view(torch.bfloat16)
+    T8 = torch.from_numpy(bits8).to(dev).view(torch.float8_e4m3fn)
+    tensors = {"f32": T32, "bf16": Tb, "bf16x2": Tb, "fp8": T8, "fp8x2": T8}
     A0 = [torch.from_numpy(a).to(dev) for a in w.init]
     numel = int(np.prod(dims))
     stream = torch.cuda.current_stream(dev)
     res = {}
-    for prec in ("f32", "bf16", "bf16x2"):
-        T = T32 if prec == "f32" else Tb
+    for prec in ("f32", "bf16", "bf16x2", "fp8", "fp8x2"):
+        T = tensors[prec]
         out = {}
         for tree, nsw in (("dt", 3), ("msdt", 4)):
             plan = cpals.Plan(dims, R, prec=prec, tree=tree, device=dev)
@@ -233,15 +237,23 @@ def precision_bench(args):
     out_bytes = (numel // dims[0]) * R * 4
     ttm_ms = res["bf16x2"]["dt"]["ttm_avg_ms"]
     achieved = (numel * esz + out_bytes) / (ttm_ms * 1e-3) / 1e9
-    # error against the FP64 oracle on the BF16 values, resynced per sweep
+    ttm8_ms = res["fp8x2"]["dt"]["ttm_avg_ms"]
+    achieved8 = (numel + out_bytes) / (ttm8_ms * 1e-3) / 1e9
+    # error against the FP64 oracle on the stored BF16 / FP8 values, resynced per sweep
     log("[bench] oracle checks")
-    T64 = synth.bf16_to_f32(bits).astype(np.float64)
-    del bits
-    normT2 = float(np.sum(T64 * T64))
     errs = {}
-    for prec in ("bf16", "bf16x2"):
+    for prec in ("bf16", "bf16x2", "fp8x2"):
+        if prec == "bf16":
+            T64 = synth.bf16_to_f32(bits).astype(np.float64)
+            del bits
+            normT2 = float(np.sum(T64 * T64))
+        elif prec == "fp8x2":
+            del T64
+            T64 = synth.fp8_to_f32(bits8).astype(np.float64)
+            del bits8
+            normT2 = float(np.sum(T64 * T64))
         plan = cpals.Plan(dims, R, prec=prec, tree="dt", device=dev)
-        plan.set_tensor(Tb)
+        plan.set_tensor(tensors[prec])
         A = [a.clone() for a in A0]
         rows = np.random.default_rng(0).choice(dims[0], 4, replace=False)
         M = plan.mttkrp(A, 0).cpu().numpy()[rows]
@@ -250,7 +262,7 @@ def precision_bench(args):
         ref = X0[rows] @ K
         refabs = np.abs(X0[rows]) @ core.krp([np.abs(w.init[1]), np.abs(w.init[2])])
         del K
-        unit = 2.0 ** -8 if prec == "bf16" else 2.0 ** -16
+        unit = 2.0 ** -8 if prec == "bf16" else 2.0 ** -16  # the factor's rounding; the tensor is exact
         rec = {"mttkrp_rows_relerr": float(np.linalg.norm(M - ref) / np.linalg.norm(ref)),
                "mttkrp_rows_err_over_bound": float(np.max(np.abs(M - ref) / (unit * refabs))),
                "sweeps": []}
@@ -276,11 +288,16 @@ def precision_bench(args):
         "vs_baseline": None,
         "dtype": "bf16x2 (first contraction), f32 levels, f64 solve",
         "data": "synthetic",
-        "config": {"workload": "order-3 dense 1024x1024x1024 stored BF16, planted rank-128 N(0,1) factors with "
+        "config": {"workload": "order-3 dense 1024x1024x1024 stored BF16 (and FP8 E4M3 after a power-of-two scale), planted rank-128 N(0,1) factors with "
                                "log-uniform column norms in [1e-2, 1], noise 1e-3, CP rank 128",
-                   "dims": list(dims), "rank": R},
+                   "dims": list(dims), "rank": R, "fp8_tensor_scale": fp8_scale},
         "by_precision": res,
         "speedup_bf16x2_vs_f32_msdt": round(res["f32"]["msdt"]["ms_per_sweep"] / res["bf16x2"]["msdt"]["ms_per_sweep"], 3),
+        "speedup_fp8x2_vs_f32_msdt": round(res["f32"]["msdt"]["ms_per_sweep"] / res["fp8x2"]["msdt"]["ms_per_sweep"], 3),
+        "roofline_fp8x2": {"kernel": "k_ttm_bf16 (FP8 tensor, split factor, first contraction)", "bound": "hbm",
+                           "achieved": round(achieved8, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                           "frac": round(achieved8 / PEAK_HBM_GBS, 4), "traffic": None,
+                           "bytes_per_launch": numel + out_bytes, "avg_launch_ms": ttm8_ms},
         "roofline": {"kernel": "k_ttm_bf16 (BF16X2, first contraction)", "bound": "hbm",
                      "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,

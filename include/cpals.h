@@ -11,9 +11,9 @@
  *     the caller and borrowed for the duration of the call (the tensor is
  *     borrowed from cp_set_tensor until the next cp_set_tensor or destroy).
  *   - Factor matrices are always FP64 (the ALS state).  The tensor is stored
- *     in the plan's precision (FP64, FP32, or BF16 for the precision path);
- *     contractions with it run in that precision (BF16: on the BF16 matrix
- *     cores with FP32 accumulation), every R x R operation (Gram matrices,
+ *     in the plan's precision (FP64, FP32, or BF16 or FP8 for the precision
+ *     path); contractions with it run in that precision (BF16 and FP8: on the
+ *     BF16 matrix cores with FP32 accumulation), every R x R operation (Gram matrices,
  *     their Hadamard products, the inverse or pseudo-inverse of Gamma, norms,
  *     the residual) runs in FP64.
  *   - All work is enqueued on the plan's HIP stream and the call returns
@@ -57,8 +57,15 @@ typedef enum {
  * contraction runs on the BF16 matrix cores with FP32 accumulation, the
  * factor rounded to BF16 (CP_BF16) or split into two BF16 parts B_hi + B_lo
  * (CP_BF16X2, about 16 significant bits); the levels below are FP32 as in
- * CP_F32. */
-typedef enum { CP_F64 = 0, CP_F32 = 1, CP_BF16 = 2, CP_BF16X2 = 3 } cp_prec;
+ * CP_F32.  CP_FP8 and CP_FP8X2 (not from the paper): the tensor is stored in
+ * FP8 E4M3 (raw bytes: sign, 4 exponent bits with bias 7, 3 mantissa bits,
+ * no infinities; the OCP "e4m3fn" format) and widened exactly to BF16 in
+ * registers, so the first contraction is that of CP_BF16 / CP_BF16X2 on the
+ * stored values with half the tensor bytes.  E4M3 spans 2^-9 .. 448: scale
+ * the tensor by a power of two so that its largest entry lies near 448
+ * before storing it (exact; the relative residual does not depend on the
+ * tensor's scale), else small entries round to zero. */
+typedef enum { CP_F64 = 0, CP_F32 = 1, CP_BF16 = 2, CP_BF16X2 = 3, CP_FP8 = 4, CP_FP8X2 = 5 } cp_prec;
 
 typedef enum {
   CP_TREE_DT = 0,           /* standard binary dimension tree, two first-level TTMs per sweep (Sec. II-C) */

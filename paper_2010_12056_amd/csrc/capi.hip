@@ -133,6 +133,16 @@ struct cp_plan_s {
 
 namespace {
 
+// Low-precision tensors: the first contraction on the BF16 matrix cores with
+// a BF16 factor (split in two parts for the X2 variants); FP32 below.
+bool lowp(cp_prec q) { return q == CP_BF16 || q == CP_BF16X2 || q == CP_FP8 || q == CP_FP8X2; }
+bool split_factor(cp_prec q) { return q == CP_BF16X2 || q == CP_FP8X2; }
+bool fp8(cp_prec q) { return q == CP_FP8 || q == CP_FP8X2; }
+
+// The first contraction of a low-precision tensor X (P x K x Q) with the
+// FP32 factor shadow A (K x R) into FP32 C.
+hipError_t lowp_first_level(cp_plan p, const void* X, const float* A, float* C, int64_t P, int64_t K, int64_t Q);
+
 cp_status fail(cp_plan p, cp_status s, const char* fmt, ...) {
   if (p) {
     char buf[512];
@@ -243,12 +253,12 @@ void plan_layout(cp_plan p) {
   take(sizeof(DevStats));                        // stats
   take(16 * sizeof(float));                      // sw_in
   take(16 * sizeof(float));                      // sw_out
-  const bool bf = (p->prec == CP_BF16 || p->prec == CP_BF16X2);
+  const bool bf = lowp(p->prec);
   const int64_t kc = combined_k(p);  // contraction length of the combined first level (0: none)
   take((size_t)kc * R * p->esz);     // krp
   const int64_t kb = std::max(smax, kc);
   take(bf ? (size_t)R * bf16_factor_pitch(kb) * 2 : 0);                                 // Bt_hi
-  take(p->prec == CP_BF16X2 ? (size_t)R * bf16_factor_pitch(kb) * 2 : 0);               // Bt_lo
+  take(split_factor(p->prec) ? (size_t)R * bf16_factor_pitch(kb) * 2 : 0);              // Bt_lo
   // slots for depths 1..N-2 (depth d keeps N - d modes)
   std::vector<int64_t> sorted(p->dims, p->dims + N);
   std::sort(sorted.begin(), sorted.end(), std::greater<int64_t>());
@@ -288,7 +298,7 @@ void plan_carve(cp_plan p) {
   p->krp = next();
   p->Bt_hi = (uint16_t*)next();
   void* lo = next();
-  p->Bt_lo = (p->prec == CP_BF16X2) ? (uint16_t*)lo : nullptr;
+  p->Bt_lo = split_factor(p->prec) ? (uint16_t*)lo : nullptr;
   for (int d = 1; d <= N - 2; ++d) p->slot_buf[d] = next();
 }
 
@@ -337,6 +347,13 @@ void contract_shape(cp_plan p, uint32_t set, int c, int64_t* P, int64_t* I, int6
   *Q = qq;
 }
 
+hipError_t lowp_first_level(cp_plan p, const void* X, const float* A, float* C, int64_t P, int64_t K, int64_t Q) {
+  hipError_t e = launch_split_factor(A, K, p->R, p->Bt_hi, p->Bt_lo, p->st);
+  if (e != hipSuccess) return e;
+  if (fp8(p->prec)) return launch_ttm_fp8((const uint8_t*)X, p->Bt_hi, p->Bt_lo, C, P, K, Q, p->R, p->st);
+  return launch_ttm_bf16((const uint16_t*)X, p->Bt_hi, p->Bt_lo, C, P, K, Q, p->R, p->st);
+}
+
 // One contraction: input node `in` (or the tensor when in_set is the full
 // set) keeping in_set, contracting mode c, into `out` (tensor precision, or
 // FP64 when out_f64).
@@ -349,9 +366,8 @@ cp_status contract(cp_plan p, const void* in, uint32_t in_set, int c, void* out,
     if (out_f64) return fail(p, CP_ERR_STATE, "internal: first-level contraction into FP64");
     ++p->ttm_count;
     ProfScope ps(p, CP_PHASE_TTM);
-    if (p->prec == CP_BF16 || p->prec == CP_BF16X2) {
-      HIP_TRY(p, launch_split_factor((const float*)A, I, p->R, p->Bt_hi, p->Bt_lo, p->st));
-      HIP_TRY(p, launch_ttm_bf16((const uint16_t*)in, p->Bt_hi, p->Bt_lo, (float*)out, P, I, Q, p->R, p->st));
+    if (lowp(p->prec)) {
+      HIP_TRY(p, lowp_first_level(p, in, (const float*)A, (float*)out, P, I, Q));
     } else {
       HIP_TRY(p, launch_ttm<TT>((const TT*)in, A, (TT*)out, P, I, Q, p->R, p->st));
     }
@@ -383,9 +399,8 @@ cp_status contract_combined(cp_plan p, void* out) {
   ProfScope ps(p, CP_PHASE_TTM);
   HIP_TRY(p, launch_krp2<TT>((const TT*)p->Ash[N - 2], p->dims[N - 2], (const TT*)p->Ash[N - 1], p->dims[N - 1],
                              p->R, (TT*)p->krp, p->st));
-  if (p->prec == CP_BF16 || p->prec == CP_BF16X2) {
-    HIP_TRY(p, launch_split_factor((const float*)p->krp, K, p->R, p->Bt_hi, p->Bt_lo, p->st));
-    HIP_TRY(p, launch_ttm_bf16((const uint16_t*)p->T, p->Bt_hi, p->Bt_lo, (float*)out, P, K, 1, p->R, p->st));
+  if (lowp(p->prec)) {
+    HIP_TRY(p, lowp_first_level(p, p->T, (const float*)p->krp, (float*)out, P, K, 1));
   } else {
     HIP_TRY(p, launch_ttm<TT>((const TT*)p->T, (const TT*)p->krp, (TT*)out, P, K, 1, p->R, p->st));
   }
@@ -904,7 +919,7 @@ cp_status cp_plan_create(cp_plan* out, int order, const int64_t* dims, int rank,
   *out = nullptr;
   if (order < 3 || order > kMaxOrder) return CP_ERR_UNSUPPORTED;
   if (rank < 1 || rank > kMaxRank) return CP_ERR_UNSUPPORTED;
-  if (prec != CP_F64 && prec != CP_F32 && prec != CP_BF16 && prec != CP_BF16X2) return CP_ERR_UNSUPPORTED;
+  if (prec != CP_F64 && prec != CP_F32 && !lowp(prec)) return CP_ERR_UNSUPPORTED;
   if (tree != CP_TREE_DT && tree != CP_TREE_DT_COMBINED && tree != CP_TREE_MSDT) return CP_ERR_UNSUPPORTED;
   double numel = 1.0;
   for (int m = 0; m < order; ++m) {
@@ -954,7 +969,9 @@ cp_status cp_set_tensor(cp_plan p, const void* T) {
   for (int m = 0; m < p->N; ++m) numel *= p->dims[m];
   if (p->prec == CP_F64) {
     HIP_TRY(p, launch_norm2<double>((const double*)T, numel, p->normParts, kNormParts, p->stats, p->st));
-  } else if (p->prec == CP_BF16 || p->prec == CP_BF16X2) {
+  } else if (fp8(p->prec)) {
+    HIP_TRY(p, launch_norm2<fp8e4m3>((const fp8e4m3*)T, numel, p->normParts, kNormParts, p->stats, p->st));
+  } else if (lowp(p->prec)) {
     HIP_TRY(p, launch_norm2<bf16>((const bf16*)T, numel, p->normParts, kNormParts, p->stats, p->st));
   } else {
     HIP_TRY(p, launch_norm2<float>((const float*)T, numel, p->normParts, kNormParts, p->stats, p->st));

@@ -24,6 +24,15 @@ struct bf16 {
   __device__ explicit operator double() const { return (double)__uint_as_float((uint32_t)bits << 16); }
 };
 
+// An FP8 E4M3 tensor element (bias 7, no infinities), decoded exactly by the
+// hardware conversion.
+struct fp8e4m3 {
+  uint8_t bits;
+  __device__ explicit operator double() const {
+    return (double)__builtin_amdgcn_cvt_pk_f32_fp8((int)bits, false)[0];
+  }
+};
+
 constexpr int kMaxOrder = 8;
 constexpr int kMaxRank = 128;
 
@@ -39,6 +48,9 @@ int bf16_factor_pitch(int64_t K);
 hipError_t launch_split_factor(const float* A, int64_t K, int R, uint16_t* hi, uint16_t* lo, hipStream_t st);
 hipError_t launch_ttm_bf16(const uint16_t* X, const uint16_t* Bhi, const uint16_t* Blo, float* C, int64_t P,
                            int64_t K, int64_t Q, int R, hipStream_t st);
+// The same with an FP8 (E4M3) tensor, widened exactly to BF16 in registers.
+hipError_t launch_ttm_fp8(const uint8_t* X, const uint16_t* Bhi, const uint16_t* Blo, float* C, int64_t P,
+                          int64_t K, int64_t Q, int R, hipStream_t st);
 
 // Y[p][q][r] = sum_i X[p][i][q][r] * A[i][r]; accumulation in the output type.
 template <typename TI, typename TO>

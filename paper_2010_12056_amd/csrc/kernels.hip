@@ -1163,12 +1163,23 @@ __device__ inline double piece_norm2(u32x4 v) {
       const double x = (double)__uint_as_float(v[u]);
       s += x * x;
     }
-  } else {
+  } else if constexpr (sizeof(T) == 2) {
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const uint32_t w = v[u >> 1];
       const double x = (double)__uint_as_float((u & 1) ? (w & 0xffff0000u) : (w << 16));
       s += x * x;
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)v[u], false);  // bytes 0, 1
+      const auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)v[u], true);   // bytes 2, 3
+      const double x0 = lo[0], x1 = lo[1], x2 = hi[0], x3 = hi[1];
+      s += x0 * x0;
+      s += x1 * x1;
+      s += x2 * x2;
+      s += x3 * x3;
     }
   }
   return s;
@@ -2536,6 +2547,7 @@ template hipError_t launch_convert<float>(const double*, float*, int64_t, hipStr
 template hipError_t launch_convert<double>(const double*, double*, int64_t, hipStream_t);
 template hipError_t launch_norm2<float>(const float*, int64_t, double*, int, DevStats*, hipStream_t);
 template hipError_t launch_norm2<bf16>(const bf16*, int64_t, double*, int, DevStats*, hipStream_t);
+template hipError_t launch_norm2<fp8e4m3>(const fp8e4m3*, int64_t, double*, int, DevStats*, hipStream_t);
 template hipError_t launch_norm2<double>(const double*, int64_t, double*, int, DevStats*,
                                          hipStream_t);
 template hipError_t launch_update<float>(const UpdateArgs<float>&, int, hipStream_t);

@@ -28,6 +28,19 @@
 //      16-byte load per index and swap halves across the pair), then
 //      transposes the 8 x 4 block in registers, so that block u gets row
 //      q0 + 4 i + u.
+//
+// FP8 tensor (E4M3: 4 exponent bits with bias 7, 3 mantissa bits, no
+// infinities): every FP8 value is a BF16 value, so the hardware conversion
+// to BF16 is exact and the products are those of the stored tensor with the
+// BF16 (or split) factor, on the same matrix cores; the tensor's bytes are
+// halved.  Both layouts load a whole chunk (64 indices) per register set:
+// lane group g holds indices 16 g .. 16 g + 15, step s of the chunk uses
+// 16 g + 8 s .. 16 g + 8 s + 7 (the factor is read at the same offsets).
+//   KC: one 16-byte load per row.
+//   otherwise: one 4-byte load (four consecutive q) per index; an in-register
+//      4 x 4 byte transpose puts each q's four consecutive indices in one word.
+#include <type_traits>
+
 #include "kernels.h"
 
 namespace cpals {
@@ -70,15 +83,36 @@ __device__ inline bf16x8 as_bf16x8(u32x4 v) { return __builtin_bit_cast(bf16x8, 
 // Lane source of one workgroup tile in the unguarded layout: KC, the four
 // row pointers (rows row0 + 16 u + l16, clamped to P - 1) at index 8 g;
 // otherwise p[0] points at k = 8 g + 4 h, q = qpair (clamped to Q - 8).
+// FP8, KC: rows as above at index 16 g; otherwise p[0] points at k = 16 g,
+// q = q0 + 4 (lane % 16) (clamped to Q - 4).
+template <typename E>
 struct LaneSrc {
-  const uint16_t* p[4];
+  const E* p[4];
 };
 
-template <bool KC, int NCB, bool SPLIT, bool FAST>
-__global__ __launch_bounds__(512) void k_ttm_bf16(const uint16_t* __restrict__ X, const uint16_t* __restrict__ Bhi,
+// Two E4M3 values (word half `hi` of w) as two BF16 values, exactly.
+template <bool HI>
+__device__ inline uint32_t fp8_pair_bf16(uint32_t w) {
+  return __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(w, 1.0f, HI));
+}
+
+// Bytes of four words x0..x3 transposed: byte b of result t[j] is byte j of x_b.
+__device__ inline void byte_transpose4(uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3, uint32_t (&t)[4]) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int sh = 8 * j;
+    t[j] = ((x0 >> sh) & 0xffu) | (((x1 >> sh) & 0xffu) << 8) | (((x2 >> sh) & 0xffu) << 16) | (((x3 >> sh) & 0xffu) << 24);
+  }
+}
+
+template <bool KC, int NCB, bool SPLIT, bool FAST, bool F8>
+__global__ __launch_bounds__(512) void k_ttm_bf16(const void* __restrict__ Xv, const uint16_t* __restrict__ Bhi,
                                                   const uint16_t* __restrict__ Blo, float* __restrict__ C,
                                                   int64_t P, int64_t K, int64_t Q, int R, int Kp, int64_t tilesQ,
                                                   int64_t ntiles, int vec) {
+  using E = typename std::conditional<F8, uint8_t, uint16_t>::type;
+  using Src = LaneSrc<E>;
+  const E* __restrict__ X = (const E*)Xv;
   constexpr int NC = NCB * 16;
   constexpr int NPART = SPLIT ? 2 : 1;
   constexpr int BITEMS = NPART * NC * (KB / 8);  // 16-byte pieces of one factor chunk
@@ -119,7 +153,7 @@ __global__ __launch_bounds__(512) void k_ttm_bf16(const uint16_t* __restrict__ X
   };
 
   // ---- tile addressing ----
-  auto tile_rows = [&](int64_t tile, int64_t& row0, const uint16_t*& Xb, float*& Cb, int64_t& nrows) {
+  auto tile_rows = [&](int64_t tile, int64_t& row0, const E*& Xb, float*& Cb, int64_t& nrows) {
     if (KC) {
       row0 = tile * kTileRows + wave * 64;
       Xb = X;
@@ -134,17 +168,21 @@ __global__ __launch_bounds__(512) void k_ttm_bf16(const uint16_t* __restrict__ X
     }
   };
   auto lane_src = [&](int64_t tile) {
-    LaneSrc s;
+    Src s;
     int64_t row0, nrows;
-    const uint16_t* Xb;
+    const E* Xb;
     float* Cb;
     tile_rows(tile, row0, Xb, Cb, nrows);
     if (KC) {
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int64_t r = row0 + 16 * u + l16;
-        s.p[u] = Xb + (r < nrows ? r : nrows - 1) * K + 8 * g;
+        s.p[u] = Xb + (r < nrows ? r : nrows - 1) * K + (F8 ? 16 : 8) * g;
       }
+    } else if (F8) {
+      const int64_t q = row0 + 4 * l16;
+      s.p[0] = Xb + (int64_t)(16 * g) * Q + (q < Q - 4 ? q : Q - 4);
+      s.p[1] = s.p[2] = s.p[3] = s.p[0];
     } else {
       const int64_t qp = row0 + 8 * (l16 >> 1);
       s.p[0] = Xb + (int64_t)(8 * g + 4 * (l16 & 1)) * Q + (qp < Q - 8 ? qp : Q - 8);
@@ -160,7 +198,8 @@ __global__ __launch_bounds__(512) void k_ttm_bf16(const uint16_t* __restrict__ X
   // meanwhile.
   // Guarded layout: the operands are formed at load time with every index
   // checked (indices past K read as zero).
-  auto issue = [&](const LaneSrc& s, int64_t tile, int ks, u32x4 (&r)[4]) {
+  auto issue = [&](const Src& s, int64_t tile, int ks, u32x4 (&r)[4]) {
+    if constexpr (!F8) {
     if (FAST) {
       // indices past K: KC reads the row's last eight (K % 8 == 0, so a
       // piece is wholly inside or wholly past), otherwise row K - 1; the
@@ -180,7 +219,7 @@ __global__ __launch_bounds__(512) void k_ttm_bf16(const uint16_t* __restrict__ X
       return;
     }
     int64_t row0, nrows;
-    const uint16_t* Xb;
+    const E* Xb;
     float* Cb;
     tile_rows(tile, row0, Xb, Cb, nrows);
     const int kb = ks + 8 * g;  // this lane's eight indices kb .. kb + 7
@@ -227,6 +266,91 @@ __global__ __launch_bounds__(512) void k_ttm_bf16(const uint16_t* __restrict__ X
         r[u][m] = (u & 1) ? ((x0 >> 16) | (x1 & 0xffff0000u)) : ((x0 & 0xffffu) | (x1 << 16));
       }
     }
+    }
+  };
+
+  // ---- FP8: the chunk from ks (64 indices) into registers.  KC: r[u] holds
+  // row u's indices 16 g .. 16 g + 15; otherwise word r[i / 4][i % 4] holds
+  // the lane's four q at index 16 g + i.  Unguarded (FAST: 16-byte aligned
+  // rows with K a multiple of 16 for KC, 4-byte aligned with Q a multiple of
+  // 4 otherwise): indices past K read clamped addresses, cancelled by the
+  // factor's zero padding.  Guarded: indices past K and q past Q read as
+  // zero; vec: 4-byte loads allowed (KC, K a multiple of 4, aligned). ----
+  auto issue8 = [&](const Src& s, int64_t tile, int ks, u32x4 (&r)[4]) {
+    if constexpr (F8) {
+      if (FAST) {
+        if (KC) {
+          const int kc = ks <= K - 16 - 16 * g ? ks : (int)K - 16 - 16 * g;
+#pragma unroll
+          for (int u = 0; u < 4; ++u) r[u] = *(const u32x4*)(s.p[u] + kc);
+        } else {
+#pragma unroll
+          for (int i = 0; i < 16; ++i) {
+            const int64_t k = ks + 16 * g + i < K ? ks + 16 * g + i : K - 1;
+            r[i >> 2][i & 3] = *(const uint32_t*)(s.p[0] + (k - 16 * g) * Q);
+          }
+        }
+        return;
+      }
+      int64_t row0, nrows;
+      const E* Xb;
+      float* Cb;
+      tile_rows(tile, row0, Xb, Cb, nrows);
+      const int64_t kb = ks + 16 * g;
+      if (KC) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          int64_t rr = row0 + 16 * u + l16;
+          rr = rr < nrows ? rr : nrows - 1;
+          const E* src = Xb + rr * K + kb;
+#pragma unroll
+          for (int w = 0; w < 4; ++w) {
+            const int64_t k = kb + 4 * w;
+            uint32_t x = 0;
+            if (vec && k + 4 <= K) {
+              x = *(const uint32_t*)(src + 4 * w);
+            } else {
+#pragma unroll
+              for (int b = 0; b < 4; ++b)
+                if (k + b < K) x |= (uint32_t)src[4 * w + b] << (8 * b);
+            }
+            r[u][w] = x;
+          }
+        }
+      } else {
+        const int64_t q = row0 + 4 * l16;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          const int64_t k = kb + i;
+          uint32_t w = 0;
+          if (k < K) {
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+              if (q + b < Q) w |= (uint32_t)Xb[k * Q + q + b] << (8 * b);
+          }
+          r[i >> 2][i & 3] = w;
+        }
+      }
+    }
+  };
+  // FP8 operands of step s (0 or 1) of the chunk in r.
+  auto operands8 = [&](const u32x4 (&r)[4], int s, bf16x8 (&a)[4]) {
+    if (KC) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const uint32_t w0 = r[u][2 * s], w1 = r[u][2 * s + 1];
+        a[u] = as_bf16x8(u32x4{fp8_pair_bf16<false>(w0), fp8_pair_bf16<true>(w0), fp8_pair_bf16<false>(w1),
+                               fp8_pair_bf16<true>(w1)});
+      }
+      return;
+    }
+    uint32_t ta[4], tb[4];  // indices 8 s + 0..3 and 8 s + 4..7, one word per q
+    byte_transpose4(r[2 * s][0], r[2 * s][1], r[2 * s][2], r[2 * s][3], ta);
+    byte_transpose4(r[2 * s + 1][0], r[2 * s + 1][1], r[2 * s + 1][2], r[2 * s + 1][3], tb);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      a[u] = as_bf16x8(u32x4{fp8_pair_bf16<false>(ta[u]), fp8_pair_bf16<true>(ta[u]), fp8_pair_bf16<false>(tb[u]),
+                             fp8_pair_bf16<true>(tb[u])});
   };
   // Operands of one step.  Unguarded q-contiguous layout: lanes 2m and 2m + 1
   // loaded the same eight q at k = kb + 4h + j (h = l16 & 1, j < 4); each
@@ -264,12 +388,11 @@ __global__ __launch_bounds__(512) void k_ttm_bf16(const uint16_t* __restrict__ X
   };
 
   f32x4 acc[4][NCB];
-  auto multiply = [&](const u32x4 (&r)[4], const uint16_t* bs, int kl) {
-    bf16x8 a[4];
-    operands(r, a);
+  // the step's products; the lane's factor indices start at ko of the chunk
+  auto mfma_step = [&](const bf16x8 (&a)[4], const uint16_t* bs, int ko) {
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) {
-      const uint16_t* bp = bs + (cb * 16 + l16) * KPITCH + kl + 8 * g;
+      const uint16_t* bp = bs + (cb * 16 + l16) * KPITCH + ko;
       const bf16x8 bh = as_bf16x8(*(const u32x4*)bp);
 #pragma unroll
       for (int u = 0; u < 4; ++u) acc[u][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[u], bh, acc[u][cb], 0, 0, 0);
@@ -280,6 +403,16 @@ __global__ __launch_bounds__(512) void k_ttm_bf16(const uint16_t* __restrict__ X
           acc[u][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[u], bl, acc[u][cb], 0, 0, 0);
       }
     }
+  };
+  auto multiply = [&](const u32x4 (&r)[4], const uint16_t* bs, int kl) {
+    bf16x8 a[4];
+    operands(r, a);
+    mfma_step(a, bs, kl + 8 * g);
+  };
+  auto multiply8 = [&](const u32x4 (&r)[4], const uint16_t* bs, int s) {
+    bf16x8 a[4];
+    operands8(r, s, a);
+    mfma_step(a, bs, 16 * g + 8 * s);
   };
 
   // ---- main loop: the workgroup's waves step through the same (tile, chunk)
@@ -292,18 +425,44 @@ __global__ __launch_bounds__(512) void k_ttm_bf16(const uint16_t* __restrict__ X
     load_b(0, bv);
     store_b(0, bv);
   }
-  LaneSrc cur = FAST ? lane_src(tile) : LaneSrc{};
+  Src cur = FAST ? lane_src(tile) : Src{};
   u32x4 ra[4], rb[4];
-  issue(cur, tile, 0, ra);
+  if (F8)
+    issue8(cur, tile, 0, ra);
+  else
+    issue(cur, tile, 0, ra);
   __syncthreads();
   int buf = 0;
   for (; tile < ntiles; tile += gridDim.x) {
     const int64_t tn = tile + gridDim.x < ntiles ? tile + gridDim.x : tile;
-    const LaneSrc nxt = FAST ? lane_src(tn) : LaneSrc{};
+    const Src nxt = FAST ? lane_src(tn) : Src{};
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb) acc[u][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    if (F8) {
+      // one register set per chunk: the next chunk's loads are in flight
+      // during both steps of the current one
+      for (int ch = 0; ch < nch; ++ch) {
+        const bool more = ch + 1 < nch;
+        u32x4 bv[BPER];
+        load_b(more ? ch + 1 : 0, bv);
+        {
+          Src sn;
+#pragma unroll
+          for (int u = 0; u < 4; ++u) sn.p[u] = more ? cur.p[u] : nxt.p[u];
+          issue8(sn, more ? tile : tn, more ? (ch + 1) * KB : 0, rb);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        multiply8(ra, Bs[buf], 0);
+        multiply8(ra, Bs[buf], 1);
+        store_b(buf ^ 1, bv);
+        buf ^= 1;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) ra[u] = rb[u];
+        __syncthreads();
+      }
+    } else
     for (int ch = 0; ch < nch; ++ch) {
       const bool more = ch + 1 < nch;
       u32x4 bv[BPER];
@@ -312,7 +471,7 @@ __global__ __launch_bounds__(512) void k_ttm_bf16(const uint16_t* __restrict__ X
       __builtin_amdgcn_sched_barrier(0);
       multiply(ra, Bs[buf], 0);
       {
-        LaneSrc sn;
+        Src sn;
 #pragma unroll
         for (int u = 0; u < 4; ++u) sn.p[u] = more ? cur.p[u] : nxt.p[u];
         issue(sn, more ? tile : tn, more ? (ch + 1) * KB : 0, ra);
@@ -326,7 +485,7 @@ __global__ __launch_bounds__(512) void k_ttm_bf16(const uint16_t* __restrict__ X
 
     // ---- store: register v of block u is output row 4 g + v of the block ----
     int64_t row0, nrows;
-    const uint16_t* Xb;
+    const E* Xb;
     float* Cb;
     tile_rows(tile, row0, Xb, Cb, nrows);
 #pragma unroll
@@ -344,34 +503,56 @@ __global__ __launch_bounds__(512) void k_ttm_bf16(const uint16_t* __restrict__ X
   }
 }
 
-template <bool KC, int NCB, bool SPLIT, bool FAST>
-hipError_t launch_one(const uint16_t* X, const uint16_t* Bhi, const uint16_t* Blo, float* C, int64_t P, int64_t K,
+template <bool KC, int NCB, bool SPLIT, bool FAST, bool F8>
+hipError_t launch_one(const void* X, const uint16_t* Bhi, const uint16_t* Blo, float* C, int64_t P, int64_t K,
                       int64_t Q, int R, int Kp, int vec, hipStream_t st) {
   constexpr int NC = NCB * 16;
   const int64_t tilesQ = KC ? 1 : (Q + kTileRows - 1) / kTileRows;
   const int64_t ntiles = KC ? (P + kTileRows - 1) / kTileRows : P * tilesQ;
   const unsigned nx = (unsigned)(ntiles < 256 ? ntiles : 256);  // one resident workgroup per CU
   const unsigned ny = (unsigned)((R + NC - 1) / NC);
-  hipLaunchKernelGGL((k_ttm_bf16<KC, NCB, SPLIT, FAST>), dim3(nx, ny), dim3(kThreads), 0, st, X, Bhi, Blo, C, P, K,
-                     Q, R, Kp, tilesQ, ntiles, vec);
+  hipLaunchKernelGGL((k_ttm_bf16<KC, NCB, SPLIT, FAST, F8>), dim3(nx, ny), dim3(kThreads), 0, st, X, Bhi, Blo, C, P,
+                     K, Q, R, Kp, tilesQ, ntiles, vec);
   return hipGetLastError();
 }
 
-template <bool KC, bool SPLIT>
-hipError_t launch_ncb(const uint16_t* X, const uint16_t* Bhi, const uint16_t* Blo, float* C, int64_t P, int64_t K,
+template <bool KC, bool SPLIT, bool F8>
+hipError_t launch_ncb(const void* X, const uint16_t* Bhi, const uint16_t* Blo, float* C, int64_t P, int64_t K,
                       int64_t Q, int R, int Kp, hipStream_t st) {
-  // KC: 16-byte row loads; otherwise 2 = 16-byte loads shared by lane pairs, 1 = 8-byte loads
-  const int vec = KC ? (K % 8 == 0 && ((uintptr_t)X % 16) == 0)
-                     : ((Q % 8 == 0 && ((uintptr_t)X % 16) == 0) ? 2 : (Q % 4 == 0 && ((uintptr_t)X % 8) == 0));
-  const bool fast = KC ? vec == 1 : vec == 2;
-#define CPALS_BF16_NCB(NCB)                                                                     \
-  return fast ? launch_one<KC, NCB, SPLIT, true>(X, Bhi, Blo, C, P, K, Q, R, Kp, vec, st)      \
-              : launch_one<KC, NCB, SPLIT, false>(X, Bhi, Blo, C, P, K, Q, R, Kp, vec, st)
+  const uintptr_t a = (uintptr_t)X;
+  int vec;
+  bool fast;
+  if (F8) {
+    // KC: unguarded with 16-byte rows, else 4-byte loads where whole; otherwise
+    // unguarded with 4-byte aligned groups of four q
+    vec = KC ? (K % 4 == 0 && a % 4 == 0) : 0;
+    fast = KC ? (K % 16 == 0 && a % 16 == 0) : (Q % 4 == 0 && a % 4 == 0);
+  } else {
+    // KC: 16-byte row loads; otherwise 2 = 16-byte loads shared by lane pairs, 1 = 8-byte loads
+    vec = KC ? (K % 8 == 0 && a % 16 == 0) : ((Q % 8 == 0 && a % 16 == 0) ? 2 : (Q % 4 == 0 && a % 8 == 0));
+    fast = KC ? vec == 1 : vec == 2;
+  }
+#define CPALS_BF16_NCB(NCB)                                                                         \
+  return fast ? launch_one<KC, NCB, SPLIT, true, F8>(X, Bhi, Blo, C, P, K, Q, R, Kp, vec, st)      \
+              : launch_one<KC, NCB, SPLIT, false, F8>(X, Bhi, Blo, C, P, K, Q, R, Kp, vec, st)
   if (R <= 16) CPALS_BF16_NCB(1);
   if (R <= 32) CPALS_BF16_NCB(2);
   if (R <= 64) CPALS_BF16_NCB(4);
   CPALS_BF16_NCB(8);
 #undef CPALS_BF16_NCB
+}
+
+template <bool F8>
+hipError_t launch_lowp(const void* X, const uint16_t* Bhi, const uint16_t* Blo, float* C, int64_t P, int64_t K,
+                       int64_t Q, int R, hipStream_t st) {
+  if (R < 1 || R > kMaxRank || K < 1 || P < 1 || Q < 1) return hipErrorInvalidValue;
+  const int Kp = bf16_factor_pitch(K);
+  if (Q == 1) {
+    return Blo ? launch_ncb<true, true, F8>(X, Bhi, Blo, C, P, K, Q, R, Kp, st)
+               : launch_ncb<true, false, F8>(X, Bhi, Blo, C, P, K, Q, R, Kp, st);
+  }
+  return Blo ? launch_ncb<false, true, F8>(X, Bhi, Blo, C, P, K, Q, R, Kp, st)
+             : launch_ncb<false, false, F8>(X, Bhi, Blo, C, P, K, Q, R, Kp, st);
 }
 
 }  // namespace
@@ -388,14 +569,12 @@ hipError_t launch_split_factor(const float* A, int64_t K, int R, uint16_t* hi, u
 
 hipError_t launch_ttm_bf16(const uint16_t* X, const uint16_t* Bhi, const uint16_t* Blo, float* C, int64_t P,
                            int64_t K, int64_t Q, int R, hipStream_t st) {
-  if (R < 1 || R > kMaxRank || K < 1 || P < 1 || Q < 1) return hipErrorInvalidValue;
-  const int Kp = bf16_factor_pitch(K);
-  if (Q == 1) {
-    return Blo ? launch_ncb<true, true>(X, Bhi, Blo, C, P, K, Q, R, Kp, st)
-               : launch_ncb<true, false>(X, Bhi, Blo, C, P, K, Q, R, Kp, st);
-  }
-  return Blo ? launch_ncb<false, true>(X, Bhi, Blo, C, P, K, Q, R, Kp, st)
-             : launch_ncb<false, false>(X, Bhi, Blo, C, P, K, Q, R, Kp, st);
+  return launch_lowp<false>(X, Bhi, Blo, C, P, K, Q, R, st);
+}
+
+hipError_t launch_ttm_fp8(const uint8_t* X, const uint16_t* Bhi, const uint16_t* Blo, float* C, int64_t P,
+                          int64_t K, int64_t Q, int R, hipStream_t st) {
+  return launch_lowp<true>(X, Bhi, Blo, C, P, K, Q, R, st);
 }
 
 }  // namespace cpals

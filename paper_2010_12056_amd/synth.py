@@ -173,6 +173,68 @@ def bf16_to_f32(bits):
     return (np.asarray(bits, dtype=np.uint16).astype(np.uint32) << np.uint32(16)).view(np.float32)
 
 
+FP8_MAX = 448.0  # largest finite E4M3 value, 1.75 * 2^8
+
+
+def _fp8_table():
+    """The 256 E4M3 values: sign bit, 4-bit exponent with bias 7, 3-bit
+    mantissa; exponent 0 holds the subnormals m 2^-9; exponent 15 with
+    mantissa 7 is NaN (there are no infinities)."""
+    b = np.arange(256, dtype=np.int64)
+    e, m = (b >> 3) & 15, b & 7
+    mag = np.where(e > 0, np.ldexp(8.0 + m, e - 10), np.ldexp(m.astype(np.float64), -9))
+    v = np.where((b & 0x80) != 0, -mag, mag)
+    return np.where((e == 15) & (m == 7), np.nan, v).astype(np.float32)
+
+
+_FP8_VALUES = _fp8_table()
+
+
+def fp8_to_f32(bits):
+    """The FP32 values of raw FP8 E4M3 patterns (exact)."""
+    return _FP8_VALUES[np.asarray(bits, dtype=np.uint8)]
+
+
+def fp8_scale(x):
+    """The largest power of two s with max |x| s <= FP8_MAX: the tensor times
+    s uses E4M3's range (17 binades down to the subnormals) from the top.
+    Scaling by a power of two is exact, and the relative residual of a CP
+    fit does not depend on the tensor's scale."""
+    m = float(np.max(np.abs(x)))
+    if not np.isfinite(m) or m == 0.0:
+        return 1.0
+    s = 2.0 ** np.floor(np.log2(FP8_MAX / m))
+    while m * s > FP8_MAX:  # guard the logarithm's rounding
+        s /= 2
+    return float(s)
+
+
+def fp8_bits(x, scale=1.0, block=1 << 26):
+    """Round FP32 values (times `scale`, a power of two, applied exactly) to
+    FP8 E4M3 (nearest, ties to even); returns the raw 8-bit patterns (uint8).  Non-finite values, and values whose rounding
+    exceeds FP8_MAX, are rejected.  Storage conversion of a generated
+    tensor.  From 2^-6 up the FP32 pattern keeps its top 3 mantissa bits
+    (rounded; a carry moves to the next binade) and its exponent is rebased
+    from bias 127 to 7; below, the value is a multiple of 2^-9 (subnormals)."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    flat = x.reshape(-1)
+    out = np.empty(flat.shape, dtype=np.uint8)
+    for s0 in range(0, flat.size, block):
+        xs = flat[s0:s0 + block]
+        if scale != 1.0:
+            xs = xs * np.float32(scale)
+        u = xs.view(np.uint32)
+        a = u & np.uint32(0x7FFFFFFF)
+        r = (a + np.uint32(0x7FFFF) + ((a >> np.uint32(20)) & np.uint32(1))) >> np.uint32(20)
+        with np.errstate(over="ignore", invalid="ignore"):  # large or non-finite inputs take the other branch
+            sub = np.rint(np.minimum(a.view(np.float32) * np.float32(512.0), np.float32(8.0))).astype(np.int32)
+        code = np.where(a >= np.uint32(0x3C800000), r.astype(np.int32) - 960, sub)
+        if code.size and code.max() > 0x7E:  # infinities and NaN land here too
+            raise ValueError("fp8_bits: non-finite value or value beyond the E4M3 range")
+        out[s0:s0 + block] = (code | ((u >> np.uint32(24)) & np.uint32(0x80)).astype(np.int32)).astype(np.uint8)
+    return out.reshape(x.shape)
+
+
 
 def batch_workload(count=512, seed=5001, smin=16, smax=96, ranks=(4, 8, 16, 32), noise_rel=1e-3):
     """Many small independent order-3 FP32 tensors: each mode size iid

@@ -164,3 +164,26 @@ def test_batch_create_layout_and_argument_checks():
     assert L.cp_batch_set_workspace(b, ctypes.c_void_p(256 + 8), n.value) == cpals.CP_ERR_ARG  # misaligned
     assert L.cp_batch_set_workspace(b, ctypes.c_void_p(256), n.value - 1) == cpals.CP_ERR_ARG  # too small
     L.cp_batch_destroy(b)
+
+
+def test_low_precision_plans_share_the_factor_staging():
+    """BF16 and FP8 tensors use the same BF16 factor staging: equal workspace
+    per factor variant, the split variants one more transposed factor."""
+    from paper_2010_12056_amd import cpals
+
+    L = _lib()
+    dims = (ctypes.c_int64 * 3)(96, 80, 72)
+    need = {}
+    for prec in (cpals.CP_F32, cpals.CP_BF16, cpals.CP_BF16X2, cpals.CP_FP8, cpals.CP_FP8X2):
+        h = ctypes.c_void_p()
+        assert L.cp_plan_create(ctypes.byref(h), 3, dims, 40, prec, cpals.CP_TREE_DT, None) == cpals.CP_OK
+        n = ctypes.c_size_t()
+        assert L.cp_plan_workspace_size(h, ctypes.byref(n)) == cpals.CP_OK
+        need[prec] = n.value
+        assert L.cp_plan_destroy(h) == cpals.CP_OK
+    assert need[cpals.CP_FP8] == need[cpals.CP_BF16] and need[cpals.CP_FP8X2] == need[cpals.CP_BF16X2]
+    pitch = (96 + 63) // 64 * 64  # the longest mode, padded to the 64-index chunk
+    assert need[cpals.CP_BF16X2] - need[cpals.CP_BF16] >= 40 * pitch * 2 - 256  # regions 256-byte aligned
+    assert need[cpals.CP_BF16] > need[cpals.CP_F32]
+    h = ctypes.c_void_p()
+    assert L.cp_plan_create(ctypes.byref(h), 3, dims, 40, 6, cpals.CP_TREE_DT, None) == cpals.CP_ERR_UNSUPPORTED

@@ -36,7 +36,8 @@
 // halved.  Both layouts load a whole chunk (64 indices) per register set:
 // lane group g holds indices 16 g .. 16 g + 15, step s of the chunk uses
 // 16 g + 8 s .. 16 g + 8 s + 7 (the factor is read at the same offsets).
-//   KC: one 16-byte load per row.
+//   KC: one 16-byte load per row; with DEEP, three register sets (the next
+//      two chunks in flight).
 //   otherwise: one 4-byte load (four consecutive q) per index; an in-register
 //      4 x 4 byte transpose puts each q's four consecutive indices in one word.
 #include <type_traits>
@@ -105,7 +106,7 @@ __device__ inline void byte_transpose4(uint32_t x0, uint32_t x1, uint32_t x2, ui
   }
 }
 
-template <bool KC, int NCB, bool SPLIT, bool FAST, bool F8>
+template <bool KC, int NCB, bool SPLIT, bool FAST, bool F8, bool DEEP>
 __global__ __launch_bounds__(512) void k_ttm_bf16(const void* __restrict__ Xv, const uint16_t* __restrict__ Bhi,
                                                   const uint16_t* __restrict__ Blo, float* __restrict__ C,
                                                   int64_t P, int64_t K, int64_t Q, int R, int Kp, int64_t tilesQ,
@@ -426,11 +427,13 @@ __global__ __launch_bounds__(512) void k_ttm_bf16(const void* __restrict__ Xv, c
     store_b(0, bv);
   }
   Src cur = FAST ? lane_src(tile) : Src{};
-  u32x4 ra[4], rb[4];
-  if (F8)
+  u32x4 ra[4], rb[4], rc[4];
+  if (F8) {
     issue8(cur, tile, 0, ra);
-  else
+    if (DEEP) issue8(cur, tile, KB, rb);
+  } else {
     issue(cur, tile, 0, ra);
+  }
   __syncthreads();
   int buf = 0;
   for (; tile < ntiles; tile += gridDim.x) {
@@ -440,7 +443,33 @@ __global__ __launch_bounds__(512) void k_ttm_bf16(const void* __restrict__ Xv, c
     for (int u = 0; u < 4; ++u)
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb) acc[u][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
-    if (F8) {
+    if (F8 && DEEP) {
+      // three register sets (at least two chunks per tile): the loads of the
+      // next two chunks are in flight during the current one
+      for (int ch = 0; ch < nch; ++ch) {
+        const bool more = ch + 1 < nch;
+        u32x4 bv[BPER];
+        load_b(more ? ch + 1 : 0, bv);
+        {
+          const bool same = ch + 2 < nch;
+          Src sn;
+#pragma unroll
+          for (int u = 0; u < 4; ++u) sn.p[u] = same ? cur.p[u] : nxt.p[u];
+          issue8(sn, same ? tile : tn, (same ? ch + 2 : ch + 2 - nch) * KB, rc);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        multiply8(ra, Bs[buf], 0);
+        multiply8(ra, Bs[buf], 1);
+        store_b(buf ^ 1, bv);
+        buf ^= 1;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          ra[u] = rb[u];
+          rb[u] = rc[u];
+        }
+        __syncthreads();
+      }
+    } else if (F8) {
       // one register set per chunk: the next chunk's loads are in flight
       // during both steps of the current one
       for (int ch = 0; ch < nch; ++ch) {
@@ -503,7 +532,7 @@ __global__ __launch_bounds__(512) void k_ttm_bf16(const void* __restrict__ Xv, c
   }
 }
 
-template <bool KC, int NCB, bool SPLIT, bool FAST, bool F8>
+template <bool KC, int NCB, bool SPLIT, bool FAST, bool F8, bool DEEP = false>
 hipError_t launch_one(const void* X, const uint16_t* Bhi, const uint16_t* Blo, float* C, int64_t P, int64_t K,
                       int64_t Q, int R, int Kp, int vec, hipStream_t st) {
   constexpr int NC = NCB * 16;
@@ -511,8 +540,8 @@ hipError_t launch_one(const void* X, const uint16_t* Bhi, const uint16_t* Blo, f
   const int64_t ntiles = KC ? (P + kTileRows - 1) / kTileRows : P * tilesQ;
   const unsigned nx = (unsigned)(ntiles < 256 ? ntiles : 256);  // one resident workgroup per CU
   const unsigned ny = (unsigned)((R + NC - 1) / NC);
-  hipLaunchKernelGGL((k_ttm_bf16<KC, NCB, SPLIT, FAST, F8>), dim3(nx, ny), dim3(kThreads), 0, st, X, Bhi, Blo, C, P,
-                     K, Q, R, Kp, tilesQ, ntiles, vec);
+  hipLaunchKernelGGL((k_ttm_bf16<KC, NCB, SPLIT, FAST, F8, DEEP>), dim3(nx, ny), dim3(kThreads), 0, st, X, Bhi, Blo,
+                     C, P, K, Q, R, Kp, tilesQ, ntiles, vec);
   return hipGetLastError();
 }
 
@@ -532,9 +561,18 @@ hipError_t launch_ncb(const void* X, const uint16_t* Bhi, const uint16_t* Blo, f
     vec = KC ? (K % 8 == 0 && a % 16 == 0) : ((Q % 8 == 0 && a % 16 == 0) ? 2 : (Q % 4 == 0 && a % 8 == 0));
     fast = KC ? vec == 1 : vec == 2;
   }
-#define CPALS_BF16_NCB(NCB)                                                                         \
-  return fast ? launch_one<KC, NCB, SPLIT, true, F8>(X, Bhi, Blo, C, P, K, Q, R, Kp, vec, st)      \
-              : launch_one<KC, NCB, SPLIT, false, F8>(X, Bhi, Blo, C, P, K, Q, R, Kp, vec, st)
+  // FP8 contiguous rows, one factor part, unguarded, at least two chunks:
+  // three register sets (0.44 -> 0.34 ms at 1024^3, R = 128; the
+  // q-contiguous layouts, with 16 four-byte loads per chunk, were 7 % slower)
+  const bool deep = F8 && KC && !SPLIT && fast && Kp >= 2 * KB;
+#define CPALS_BF16_NCB(NCB)                                                                                 \
+  do {                                                                                                     \
+    if constexpr (F8 && KC && !SPLIT) {                                                                    \
+      if (deep) return launch_one<KC, NCB, SPLIT, true, F8, true>(X, Bhi, Blo, C, P, K, Q, R, Kp, vec, st); \
+    }                                                                                                      \
+    return fast ? launch_one<KC, NCB, SPLIT, true, F8>(X, Bhi, Blo, C, P, K, Q, R, Kp, vec, st)            \
+                : launch_one<KC, NCB, SPLIT, false, F8>(X, Bhi, Blo, C, P, K, Q, R, Kp, vec, st);          \
+  } while (0)
   if (R <= 16) CPALS_BF16_NCB(1);
   if (R <= 32) CPALS_BF16_NCB(2);
   if (R <= 64) CPALS_BF16_NCB(4);

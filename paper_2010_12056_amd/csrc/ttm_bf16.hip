@@ -564,10 +564,10 @@ hipError_t launch_ncb(const void* X, const uint16_t* Bhi, const uint16_t* Blo, f
   // FP8 contiguous rows, one factor part, unguarded, at least two chunks:
   // three register sets (0.44 -> 0.34 ms at 1024^3, R = 128; the
   // q-contiguous layouts, with 16 four-byte loads per chunk, were 7 % slower)
-  const bool deep = F8 && KC && !SPLIT && fast && Kp >= 2 * KB;
+  const bool deep = F8 && KC && fast && Kp >= 2 * KB;
 #define CPALS_BF16_NCB(NCB)                                                                                 \
   do {                                                                                                     \
-    if constexpr (F8 && KC && !SPLIT) {                                                                    \
+    if constexpr (F8 && KC && (!SPLIT || NCB <= 4)) {                                                      \
       if (deep) return launch_one<KC, NCB, SPLIT, true, F8, true>(X, Bhi, Blo, C, P, K, Q, R, Kp, vec, st); \
     }                                                                                                      \
     return fast ? launch_one<KC, NCB, SPLIT, true, F8>(X, Bhi, Blo, C, P, K, Q, R, Kp, vec, st)            \
@@ -575,7 +575,9 @@ hipError_t launch_ncb(const void* X, const uint16_t* Bhi, const uint16_t* Blo, f
   } while (0)
   if (R <= 16) CPALS_BF16_NCB(1);
   if (R <= 32) CPALS_BF16_NCB(2);
-  if (R <= 64) CPALS_BF16_NCB(4);
+  // FP8 rows with the split factor: 128 columns in one pass need more than 256
+  // registers (spills); two 64-column passes read the tensor twice instead
+  if (R <= 64 || (F8 && KC && SPLIT)) CPALS_BF16_NCB(4);
   CPALS_BF16_NCB(8);
 #undef CPALS_BF16_NCB
 }

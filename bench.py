@@ -239,15 +239,17 @@ def precision_bench(args):
     achieved = (numel * esz + out_bytes) / (ttm_ms * 1e-3) / 1e9
     ttm8_ms = res["fp8x2"]["dt"]["ttm_avg_ms"]
     achieved8 = (numel + out_bytes) / (ttm8_ms * 1e-3) / 1e9
+    ttm8s_ms = res["fp8"]["dt"]["ttm_avg_ms"]
+    achieved8s = (numel + out_bytes) / (ttm8s_ms * 1e-3) / 1e9
     # error against the FP64 oracle on the stored BF16 / FP8 values, resynced per sweep
     log("[bench] oracle checks")
     errs = {}
-    for prec in ("bf16", "bf16x2", "fp8x2"):
+    for prec in ("bf16", "bf16x2", "fp8", "fp8x2"):
         if prec == "bf16":
             T64 = synth.bf16_to_f32(bits).astype(np.float64)
             del bits
             normT2 = float(np.sum(T64 * T64))
-        elif prec == "fp8x2":
+        elif prec == "fp8":
             del T64
             T64 = synth.fp8_to_f32(bits8).astype(np.float64)
             del bits8
@@ -262,7 +264,7 @@ def precision_bench(args):
         ref = X0[rows] @ K
         refabs = np.abs(X0[rows]) @ core.krp([np.abs(w.init[1]), np.abs(w.init[2])])
         del K
-        unit = 2.0 ** -8 if prec == "bf16" else 2.0 ** -16  # the factor's rounding; the tensor is exact
+        unit = 2.0 ** -8 if prec in ("bf16", "fp8") else 2.0 ** -16  # the factor's rounding; the tensor is exact
         rec = {"mttkrp_rows_relerr": float(np.linalg.norm(M - ref) / np.linalg.norm(ref)),
                "mttkrp_rows_err_over_bound": float(np.max(np.abs(M - ref) / (unit * refabs))),
                "sweeps": []}
@@ -294,6 +296,10 @@ def precision_bench(args):
         "by_precision": res,
         "speedup_bf16x2_vs_f32_msdt": round(res["f32"]["msdt"]["ms_per_sweep"] / res["bf16x2"]["msdt"]["ms_per_sweep"], 3),
         "speedup_fp8x2_vs_f32_msdt": round(res["f32"]["msdt"]["ms_per_sweep"] / res["fp8x2"]["msdt"]["ms_per_sweep"], 3),
+        "roofline_fp8": {"kernel": "k_ttm_bf16 (FP8 tensor, BF16 factor, first contraction)", "bound": "hbm",
+                         "achieved": round(achieved8s, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                         "frac": round(achieved8s / PEAK_HBM_GBS, 4), "traffic": None,
+                         "bytes_per_launch": numel + out_bytes, "avg_launch_ms": ttm8s_ms},
         "roofline_fp8x2": {"kernel": "k_ttm_bf16 (FP8 tensor, split factor, first contraction)", "bound": "hbm",
                            "achieved": round(achieved8, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                            "frac": round(achieved8 / PEAK_HBM_GBS, 4), "traffic": None,

@@ -1,4 +1,4 @@
-// First-level contraction of a BF16 tensor with one factor on the matrix
+// First-level contraction of a BF16 or FP8 tensor with one factor on the matrix
 // cores (v_mfma_f32_16x16x32_bf16, FP32 accumulation):
 //   C[p][q][r] = sum_k X[p][k][q] * B[k][r]
 // B is the factor rounded to BF16 (one product) or split into BF16 parts

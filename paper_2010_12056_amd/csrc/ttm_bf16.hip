@@ -106,7 +106,11 @@ __device__ inline void byte_transpose4(uint32_t x0, uint32_t x1, uint32_t x2, ui
   }
 }
 
-template <bool KC, int NCB, bool SPLIT, bool FAST, bool F8, bool DEEP>
+constexpr int TPITCH = 528;  // FP8 chunk stage row pitch (bytes): 512 q plus 16 to spread the banks
+
+typedef int i32x2 __attribute__((ext_vector_type(2)));
+
+template <bool KC, int NCB, bool SPLIT, bool FAST, bool F8, bool DEEP, bool TR>
 __global__ __launch_bounds__(512) void k_ttm_bf16(const void* __restrict__ Xv, const uint16_t* __restrict__ Bhi,
                                                   const uint16_t* __restrict__ Blo, float* __restrict__ C,
                                                   int64_t P, int64_t K, int64_t Q, int R, int Kp, int64_t tilesQ,
@@ -119,6 +123,8 @@ __global__ __launch_bounds__(512) void k_ttm_bf16(const void* __restrict__ Xv, c
   constexpr int BITEMS = NPART * NC * (KB / 8);  // 16-byte pieces of one factor chunk
   constexpr int BPER = (BITEMS + kThreads - 1) / kThreads;
   __shared__ __align__(16) uint16_t Bs[2][NPART * NC * KPITCH];  // [buffer][part][column][index]
+  // FP8 q-contiguous with TR: the workgroup's chunk of the tensor, [buffer][index][q]
+  __shared__ __align__(16) uint8_t Ts[TR ? 2 * KB * TPITCH : 16];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, l16 = lane & 15;
   const int c0 = blockIdx.y * NC;
@@ -388,6 +394,51 @@ __global__ __launch_bounds__(512) void k_ttm_bf16(const void* __restrict__ Xv, c
     }
   };
 
+  // ---- FP8, q-contiguous, TR (Q a multiple of 16, 16-byte aligned): the
+  // chunk (64 indices x the tile's 512 q) goes HBM -> registers -> LDS with
+  // 16-byte loads, thread tid taking pieces tid + 512 m (index piece / 32,
+  // q offset 16 (piece % 32)); indices past K read row K - 1 (cancelled by
+  // the factor's zero padding), q past Q the last 16 (never stored) ----
+  auto load_t = [&](int64_t t, int ch, u32x4 (&tv)[4]) {
+    if constexpr (TR) {
+      const int64_t p = t / tilesQ;
+      const int64_t tq0 = (t - p * tilesQ) * kTileRows;
+      const E* Xb = X + p * K * Q;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int piece = tid + kThreads * m;
+        const int64_t k = (int64_t)ch * KB + (piece >> 5);
+        const int64_t q = tq0 + 16 * (piece & 31);
+        tv[m] = *(const u32x4*)(Xb + (k < K ? k : K - 1) * Q + (q <= Q - 16 ? q : Q - 16));
+      }
+    }
+  };
+  auto store_t = [&](int b, const u32x4 (&tv)[4]) {
+    if constexpr (TR) {
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int piece = tid + kThreads * m;
+        *(u32x4*)(Ts + b * KB * TPITCH + (piece >> 5) * TPITCH + 16 * (piece & 31)) = tv[m];
+      }
+    }
+  };
+  // Operands of step s from the stage: block u holds the wave's q rows
+  // 16 u .. 16 u + 15; the transposing read gives lane (g, i) indices
+  // 32 s + 8 g .. + 7 of q row i when lane t of the group points at index
+  // 32 s + 8 g + t / 2, q 16 u + 8 (t % 2).
+  auto operands_tr = [&](int b, int s8, bf16x8 (&a)[4]) {
+    if constexpr (TR) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int off = b * KB * TPITCH + (32 * s8 + 8 * g + (l16 >> 1)) * TPITCH + wave * 64 + 16 * u + 8 * (l16 & 1);
+        const i32x2 v = __builtin_amdgcn_ds_read_tr8_b64_v2i32((__attribute__((address_space(3))) i32x2*)(Ts + off));
+        const uint32_t w0 = (uint32_t)v[0], w1 = (uint32_t)v[1];
+        a[u] = as_bf16x8(u32x4{fp8_pair_bf16<false>(w0), fp8_pair_bf16<true>(w0), fp8_pair_bf16<false>(w1),
+                               fp8_pair_bf16<true>(w1)});
+      }
+    }
+  };
+
   f32x4 acc[4][NCB];
   // the step's products; the lane's factor indices start at ko of the chunk
   auto mfma_step = [&](const bf16x8 (&a)[4], const uint16_t* bs, int ko) {
@@ -428,7 +479,11 @@ __global__ __launch_bounds__(512) void k_ttm_bf16(const void* __restrict__ Xv, c
   }
   Src cur = FAST ? lane_src(tile) : Src{};
   u32x4 ra[4], rb[4], rc[4];
-  if (F8) {
+  if (TR) {
+    u32x4 tv[4];
+    load_t(tile, 0, tv);
+    store_t(0, tv);
+  } else if (F8) {
     issue8(cur, tile, 0, ra);
     if (DEEP) issue8(cur, tile, KB, rb);
   } else {
@@ -443,7 +498,25 @@ __global__ __launch_bounds__(512) void k_ttm_bf16(const void* __restrict__ Xv, c
     for (int u = 0; u < 4; ++u)
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb) acc[u][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
-    if (F8 && DEEP) {
+    if (F8 && TR) {
+      for (int ch = 0; ch < nch; ++ch) {
+        const bool more = ch + 1 < nch;
+        u32x4 bv[BPER], tv[4];
+        load_b(more ? ch + 1 : 0, bv);
+        load_t(more ? tile : tn, more ? ch + 1 : 0, tv);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int s8 = 0; s8 < 2; ++s8) {
+          bf16x8 a[4];
+          operands_tr(buf, s8, a);
+          mfma_step(a, Bs[buf], 32 * s8 + 8 * g);
+        }
+        store_b(buf ^ 1, bv);
+        store_t(buf ^ 1, tv);
+        buf ^= 1;
+        __syncthreads();
+      }
+    } else if (F8 && DEEP) {
       // three register sets (at least two chunks per tile): the loads of the
       // next two chunks are in flight during the current one
       for (int ch = 0; ch < nch; ++ch) {
@@ -524,7 +597,7 @@ __global__ __launch_bounds__(512) void k_ttm_bf16(const void* __restrict__ Xv, c
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int i = 4 * g + v;
-          const int64_t r = KC ? row0 + 16 * u + i : row0 + 4 * i + u;
+          const int64_t r = (KC || TR) ? row0 + 16 * u + i : row0 + 4 * i + u;
           const int c = c0 + cb * 16 + l16;
           if (r < nrows && c < R) Cb[r * R + c] = acc[u][cb][v];
         }
@@ -532,7 +605,7 @@ __global__ __launch_bounds__(512) void k_ttm_bf16(const void* __restrict__ Xv, c
   }
 }
 
-template <bool KC, int NCB, bool SPLIT, bool FAST, bool F8, bool DEEP = false>
+template <bool KC, int NCB, bool SPLIT, bool FAST, bool F8, bool DEEP = false, bool TR = false>
 hipError_t launch_one(const void* X, const uint16_t* Bhi, const uint16_t* Blo, float* C, int64_t P, int64_t K,
                       int64_t Q, int R, int Kp, int vec, hipStream_t st) {
   constexpr int NC = NCB * 16;
@@ -540,7 +613,7 @@ hipError_t launch_one(const void* X, const uint16_t* Bhi, const uint16_t* Blo, f
   const int64_t ntiles = KC ? (P + kTileRows - 1) / kTileRows : P * tilesQ;
   const unsigned nx = (unsigned)(ntiles < 256 ? ntiles : 256);  // one resident workgroup per CU
   const unsigned ny = (unsigned)((R + NC - 1) / NC);
-  hipLaunchKernelGGL((k_ttm_bf16<KC, NCB, SPLIT, FAST, F8, DEEP>), dim3(nx, ny), dim3(kThreads), 0, st, X, Bhi, Blo,
+  hipLaunchKernelGGL((k_ttm_bf16<KC, NCB, SPLIT, FAST, F8, DEEP, TR>), dim3(nx, ny), dim3(kThreads), 0, st, X, Bhi, Blo,
                      C, P, K, Q, R, Kp, tilesQ, ntiles, vec);
   return hipGetLastError();
 }
@@ -565,10 +638,15 @@ hipError_t launch_ncb(const void* X, const uint16_t* Bhi, const uint16_t* Blo, f
   // three register sets (0.44 -> 0.34 ms at 1024^3, R = 128; the
   // q-contiguous layouts, with 16 four-byte loads per chunk, were 7 % slower)
   const bool deep = F8 && KC && fast && Kp >= 2 * KB;
+  // FP8 q-contiguous with Q a multiple of 16, 16-byte aligned: the chunk staged through LDS
+  const bool tr = F8 && !KC && Q % 16 == 0 && a % 16 == 0;
 #define CPALS_BF16_NCB(NCB)                                                                                 \
   do {                                                                                                     \
     if constexpr (F8 && KC && (!SPLIT || NCB <= 4)) {                                                      \
       if (deep) return launch_one<KC, NCB, SPLIT, true, F8, true>(X, Bhi, Blo, C, P, K, Q, R, Kp, vec, st); \
+    }                                                                                                      \
+    if constexpr (F8 && !KC) {                                                                             \
+      if (tr) return launch_one<KC, NCB, SPLIT, true, F8, false, true>(X, Bhi, Blo, C, P, K, Q, R, Kp, vec, st); \
     }                                                                                                      \
     return fast ? launch_one<KC, NCB, SPLIT, true, F8>(X, Bhi, Blo, C, P, K, Q, R, Kp, vec, st)            \
                 : launch_one<KC, NCB, SPLIT, false, F8>(X, Bhi, Blo, C, P, K, Q, R, Kp, vec, st);          \

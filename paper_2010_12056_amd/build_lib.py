@@ -1,6 +1,10 @@
 """Build the HIP library libcpals.so in-tree for gfx950 (hipcc cross-compiles
 without a GPU).  `python -m paper_2010_12056_amd.build_lib` or
-`build_lib.build()`."""
+`build_lib.build()`.
+
+Each source is compiled to its own object in parallel (they share no device
+code across files: every launcher is a host function), then the objects are
+linked into the shared library."""
 
 import os
 import subprocess
@@ -10,6 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcpals.so")
+OBJ_DIR = os.path.join(HERE, "_build")
 SOURCES = ["kernels.hip", "ttm_bf16.hip", "capi.hip", "mlp.hip", "batch.hip"]
 
 HIPCC_FLAGS = [
@@ -17,7 +22,6 @@ HIPCC_FLAGS = [
     "-O3",
     "-std=c++17",
     "-fPIC",
-    "-shared",
     # never emit packed FP32 arithmetic (v_pk_*_f32)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-result",
@@ -26,14 +30,31 @@ HIPCC_FLAGS = [
 
 def build(verbose=False):
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    cmd = [hipcc, *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"),
-           *[os.path.join(CSRC, s) for s in SOURCES], "-o", LIB + ".tmp"]
+    os.makedirs(OBJ_DIR, exist_ok=True)
+    procs = []
+    objs = []
+    for s in SOURCES:
+        obj = os.path.join(OBJ_DIR, os.path.splitext(s)[0] + ".o")
+        cmd = [hipcc, *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-c", os.path.join(CSRC, s), "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((s, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))
+        objs.append(obj)
+    failed = []
+    for s, pr in procs:
+        out, _ = pr.communicate()
+        if pr.returncode != 0:
+            sys.stderr.write(out)
+            failed.append(s)
+    if failed:
+        raise RuntimeError(f"hipcc failed on {', '.join(failed)}")
+    cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", LIB + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building libcpals.so")
+        raise RuntimeError("hipcc failed linking libcpals.so")
     os.replace(LIB + ".tmp", LIB)
     return LIB
 

@@ -133,6 +133,15 @@ WORKLOADS = {
                        dtype=np.float64),
     "o3_r40_long_f64": dict(dims=(1400, 12, 10), R=40, seed=1004, kind="normal", noise_rel=1e-3,
                             dtype=np.float64),
+    # orders 5 and 6 (the PP dimension tree's levels 3 and 4, five or more
+    # pair corrections per mode, the multi-pair bracket of Eq. (7)), FP64
+    "o5_small_f64": dict(dims=(9, 8, 7, 6, 5), R=6, seed=5101, kind="uniform", noise_rel=1e-3,
+                         dtype=np.float64),
+    "o6_small_f64": dict(dims=(7, 8, 6, 9, 5, 6), R=8, seed=5103, kind="uniform", noise_rel=1e-3,
+                         dtype=np.float64),
+    # the order-6 collinear family at an oracle-sized shape
+    "o6_col_small_f64": dict(dims=(10,) * 6, R=8, seed=4201, kind="collinear", noise_rel=1e-2,
+                             dtype=np.float64),
     # Shape-only stand-ins for the paper's real tensors (the data themselves
     # are not available): the shapes and CP ranks of its experiments, planted
     # non-negative rank-R factors (Uniform[0, 1)), noise 1e-2, clipped at zero.

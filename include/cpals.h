@@ -106,7 +106,10 @@ typedef struct {
                             this call ended (the phase broke down, or the regular sweep closing it
                             found a lower exact fitness than at its start); the factors are then
                             back at their values when the phase began and `fitness` is theirs */
-  int pad;
+  int r_clamped;         /* 1 when the numerator of Eq. (3) came out negative, so r was reported
+                            as 0 (fitness 1).  After an approximated sweep this means the PP
+                            estimate broke down (M~^(N) far from the exact MTTKRP); after an exact
+                            sweep, that r is below what Eq. (3) resolves in floating point */
 } cp_sweep_info;
 
 /* Create a plan for an order-`order` tensor of dims `dims` (host array of

@@ -39,7 +39,7 @@ class SweepInfo(ctypes.Structure):
         ("ttm_count", ctypes.c_int),
         ("pinv_updates", ctypes.c_int),
         ("rolled_back", ctypes.c_int),
-        ("pad", ctypes.c_int),
+        ("r_clamped", ctypes.c_int),
     ]
 
     def as_dict(self, order):
@@ -52,6 +52,7 @@ class SweepInfo(ctypes.Structure):
             "ttm_count": self.ttm_count,
             "pinv_updates": self.pinv_updates,
             "rolled_back": bool(self.rolled_back),
+            "r_clamped": bool(self.r_clamped),
         }
 
 

@@ -687,6 +687,7 @@ cp_status fill_info(cp_plan p, cp_sweep_info* info, int kind) {
     info->ttm_count = p->ttm_count;
     info->pinv_updates = h.pinv_count - pinv_seen;
     info->rolled_back = 0;
+    info->r_clamped = h.r_clamped;
   }
   if (h.status & 1) return fail(p, CP_ERR_NOT_SPD, "a Gamma matrix had non-finite entries");
   if (h.status & 2) return fail(p, CP_ERR_NUMERIC, "non-finite residual");
@@ -955,7 +956,7 @@ cp_status cp_plan_set_workspace(cp_plan p, void* dptr, size_t bytes) {
   p->ws_bytes = bytes;
   plan_carve(p);
   drop_cache(p);
-  HIP_TRY(p, hipMemsetAsync(p->stats, 0, sizeof(DevStats), p->st));
+  HIP_TRY(p, launch_zero_bytes(p->stats, sizeof(DevStats), p->st));
   return CP_OK;
 }
 
@@ -964,7 +965,7 @@ cp_status cp_set_tensor(cp_plan p, const void* T) {
   if (!p->ws) return fail(p, CP_ERR_STATE, "no workspace attached");
   p->T = T;
   drop_cache(p);
-  HIP_TRY(p, hipMemsetAsync(&p->stats->status, 0, sizeof(int), p->st));
+  HIP_TRY(p, launch_zero_bytes(&p->stats->status, sizeof(int), p->st));
   int64_t numel = 1;
   for (int m = 0; m < p->N; ++m) numel *= p->dims[m];
   if (p->prec == CP_F64) {
@@ -1099,6 +1100,7 @@ cp_status cp_pp_sweep(cp_plan p, double* const* A, double pp_tol, cp_pp_mode mod
         info->ttm_count = p->ttm_count;
         info->pinv_updates = h.pinv_count - pinv_seen;
         info->rolled_back = 1;
+        info->r_clamped = 0;
       }
       return CP_OK;
     }
@@ -1163,7 +1165,7 @@ cp_status cp_fitness(cp_plan p, const double* const* A, double* fitness) {
 cp_status cp_reset(cp_plan p) {
   if (!p) return CP_ERR_ARG;
   drop_cache(p);
-  if (p->ws) HIP_TRY(p, hipMemsetAsync(&p->stats->status, 0, sizeof(int), p->st));
+  if (p->ws) HIP_TRY(p, launch_zero_bytes(&p->stats->status, sizeof(int), p->st));
   return CP_OK;
 }
 

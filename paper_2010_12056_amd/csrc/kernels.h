@@ -16,6 +16,7 @@ struct DevStats {
   int pinv_pending;   // set by the elimination when a pivot fell below its tolerance
   int pinv_count;     // updates that used the pseudo-inverse (cumulative)
   unsigned ticket;    // arrival counter of k_update (0 between launches)
+  int r_clamped;      // the last residual's Eq. (3) numerator was negative (r reported as 0)
 };
 
 // A BF16 tensor element: the upper 16 bits of an FP32 value.

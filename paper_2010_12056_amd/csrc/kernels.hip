@@ -1882,6 +1882,7 @@ __global__ __launch_bounds__(256) void k_update(UpdateArgs<T> a) {
       a.stats->fit_num = num;
       const double r = sqrt((num > 0.0 ? num : 0.0) / tn);
       a.stats->r = r;
+      a.stats->r_clamped = (num < 0.0) ? 1 : 0;
       if (!isfinite(r)) a.stats->status |= 2;
     }
   }
@@ -2006,6 +2007,7 @@ __global__ __launch_bounds__(256) void k_fitness(const double* __restrict__ M, c
     const double num = t2 + tgs - 2.0 * tma;
     stats->fit_num = num;
     stats->r = sqrt((num > 0.0 ? num : 0.0) / t2);
+    stats->r_clamped = (num < 0.0) ? 1 : 0;
   }
 }
 
@@ -2464,6 +2466,7 @@ __global__ __launch_bounds__(256) void k_update_reduce(UpdateArgs<T> a, int G) {
       a.stats->fit_num = num;
       const double r = sqrt((num > 0.0 ? num : 0.0) / tn);
       a.stats->r = r;
+      a.stats->r_clamped = (num < 0.0) ? 1 : 0;
       if (!isfinite(r)) a.stats->status |= 2;
     }
   }

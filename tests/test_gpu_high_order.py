@@ -123,6 +123,7 @@ def test_pp_forced_schedule_high_order(dev, tree, name):
         pp.pp_als_step(st, force=kind)
         assert info["kind"] == kind
         assert info["fitness_is_exact"] == (kind == "exact")
+        assert not info["r_clamped"], (step, kind)
         assert abs(info["fitness"] - st.last_fit_est) <= 1e-9, (step, kind, info["fitness"], st.last_fit_est)
         f_exact = audit.fitness(A)
         assert abs(f_exact - st.last_fit_exact) <= 1e-9, (step, kind, f_exact, st.last_fit_exact)

@@ -140,6 +140,23 @@ cp_status cp_set_tensor(cp_plan plan, const void* T);
  * caller, but drops the plan's cached sweep state (as cp_reset). */
 cp_status cp_mttkrp(cp_plan plan, const double* const* A, int mode, double* M);
 
+/* Allocation-free MTTKRP, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Computes what cp_mttkrp computes, with the same kernels, for
+ * a tensor T of `order` dims `dims` (host array) in precision `prec`, factors
+ * A (host array of `order` device FP64 pointers, A[mode] not read) and rank
+ * `rank`, into M (device FP64, dims[mode] x rank), enqueued on `hip_stream`
+ * of the current device.  No plan, no workspace: the intermediates live in a
+ * static device array of 64 MiB that each device holds from library load
+ * until the process ends; nothing is allocated or freed.  CP_ERR_UNSUPPORTED
+ * when the intermediates would not fit (the factor shadows plus the nodes of
+ * the mode's tree path, e.g. order 4, 64^4, R = 32 in FP32 needs 32.5 MiB).
+ * Calls that overlap on one device share that array and race: serialize
+ * them (one stream, or events).  The error text of a failing call is
+ * cp_last_error(NULL) on the same thread. */
+cp_status cp_mttkrp_static(int order, const int64_t* dims, int rank, cp_prec prec, const void* T,
+                           const double* const* A, int mode, double* M, void* hip_stream);
+
 /* As cp_mttkrp, but the first contraction with the tensor uses mode
  * `root_mode` (!= mode), the rest of the path contracts the remaining modes
  * one at a time in increasing distance from `mode`.  Exercises every
@@ -242,6 +259,8 @@ cp_status cp_profile_read(cp_plan plan, double* ms, int64_t* launches);
 cp_status cp_plan_destroy(cp_plan plan);
 
 const char* cp_status_str(cp_status s);
+/* Message of the last failing call on `plan`; with plan == NULL, of the last
+ * failing plan-free call (cp_mttkrp_static) on this thread. */
 const char* cp_last_error(cp_plan plan);
 
 /* ---------------------------------------------------------------------------

@@ -71,6 +71,9 @@ EXPORTS = {
     "cp_plan_set_workspace": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]),
     "cp_set_tensor": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "cp_mttkrp": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_void_p]),
+    "cp_mttkrp_static": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int64), ctypes.c_int, ctypes.c_int,
+                                        ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p), ctypes.c_int,
+                                        ctypes.c_void_p, ctypes.c_void_p]),
     "cp_mttkrp_rooted": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p), ctypes.c_int,
                                         ctypes.c_int, ctypes.c_void_p]),
     "cp_als_sweep": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(SweepInfo)]),
@@ -132,6 +135,23 @@ def _ptrs(tensors):
     for i, t in enumerate(tensors):
         arr[i] = None if t is None else ctypes.c_void_p(t.data_ptr())
     return arr
+
+
+def mttkrp_static(T, A, mode, rank, prec="f32", out=None):
+    """M = MTTKRP of `mode` through cp_mttkrp_static (no plan, no workspace:
+    the library's static device scratch holds the intermediates).  T: device
+    tensor in `prec`; A: list of FP64 device factors (A[mode] may be None)."""
+    L = lib()
+    dims = tuple(int(d) for d in T.shape)
+    N = len(dims)
+    M = out if out is not None else torch.empty((dims[mode], rank), dtype=torch.float64, device=T.device)
+    d = (ctypes.c_int64 * N)(*dims)
+    st = torch.cuda.current_stream(T.device).cuda_stream
+    s = L.cp_mttkrp_static(N, d, int(rank), PRECS[prec], ctypes.c_void_p(T.data_ptr()), _ptrs(A), int(mode),
+                           ctypes.c_void_p(M.data_ptr()), ctypes.c_void_p(st))
+    if s != CP_OK:
+        raise CpalsError(s, L.cp_last_error(None).decode())
+    return M
 
 
 class Plan:

@@ -23,6 +23,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -912,6 +913,80 @@ cp_status judge_rollback(cp_plan p, double* const* A) {
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Allocation-free MTTKRP (cp_mttkrp_static).  Its intermediates (factor
+// shadows, the nodes of the dimension-tree path, the BF16 factor parts) live
+// in this file-scope device array instead of a caller workspace.  Every
+// device the library runs on holds its own copy from module load until the
+// process ends.  On the host the array's name is only a stand-in: device
+// memory is reached through the address hipGetSymbolAddress gives for the
+// current device, looked up once per device and kept.
+// ---------------------------------------------------------------------------
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+thread_local std::string g_static_err;
+
+cp_status static_fail(cp_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_static_err = buf;
+  return s;
+}
+
+// This device's copy of `scratch` (device `dev` must be current).
+hipError_t static_scratch(int dev, void** out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+// Carve the scratch of an MTTKRP of `mode` along the standard tree path:
+// the factor shadows, the BF16 factor parts of a low-precision tensor, and
+// one node per depth of that path, each region 256-byte aligned.  With
+// base == nullptr only the total is computed.
+size_t static_layout(cp_plan p, int mode, char* base) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char* at = base ? base + off : nullptr;
+    off += align_up(bytes ? bytes : 1);
+    return at;
+  };
+  int64_t smax = 0;
+  for (int m = 0; m < p->N; ++m) {
+    p->Ash[m] = take((size_t)p->dims[m] * p->R * p->esz);
+    smax = std::max(smax, p->dims[m]);
+  }
+  const size_t bt = lowp(p->prec) ? (size_t)p->R * bf16_factor_pitch(smax) * 2 : 0;
+  p->Bt_hi = (uint16_t*)take(bt);
+  void* lo = take(split_factor(p->prec) ? bt : 0);
+  p->Bt_lo = split_factor(p->prec) ? (uint16_t*)lo : nullptr;
+  const std::vector<int> seq = dt_path(p->N, mode);
+  uint32_t set = full_set(p->N);
+  for (int d = 1; d <= p->N - 2; ++d) {
+    set &= ~(1u << seq[d - 1]);
+    p->slot_cap[d] = (size_t)node_numel(p, set) * p->esz;
+    p->slot_buf[d] = take(p->slot_cap[d]);
+  }
+  return off;
+}
+
+}  // namespace
+
 extern "C" {
 
 cp_status cp_plan_create(cp_plan* out, int order, const int64_t* dims, int rank, cp_prec prec,
@@ -1229,6 +1304,53 @@ cp_status cp_plan_destroy(cp_plan p) {
   return CP_OK;
 }
 
+cp_status cp_mttkrp_static(int order, const int64_t* dims, int rank, cp_prec prec, const void* T,
+                           const double* const* A, int mode, double* M, void* hip_stream) {
+  g_static_err.clear();
+  if (!dims || !T || !A || !M) return static_fail(CP_ERR_ARG, "null argument");
+  if (order < 3 || order > kMaxOrder || rank < 1 || rank > kMaxRank)
+    return static_fail(CP_ERR_UNSUPPORTED, "order %d / rank %d outside the limits", order, rank);
+  if (prec != CP_F64 && prec != CP_F32 && !lowp(prec)) return static_fail(CP_ERR_UNSUPPORTED, "bad precision");
+  if (mode < 0 || mode >= order) return static_fail(CP_ERR_ARG, "bad mode %d", mode);
+  for (int m = 0; m < order; ++m) {
+    if (dims[m] < 1) return static_fail(CP_ERR_ARG, "dims[%d] = %lld", m, (long long)dims[m]);
+    if (m != mode && !A[m]) return static_fail(CP_ERR_ARG, "null factor %d", m);
+  }
+  cp_plan_s pl;
+  cp_plan p = &pl;
+  p->N = order;
+  p->R = rank;
+  for (int m = 0; m < order; ++m) p->dims[m] = dims[m];
+  p->prec = prec;
+  p->tree = CP_TREE_DT;
+  p->st = (hipStream_t)hip_stream;
+  p->esz = (prec == CP_F64) ? 8 : 4;
+  const size_t need = static_layout(p, mode, nullptr);
+  if (need > kStaticScratchBytes)
+    return static_fail(CP_ERR_UNSUPPORTED, "needs %zu bytes of scratch; the static scratch holds %zu", need,
+                       kStaticScratchBytes);
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return static_fail(CP_ERR_HIP, "hipGetDevice failed: %s", hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return static_fail(CP_ERR_UNSUPPORTED, "device %d", dev);
+  void* base = nullptr;
+  e = static_scratch(dev, &base);
+  if (e != hipSuccess) return static_fail(CP_ERR_HIP, "hipGetSymbolAddress failed: %s", hipGetErrorString(e));
+  static_layout(p, mode, (char*)base);
+  p->ws = (char*)base;
+  p->ws_bytes = kStaticScratchBytes;
+  p->T = T;
+  for (int m = 0; m < order; ++m) {
+    if (m == mode) continue;
+    const cp_status s = convert_factor(p, A[m], p->Ash[m], p->dims[m] * p->R);
+    if (s != CP_OK) return static_fail(s, "%s", p->err.c_str());
+    ++p->ver[m];
+  }
+  const cp_status s = run_path(p, dt_path(order, mode), M);
+  if (s != CP_OK) return static_fail(s, "%s", p->err.c_str());
+  return CP_OK;
+}
+
 const char* cp_status_str(cp_status s) {
   switch (s) {
     case CP_OK: return "ok";
@@ -1243,7 +1365,7 @@ const char* cp_status_str(cp_status s) {
 }
 
 const char* cp_last_error(cp_plan p) {
-  if (!p) return "null plan";
+  if (!p) return g_static_err.empty() ? "null plan" : g_static_err.c_str();
   return p->err.c_str();
 }
 

@@ -187,3 +187,27 @@ def test_low_precision_plans_share_the_factor_staging():
     assert need[cpals.CP_BF16] > need[cpals.CP_F32]
     h = ctypes.c_void_p()
     assert L.cp_plan_create(ctypes.byref(h), 3, dims, 40, 6, cpals.CP_TREE_DT, None) == cpals.CP_ERR_UNSUPPORTED
+
+
+def test_static_mttkrp_argument_checks():
+    """The allocation-free MTTKRP checks its arguments and the size of its
+    intermediates against the static scratch before touching the device."""
+    from paper_2010_12056_amd import cpals
+
+    L = _lib()
+    dims = (ctypes.c_int64 * 4)(16, 16, 16, 16)
+    A = (ctypes.c_void_p * 4)(256, 256, 256, 256)
+    T = ctypes.c_void_p(256)
+    M = ctypes.c_void_p(256)
+    f = L.cp_mttkrp_static
+    assert f(4, dims, 8, cpals.CP_F32, None, A, 0, M, None) == cpals.CP_ERR_ARG
+    assert f(4, dims, 8, cpals.CP_F32, T, A, 4, M, None) == cpals.CP_ERR_ARG
+    assert f(2, dims, 8, cpals.CP_F32, T, A, 0, M, None) == cpals.CP_ERR_UNSUPPORTED
+    assert f(4, dims, 129, cpals.CP_F32, T, A, 0, M, None) == cpals.CP_ERR_UNSUPPORTED
+    A[2] = None
+    assert f(4, dims, 8, cpals.CP_F32, T, A, 0, M, None) == cpals.CP_ERR_ARG
+    assert b"null factor 2" in L.cp_last_error(None)
+    A[2] = 256
+    big = (ctypes.c_int64 * 4)(128, 128, 128, 128)  # first node 128^3 x 64 FP32 = 512 MiB
+    assert f(4, big, 64, cpals.CP_F32, T, A, 0, M, None) == cpals.CP_ERR_UNSUPPORTED
+    assert b"static scratch" in L.cp_last_error(None)

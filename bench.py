@@ -5,14 +5,19 @@ Workload: order-4 dense tensor 128^4 in FP32 (synthetic: planted rank-64
 factors iid Uniform[0,1) plus Gaussian noise at 1% of the norm), CP rank
 R = 64, factors initialised iid Uniform[0,1), all generated from a seed.
 
-One step = one pass of the whole hot path from the same initial factors:
-  DT    3 sweeps with the standard dimension tree (2 first-level TTMs each)
-  MSDT  3 sweeps with the multi-sweep dimension tree (one whole tree: 4 TTMs)
-  PP    PP-ALS on the MSDT plan: 1 regular sweep, PP initialization plus one
-        approximated sweep, then 3 approximated sweeps (a fixed schedule)
+One step = one pass of the whole hot path from the same initial factors, the
+three methods run to the same fitness:
+  DT    10 sweeps with the standard dimension tree (2 first-level TTMs each)
+  MSDT  10 sweeps with the multi-sweep dimension tree (N TTMs per N-1 sweeps),
+        the same update order, so the same fitness up to rounding
+  PP    PP-ALS (Alg. 2 with its own activation test, tolerance 0.1) on the
+        MSDT plan, for the outer steps it needs to reach the DT run's final
+        exact fitness less 1e-4 (counted once by an audited, untimed run)
 Every sweep runs Gamma / inverse / solve / Gram / residual in FP64 on the
-GPU.  `value` is the step's effective throughput: each sweep is credited the
-flops of one standard-DT sweep of this workload, divided by the step time.
+GPU.  `value` is the step's effective throughput: each run is credited the
+flops the standard DT needs to reach the common fitness, divided by the step
+time.  Other workloads (--workload): the order-3 64^3 FP64 tensor (20
+sweeps), the precision path, the batched path, shape stand-ins.
 
 Prints one JSON line on stdout; everything else goes to stderr.
 """
@@ -131,13 +136,25 @@ def load_traffic(sha):
     return d.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(w, budget_s, dt_flops):
-    """The FP64 oracle (test infrastructure) on the host cores: exact ALS
-    sweeps (naive explicit-KRP MTTKRP) on the same tensor and init, as many
-    as fit in the budget (at least one)."""
+# sweeps of the DT and MSDT runs per workload (the PP run goes on until it
+# reaches the DT run's final exact fitness less TARGET_SLACK)
+TREE_SWEEPS = {"o4_s128_r64_f32": 10, "o3_s64_r16_f64": 20}
+PP_TOL = 0.1  # Alg. 2 tolerance (the paper's value for its application tensors, Sec. V-C)
+TARGET_SLACK = 1e-4
+PP_MAX_STEPS = 60
+
+
+def oracle_timings(w, budget_s, pp_start, target_sweeps):
+    """The FP64 oracle (test infrastructure) on the host cores, on bounded
+    samples of the same workload: naive explicit-KRP ALS sweeps from the same
+    init (their fitness is compared with the GPU's), oracle-DT and
+    oracle-MSDT sweeps (MTTKRPs through its tree cache), and one PP
+    initialization plus one approximated step of its Alg. 2, started from the
+    GPU run's factors where Alg. 2 entered PP."""
     import numpy as np
 
     import oracle
+    from oracle import pp, trees
 
     try:
         from threadpoolctl import threadpool_info
@@ -146,24 +163,331 @@ def cpu_baseline(w, budget_s, dt_flops):
     except Exception:
         threads = os.cpu_count()
     T64 = w.T.astype(np.float64)
+    N = T64.ndim
+    out = {"threads": int(threads)}
     st = oracle.AlsState.start(T64, w.init)
-    n = 0
+    rs = []
     t0 = time.perf_counter()
-    while True:
-        oracle.als_sweep(st)
-        n += 1
-        if time.perf_counter() - t0 > budget_s or n >= 8:
+    while len(rs) < target_sweeps and (not rs or time.perf_counter() - t0 < budget_s):
+        rs.append(oracle.als_sweep(st))
+    out["naive"] = {"sweeps": len(rs), "ms_per_sweep": (time.perf_counter() - t0) / len(rs) * 1e3,
+                    "fitness": [1.0 - r for r in rs]}
+    del st
+    for kind in ("dt", "msdt"):
+        st = oracle.AlsState.start(T64, w.init)
+        cache = trees.DTCache(T64, st.A)
+        n_sw, u = 0, 0
+        t0 = time.perf_counter()
+        while n_sw < 3 and (n_sw == 0 or time.perf_counter() - t0 < budget_s / 2):
+            paths = [trees.dt_path(N, n) if kind == "dt" else trees.msdt_path(N, u + n) for n in range(N)]
+            trees.als_sweep_tree(st, cache, paths)
+            u += N
+            n_sw += 1
+        out[kind] = {"sweeps": n_sw, "ms_per_sweep": (time.perf_counter() - t0) / n_sw * 1e3}
+        del st, cache
+    if pp_start is not None:
+        st = pp.PPState.start(T64, pp_start)
+        st.dA = [np.zeros_like(a) for a in st.A]  # entered from a passing test: no carried change
+        t0 = time.perf_counter()
+        pp.pp_als_step(st, force="init")
+        t1 = time.perf_counter()
+        pp.pp_als_step(st, force="approx")
+        t2 = time.perf_counter()
+        out["pp"] = {"init_step_ms": (t1 - t0) * 1e3, "approx_step_ms": (t2 - t1) * 1e3,
+                     "note": "the oracle's approximated step includes its exact-fitness audit (one naive MTTKRP)"}
+    return out
+
+
+def tree_bench(args):
+    """DT, MSDT and PP (Alg. 2) on one workload, at equal final fitness.
+
+    One step, from the same initial factors each time:
+      DT    TREE_SWEEPS sweeps with the standard dimension tree (Sec. II-C);
+      MSDT  as many sweeps with the multi-sweep dimension tree (Sec. III),
+            bit-for-bit the same update order;
+      PP    Alg. 2 (tolerance PP_TOL, its own activation test) on the MSDT
+            plan, for the number of outer steps it needs to reach the DT run's
+            final exact fitness less TARGET_SLACK (found once beforehand by an
+            untimed run whose every step is audited with cp_fitness; the timed
+            runs repeat that trajectory bit for bit, checked at the end).
+    `value` credits each run with the DT flops that reach the target fitness
+    (TREE_SWEEPS DT sweeps for DT and MSDT; the DT sweeps to target for PP),
+    divided by the step time."""
+    import numpy as np
+    import torch
+
+    from paper_2010_12056_amd import cpals, synth
+
+    dev = torch.device("cuda:0")
+    t_gen = time.perf_counter()
+    w = synth.workload(args.workload)
+    log(f"[bench] generated {args.workload} dims={w.dims} R={w.R} in {time.perf_counter() - t_gen:.1f}s")
+    prec = "f32" if w.T.dtype == np.float32 else "f64"
+    T = torch.from_numpy(w.T).to(dev)
+    A0 = [torch.from_numpy(a).to(dev) for a in w.init]
+    N = len(w.dims)
+    R = w.R
+    F_dt = dt_sweep_flops(w.dims, R)
+    numel = int(np.prod(w.dims))
+    ttm_flops = 2 * numel * R
+    if args.counters_workload:
+        plan = cpals.Plan(w.dims, R, prec=prec, tree="dt", device=dev)
+        plan.set_tensor(T)
+        for mode in (0, N - 1):  # first-level contraction over the last mode, then over mode 0
+            plan.mttkrp(A0, mode)
+        torch.cuda.synchronize()
+        src = torch.empty(128 * 2**20, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)  # calibration: reads and writes exactly 512 MiB each
+        torch.cuda.synchronize()
+        log("[bench] counters workload done")
+        return
+    n_sw = TREE_SWEEPS.get(args.workload, 10)
+    plans = {"dt": cpals.Plan(w.dims, R, prec=prec, tree="dt", device=dev),
+             "msdt": cpals.Plan(w.dims, R, prec=prec, tree="msdt", device=dev)}
+    for p in plans.values():
+        p.set_tensor(T)
+    audit = cpals.Plan(w.dims, R, prec=prec, tree="dt", device=dev)
+    audit.set_tensor(T)
+    A = {k: [a.clone() for a in A0] for k in ("dt", "msdt", "pp")}
+
+    def restart(k):
+        plan = plans["dt" if k == "dt" else "msdt"]
+        for a, a0 in zip(A[k], A0):
+            a.copy_(a0)
+        plan.reset()
+        return plan
+
+    # calibration (untimed): fitness trajectories, the target, PP's steps to it
+    log("[bench] calibration")
+    fit = {}
+    for k in ("dt", "msdt"):
+        plan = restart(k)
+        fit[k] = [plan.als_sweep(A[k])["fitness"] for _ in range(n_sw)]
+    target = fit["dt"][-1] - TARGET_SLACK
+    to_target = {k: next(i + 1 for i, f in enumerate(fit[k]) if f >= target) for k in ("dt", "msdt")}
+    plan = restart("pp")
+    pp_kinds, pp_est, pp_exact, pp_clamped = [], [], [], []
+    pp_start = None
+    while len(pp_kinds) < PP_MAX_STEPS:
+        if pp_start is None:
+            before = [a.cpu().numpy() for a in A["pp"]]
+        info = plan.pp_sweep(A["pp"], tol=PP_TOL, mode="auto")
+        if info["kind"] == "init" and pp_start is None:
+            pp_start = before
+        pp_kinds.append(info["kind"])
+        pp_est.append(info["fitness"])
+        pp_clamped.append(info["r_clamped"])
+        pp_exact.append(audit.fitness(A["pp"]))
+        if pp_exact[-1] >= target:
             break
-    dt = time.perf_counter() - t0
-    return {
-        "value": n * dt_flops / dt / 1e12,
-        "unit": "TFLOP/s (DT-equivalent)",
-        "cores": int(threads),
-        "kind": "oracle",
-        "sample": f"{n} exact FP64 ALS sweep(s) of the oracle (explicit-KRP MTTKRP) on the same "
-                  f"128^4 tensor and init, {dt:.2f} s, {dt / n * 1e3:.1f} ms/sweep",
-        "ms_per_sweep": dt / n * 1e3,
+    k_pp = len(pp_kinds)
+    pp_reached = pp_exact[-1] >= target
+    pp_final = [a.clone() for a in A["pp"]]
+    log(f"[bench] target {target:.8f}: dt {to_target['dt']} sweeps, msdt {to_target['msdt']}, "
+        f"pp {k_pp} steps {pp_kinds} reached={pp_reached}")
+    audit.close()
+
+    stream = torch.cuda.current_stream(dev)
+
+    def one_step(ev=None):
+        """ev: per run, a list of events recorded after each sweep (index 0 before the first)."""
+        for k in ("dt", "msdt", "pp"):
+            plan = restart(k)
+            if ev is not None:
+                ev[k][0].record(stream)
+            nk = k_pp if k == "pp" else n_sw
+            for i in range(nk):
+                if k == "pp":
+                    plan.pp_sweep(A[k], tol=PP_TOL, mode="auto", info=False)
+                else:
+                    plan.als_sweep(A[k], info=False)
+                if ev is not None:
+                    ev[k][i + 1].record(stream)
+
+    log("[bench] warmup")
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+    log("[bench] timed region")
+    # inside the timed region only the first-level contractions of the last
+    # timed step carry event pairs (their average launch time feeds the
+    # roofline; each pair costs device time); the other phases are timed on
+    # one more step afterwards
+    for p in plans.values():
+        p.profile(False)
+        p.profile_read()
+
+    def mk(n):
+        return [torch.cuda.Event(enable_timing=True) for _ in range(n + 1)]
+
+    evs = [{"dt": mk(n_sw), "msdt": mk(n_sw), "pp": mk(k_pp)} for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        if s == args.steps - 1:
+            for p in plans.values():
+                p.profile(True, phases=("ttm",))
+        one_step(evs[s])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    timed_phase = {}
+    for p in plans.values():
+        for ph, (ms, cnt) in p.profile_read().items():
+            a, b = timed_phase.get(ph, (0.0, 0))
+            timed_phase[ph] = (a + ms, b + cnt)
+        p.profile(True)  # every phase, for the breakdown step
+        p.profile_read()
+    # the timed PP runs followed the calibrated trajectory bit for bit
+    same = all(torch.equal(a, b) for a, b in zip(A["pp"], pp_final))
+    one_step()
+    phase = {}
+    for p in plans.values():
+        for ph, (ms, cnt) in p.profile_read().items():
+            a, b = phase.get(ph, (0.0, 0))
+            phase[ph] = (a + ms, b + cnt)
+        p.profile(False)
+
+    def sweep_ms(k):
+        """Mean over timed steps of each sweep's duration (ms), per sweep index."""
+        n = len(evs[0][k]) - 1
+        return [float(np.mean([e[k][i].elapsed_time(e[k][i + 1]) for e in evs])) for i in range(n)]
+
+    per = {k: sweep_ms(k) for k in ("dt", "msdt", "pp")}
+    log(f"[bench] {args.steps} steps, {ms_step:.3f} ms/step; per-run ms "
+        f"{ {k: round(sum(v), 3) for k, v in per.items()} }")
+    methods = {}
+    for k in ("dt", "msdt"):
+        methods[k] = {"sweeps": n_sw, "ms_per_sweep": round(sum(per[k]) / n_sw, 4),
+                      "effective_tflops": round(F_dt * n_sw / (sum(per[k]) * 1e-3) / 1e12, 3),
+                      "sweeps_to_target": to_target[k], "ms_to_target": round(sum(per[k][:to_target[k]]), 4),
+                      "final_fitness": fit[k][-1]}
+    kinds = {kk: [per["pp"][i] for i, x in enumerate(pp_kinds) if x == kk] for kk in ("exact", "init", "approx")}
+    methods["pp"] = {
+        "tolerance": PP_TOL, "steps_to_target": k_pp, "reached_target": bool(pp_reached),
+        "schedule": pp_kinds,
+        "steps_by_kind": {kk: len(v) for kk, v in kinds.items()},
+        "ms_by_kind": {kk: round(float(np.mean(v)), 4) for kk, v in kinds.items() if v},
+        "ms_to_target": round(sum(per["pp"]), 4),
+        "final_exact_fitness": pp_exact[-1],
+        "estimate_clamped_steps": int(sum(pp_clamped)),
+        "max_abs_estimate_minus_exact": float(max(abs(a - b) for a, b in zip(pp_est, pp_exact))),
+        "timed_runs_bitwise_equal_calibration": bool(same),
     }
+    methods["msdt"]["speedup_vs_dt_per_sweep"] = round(methods["dt"]["ms_per_sweep"] / methods["msdt"]["ms_per_sweep"], 3)
+    for k in ("msdt", "pp"):
+        methods[k]["speedup_vs_dt_to_target"] = round(methods["dt"]["ms_to_target"] / methods[k]["ms_to_target"], 3)
+    methods["pp"]["speedup_vs_msdt_to_target"] = round(methods["msdt"]["ms_to_target"] / methods["pp"]["ms_to_target"], 3)
+
+    # the dimension tree with its upper two levels combined (order >= 4): timed
+    # on its own, outside the step, against the DT plan's sweeps
+    if N >= 4:
+        pc = cpals.Plan(w.dims, R, prec=prec, tree="dt_combined", device=dev)
+        pc.set_tensor(T)
+        Ac = [a.clone() for a in A0]
+        c_ms = []
+        for rep in range(1 + args.steps):
+            pc.reset()
+            for a, a0 in zip(Ac, A0):
+                a.copy_(a0)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(3):
+                pc.als_sweep(Ac, info=False)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            if rep:
+                c_ms.append(e0.elapsed_time(e1) / 3)
+        pc.reset()
+        for a, a0 in zip(Ac, A0):
+            a.copy_(a0)
+        c_fit = [pc.als_sweep(Ac)["fitness"] for _ in range(3)]
+        pc.close()
+        cms = float(np.mean(c_ms))
+        methods["dt_combined"] = {
+            "sweeps": 3, "ms_per_sweep": round(cms, 4),
+            "effective_tflops": round(F_dt / (cms * 1e-3) / 1e12, 3),
+            "speedup_vs_dt_per_sweep": round(methods["dt"]["ms_per_sweep"] / cms, 3),
+            "fitness_3_sweeps": c_fit[-1], "dt_fitness_3_sweeps": fit["dt"][2],
+            "timed": "separately, not part of the step"}
+        log(f"[bench] dt_combined {methods['dt_combined']}")
+
+    credited = F_dt * (2 * n_sw + to_target["dt"])
+    value = credited / (ms_step * 1e-3) / 1e12
+    ttm_ms, ttm_n = timed_phase["ttm"]
+    ttm_avg_ms = ttm_ms / max(ttm_n, 1)
+    achieved = ttm_flops / (ttm_avg_ms * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[prec]
+    traffic = load_traffic(kernel_sha()) if args.workload == "o4_s128_r64_f32" else None
+    headline = args.workload == "o4_s128_r64_f32"
+    cfg = synth.WORKLOADS[args.workload]
+    desc = (f"order-{N} dense {'x'.join(map(str, w.dims))} {prec.upper()}, planted rank-{R} {cfg['kind']} factors"
+            f" + {cfg['noise_rel']:g} noise{', clipped at zero' if cfg.get('nonneg') else ''}, CP rank {R}")
+    out = {
+        "metric": ("ALS sweep ms & effective TFLOP/s, order-4 s=128 R=64: MSDT/PP vs plain DT" if headline else
+                   f"ALS sweep ms & effective TFLOP/s, {args.workload} ({'x'.join(map(str, w.dims))}, R={R}):"
+                   " MSDT/PP vs plain DT"),
+        "value": round(value, 3),
+        "unit": "TFLOP/s (effective: DT flops to the common target fitness / step time)",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": prec,
+        "data": "synthetic",
+        "config": {"workload": desc, "dims": list(w.dims), "rank": R,
+                   "step": f"DT {n_sw} sweeps + MSDT {n_sw} sweeps + PP (Alg. 2, tolerance {PP_TOL}) "
+                           f"{k_pp} outer steps to the DT run's final fitness - {TARGET_SLACK:g}",
+                   "target_fitness": target, "dt_sweep_gflop": round(F_dt / 1e9, 3), "parallelism": "1 GPU"},
+        "methods": methods,
+        "phase_ms_per_step": {k: round(v[0], 4) for k, v in phase.items()},
+        "phase_note": "one extra step with every phase timed (its event pairs make it slower than a timed step)",
+        "fitness_per_sweep": {"dt": fit["dt"], "msdt": fit["msdt"]},
+        "roofline": {
+            "kernel": "k_ttm (first-level contraction, FP32 MFMA)" if prec == "f32" else
+                      "k_ttm (first-level contraction, FP64 MFMA)",
+            "bound": "mfma",
+            "achieved": round(achieved, 3),
+            "peak": peak,
+            "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 4),
+            "traffic": traffic,
+            "avg_launch_ms": round(ttm_avg_ms, 5),
+            "launches": ttm_n,
+            "flops_per_launch": ttm_flops,
+        },
+        "cpu_baseline": None,
+    }
+    for p in plans.values():
+        p.close()
+    del T
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle)")
+        orc = oracle_timings(w, args.cpu_budget, pp_start, n_sw)
+        nv = orc["naive"]
+        out["cpu_baseline"] = {
+            "value": F_dt / (nv["ms_per_sweep"] * 1e-3) / 1e12,
+            "unit": "TFLOP/s (DT-equivalent)",
+            "cores": orc["threads"],
+            "kind": "oracle",
+            "sample": f"{nv['sweeps']} exact FP64 ALS sweep(s) of the oracle (explicit-KRP MTTKRP) on the same "
+                      f"tensor and init, {nv['ms_per_sweep']:.1f} ms/sweep; oracle-DT and oracle-MSDT sweeps "
+                      f"and one PP initialization + approximated step timed on their own",
+            "ms_per_sweep": nv["ms_per_sweep"],
+            "variants_ms": {"naive": round(nv["ms_per_sweep"], 1), "dt": round(orc["dt"]["ms_per_sweep"], 1),
+                            "msdt": round(orc["msdt"]["ms_per_sweep"], 1),
+                            **({"pp_init_step": round(orc["pp"]["init_step_ms"], 1),
+                                "pp_approx_step": round(orc["pp"]["approx_step_ms"], 1)} if "pp" in orc else {})},
+        }
+        d = [abs(a - b) for a, b in zip(fit["dt"], nv["fitness"])]
+        out["fitness_vs_fp64_oracle"] = {"sweeps": len(d), "max_abs_diff_dt": max(d),
+                                         "max_abs_diff_msdt": max(abs(a - b) for a, b in zip(fit["msdt"], nv["fitness"]))}
+    print(json.dumps(out), flush=True)
 
 
 PRECISION_WORKLOAD = "o3_s1024_r128_bf16"
@@ -456,226 +780,7 @@ def main():
     if args.workload == BATCH_WORKLOAD:
         batch_bench(args)
         return
-    dev = torch.device("cuda:0")
-    t_gen = time.perf_counter()
-    w = synth.workload(args.workload)
-    log(f"[bench] generated {args.workload} dims={w.dims} R={w.R} in {time.perf_counter() - t_gen:.1f}s")
-    prec = "f32" if w.T.dtype == np.float32 else "f64"
-    T = torch.from_numpy(w.T).to(dev)
-    A0 = [torch.from_numpy(a).to(dev) for a in w.init]
-    N = len(w.dims)
-    R = w.R
-    F_dt = dt_sweep_flops(w.dims, R)
-    numel = int(np.prod(w.dims))
-    ttm_flops = 2 * numel * R
-    if args.counters_workload:
-        plan = cpals.Plan(w.dims, R, prec=prec, tree="dt", device=dev)
-        plan.set_tensor(T)
-        for mode in (0, N - 1):  # first-level contraction over the last mode, then over mode 0
-            plan.mttkrp(A0, mode)
-        torch.cuda.synchronize()
-        src = torch.empty(128 * 2**20, dtype=torch.float32, device=dev).fill_(1.0)
-        dst = torch.empty_like(src)
-        dst.copy_(src)  # calibration: reads and writes exactly 512 MiB each
-        torch.cuda.synchronize()
-        log("[bench] counters workload done")
-        return
-
-    plans = {
-        "dt": cpals.Plan(w.dims, R, prec=prec, tree="dt", device=dev),
-        "msdt": cpals.Plan(w.dims, R, prec=prec, tree="msdt", device=dev),
-    }
-    plans["pp"] = plans["msdt"]
-    for k in ("dt", "msdt"):
-        plans[k].set_tensor(T)
-    A = {k: [a.clone() for a in A0] for k in ("dt", "msdt", "pp")}
-    pp_sched = ["exact", "init", "approx", "approx", "approx"]
-    sweeps = {"dt": 3, "msdt": N - 1, "pp": len(pp_sched)}
-    stream = torch.cuda.current_stream(dev)
-
-    def one_step(ev=None):
-        for k in ("dt", "msdt", "pp"):
-            plan = plans[k]
-            for a, a0 in zip(A[k], A0):
-                a.copy_(a0)
-            plan.reset()
-            if ev is not None:
-                ev[k][0].record(stream)
-            if k == "pp":
-                for kind in pp_sched:
-                    plan.pp_sweep(A[k], mode=kind, info=False)
-            else:
-                for _ in range(sweeps[k]):
-                    plan.als_sweep(A[k], info=False)
-            if ev is not None:
-                ev[k][1].record(stream)
-
-    log("[bench] warmup")
-    for _ in range(args.warmup):
-        one_step()
-    torch.cuda.synchronize()
-    # per-kind timing of single sweeps (reported breakdown, separate from the timed steps)
-    log("[bench] timed region")
-    # inside the timed region only the first-level contractions of the last
-    # timed step carry event pairs (their average launch time feeds the
-    # roofline; each pair costs device time); the other phases are timed on
-    # one more step afterwards
-    for k in ("dt", "msdt"):
-        plans[k].profile(False)
-        plans[k].profile_read()
-    evs = [{k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-            for k in ("dt", "msdt", "pp")} for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for s in range(args.steps):
-        if s == args.steps - 1:
-            for k in ("dt", "msdt"):
-                plans[k].profile(True, phases=("ttm",))
-        one_step(evs[s])
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_step = (t1 - t0) * 1e3 / args.steps
-    timed_phase = {}
-    for k in ("dt", "msdt"):
-        for ph, (ms, cnt) in plans[k].profile_read().items():
-            a, b = timed_phase.get(ph, (0.0, 0))
-            timed_phase[ph] = (a + ms, b + cnt)
-        plans[k].profile(True)  # every phase, for the breakdown step
-        plans[k].profile_read()
-    one_step()
-    phase = {}
-    for k in ("dt", "msdt"):
-        for ph, (ms, cnt) in plans[k].profile_read().items():
-            a, b = phase.get(ph, (0.0, 0))
-            phase[ph] = (a + ms, b + cnt)
-        plans[k].profile(False)
-    var_ms = {k: sum(e[k][0].elapsed_time(e[k][1]) for e in evs) / args.steps for k in ("dt", "msdt", "pp")}
-    log(f"[bench] {args.steps} steps, {ms_step:.3f} ms/step; variants {var_ms}")
-
-    # fitness check of the last step's factors against the DT run (same math)
-    infos = {}
-    for k in ("dt", "msdt"):
-        plans[k].reset()
-        for a, a0 in zip(A[k], A0):
-            a.copy_(a0)
-        infos[k] = [plans[k].als_sweep(A[k])["fitness"] for _ in range(3)]
-    log(f"[bench] fitness dt {infos['dt']} msdt {infos['msdt']}")
-
-    # PP: one timed breakdown per sweep kind on the MSDT plan
-    plan = plans["pp"]
-    plan.reset()
-    for a, a0 in zip(A["pp"], A0):
-        a.copy_(a0)
-    kind_ms = {}
-    for kind in pp_sched:
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        plan.pp_sweep(A["pp"], mode=kind, info=False)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        kind_ms.setdefault(kind, []).append(e0.elapsed_time(e1))
-
-    # the dimension tree with its upper two levels combined (order >= 4): timed
-    # on its own, outside the step, against the DT plan's sweeps
-    comb = None
-    if N >= 4:
-        pc = cpals.Plan(w.dims, R, prec=prec, tree="dt_combined", device=dev)
-        pc.set_tensor(T)
-        Ac = [a.clone() for a in A0]
-        c_ms = []
-        for rep in range(1 + args.steps):
-            pc.reset()
-            for a, a0 in zip(Ac, A0):
-                a.copy_(a0)
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            for _ in range(3):
-                pc.als_sweep(Ac, info=False)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            if rep:
-                c_ms.append(e0.elapsed_time(e1) / 3)
-        pc.reset()
-        for a, a0 in zip(Ac, A0):
-            a.copy_(a0)
-        c_fit = [pc.als_sweep(Ac)["fitness"] for _ in range(3)]
-        pc.close()
-        comb = {"ms_per_sweep": float(np.mean(c_ms)), "fitness": c_fit}
-        log(f"[bench] dt_combined {comb}")
-
-    n_sweeps = sum(sweeps.values())
-    value = n_sweeps * F_dt / (ms_step * 1e-3) / 1e12
-    ttm_ms, ttm_n = timed_phase["ttm"]
-    ttm_avg_ms = ttm_ms / max(ttm_n, 1)
-    achieved = ttm_flops / (ttm_avg_ms * 1e-3) / 1e12
-    peak = PEAK_TFLOPS[prec]
-    sha = kernel_sha()
-    traffic = load_traffic(sha) if args.workload == "o4_s128_r64_f32" else None
-    variants = {}
-    for k in ("dt", "msdt", "pp"):
-        per = var_ms[k] / sweeps[k]
-        variants[k] = {"sweeps": sweeps[k], "ms_per_sweep": round(per, 4),
-                       "effective_tflops": round(F_dt / (per * 1e-3) / 1e12, 3)}
-    variants["pp"]["ms_by_kind"] = {k: round(float(np.mean(v)), 4) for k, v in kind_ms.items()}
-    variants["msdt"]["speedup_vs_dt"] = round(variants["dt"]["ms_per_sweep"] / variants["msdt"]["ms_per_sweep"], 3)
-    variants["pp"]["approx_speedup_vs_dt"] = round(
-        variants["dt"]["ms_per_sweep"] / variants["pp"]["ms_by_kind"]["approx"], 3)
-    if comb is not None:
-        variants["dt_combined"] = {
-            "sweeps": 3, "ms_per_sweep": round(comb["ms_per_sweep"], 4),
-            "effective_tflops": round(F_dt / (comb["ms_per_sweep"] * 1e-3) / 1e12, 3),
-            "speedup_vs_dt": round(variants["dt"]["ms_per_sweep"] / comb["ms_per_sweep"], 3),
-            "fitness_3_sweeps": comb["fitness"][-1],
-            "timed": "separately, not part of the step"}
-
-    headline = args.workload == "o4_s128_r64_f32"
-    cfg = synth.WORKLOADS[args.workload]
-    desc = (f"order-{N} dense {'x'.join(map(str, w.dims))} {prec.upper()}, planted rank-{R} {cfg['kind']} factors"
-            f" + {cfg['noise_rel']:g} noise{', clipped at zero' if cfg.get('nonneg') else ''}, CP rank {R}")
-    out = {
-        "metric": ("ALS sweep ms & effective TFLOP/s, order-4 s=128 R=64: MSDT/PP vs plain DT" if headline else
-                   f"ALS sweep ms & effective TFLOP/s, {args.workload} ({'x'.join(map(str, w.dims))}, R={R}):"
-                   " MSDT/PP vs plain DT"),
-        "value": round(value, 3),
-        "unit": "TFLOP/s (effective: DT-sweep flops per sweep / time)",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": prec,
-        "data": "synthetic",
-        "config": {"workload": desc,
-                   "dims": list(w.dims), "rank": R, "sweeps_per_step": n_sweeps,
-                   "dt_sweep_gflop": round(F_dt / 1e9, 3), "parallelism": "1 GPU"},
-        "variants": variants,
-        "phase_ms_per_step": {k: round(v[0], 4) for k, v in phase.items()},
-        "phase_note": "one extra step with every phase timed (its event pairs make it slower than a timed step)",
-        "fitness_3_sweeps": {"dt": infos["dt"][-1], "msdt": infos["msdt"][-1]},
-        "roofline": {
-            "kernel": "k_ttm (first-level contraction, FP32 MFMA)",
-            "bound": "mfma",
-            "achieved": round(achieved, 3),
-            "peak": peak,
-            "unit": "TFLOP/s",
-            "frac": round(achieved / peak, 4),
-            "traffic": traffic,
-            "avg_launch_ms": round(ttm_avg_ms, 5),
-            "launches": ttm_n,
-            "flops_per_launch": ttm_flops,
-        },
-        "cpu_baseline": None,
-    }
-    for p in (plans["dt"], plans["msdt"]):
-        p.close()
-    del T
-    torch.cuda.empty_cache()
-    if not args.no_cpu_baseline:
-        log("[bench] cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget, F_dt)
-    print(json.dumps(out), flush=True)
+    tree_bench(args)
 
 
 if __name__ == "__main__":

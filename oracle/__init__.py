@@ -35,7 +35,7 @@ from .core import (  # noqa: F401
     residual_explicit,
 )
 from .als import als_sweep, als_run, AlsState  # noqa: F401
-from .trees import DTCache, dt_path, msdt_path, pp_tree_levels, dt_flops_closed, msdt_flops_closed  # noqa: F401
+from .trees import DTCache, als_sweep_tree, dt_path, msdt_path, pp_tree_levels, dt_flops_closed, msdt_flops_closed  # noqa: F401
 from .pp import (  # noqa: F401
     pp_operators,
     pp_mode_mttkrp,

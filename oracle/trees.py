@@ -26,6 +26,8 @@ from math import comb
 
 import numpy as np
 
+from .core import gamma, gram, residual_fast, spd_solve
+
 
 def _split(lo, hi):
     """Balanced binary split of positions [lo, hi]: the left part takes the
@@ -188,3 +190,24 @@ def pp_tree_levels(N, order=None):
         assert len(nodes) == comb(l + 2, 2)
         levels.append(nodes)
     return levels
+
+
+def als_sweep_tree(st, cache, paths):
+    """One sweep of Alg. 1, as `oracle.als.als_sweep`, with each MTTKRP walked
+    down a tree by `cache` (a DTCache built on st.T sharing the list st.A):
+    paths[n] is the contraction sequence of the n-th update, e.g.
+    dt_path(N, n) for the standard tree (Sec. II-C) or msdt_path(N, u) with
+    the global update count u for MSDT (Sec. III).  Returns the new residual
+    of Eq. (3)."""
+    N = st.T.ndim
+    G = M = None
+    for n in range(N):
+        G = gamma(st.S, n)
+        M = cache.mttkrp(paths[n])
+        st.A[n], pinv = spd_solve(G, M)
+        st.used_pinv |= pinv
+        cache.bump(n)
+        st.S[n] = gram(st.A[n])
+    st.r_old = st.r
+    st.r = residual_fast(st.normT2, G, st.S[N - 1], M, st.A[N - 1])
+    return st.r

@@ -165,3 +165,32 @@ def test_pp_tree_family(N):
     if N == 4:
         # Fig. 1b: M_p^(1,2,3), M_p^(1,3,4), M_p^(2,3,4)
         assert set(levels[0]) == {frozenset({0, 1, 2}), frozenset({0, 2, 3}), frozenset({1, 2, 3})}
+
+
+@pytest.mark.parametrize("N", [3, 4])
+def test_tree_sweeps_follow_the_naive_sweep(N):
+    """The oracle's DT and MSDT sweeps (MTTKRPs walked down the trees, used
+    for the host timings) follow the naive-MTTKRP sweep's trajectory: the same
+    residual after every sweep and the same factors, over two whole MSDT
+    trees (Sec. III: no accuracy loss)."""
+    from oracle import als
+
+    dims = {3: (7, 6, 5), 4: (6, 5, 4, 7)}[N]
+    T, A0, _ = _small_planted(dims, 3, 50 + N)
+    sweeps = 2 * (N - 1)
+    ref = als.AlsState.start(T, A0)
+    st_dt = als.AlsState.start(T, A0)
+    st_ms = als.AlsState.start(T, A0)
+    c_dt = trees.DTCache(T, st_dt.A)
+    c_ms = trees.DTCache(T, st_ms.A)
+    u = 0
+    for _ in range(sweeps):
+        r = als.als_sweep(ref)
+        r_dt = trees.als_sweep_tree(st_dt, c_dt, [trees.dt_path(N, n) for n in range(N)])
+        r_ms = trees.als_sweep_tree(st_ms, c_ms, [trees.msdt_path(N, u + n) for n in range(N)])
+        u += N
+        assert abs(r_dt - r) <= 1e-12 and abs(r_ms - r) <= 1e-12
+        for n in range(N):
+            np.testing.assert_allclose(st_dt.A[n], ref.A[n], rtol=1e-10, atol=1e-12)
+            np.testing.assert_allclose(st_ms.A[n], ref.A[n], rtol=1e-10, atol=1e-12)
+    assert c_dt.ttm_count == 2 * sweeps and c_ms.ttm_count == N * sweeps // (N - 1)

@@ -18,8 +18,9 @@
 // (four 16-row MFMA blocks u) by 16 * NCB factor columns.  The factor is kept
 // transposed (Bt[c][k], k contiguous) and staged through LDS in chunks of 64
 // indices, double-buffered (the next chunk is loaded while the current one is
-// used; one barrier per chunk); the tensor goes from HBM straight to
-// registers, one contraction step (32 indices) ahead of the matrix cores.
+// used; one barrier per chunk).  The tensor goes from HBM straight to
+// registers, one contraction step (32 indices) ahead of the matrix cores,
+// except in the FP8 q-contiguous layout with Q a multiple of 16 (below).
 //   KC (contraction index contiguous, Q == 1): X is P x K row-major; lane
 //      (i = lane % 16, g = lane / 16) of block u loads row 16 u + i, indices
 //      8 g .. 8 g + 7 of the step, as one 16-byte load.
@@ -38,8 +39,14 @@
 // 16 g + 8 s .. 16 g + 8 s + 7 (the factor is read at the same offsets).
 //   KC: one 16-byte load per row; with DEEP, three register sets (the next
 //      two chunks in flight).
-//   otherwise: one 4-byte load (four consecutive q) per index; an in-register
-//      4 x 4 byte transpose puts each q's four consecutive indices in one word.
+//   otherwise, TR (Q a multiple of 16, 16-byte aligned): the workgroup's chunk
+//      of the tensor (64 indices x 512 q) goes HBM -> registers -> LDS with
+//      16-byte loads, double-buffered in static LDS, and each lane reads its
+//      operands back with the transposing 8-bit LDS read (ds_read_tr8_b64),
+//      which hands it eight consecutive indices of one q.
+//   otherwise (other Q): one 4-byte load (four consecutive q) per index; an
+//      in-register 4 x 4 byte transpose puts each q's four consecutive indices
+//      in one word.
 #include <type_traits>
 
 #include "kernels.h"
@@ -656,8 +663,9 @@ hipError_t launch_ncb(const void* X, const uint16_t* Bhi, const uint16_t* Blo, f
   // FP8 rows with the split factor: 128 columns in one pass need more than 256
   // registers (spills); two 64-column passes read the tensor twice instead
   if (R <= 64 || (F8 && KC && SPLIT)) CPALS_BF16_NCB(4);
-  CPALS_BF16_NCB(8);
+  if constexpr (!(F8 && KC && SPLIT)) CPALS_BF16_NCB(8);  // not instantiated where never taken
 #undef CPALS_BF16_NCB
+  return hipErrorInvalidValue;
 }
 
 template <bool F8>

@@ -69,14 +69,17 @@ typedef enum { CP_F64 = 0, CP_F32 = 1, CP_BF16 = 2, CP_BF16X2 = 3, CP_FP8 = 4, C
 
 typedef enum {
   CP_TREE_DT = 0,           /* standard binary dimension tree, two first-level TTMs per sweep (Sec. II-C) */
-  CP_TREE_DT_COMBINED = 1,  /* as CP_TREE_DT, with the upper two levels of the half that keeps the
-                               leading modes combined (the memory / computation trade-off of Sec. IV):
-                               for order >= 4 its first node is the tensor, viewed as
+  CP_TREE_DT_COMBINED = 1,  /* as CP_TREE_DT, with the upper two levels of each half combined (the
+                               memory / computation trade-off of Sec. IV), order >= 4: the half that
+                               keeps the leading modes starts from the tensor, viewed as
                                (s_0 ... s_{N-3}) x (s_{N-2} s_{N-1}), times the Khatri-Rao product of
-                               A^(N-2) and A^(N-1), so the order-(N-1) intermediate of the last mode
-                               is never formed (the same flops; less memory and traffic, a gain when
-                               s_{N-1} is small next to R).  Order 3: identical to CP_TREE_DT.  The
-                               PP initialization keeps its own tree (Fig. 1b). */
+                               A^(N-2) and A^(N-1); in FP32 plans the half that keeps the trailing modes
+                               starts from the Khatri-Rao product of A^(0) and A^(1) times the tensor
+                               viewed as (s_0 s_1) x (s_2 ... s_{N-1}).  The order-(N-1)
+                               intermediates are never formed (the same flops, far less memory and
+                               traffic); long contractions are split over workgroup layers and summed
+                               in a fixed order.  Order 3: identical to CP_TREE_DT.  The PP
+                               initialization keeps its own tree (Fig. 1b). */
   CP_TREE_MSDT = 2          /* multi-sweep dimension tree, N first-level TTMs per N-1 sweeps (Sec. III) */
 } cp_tree;
 

@@ -102,6 +102,9 @@ struct cp_plan_s {
   float* sw_in = nullptr;   // workspace: normalized features
   float* sw_out = nullptr;  // workspace: probability
   void* krp = nullptr;        // CP_TREE_DT_COMBINED (order >= 4): Khatri-Rao product of the last two factors
+  void* parts = nullptr;      // split-K partial products of the combined contractions
+  int split_z = 1;            // layers of the leading half's combined contraction
+  int split_zr = 1;           // layers of the trailing half's
   uint16_t* Bt_hi = nullptr;  // BF16 plans: transposed BF16 factor of the first contraction
   uint16_t* Bt_lo = nullptr;  // BF16X2 plans: its remainder part
   int pinv_seen = 0;         // stats->pinv_count at the last report
@@ -220,6 +223,16 @@ int64_t combined_k(cp_plan p) {
   return p->dims[p->N - 2] * p->dims[p->N - 1];
 }
 
+// The same for the half that keeps the trailing modes: it starts by
+// contracting modes 0 then 1, so its first node is the tensor, viewed as
+// (s_0 s_1) x (s_2 ... s_{N-1}), contracted over its leading index with the
+// Khatri-Rao product of A^(0) and A^(1).  FP32 plans (the long-K kernel of
+// that layout is FP32).
+int64_t combined_k_right(cp_plan p) {
+  if (p->tree != CP_TREE_DT_COMBINED || p->N < 4 || p->prec != CP_F32) return 0;
+  return p->dims[0] * p->dims[1];
+}
+
 void plan_layout(cp_plan p) {
   const int N = p->N, R = p->R;
   p->regions.clear();
@@ -255,8 +268,19 @@ void plan_layout(cp_plan p) {
   take(16 * sizeof(float));                      // sw_in
   take(16 * sizeof(float));                      // sw_out
   const bool bf = lowp(p->prec);
-  const int64_t kc = combined_k(p);  // contraction length of the combined first level (0: none)
-  take((size_t)kc * R * p->esz);     // krp
+  const int64_t kc = combined_k(p);         // contraction length of the combined first levels (0: none)
+  const int64_t kcr = combined_k_right(p);
+  take((size_t)std::max(kc, kcr) * R * p->esz);  // krp (one half at a time)
+  {
+    int64_t P = 1, Q = 1;
+    for (int m = 0; m < N - 2; ++m) P *= p->dims[m];
+    for (int m = 2; m < N; ++m) Q *= p->dims[m];
+    p->split_z = (kc > 0 && !lowp(p->prec)) ? ttm_split_layers(P, kc, 1, R, (int)p->esz) : 1;
+    p->split_zr = kcr > 0 ? ttm_split_layers(1, kcr, Q, R, (int)p->esz) : 1;
+    const size_t pl = p->split_z > 1 ? (size_t)p->split_z * P : 0;
+    const size_t pr = p->split_zr > 1 ? (size_t)p->split_zr * Q : 0;
+    take(std::max(pl, pr) * R * p->esz);  // parts
+  }
   const int64_t kb = std::max(smax, kc);
   take(bf ? (size_t)R * bf16_factor_pitch(kb) * 2 : 0);                                 // Bt_hi
   take(split_factor(p->prec) ? (size_t)R * bf16_factor_pitch(kb) * 2 : 0);              // Bt_lo
@@ -297,6 +321,7 @@ void plan_carve(cp_plan p) {
   p->sw_in = (float*)next();
   p->sw_out = (float*)next();
   p->krp = next();
+  p->parts = next();
   p->Bt_hi = (uint16_t*)next();
   void* lo = next();
   p->Bt_lo = split_factor(p->prec) ? (uint16_t*)lo : nullptr;
@@ -387,31 +412,48 @@ cp_status contract_any(cp_plan p, const void* in, uint32_t in_set, int c, void* 
   return contract<float>(p, in, in_set, c, out, out_f64);
 }
 
-// The combined first level: node (modes 0 .. N-3, R) = T viewed as
-// (s_0 ... s_{N-3}) x (s_{N-2} s_{N-1}) times the Khatri-Rao product of the
-// shadows of A^(N-2) and A^(N-1).
+// The combined first level of one half.  side 1 (leading half): node
+// (modes 0 .. N-3, R) = T viewed as (s_0 ... s_{N-3}) x (s_{N-2} s_{N-1})
+// times the Khatri-Rao product of the shadows of A^(N-2) and A^(N-1).
+// side 2 (trailing half): node (modes 2 .. N-1, R) = the Khatri-Rao product
+// of A^(0) and A^(1), transposed, times T viewed as (s_0 s_1) x (s_2 ...).
 template <typename TT>
-cp_status contract_combined(cp_plan p, void* out) {
+cp_status contract_combined(cp_plan p, int side, void* out) {
   const int N = p->N;
+  ++p->ttm_count;
+  ProfScope ps(p, CP_PHASE_TTM);
+  if (side == 2) {
+    int64_t Q = 1;
+    for (int m = 2; m < N; ++m) Q *= p->dims[m];
+    const int64_t K = combined_k_right(p);
+    HIP_TRY(p, launch_krp2<TT>((const TT*)p->Ash[0], p->dims[0], (const TT*)p->Ash[1], p->dims[1], p->R,
+                               (TT*)p->krp, p->st));
+    HIP_TRY(p, launch_ttm_split<TT>((const TT*)p->T, (const TT*)p->krp, (TT*)out, 1, K, Q, p->R, (TT*)p->parts,
+                                    p->split_zr, p->st));
+    return CP_OK;
+  }
   int64_t P = 1;
   for (int m = 0; m < N - 2; ++m) P *= p->dims[m];
   const int64_t K = combined_k(p);
-  ++p->ttm_count;
-  ProfScope ps(p, CP_PHASE_TTM);
   HIP_TRY(p, launch_krp2<TT>((const TT*)p->Ash[N - 2], p->dims[N - 2], (const TT*)p->Ash[N - 1], p->dims[N - 1],
                              p->R, (TT*)p->krp, p->st));
   if (lowp(p->prec)) {
     HIP_TRY(p, lowp_first_level(p, p->T, (const float*)p->krp, (float*)out, P, K, 1));
   } else {
-    HIP_TRY(p, launch_ttm<TT>((const TT*)p->T, (const TT*)p->krp, (TT*)out, P, K, 1, p->R, p->st));
+    HIP_TRY(p, launch_ttm_split<TT>((const TT*)p->T, (const TT*)p->krp, (TT*)out, P, K, 1, p->R, (TT*)p->parts,
+                                    p->split_z, p->st));
   }
   return CP_OK;
 }
 
-// Whether a path from the tensor takes the combined first level: it starts
-// with the contractions of modes N-1 and N-2 and goes on below that node.
-bool path_combines(cp_plan p, const std::vector<int>& seq) {
-  return combined_k(p) > 0 && seq.size() >= 3 && seq[0] == p->N - 1 && seq[1] == p->N - 2;
+// Whether a path from the tensor takes a combined first level: 1 when it
+// starts with the contractions of modes N-1 and N-2, 2 when with modes 0 and
+// 1, and goes on below that node; 0 otherwise.
+int path_combines(cp_plan p, const std::vector<int>& seq) {
+  if (seq.size() < 3) return 0;
+  if (combined_k(p) > 0 && seq[0] == p->N - 1 && seq[1] == p->N - 2) return 1;
+  if (combined_k_right(p) > 0 && seq[0] == 0 && seq[1] == 1) return 2;
+  return 0;
 }
 
 // Walk a root-to-leaf contraction sequence; M (FP64, s_leaf x R) receives the leaf.
@@ -439,10 +481,12 @@ cp_status run_path(cp_plan p, const std::vector<int>& seq, double* M) {
   std::vector<uint32_t> sets;
   const int start = path_start(p, seq, &sets);
   int d = start + 1;
-  if (d == 1 && path_combines(p, seq)) {
+  const int side = (d == 1) ? path_combines(p, seq) : 0;
+  if (side) {
     if ((size_t)node_numel(p, sets[2]) * p->esz > p->slot_cap[2])
       return fail(p, CP_ERR_STATE, "internal: slot 2 too small");
-    CP_TRY(p->prec == CP_F64 ? contract_combined<double>(p, p->slot_buf[2]) : contract_combined<float>(p, p->slot_buf[2]));
+    CP_TRY(p->prec == CP_F64 ? contract_combined<double>(p, side, p->slot_buf[2])
+                             : contract_combined<float>(p, side, p->slot_buf[2]));
     slot_record(p, 2, sets[2]);
     d = 3;
   }
@@ -558,11 +602,12 @@ cp_status form_gamma(cp_plan p, int n, bool pp) {
 
 // Whether the update of mode n also inverts the next mode's Gamma (inside
 // its last workgroup) instead of leaving it to the second stream: worth it
-// when the next MTTKRP is short, so that nothing would hide the inverse:
-// in PP sweeps (the first-order correction) and in exact sweeps when the
-// next path starts from a cached node.  Called after ver[n] moved on.
+// in exact sweeps when the next MTTKRP is short (the next path starts from a
+// cached node), so that nothing would hide the inverse.  In PP sweeps the
+// first-order correction kernel of the next mode inverts it in a workgroup
+// of its own.  Called after ver[n] moved on.
 bool inline_next_inverse(cp_plan p, int n, bool pp) {
-  if (pp) return true;
+  if (pp) return false;  // the next PP correction kernel inverts it alongside
   if (n == p->N - 1) return false;
   const std::vector<int> seq =
       (p->tree == CP_TREE_MSDT) ? msdt_path(p->N, p->msdt_u) : dt_path(p->N, n + 1);
@@ -817,7 +862,7 @@ cp_status pp_init(cp_plan p, double* const* A) {
 }
 
 template <typename TT>
-cp_status pp_first_order(cp_plan p, int n) {
+cp_status pp_first_order(cp_plan p, int n, bool inv) {
   PPArgs<TT> a{};
   for (int i = 0; i < p->N; ++i) {
     a.dims[i] = p->dims[i];
@@ -832,6 +877,9 @@ cp_status pp_first_order(cp_plan p, int n) {
   a.N = p->N;
   a.n = n;
   a.R = p->R;
+  a.Gamma = p->Gamma;
+  a.Ginv = inv ? p->Ginv : nullptr;
+  a.stats = p->stats;
   ProfScope ps(p, CP_PHASE_PP);
   HIP_TRY(p, launch_pp_mttkrp<TT>(a, p->st));
   return CP_OK;
@@ -839,11 +887,14 @@ cp_status pp_first_order(cp_plan p, int n) {
 
 cp_status approx_sweep(cp_plan p, double* const* A) {
   for (int n = 0; n < p->N; ++n) {
-    CP_TRY(launch_prep_forked(p, n, true));
+    // Gamma^(n)^-1 in a workgroup of the correction kernel, unless the
+    // previous update left it
+    const bool inv = p->ginv_ready != n;
+    p->ginv_ready = -1;
     if (p->prec == CP_F64) {
-      CP_TRY(pp_first_order<double>(p, n));
+      CP_TRY(pp_first_order<double>(p, n, inv));
     } else {
-      CP_TRY(pp_first_order<float>(p, n));
+      CP_TRY(pp_first_order<float>(p, n, inv));
     }
     CP_TRY(finish_update(p, n, A[n], true));
   }

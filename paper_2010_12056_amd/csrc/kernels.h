@@ -61,6 +61,20 @@ hipError_t launch_mttv(const TI* X, const TI* A, TO* Y, int64_t P, int64_t I, in
 // dst[i] = (T) src[i] for n elements.
 template <typename T>
 hipError_t launch_convert(const double* src, T* dst, int64_t n, hipStream_t st);
+
+// Layers of a split-K form of a long-K first-level contraction (X is P x K x
+// Q; Q = 1 on any type, Q >= 64 in FP32): 1 when a single pass fills the
+// chip; at most kMaxSplitLayers.
+constexpr int kMaxSplitLayers = 16;
+int ttm_split_layers(int64_t P, int64_t K, int64_t Q, int R, int esz);
+
+// The first-level contraction C[p][q][r] = sum_k X[p][k][q] B[k][r] with K
+// split over Z workgroup layers: partials in `parts` (Z P Q R elements),
+// added in layer order into C (deterministic).  Z <= 1: launch_ttm.
+template <typename T>
+hipError_t launch_ttm_split(const T* X, const T* B, T* C, int64_t P, int64_t K, int64_t Q, int R, T* parts, int Z,
+                            hipStream_t st);
+
 // B (sa sb x R) = Khatri-Rao product of Aa (sa x R) and Ab (sb x R), row i sb + j.
 template <typename T>
 hipError_t launch_krp2(const T* Aa, int64_t sa, const T* Ab, int64_t sb, int R, T* B, hipStream_t st);
@@ -171,6 +185,9 @@ struct PPArgs {
   const double* Mp;
   double* M;
   int N, n, R;
+  const double* Gamma;  // with Ginv: Gamma^(n), inverted into Ginv by an extra workgroup
+  double* Ginv;         // null: no inverse
+  DevStats* stats;
 };
 template <typename T>
 hipError_t launch_pp_mttkrp(const PPArgs<T>& a, hipStream_t st);

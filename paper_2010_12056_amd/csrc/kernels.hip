@@ -14,6 +14,7 @@
 // runs give bitwise-identical results.
 #include <math.h>
 
+#include <algorithm>
 #include <atomic>
 
 #include "kernels.h"
@@ -532,10 +533,14 @@ __global__ __launch_bounds__(512) void k_ttm_kc32(const float* __restrict__ X, c
 // through the same (tile, chunk) sequence, a wave past the last tile
 // recomputing the last one without storing it.  The rows of the next chunk
 // (or of the next tile's first) are in flight while a chunk is multiplied.
+//
+// Split K (gridDim.z > 1): workgroup z takes chunks [z cps, (z + 1) cps) of
+// every tile and writes its partial product to C + z P R; k_sum_parts adds
+// the partials in z order.
 template <typename T, int NCB>
 __global__ __launch_bounds__(512) void k_ttm_kcx(const T* __restrict__ X, const T* __restrict__ B,
                                                  T* __restrict__ C, int64_t P, int64_t K, int R,
-                                                 int64_t ntiles, int vec) {
+                                                 int64_t ntiles, int vec, int cps) {
   constexpr int V = 16 / sizeof(T);
   constexpr int KT = 4 * V;
   constexpr int NTS = 8;
@@ -548,7 +553,11 @@ __global__ __launch_bounds__(512) void k_ttm_kcx(const T* __restrict__ X, const 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, l16 = lane & 15;
   const int c0 = blockIdx.y * NC;
-  const int nch = (int)((K + KP - 1) / KP);
+  const int nall = (int)((K + KP - 1) / KP);
+  const int cbeg = (int)blockIdx.z * cps;
+  const int cend = cbeg + cps < nall ? cbeg + cps : nall;
+  const int nch = cend - cbeg;
+  C += (int64_t)blockIdx.z * P * R;
   auto load_b = [&](int c, T (&bv)[BPER]) {
 #pragma unroll
     for (int q = 0; q < BPER; ++q) {
@@ -586,14 +595,14 @@ __global__ __launch_bounds__(512) void k_ttm_kcx(const T* __restrict__ X, const 
   };
   const int64_t stride = (int64_t)gridDim.x * kTtmWaves;
   int64_t tb = (int64_t)blockIdx.x * kTtmWaves;
-  if (tb >= ntiles) return;  // uniform: the whole workgroup
+  if (tb >= ntiles || nch < 1) return;  // uniform: the whole workgroup
   {
     T bv[BPER];
-    load_b(0, bv);
+    load_b(cbeg, bv);
     store_b(0, bv);
   }
   VT an[NTS];
-  load_rows(tb + wave < ntiles ? tb + wave : ntiles - 1, 0, an);
+  load_rows(tb + wave < ntiles ? tb + wave : ntiles - 1, cbeg, an);
   __syncthreads();
   int buf = 0;
   for (; tb < ntiles; tb += stride) {
@@ -604,13 +613,13 @@ __global__ __launch_bounds__(512) void k_ttm_kcx(const T* __restrict__ X, const 
     typename Mma<T>::acc_t acc[NCB];
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) acc[cb] = Mma<T>::zero();
-    for (int c = 0; c < nch; ++c) {
+    for (int c = cbeg; c < cend; ++c) {
       VT a[NTS];
 #pragma unroll
       for (int s2 = 0; s2 < NTS; ++s2) a[s2] = an[s2];
       // the factor's next chunk first, then the next rows
-      const bool more = c + 1 < nch;
-      const int cn = more ? c + 1 : 0;
+      const bool more = c + 1 < cend;
+      const int cn = more ? c + 1 : cbeg;
       T bv[BPER];
       load_b(cn, bv);
       load_rows(more ? tile : tnext, cn, an);
@@ -643,6 +652,25 @@ __global__ __launch_bounds__(512) void k_ttm_kcx(const T* __restrict__ X, const 
           if (tile * 16 + r < P && col < R) ct[r * R + col] = acc[cb][v];
         }
     }
+  }
+}
+
+// C[i] = sum over z of parts[z][i] in z order (the split-K partials of
+// k_ttm_kcx), 16-byte pieces; n is a multiple of the piece.
+template <typename T>
+__global__ __launch_bounds__(256) void k_sum_parts(const T* __restrict__ parts, T* __restrict__ C, int64_t n,
+                                                   int Z) {
+  typedef typename Vec16<T>::type VT;
+  constexpr int V = 16 / sizeof(T);
+  const int64_t nv = n / V;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nv; i += (int64_t)gridDim.x * 256) {
+    VT acc = ((const VT*)parts)[i];
+    for (int z = 1; z < Z; ++z) {
+      const VT v = ((const VT*)(parts + (int64_t)z * n))[i];
+#pragma unroll
+      for (int u = 0; u < V; ++u) acc[u] += v[u];
+    }
+    ((VT*)C)[i] = acc;
   }
 }
 
@@ -894,7 +922,7 @@ __global__ __launch_bounds__(512) void k_ttm_q(const float* __restrict__ X, cons
 template <int NCB>
 __global__ __launch_bounds__(512) void k_ttm_qx(const float* __restrict__ X, const float* __restrict__ B,
                                                 float* __restrict__ C, int64_t P, int64_t K, int64_t Q,
-                                                int R, int64_t tilesQ, int64_t ntiles, int vec) {
+                                                int R, int64_t tilesQ, int64_t ntiles, int vec, int cps) {
   constexpr int KCH = 128;
   constexpr int pitch = KCH + 4;
   constexpr int NC = NCB * 16;
@@ -904,7 +932,12 @@ __global__ __launch_bounds__(512) void k_ttm_qx(const float* __restrict__ X, con
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane >> 4, l16 = lane & 15;
   const int c0 = blockIdx.y * NC;
-  const int nch = (int)((K + KCH - 1) / KCH);
+  // split K (gridDim.z > 1): this layer takes chunks [cbeg, cend) and writes
+  // its partial product to C + z P Q R
+  const int nall = (int)((K + KCH - 1) / KCH);
+  const int cbeg = (int)blockIdx.z * cps;
+  const int cend = cbeg + cps < nall ? cbeg + cps : nall;
+  C += (int64_t)blockIdx.z * P * Q * R;
   // quarter j of factor chunk c: the thread's elements q = j BQ .. j BQ + BQ - 1
   auto load_b = [&](int c, int j, float (&bv)[BQ]) {
 #pragma unroll
@@ -943,15 +976,16 @@ __global__ __launch_bounds__(512) void k_ttm_qx(const float* __restrict__ X, con
   };
   const int64_t stride = (int64_t)gridDim.x * kTtmWaves;
   int64_t tb = (int64_t)blockIdx.x * kTtmWaves;
-  if (tb >= ntiles) return;  // uniform: the whole workgroup
+  if (tb >= ntiles || cbeg >= cend) return;  // uniform: the whole workgroup
   for (int j = 0; j < 4; ++j) {
     float bv[BQ];
-    load_b(0, j, bv);
+    load_b(cbeg, j, bv);
     store_b(0, j, bv);
   }
-  const int npc = (int)((K + 31) / 32);  // 32-index pieces
+  const int pall = (int)((K + 31) / 32);                  // 32-index pieces of K
+  const int npc = cend * 4 < pall ? cend * 4 : pall;      // end of this layer's pieces
   f32x4 an[8];
-  load_piece(tb + wave < ntiles ? tb + wave : ntiles - 1, 0, an);
+  load_piece(tb + wave < ntiles ? tb + wave : ntiles - 1, (int64_t)cbeg * KCH, an);
   __syncthreads();
   int buf = 0;
   for (; tb < ntiles; tb += stride) {
@@ -964,8 +998,8 @@ __global__ __launch_bounds__(512) void k_ttm_qx(const float* __restrict__ X, con
     for (int u = 0; u < 4; ++u)
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb) acc[u][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int c = 0; c < nch; ++c) {
-      const int cn = c + 1 < nch ? c + 1 : 0;
+    for (int c = cbeg; c < cend; ++c) {
+      const int cn = c + 1 < cend ? c + 1 : cbeg;
       const int pend = (c + 1) * 4 < npc ? (c + 1) * 4 : npc;  // pieces of this chunk
       // piece j of the chunk loads quarter j of the next chunk's factor and
       // writes it into the other buffer after its products (that buffer was
@@ -978,7 +1012,7 @@ __global__ __launch_bounds__(512) void k_ttm_qx(const float* __restrict__ X, con
         float bv[BQ];
         load_b(cn, pc - c * 4, bv);
         const bool more = pc + 1 < npc;
-        load_piece(more ? tile : tnext, more ? (int64_t)(pc + 1) * 32 : 0, an);
+        load_piece(more ? tile : tnext, more ? (int64_t)(pc + 1) * 32 : (int64_t)cbeg * KCH, an);
         __builtin_amdgcn_sched_barrier(0);
         const int kl = (pc - c * 4) * 32;
 #pragma unroll
@@ -1349,41 +1383,6 @@ __device__ inline double block_max(double v, double* red) {
   return out;
 }
 
-// Ginv = Gamma^-1 (gj_inverse_lds) in one workgroup.  A pivot at or below
-// R eps max(diag) hands over to k_pinv (stats->pinv_pending).
-template <int RP>
-__global__ __launch_bounds__(256) void k_inv_blk(const double* __restrict__ Gm, double* __restrict__ Gi, int R,
-                                                 DevStats* stats) {
-  constexpr int P = RP + 1;
-  __shared__ double A[RP * P];
-  __shared__ double red[256];
-  __shared__ int fail;
-  const int tid = threadIdx.x;
-  // every load in flight before the first store (the matrix was just written
-  // by another kernel: each load is a trip to the shared cache)
-  constexpr int PER = RP * RP / 256;
-  double vals[PER];
-#pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    const int e = tid + 256 * q, i = e / RP, j = e - i * RP;
-    vals[q] = (i < R && j < R) ? Gm[i * R + j] : (i == j ? 1.0 : 0.0);
-  }
-  double dm = 0.0;
-#pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    const int e = tid + 256 * q, i = e / RP, j = e - i * RP;
-    A[i * P + j] = vals[q];
-    if (i == j && i < R) dm = fmax(dm, vals[q]);
-  }
-  const double tol = block_max(dm, red) * (double)R * 2.220446049250313e-16;
-  const bool ok = gj_inverse_lds<RP>(A, tol, red, &fail);
-  for (int e = tid; e < R * R; e += 256) {
-    const int i = e / R, j = e - i * R;
-    Gi[e] = ok ? A[i * P + j] : 0.0;
-  }
-  if (!ok && tid == 0) stats->pinv_pending = 1;
-}
-
 // LDS doubles used by pinv_lds for rank R.
 __host__ __device__ inline size_t pinv_lds_doubles(int R) { return (size_t)R * (R + 1) + R + 128 + 64 + 2; }
 
@@ -1520,13 +1519,62 @@ __device__ void pinv_lds(const double* __restrict__ Gm, double* __restrict__ Gi,
   }
 }
 
-// Gamma^dagger when k_inv_blk gave up (stats->pinv_pending; otherwise the
-// kernel returns at once).
-__global__ __launch_bounds__(512) void k_pinv(const double* __restrict__ Gm, double* __restrict__ Gi, int R,
-                                              DevStats* stats) {
-  if (stats->pinv_pending == 0) return;  // uniform
+// LDS doubles of gamma_inverse_wg for padded rank RP and rank R.
+__host__ __device__ inline size_t gamma_inverse_lds_doubles(int RP, int R) {
+  const size_t gj = (size_t)RP * (RP + 1) + 256 + 1;
+  const size_t pv = pinv_lds_doubles(R);
+  return gj > pv ? gj : pv;
+}
+
+// Gi = Gm^dagger by one workgroup of 256 threads: the blocked Gauss-Jordan
+// inverse (gj_inverse_lds), and when a pivot falls to R eps max(diag) or
+// below, the Jacobi pseudo-inverse (pinv_lds) in the same workgroup.
+template <int RP>
+__device__ __forceinline__ void gamma_inverse_wg(const double* __restrict__ Gm, double* __restrict__ Gi, int R, DevStats* stats,
+                                 double* lds) {
+  constexpr int P = RP + 1;
+  double* A = lds;
+  double* red = A + RP * P;
+  int* fail = (int*)(red + 256);
+  const int tid = threadIdx.x;
+  // the matrix was just written by another kernel or workgroup: every load
+  // of a batch in flight before the first store (batches of at most 16)
+  constexpr int PER = RP * RP / 256;
+  constexpr int BAT = PER < 16 ? PER : 16;
+  double dm = 0.0;
+#pragma unroll
+  for (int q0 = 0; q0 < PER; q0 += BAT) {
+    double vals[BAT];
+#pragma unroll
+    for (int q = 0; q < BAT; ++q) {
+      const int e = tid + 256 * (q0 + q), i = e / RP, j = e - i * RP;
+      vals[q] = (i < R && j < R) ? Gm[i * R + j] : (i == j ? 1.0 : 0.0);
+    }
+#pragma unroll
+    for (int q = 0; q < BAT; ++q) {
+      const int e = tid + 256 * (q0 + q), i = e / RP, j = e - i * RP;
+      A[i * P + j] = vals[q];
+      if (i == j && i < R) dm = fmax(dm, vals[q]);
+    }
+  }
+  const double tol = block_max(dm, red) * (double)R * 2.220446049250313e-16;
+  if (gj_inverse_lds<RP>(A, tol, fail)) {
+    for (int e = tid; e < R * R; e += 256) {
+      const int i = e / R, j = e - i * R;
+      Gi[e] = A[i * P + j];
+    }
+  } else {
+    __syncthreads();
+    pinv_lds<256>(Gm, Gi, R, stats, lds);
+  }
+}
+
+// Ginv = Gamma^dagger in one workgroup (gamma_inverse_wg).
+template <int RP>
+__global__ __launch_bounds__(256) void k_inv_blk(const double* __restrict__ Gm, double* __restrict__ Gi, int R,
+                                                 DevStats* stats) {
   extern __shared__ double lds_d[];
-  pinv_lds<512>(Gm, Gi, R, stats, lds_d);
+  gamma_inverse_wg<RP>(Gm, Gi, R, stats, lds_d);
 }
 
 // LDS doubles of k_update's solve phase for padded rank RP: the R x R
@@ -1562,7 +1610,6 @@ __global__ __launch_bounds__(256) void k_update(UpdateArgs<T> a) {
   constexpr bool kGramInRegs = !(RP == 128 && PP);
   extern __shared__ double lds[];
   __shared__ double sh[256];
-  __shared__ double xb[144];
   __shared__ int flag;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int l16 = lane & 15, lg = lane >> 4;
@@ -1750,127 +1797,137 @@ __global__ __launch_bounds__(256) void k_update(UpdateArgs<T> a) {
     }
   }
   if (!a.fused) return;  // k_update_reduce sums the partials
-  // ticket: the last workgroup to arrive does the reductions
+  // The reductions, spread over the G workgroups.  Each waits until every
+  // workgroup has written its partials (arrival count G; all G <= 16
+  // workgroups are resident at once, and the wait is bounded), then takes
+  // a contiguous slice of the R x R entries: S^(n) (and dS^(n)) = the
+  // partials summed in workgroup order, its share of <Gamma^(n), S^(n)>,
+  // and the entries of Gamma^(nx) (Eq. (1)) and, in PP, W^(nx) (the bracket
+  // of Eq. (7)), with S^(n) and dS^(n) from registers.  Every workgroup read
+  // Gamma, W and Ginv before arriving, and each overwrites only its own
+  // slice of Gamma and W.  The last to finish its slice (arrival count 2G)
+  // adds the norms and shares in workgroup order, forms the residual of
+  // Eq. (3) after the last mode, and, when inv_next is set, inverts
+  // Gamma^(nx) into Ginv (gamma_inverse_wg).
+  const int n = a.n, N = a.N, nx = (n + 1) % N, G = gridDim.x;
   __threadfence();
   __syncthreads();
-  if (tid == 0) flag = (atomicAdd(a.ticket, 1u) == gridDim.x - 1) ? 1 : 0;
+  if (tid == 0) {
+    __hip_atomic_fetch_add(a.ticket, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    int spins = 0;
+    while (__hip_atomic_load(a.ticket, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < (unsigned)G) {
+      __builtin_amdgcn_s_sleep(2);
+      if (++spins == (1 << 22)) {  // never expected: the results are then flagged, not waited for
+        atomicOr(&a.stats->status, 4);
+        break;
+      }
+    }
+  }
+  __syncthreads();
+  __threadfence();
+  {
+    const int per = (RR + G - 1) / G;
+    const int e0 = (int)blockIdx.x * per;
+    const int e1 = e0 + per < RR ? e0 + per : RR;
+    double* const Sn = a.S[n];
+    double* const dSn = a.dS[n];
+    const double* __restrict__ const pS = a.partS;
+    const double* __restrict__ const pdS = a.partdS;
+    const double* Sm[kMaxOrder];
+    const double* dSm[kMaxOrder];
+#pragma unroll
+    for (int m = 0; m < kMaxOrder; ++m) {
+      const bool use = m < N && m != n && m != nx;
+      Sm[m] = use ? a.S[m] : nullptr;
+      dSm[m] = (use && pp) ? a.dS[m] : nullptr;
+    }
+    constexpr int EB = 2;
+    double gsum = 0.0;
+    for (int j0 = e0 + tid; j0 < e1; j0 += 256 * EB) {
+      // every load of the batch in flight before the first use (indices
+      // clamped into the slice, out-of-range entries discarded afterwards)
+      int ei[EB];
+      bool in[EB];
+      double gm[EB], sv[EB], dv[EB], sm[kMaxOrder][EB], dm[kMaxOrder][EB];
+#pragma unroll
+      for (int u = 0; u < EB; ++u) {
+        const int e = j0 + 256 * u;
+        in[u] = e < e1;
+        ei[u] = in[u] ? e : e0;
+        gm[u] = a.Gamma[ei[u]];
+        sv[u] = 0.0;
+        dv[u] = 0.0;
+      }
+#pragma unroll
+      for (int m = 0; m < kMaxOrder; ++m)
+#pragma unroll
+        for (int u = 0; u < EB; ++u) {
+          sm[m][u] = Sm[m] ? Sm[m][ei[u]] : 1.0;
+          dm[m][u] = dSm[m] ? dSm[m][ei[u]] : 0.0;
+        }
+      for (int b0 = 0; b0 < G; b0 += 8) {
+        double pv[8][EB], pd[8][EB];
+#pragma unroll
+        for (int bb = 0; bb < 8; ++bb) {
+          const int64_t off = (int64_t)(b0 + bb < G ? b0 + bb : G - 1) * RR;
+#pragma unroll
+          for (int u = 0; u < EB; ++u) {
+            pv[bb][u] = pS[off + ei[u]];
+            if (pp) pd[bb][u] = pdS[off + ei[u]];
+          }
+        }
+#pragma unroll
+        for (int bb = 0; bb < 8; ++bb) {
+          const bool inb = b0 + bb < G;
+#pragma unroll
+          for (int u = 0; u < EB; ++u) {
+            sv[u] += inb ? pv[bb][u] : 0.0;
+            if (pp) dv[u] += inb ? pd[bb][u] : 0.0;
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < EB; ++u) {
+        if (!in[u]) continue;
+        const int e = ei[u];
+        Sn[e] = sv[u];
+        if (pp) dSn[e] = dv[u];
+        gsum += gm[u] * sv[u];
+        // products over m != nx in increasing m (the coefficient of t^2 of
+        // the product of S^(m) + t dS^(m) is the bracket of Eq. (7))
+        double v = 1.0, f0 = 1.0, f1 = 0.0, f2 = 0.0;
+#pragma unroll
+        for (int m = 0; m < kMaxOrder; ++m) {
+          const double smv = (m == n) ? sv[u] : sm[m][u];
+          const double dmv = (m == n) ? (pp ? dv[u] : 0.0) : dm[m][u];
+          v *= smv;
+          if (pp) {
+            f2 = f2 * smv + f1 * dmv;
+            f1 = f1 * smv + f0 * dmv;
+            f0 = f0 * smv;
+          }
+        }
+        a.Gamma[e] = v;
+        if (pp) a.W[e] = f2;
+      }
+    }
+    double g1[1] = {gsum};
+    block_sums<1>(g1, sh);
+    if (tid == 0) a.partSc[blockIdx.x * 4 + 3] = g1[0];
+  }
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) flag = (atomicAdd(a.ticket, 1u) == 2u * (unsigned)G - 1u) ? 1 : 0;
   __syncthreads();
   if (!flag) return;  // uniform
   __threadfence();
   if (tid == 0) atomicExch(a.ticket, 0u);
-  const int n = a.n, N = a.N, nx = (n + 1) % N, G = gridDim.x;
-  constexpr int P = RP + 1;
-  double* Aj = lds;  // RP x P: Gamma^(nx) for the inverse (solve buffers are done)
-  // (1) S^(n) (and dS^(n)) = the partials summed in workgroup order; thread
-  // t owns entries t + 256 j.  Batches of entries with every partial load in
-  // flight: the sums are a chain of round trips to the shared cache.
-  // Loads are unconditional (indices clamped into range, out-of-range values
-  // masked afterwards) so that a batch issues them all before any wait.
-  constexpr int EB = PP ? 4 : 8;
-  double* const Sn = a.S[n];
-  double* const dSn = a.dS[n];
-  const double* __restrict__ const pS = a.partS;
-  const double* __restrict__ const pdS = a.partdS;
-  double gsum = 0.0;
-  for (int j0 = 0; j0 * 256 < RR; j0 += EB) {
-    int ei[EB];
-    double sv[EB], dv[EB], gm[EB];
-#pragma unroll
-    for (int u = 0; u < EB; ++u) {
-      const int e = tid + 256 * (j0 + u);
-      ei[u] = e < RR ? e : 0;
-      sv[u] = 0.0;
-      dv[u] = 0.0;
-      gm[u] = a.Gamma[ei[u]];
-    }
-    for (int b0 = 0; b0 < G; b0 += 8) {
-      double pv[8][EB], pd[8][EB];
-#pragma unroll
-      for (int bb = 0; bb < 8; ++bb) {
-        const int64_t off = (int64_t)(b0 + bb < G ? b0 + bb : G - 1) * RR;
-#pragma unroll
-        for (int u = 0; u < EB; ++u) {
-          pv[bb][u] = pS[off + ei[u]];
-          if (pp) pd[bb][u] = pdS[off + ei[u]];
-        }
-      }
-#pragma unroll
-      for (int bb = 0; bb < 8; ++bb) {
-        const bool in = b0 + bb < G;
-#pragma unroll
-        for (int u = 0; u < EB; ++u) {
-          sv[u] += in ? pv[bb][u] : 0.0;
-          if (pp) dv[u] += in ? pd[bb][u] : 0.0;
-        }
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < EB; ++u) {
-      const int e = tid + 256 * (j0 + u);
-      if (e < RR) {
-        Sn[e] = sv[u];
-        if (pp) dSn[e] = dv[u];
-        gsum += gm[u] * sv[u];
-      }
-    }
-  }
-  // (2) entries of Gamma^(nx) (Eq. (1)) and, in PP, W^(nx) (the bracket of
-  // Eq. (7)) from the Gram matrices, S^(n) and dS^(n) as just written by
-  // this thread; W is only read by PP updates, which follow a PP
-  // initialization (W = 0) or another PP update.
-  const double* Sm[kMaxOrder];
-  const double* dSm[kMaxOrder];
-#pragma unroll
-  for (int m = 0; m < kMaxOrder; ++m) {
-    const bool use = m < N && m != nx;
-    Sm[m] = use ? a.S[m] : nullptr;
-    dSm[m] = use ? a.dS[m] : nullptr;
-  }
-  double dmax = 0.0;
-  for (int j0 = 0; j0 * 256 < RR; j0 += EB) {
-    int ei[EB];
-#pragma unroll
-    for (int u = 0; u < EB; ++u) {
-      const int e = tid + 256 * (j0 + u);
-      ei[u] = e < RR ? e : 0;
-    }
-    double sm[kMaxOrder][EB], dm[kMaxOrder][EB];
-#pragma unroll
-    for (int m = 0; m < kMaxOrder; ++m)
-#pragma unroll
-      for (int u = 0; u < EB; ++u) {
-        sm[m][u] = Sm[m] ? Sm[m][ei[u]] : 1.0;
-        dm[m][u] = (pp && dSm[m]) ? dSm[m][ei[u]] : 0.0;
-      }
-#pragma unroll
-    for (int u = 0; u < EB; ++u) {
-      const int e = tid + 256 * (j0 + u);
-      double v = 1.0, f0 = 1.0, f1 = 0.0, f2 = 0.0;
-#pragma unroll
-      for (int m = 0; m < kMaxOrder; ++m) {
-        v *= sm[m][u];
-        if (pp) {
-          f2 = f2 * sm[m][u] + f1 * dm[m][u];
-          f1 = f1 * sm[m][u] + f0 * dm[m][u];
-          f0 = f0 * sm[m][u];
-        }
-      }
-      if (e < RR) {
-        a.Gamma[e] = v;
-        if (pp) a.W[e] = f2;
-        if (a.inv_next) {
-          const int i = e / R, j = e - i * R;
-          Aj[i * P + j] = v;
-          if (i == j) dmax = fmax(dmax, v);
-        }
-      }
-    }
-  }
-  double v4[4] = {0.0, 0.0, 0.0, gsum};
+  double v4[4] = {0.0, 0.0, 0.0, 0.0};
   for (int b = tid; b < G; b += 256) {
     v4[0] += a.partSc[b * 4 + 0];
     v4[1] += a.partSc[b * 4 + 1];
     v4[2] += a.partSc[b * 4 + 2];
+    v4[3] += a.partSc[b * 4 + 3];
   }
   block_sums<4>(v4, sh);
   if (tid == 0) {
@@ -1887,26 +1944,21 @@ __global__ __launch_bounds__(256) void k_update(UpdateArgs<T> a) {
     }
   }
   if (!a.inv_next) return;  // uniform
-  for (int e = tid; e < RP * RP; e += 256) {
-    const int i = e / RP, j = e - i * RP;
-    if (i >= R || j >= R) Aj[i * P + j] = (i == j) ? 1.0 : 0.0;
-  }
-  const double tol = block_max(dmax, sh) * (double)R * 2.220446049250313e-16;
-  if (gj_inverse_lds<RP>(Aj, tol, xb, &flag)) {
-    for (int e = tid; e < RR; e += 256) {
-      const int i = e / R, j = e - i * R;
-      a.Ginv[e] = Aj[i * P + j];
-    }
-  } else {
-    // Gamma^(nx) as written above (this workgroup's own stores)
-    __threadfence_block();
-    __syncthreads();
-    pinv_lds<256>(a.Gamma, a.Ginv, R, a.stats, lds);
-  }
+  __syncthreads();
+  gamma_inverse_wg<RP>(a.Gamma, a.Ginv, R, a.stats, lds);
 }
 
-template <typename T>
+//
+// With a.Ginv set, the grid has one more workgroup, which inverts Gamma^(n)
+// (formed by the previous update) into a.Ginv meanwhile: the inverse is off
+// the update's critical path.
+template <typename T, int RP>
 __global__ __launch_bounds__(256) void k_pp_mttkrp(PPArgs<T> a) {
+  if (a.Ginv && blockIdx.x == gridDim.x - 1) {  // uniform
+    extern __shared__ double lds_inv[];
+    gamma_inverse_wg<RP>(a.Gamma, a.Ginv, a.R, a.stats, lds_inv);
+    return;
+  }
   __shared__ double red[256];
   const int tid = threadIdx.x, R = a.R;
   const int G = 256 / R;
@@ -2118,7 +2170,33 @@ hipError_t launch_ttm_kcx(const T* X, const T* B, T* C, int64_t P, int64_t K, in
   const unsigned nx = (unsigned)(want < 256 ? want : 256);
   const unsigned ny = (unsigned)((R + NCB * 16 - 1) / (NCB * 16));
   const int vec = (K % V == 0 && ((uintptr_t)X % 16) == 0) ? 1 : 0;
-  hipLaunchKernelGGL((k_ttm_kcx<T, NCB>), dim3(nx, ny), dim3(kTtmThreads), 0, st, X, B, C, P, K, R, ntiles, vec);
+  const int nch = (int)((K + 4 * V * 8 - 1) / (4 * V * 8));
+  hipLaunchKernelGGL((k_ttm_kcx<T, NCB>), dim3(nx, ny), dim3(kTtmThreads), 0, st, X, B, C, P, K, R, ntiles, vec,
+                     nch);
+  return hipGetLastError();
+}
+
+// The same contraction with K split over Z workgroup layers (partials in
+// `parts`, Z P R elements) and a fixed-order sum into C.
+template <typename T, int NCB>
+hipError_t launch_ttm_kcx_split(const T* X, const T* B, T* C, int64_t P, int64_t K, int R, T* parts, int Z,
+                                hipStream_t st) {
+  constexpr int V = 16 / sizeof(T);
+  const int64_t ntiles = (P + 15) / 16;
+  const int64_t want = (ntiles + kTtmWaves - 1) / kTtmWaves;
+  const unsigned nx = (unsigned)(want < 256 ? want : 256);
+  const unsigned ny = (unsigned)((R + NCB * 16 - 1) / (NCB * 16));
+  const int vec = (K % V == 0 && ((uintptr_t)X % 16) == 0) ? 1 : 0;
+  const int nch = (int)((K + 4 * V * 8 - 1) / (4 * V * 8));
+  const int cps = (nch + Z - 1) / Z;
+  const int z = (nch + cps - 1) / cps;  // layers that have chunks
+  hipLaunchKernelGGL((k_ttm_kcx<T, NCB>), dim3(nx, ny, (unsigned)z), dim3(kTtmThreads), 0, st, X, B, parts, P, K,
+                     R, ntiles, vec, cps);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t n = P * R;
+  const int64_t nb = (n / V + 255) / 256;
+  hipLaunchKernelGGL((k_sum_parts<T>), dim3((unsigned)(nb < 2048 ? nb : 2048)), dim3(256), 0, st, parts, C, n, z);
   return hipGetLastError();
 }
 
@@ -2144,8 +2222,33 @@ hipError_t launch_ttm_qx(const float* X, const float* B, float* C, int64_t P, in
   const unsigned nx = (unsigned)(want < 256 ? want : 256);
   const unsigned ny = (unsigned)((R + NCB * 16 - 1) / (NCB * 16));
   const int vec = (Q % 4 == 0 && ((uintptr_t)X % 16) == 0) ? 1 : 0;
+  const int nch = (int)((K + 127) / 128);
   hipLaunchKernelGGL((k_ttm_qx<NCB>), dim3(nx, ny), dim3(kTtmThreads), 0, st, X, B, C, P, K, Q, R, tilesQ, ntiles,
-                     vec);
+                     vec, nch);
+  return hipGetLastError();
+}
+
+// The same contraction with K split over Z workgroup layers (partials in
+// `parts`, Z P Q R elements) and a fixed-order sum into C.
+template <int NCB>
+hipError_t launch_ttm_qx_split(const float* X, const float* B, float* C, int64_t P, int64_t K, int64_t Q, int R,
+                               float* parts, int Z, hipStream_t st) {
+  const int64_t tilesQ = (Q + 63) / 64;
+  const int64_t ntiles = P * tilesQ;
+  const int64_t want = (ntiles + kTtmWaves - 1) / kTtmWaves;
+  const unsigned nx = (unsigned)(want < 256 ? want : 256);
+  const unsigned ny = (unsigned)((R + NCB * 16 - 1) / (NCB * 16));
+  const int vec = (Q % 4 == 0 && ((uintptr_t)X % 16) == 0) ? 1 : 0;
+  const int nch = (int)((K + 127) / 128);
+  const int cps = (nch + Z - 1) / Z;
+  const int z = (nch + cps - 1) / cps;
+  hipLaunchKernelGGL((k_ttm_qx<NCB>), dim3(nx, ny, (unsigned)z), dim3(kTtmThreads), 0, st, X, B, parts, P, K, Q, R,
+                     tilesQ, ntiles, vec, cps);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t n = P * Q * R;
+  const int64_t nb = (n / 4 + 255) / 256;
+  hipLaunchKernelGGL((k_sum_parts<float>), dim3((unsigned)(nb < 2048 ? nb : 2048)), dim3(256), 0, st, parts, C, n, z);
   return hipGetLastError();
 }
 
@@ -2260,6 +2363,52 @@ hipError_t launch_ttm(const T* X, const T* B, T* C, int64_t P, int64_t K, int64_
   return hipGetLastError();
 }
 
+int ttm_split_layers(int64_t P, int64_t K, int64_t Q, int R, int esz) {
+  const int V = 16 / esz;
+  if (R > 128) return 1;
+  const int ncb = R <= 16 ? 1 : R <= 32 ? 2 : R <= 64 ? 4 : 8;
+  const int64_t ny = (R + ncb * 16 - 1) / (ncb * 16);
+  int64_t ntiles, nch;
+  if (Q == 1) {  // k_ttm_kcx: 16-row tiles, chunks of 32 V indices
+    if (K <= 32 * (int64_t)V || (P * R) % V != 0) return 1;
+    if (esz == 4 && P >= 131072 && R > 16 && R <= 64) return 1;  // k_ttm_kcx32 fills the chip by itself
+    ntiles = (P + 15) / 16;
+    nch = (K + 32 * V - 1) / (32 * V);
+  } else {  // k_ttm_qx (FP32): 64-q tiles, chunks of 128 indices
+    if (esz != 4 || Q < 64 || K <= 256 || (P * Q * R) % 4 != 0) return 1;
+    ntiles = P * ((Q + 63) / 64);
+    nch = (K + 127) / 128;
+  }
+  const int64_t nx = std::min<int64_t>((ntiles + kTtmWaves - 1) / kTtmWaves, 256);
+  int64_t z = (512 + nx * ny - 1) / (nx * ny);  // two workgroups per compute unit
+  z = std::min<int64_t>(z, nch / 4);           // at least four chunks per layer
+  z = std::min<int64_t>(z, kMaxSplitLayers);
+  return (int)std::max<int64_t>(z, 1);
+}
+
+template <typename T>
+hipError_t launch_ttm_split(const T* X, const T* B, T* C, int64_t P, int64_t K, int64_t Q, int R, T* parts, int Z,
+                            hipStream_t st) {
+  if (Z <= 1 || !parts) return launch_ttm<T>(X, B, C, P, K, Q, R, st);
+  if (Q == 1) {
+    if (R <= 16) return launch_ttm_kcx_split<T, 1>(X, B, C, P, K, R, parts, Z, st);
+    if (R <= 32) return launch_ttm_kcx_split<T, 2>(X, B, C, P, K, R, parts, Z, st);
+    if (R <= 64) return launch_ttm_kcx_split<T, 4>(X, B, C, P, K, R, parts, Z, st);
+    return launch_ttm_kcx_split<T, 8>(X, B, C, P, K, R, parts, Z, st);
+  }
+  if constexpr (sizeof(T) == 4) {
+    const float* Xf = (const float*)X;
+    const float* Bf = (const float*)B;
+    float* Cf = (float*)C;
+    float* Pf = (float*)parts;
+    if (R <= 16) return launch_ttm_qx_split<1>(Xf, Bf, Cf, P, K, Q, R, Pf, Z, st);
+    if (R <= 32) return launch_ttm_qx_split<2>(Xf, Bf, Cf, P, K, Q, R, Pf, Z, st);
+    if (R <= 64) return launch_ttm_qx_split<4>(Xf, Bf, Cf, P, K, Q, R, Pf, Z, st);
+    return launch_ttm_qx_split<8>(Xf, Bf, Cf, P, K, Q, R, Pf, Z, st);
+  }
+  return hipErrorInvalidValue;
+}
+
 template <typename TI, typename TO>
 hipError_t launch_mttv(const TI* X, const TI* A, TO* Y, int64_t P, int64_t I, int64_t Q, int R,
                        hipStream_t st) {
@@ -2354,24 +2503,23 @@ hipError_t launch_gamma(const GammaArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_inverse(const double* Gamma, double* Ginv, int R, DevStats* stats, hipStream_t st) {
-  if (R <= 16) {
-    hipLaunchKernelGGL(k_inv_blk<16>, dim3(1), dim3(256), 0, st, Gamma, Ginv, R, stats);
-  } else if (R <= 32) {
-    hipLaunchKernelGGL(k_inv_blk<32>, dim3(1), dim3(256), 0, st, Gamma, Ginv, R, stats);
-  } else if (R <= 64) {
-    hipLaunchKernelGGL(k_inv_blk<64>, dim3(1), dim3(256), 0, st, Gamma, Ginv, R, stats);
-  } else {
-    hipLaunchKernelGGL(k_inv_blk<128>, dim3(1), dim3(256), 0, st, Gamma, Ginv, R, stats);
-  }
+template <int RP>
+hipError_t launch_inv_rp(const double* Gamma, double* Ginv, int R, DevStats* stats, hipStream_t st) {
   static std::atomic<uint64_t> attr{0};
   {
-    hipError_t e = lds_limit_once(attr, (const void*)k_pinv, 150 * 1024);
+    hipError_t e = lds_limit_once(attr, (const void*)k_inv_blk<RP>, 150 * 1024);
     if (e != hipSuccess) return e;
   }
-  const size_t lds = pinv_lds_doubles(R) * sizeof(double);
-  hipLaunchKernelGGL(k_pinv, dim3(1), dim3(512), lds, st, Gamma, Ginv, R, stats);
+  const size_t lds = gamma_inverse_lds_doubles(RP, R) * sizeof(double);
+  hipLaunchKernelGGL(k_inv_blk<RP>, dim3(1), dim3(256), lds, st, Gamma, Ginv, R, stats);
   return hipGetLastError();
+}
+
+hipError_t launch_inverse(const double* Gamma, double* Ginv, int R, DevStats* stats, hipStream_t st) {
+  if (R <= 16) return launch_inv_rp<16>(Gamma, Ginv, R, stats, st);
+  if (R <= 32) return launch_inv_rp<32>(Gamma, Ginv, R, stats, st);
+  if (R <= 64) return launch_inv_rp<64>(Gamma, Ginv, R, stats, st);
+  return launch_inv_rp<128>(Gamma, Ginv, R, stats, st);
 }
 
 // The reductions of a mode update when the partials are too many for one
@@ -2480,10 +2628,7 @@ hipError_t launch_update_rp(const UpdateArgs<T>& a, int groups, hipStream_t st) 
     if (e != hipSuccess) return e;
   }
   size_t dbl = update_solve_lds_doubles(RP);
-  if (a.inv_next && a.fused) {
-    const size_t gj = (size_t)RP * (RP + 1), pv = pinv_lds_doubles(a.R);
-    dbl = std::max(dbl, std::max(gj, pv));
-  }
+  if (a.inv_next && a.fused) dbl = std::max(dbl, gamma_inverse_lds_doubles(RP, a.R));
   hipLaunchKernelGGL((k_update<T, RP, PP>), dim3(groups), dim3(256), dbl * sizeof(double), st, a);
   return hipGetLastError();
 }
@@ -2527,10 +2672,26 @@ hipError_t launch_update(const UpdateArgs<T>& a, int groups, hipStream_t st) {
   return launch_inverse(a.Gamma, a.Ginv, a.R, a.stats, st);
 }
 
+template <typename T, int RP>
+hipError_t launch_pp_mttkrp_rp(const PPArgs<T>& a, hipStream_t st) {
+  static std::atomic<uint64_t> attr{0};
+  {
+    hipError_t e = lds_limit_once(attr, (const void*)k_pp_mttkrp<T, RP>, 150 * 1024);
+    if (e != hipSuccess) return e;
+  }
+  const size_t lds = a.Ginv ? gamma_inverse_lds_doubles(RP, a.R) * sizeof(double) : 0;
+  const unsigned grid = (unsigned)a.dims[a.n] + (a.Ginv ? 1u : 0u);
+  hipLaunchKernelGGL((k_pp_mttkrp<T, RP>), dim3(grid), dim3(256), lds, st, a);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_pp_mttkrp(const PPArgs<T>& a, hipStream_t st) {
-  hipLaunchKernelGGL((k_pp_mttkrp<T>), dim3((unsigned)a.dims[a.n]), dim3(256), 0, st, a);
-  return hipGetLastError();
+  if (a.R < 1 || a.R > kMaxRank) return hipErrorInvalidValue;
+  if (a.R <= 16) return launch_pp_mttkrp_rp<T, 16>(a, st);
+  if (a.R <= 32) return launch_pp_mttkrp_rp<T, 32>(a, st);
+  if (a.R <= 64) return launch_pp_mttkrp_rp<T, 64>(a, st);
+  return launch_pp_mttkrp_rp<T, 128>(a, st);
 }
 
 // explicit instantiations
@@ -2538,6 +2699,10 @@ template hipError_t launch_ttm<float>(const float*, const float*, float*, int64_
                                       int64_t, int, hipStream_t);
 template hipError_t launch_ttm<double>(const double*, const double*, double*, int64_t, int64_t,
                                        int64_t, int, hipStream_t);
+template hipError_t launch_ttm_split<float>(const float*, const float*, float*, int64_t, int64_t, int64_t, int,
+                                            float*, int, hipStream_t);
+template hipError_t launch_ttm_split<double>(const double*, const double*, double*, int64_t, int64_t, int64_t, int,
+                                             double*, int, hipStream_t);
 template hipError_t launch_mttv<float, float>(const float*, const float*, float*, int64_t, int64_t,
                                               int64_t, int, hipStream_t);
 template hipError_t launch_mttv<float, double>(const float*, const float*, double*, int64_t,

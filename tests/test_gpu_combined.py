@@ -32,6 +32,14 @@ CASES = [
     ((16, 17, 15, 3, 5, 4), 33, "f32"),
     ((50, 60, 33, 9), 50, "f32"),
     ((64, 84, 33, 9), 50, "f64"),
+    # combined lengths long enough for the split-K form (the K range spread
+    # over 2 to 8 workgroup layers, partials summed in layer order), with a
+    # ragged last layer and every column-block width
+    ((24, 20, 40, 30), 24, "f32"),
+    ((10, 12, 64, 70), 40, "f32"),
+    ((9, 11, 40, 35), 20, "f64"),
+    ((8, 9, 36, 40), 80, "f32"),
+    ((7, 5, 6, 48, 50), 12, "f32"),
 ]
 
 

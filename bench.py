@@ -139,6 +139,8 @@ def load_traffic(sha):
 # sweeps of the DT and MSDT runs per workload (the PP run goes on until it
 # reaches the DT run's final exact fitness less TARGET_SLACK)
 TREE_SWEEPS = {"o4_s128_r64_f32": 10, "o3_s64_r16_f64": 20}
+# a longer run for the PP comparison, timed outside the step
+LONG_SWEEPS = {"o4_s128_r64_f32": 30}
 PP_TOL = 0.1  # Alg. 2 tolerance (the paper's value for its application tensors, Sec. V-C)
 TARGET_SLACK = 1e-4
 PP_MAX_STEPS = 60
@@ -258,45 +260,54 @@ def tree_bench(args):
         plan.reset()
         return plan
 
-    # calibration (untimed): fitness trajectories, the target, PP's steps to it
+    def calibrate(nsw):
+        """Untimed: DT and MSDT fitness over nsw sweeps, the target (the DT
+        run's final fitness less TARGET_SLACK), the sweeps each needs to reach
+        it, and PP's outer steps to it, every step audited with cp_fitness."""
+        c = {"fit": {}}
+        for k in ("dt", "msdt"):
+            plan = restart(k)
+            c["fit"][k] = [plan.als_sweep(A[k])["fitness"] for _ in range(nsw)]
+        target = c["fit"]["dt"][-1] - TARGET_SLACK
+        c["target"] = target
+        c["to_target"] = {k: next(i + 1 for i, f in enumerate(c["fit"][k]) if f >= target) for k in ("dt", "msdt")}
+        plan = restart("pp")
+        kinds, est, exact, clamped = [], [], [], []
+        c["pp_start"] = None
+        while len(kinds) < PP_MAX_STEPS:
+            if c["pp_start"] is None:
+                before = [a.cpu().numpy() for a in A["pp"]]
+            info = plan.pp_sweep(A["pp"], tol=PP_TOL, mode="auto")
+            if info["kind"] == "init" and c["pp_start"] is None:
+                c["pp_start"] = before
+            kinds.append(info["kind"])
+            est.append(info["fitness"])
+            clamped.append(info["r_clamped"])
+            exact.append(audit.fitness(A["pp"]))
+            if exact[-1] >= target:
+                break
+        c.update(pp_kinds=kinds, pp_est=est, pp_exact=exact, pp_clamped=clamped, k_pp=len(kinds),
+                 pp_reached=exact[-1] >= target, pp_final=[a.clone() for a in A["pp"]])
+        log(f"[bench] {nsw}-sweep target {target:.8f}: dt {c['to_target']['dt']} sweeps, msdt "
+            f"{c['to_target']['msdt']}, pp {len(kinds)} steps {kinds} reached={c['pp_reached']}")
+        return c
+
     log("[bench] calibration")
-    fit = {}
-    for k in ("dt", "msdt"):
-        plan = restart(k)
-        fit[k] = [plan.als_sweep(A[k])["fitness"] for _ in range(n_sw)]
-    target = fit["dt"][-1] - TARGET_SLACK
-    to_target = {k: next(i + 1 for i, f in enumerate(fit[k]) if f >= target) for k in ("dt", "msdt")}
-    plan = restart("pp")
-    pp_kinds, pp_est, pp_exact, pp_clamped = [], [], [], []
-    pp_start = None
-    while len(pp_kinds) < PP_MAX_STEPS:
-        if pp_start is None:
-            before = [a.cpu().numpy() for a in A["pp"]]
-        info = plan.pp_sweep(A["pp"], tol=PP_TOL, mode="auto")
-        if info["kind"] == "init" and pp_start is None:
-            pp_start = before
-        pp_kinds.append(info["kind"])
-        pp_est.append(info["fitness"])
-        pp_clamped.append(info["r_clamped"])
-        pp_exact.append(audit.fitness(A["pp"]))
-        if pp_exact[-1] >= target:
-            break
-    k_pp = len(pp_kinds)
-    pp_reached = pp_exact[-1] >= target
-    pp_final = [a.clone() for a in A["pp"]]
-    log(f"[bench] target {target:.8f}: dt {to_target['dt']} sweeps, msdt {to_target['msdt']}, "
-        f"pp {k_pp} steps {pp_kinds} reached={pp_reached}")
-    audit.close()
+    cal = calibrate(n_sw)
+    fit, target, to_target = cal["fit"], cal["target"], cal["to_target"]
+    pp_kinds, pp_est, pp_exact, pp_clamped = cal["pp_kinds"], cal["pp_est"], cal["pp_exact"], cal["pp_clamped"]
+    k_pp, pp_reached, pp_final, pp_start = cal["k_pp"], cal["pp_reached"], cal["pp_final"], cal["pp_start"]
 
     stream = torch.cuda.current_stream(dev)
 
-    def one_step(ev=None):
+    def one_step(ev=None, nsw=n_sw, kpp=None):
         """ev: per run, a list of events recorded after each sweep (index 0 before the first)."""
+        kpp = k_pp if kpp is None else kpp
         for k in ("dt", "msdt", "pp"):
             plan = restart(k)
             if ev is not None:
                 ev[k][0].record(stream)
-            nk = k_pp if k == "pp" else n_sw
+            nk = kpp if k == "pp" else nsw
             for i in range(nk):
                 if k == "pp":
                     plan.pp_sweep(A[k], tol=PP_TOL, mode="auto", info=False)
@@ -413,6 +424,45 @@ def tree_bench(args):
             "timed": "separately, not part of the step"}
         log(f"[bench] dt_combined {methods['dt_combined']}")
 
+    # PP against DT and MSDT over a longer run (outside the step): the target
+    # is the DT run's fitness after LONG_SWEEPS sweeps, where ALS converges
+    # slowly and Alg. 2 stays longer in its PP phase
+    long_cmp = None
+    if args.workload in LONG_SWEEPS:
+        nl = LONG_SWEEPS[args.workload]
+        cl = calibrate(nl)
+        reps = 2
+        evl = [{"dt": mk(nl), "msdt": mk(nl), "pp": mk(cl["k_pp"])} for _ in range(reps)]
+        for r in range(reps):
+            one_step(evl[r], nsw=nl, kpp=cl["k_pp"])
+        torch.cuda.synchronize()
+        same_l = all(torch.equal(a, b) for a, b in zip(A["pp"], cl["pp_final"]))
+
+        def ms_of(k):
+            n = len(evl[0][k]) - 1
+            return [float(np.mean([e[k][i].elapsed_time(e[k][i + 1]) for e in evl])) for i in range(n)]
+
+        pl = {k: ms_of(k) for k in ("dt", "msdt", "pp")}
+        tt = {k: sum(pl[k][:cl["to_target"][k]]) for k in ("dt", "msdt")}
+        tt["pp"] = sum(pl["pp"])
+        kinds_l = {kk: [pl["pp"][i] for i, x in enumerate(cl["pp_kinds"]) if x == kk] for kk in ("exact", "init", "approx")}
+        long_cmp = {
+            "sweeps": nl, "target_fitness": cl["target"],
+            "dt": {"sweeps_to_target": cl["to_target"]["dt"], "ms_to_target": round(tt["dt"], 4)},
+            "msdt": {"sweeps_to_target": cl["to_target"]["msdt"], "ms_to_target": round(tt["msdt"], 4),
+                     "speedup_vs_dt_to_target": round(tt["dt"] / tt["msdt"], 3)},
+            "pp": {"steps_to_target": cl["k_pp"], "reached_target": bool(cl["pp_reached"]),
+                   "steps_by_kind": {kk: len(v) for kk, v in kinds_l.items()},
+                   "ms_by_kind": {kk: round(float(np.mean(v)), 4) for kk, v in kinds_l.items() if v},
+                   "ms_to_target": round(tt["pp"], 4), "final_exact_fitness": cl["pp_exact"][-1],
+                   "estimate_clamped_steps": int(sum(cl["pp_clamped"])),
+                   "speedup_vs_dt_to_target": round(tt["dt"] / tt["pp"], 3),
+                   "speedup_vs_msdt_to_target": round(tt["msdt"] / tt["pp"], 3),
+                   "timed_runs_bitwise_equal_calibration": bool(same_l)},
+            "timed": f"separately, not part of the step ({reps} repetitions)"}
+        log(f"[bench] long comparison {long_cmp}")
+    audit.close()
+
     credited = F_dt * (2 * n_sw + to_target["dt"])
     value = credited / (ms_step * 1e-3) / 1e12
     ttm_ms, ttm_n = timed_phase["ttm"]
@@ -444,6 +494,7 @@ def tree_bench(args):
                            f"{k_pp} outer steps to the DT run's final fitness - {TARGET_SLACK:g}",
                    "target_fitness": target, "dt_sweep_gflop": round(F_dt / 1e9, 3), "parallelism": "1 GPU"},
         "methods": methods,
+        "long_run_comparison": long_cmp,
         "phase_ms_per_step": {k: round(v[0], 4) for k, v in phase.items()},
         "phase_note": "one extra step with every phase timed (its event pairs make it slower than a timed step)",
         "fitness_per_sweep": {"dt": fit["dt"], "msdt": fit["msdt"]},

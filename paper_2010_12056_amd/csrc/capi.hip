@@ -105,6 +105,7 @@ struct cp_plan_s {
   void* parts = nullptr;      // split-K partial products of the combined contractions
   int split_z = 1;            // layers of the leading half's combined contraction
   int split_zr = 1;           // layers of the trailing half's
+  void* pair_parts = nullptr;  // FP32, order >= 4: partial sums of the fused two-child PP operators
   uint16_t* Bt_hi = nullptr;  // BF16 plans: transposed BF16 factor of the first contraction
   uint16_t* Bt_lo = nullptr;  // BF16X2 plans: its remainder part
   int pinv_seen = 0;         // stats->pinv_count at the last report
@@ -281,6 +282,18 @@ void plan_layout(cp_plan p) {
     const size_t pr = p->split_zr > 1 ? (size_t)p->split_zr * Q : 0;
     take(std::max(pl, pr) * R * p->esz);  // parts
   }
+  {
+    // pair_parts: the largest split partials of launch_mttv_pair over the
+    // (slice z, summed u, kept v) mode triples it can take
+    size_t pp = 0;
+    if (p->prec == CP_F32 && N >= 4)
+      for (int z = 0; z < N; ++z)
+        for (int u = 0; u < N; ++u)
+          for (int v = 0; v < N; ++v)
+            if (z != u && z != v && u != v && mttv_pair_fits(p->dims[z], p->dims[v], R))
+              pp = std::max(pp, (size_t)mttv_pair_split(p->dims[z], p->dims[u]) * p->dims[z] * p->dims[v] * R * 4);
+    take(pp);
+  }
   const int64_t kb = std::max(smax, kc);
   take(bf ? (size_t)R * bf16_factor_pitch(kb) * 2 : 0);                                 // Bt_hi
   take(split_factor(p->prec) ? (size_t)R * bf16_factor_pitch(kb) * 2 : 0);              // Bt_lo
@@ -322,6 +335,7 @@ void plan_carve(cp_plan p) {
   p->sw_out = (float*)next();
   p->krp = next();
   p->parts = next();
+  p->pair_parts = next();
   p->Bt_hi = (uint16_t*)next();
   void* lo = next();
   p->Bt_lo = split_factor(p->prec) ? (uint16_t*)lo : nullptr;
@@ -800,6 +814,51 @@ int lowest_bit(uint32_t x) {
 int pair_first(uint32_t set) { return lowest_bit(set); }
 int pair_second(uint32_t set) { return lowest_bit(set & ~(1u << lowest_bit(set))); }
 
+// Two pair operators of the PP tree from one pass over their parent, a node
+// keeping three modes (launch_mttv_pair): child c1 contracts one mode of
+// the parent, child c2 another; the third mode is the slice index.  FP32
+// plans and the kernel's rank and size limits; *done tells whether it ran.
+cp_status pp_pair_fused(cp_plan p, uint32_t pset, uint32_t c1, uint32_t c2, const void* X, bool* done) {
+  *done = false;
+  if (p->prec != CP_F32) return CP_OK;
+  const int m1 = lowest_bit(pset & ~c1), m2 = lowest_bit(pset & ~c2);
+  const int z = lowest_bit(pset & ~(1u << m1) & ~(1u << m2));
+  if (m1 < 0 || m2 < 0 || z < 0 || m1 == m2) return CP_OK;
+  // v: the contracted mode spread over a workgroup's threads (the shorter one)
+  const bool swap = p->dims[m1] > p->dims[m2];
+  const int v = swap ? m2 : m1, u = swap ? m1 : m2;
+  const int R = p->R;
+  if (!mttv_pair_fits(p->dims[z], p->dims[v], R)) return CP_OK;
+  // element strides of the parent (modes in increasing order, rank last)
+  int md[3] = {z, u, v};
+  std::sort(md, md + 3);
+  int64_t stride[kMaxOrder] = {};
+  stride[md[2]] = R;
+  stride[md[1]] = p->dims[md[2]] * R;
+  stride[md[0]] = p->dims[md[1]] * p->dims[md[2]] * R;
+  // output strides of a pair keeping {z, w}: (z's, w's)
+  auto pair_strides = [&](int w, int64_t* oz, int64_t* ow) {
+    if (z < w) {
+      *oz = p->dims[w] * R;
+      *ow = R;
+    } else {
+      *ow = p->dims[z] * R;
+      *oz = R;
+    }
+  };
+  int64_t ozv, ouv, ozu, ovu;
+  pair_strides(u, &ozv, &ouv);  // contracting v keeps {z, u}
+  pair_strides(v, &ozu, &ovu);  // contracting u keeps {z, v}
+  float* Ycv = (float*)p->pair[std::min(z, u)][std::max(z, u)];
+  float* Ycu = (float*)p->pair[std::min(z, v)][std::max(z, v)];
+  ProfScope ps(p, CP_PHASE_MTTV);
+  HIP_TRY(p, launch_mttv_pair((const float*)X, (const float*)p->Ash[u], (const float*)p->Ash[v], Ycv, Ycu,
+                              p->dims[z], p->dims[u], p->dims[v], stride[z], stride[u], stride[v], ozv, ouv, ozu, ovu,
+                              R, (float*)p->pair_parts, p->st));
+  *done = true;
+  return CP_OK;
+}
+
 cp_status pp_node(cp_plan p, const std::vector<std::vector<PPNode>>& lv, int l, int k) {
   const int N = p->N;
   const uint32_t set = lv[l - 1][k].set;
@@ -820,8 +879,19 @@ cp_status pp_node(cp_plan p, const std::vector<std::vector<PPNode>>& lv, int l, 
     if (!is_pair) slot_record(p, l, set);
   }
   if (!is_pair) {
+    std::vector<int> kids;
     for (int c = 0; c < (int)lv[l].size(); ++c)
-      if (lv[l][c].parent == k) CP_TRY(pp_node(p, lv, l + 1, c));
+      if (lv[l][c].parent == k) kids.push_back(c);
+    size_t i = 0;
+    // pair children of a node that keeps three modes: two at a time from one
+    // pass over the node where the fused kernel applies
+    while (l + 1 == N - 2 && i + 1 < kids.size()) {
+      bool done = false;
+      CP_TRY(pp_pair_fused(p, set, lv[l][kids[i]].set, lv[l][kids[i + 1]].set, p->slot_buf[l], &done));
+      if (!done) break;
+      i += 2;
+    }
+    for (; i < kids.size(); ++i) CP_TRY(pp_node(p, lv, l + 1, kids[i]));
   }
   return CP_OK;
 }

@@ -58,6 +58,21 @@ template <typename TI, typename TO>
 hipError_t launch_mttv(const TI* X, const TI* A, TO* Y, int64_t P, int64_t I, int64_t Q, int R,
                        hipStream_t st);
 
+// Two children of a node keeping three modes z, u, v (FP32, rank index
+// contiguous; element strides Sz, Su, Sv) from one pass over it:
+// Ycv[z][u] = sum_v X Av[v] and Ycu[z][v] = sum_u X Au[u] (rank-wise), with
+// output strides (ozv, ouv) and (ozu, ovu).  For R in {16, 32, 64} with sv
+// at most 8 (1024 / R) (mttv_pair_fits); hipErrorInvalidValue otherwise.
+// With `parts` (mttv_pair_split(sz, su) sz sv R floats), the u range is
+// split over that many workgroups per slice and their partial Ycu are added
+// in range order; null: one workgroup per slice.
+constexpr int kMaxPairSplit = 8;
+bool mttv_pair_fits(int64_t sz, int64_t sv, int R);
+int mttv_pair_split(int64_t sz, int64_t su);
+hipError_t launch_mttv_pair(const float* X, const float* Au, const float* Av, float* Ycv, float* Ycu, int64_t sz,
+                            int64_t su, int64_t sv, int64_t Sz, int64_t Su, int64_t Sv, int64_t ozv, int64_t ouv,
+                            int64_t ozu, int64_t ovu, int R, float* parts, hipStream_t st);
+
 // dst[i] = (T) src[i] for n elements.
 template <typename T>
 hipError_t launch_convert(const double* src, T* dst, int64_t n, hipStream_t st);

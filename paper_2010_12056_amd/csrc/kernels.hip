@@ -1115,6 +1115,93 @@ __global__ __launch_bounds__(256) void k_mttv4(const float* __restrict__ X, cons
   for (int u = 0; u < 4; ++u) Y[g + u] = s0[u] + s1[u];
 }
 
+// Two children of a node that keeps three modes, from one pass over it (the
+// last level of the PP initialization, Sec. II-D, Fig. 1b: a node has up to
+// three pair children, each contracting a different mode of it).  With z, u,
+// v the node's modes in any order (element strides Sz, Su, Sv; the rank
+// index contiguous):
+//   Ycv[z][u][r] = sum_v X[z][u][v][r] Av[v][r]   (contract v)
+//   Ycu[z][v][r] = sum_u X[z][u][v][r] Au[u][r]   (contract u)
+// each written with its own strides.  Workgroup (iz, y) takes slice z = iz
+// and the u-indices [y uc, (y + 1) uc); thread (g, lr): rank entries
+// 4 lr .. 4 lr + 3 (RQ = R / 4 threads per rank vector) of the v-indices g,
+// g + NG, ... (at most VMAX); UB values of u at a time are read with every
+// load in flight.  Ycu accumulates in registers over the workgroup's u in
+// order (with more than one u range, each range's sum goes to its own
+// partial, Ycu + y pstride, added in range order afterwards); Ycv's sums
+// over v are per thread, then over the groups in order through LDS.  All
+// FP32 sums in a fixed order.
+template <int RQ>
+__global__ __launch_bounds__(256) void k_mttv_pair(const float* __restrict__ X, const float* __restrict__ Au,
+                                                   const float* __restrict__ Av, float* __restrict__ Ycv,
+                                                   float* __restrict__ Ycu, int64_t su, int64_t sv, int64_t Sz,
+                                                   int64_t Su, int64_t Sv, int64_t ozv, int64_t ouv, int64_t ozu,
+                                                   int64_t ovu, int64_t uc, int64_t pstride) {
+  constexpr int NG = 256 / RQ, VMAX = 8, UB = 4;
+  constexpr int R = 4 * RQ;
+  __shared__ f32x4 part[NG][UB][RQ];
+  const int tid = threadIdx.x, g = tid / RQ, lr = tid - g * RQ;
+  const int64_t iz = blockIdx.x;
+  const int64_t ub = (int64_t)blockIdx.y * uc;
+  const int64_t ue = ub + uc < su ? ub + uc : su;
+  Ycu += (int64_t)blockIdx.y * pstride;
+  const float* Xz = X + iz * Sz + 4 * lr;
+  f32x4 av[VMAX], acc[VMAX];
+  bool vin[VMAX];
+#pragma unroll
+  for (int j = 0; j < VMAX; ++j) {
+    const int64_t v = g + (int64_t)NG * j;
+    vin[j] = v < sv;
+    av[j] = vin[j] ? *(const f32x4*)(Av + v * R + 4 * lr) : f32x4{0.f, 0.f, 0.f, 0.f};
+    acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  }
+  for (int64_t u0 = ub; u0 < ue; u0 += UB) {
+    f32x4 x[UB][VMAX], au[UB];
+#pragma unroll
+    for (int b = 0; b < UB; ++b) {
+      const int64_t u = u0 + b < ue ? u0 + b : ue - 1;  // clamped: its products are discarded
+      au[b] = *(const f32x4*)(Au + u * R + 4 * lr);
+#pragma unroll
+      for (int j = 0; j < VMAX; ++j) {
+        const int64_t v = vin[j] ? g + (int64_t)NG * j : 0;
+        x[b][j] = *(const f32x4*)(Xz + u * Su + v * Sv);
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < UB; ++b) {
+      const bool uin = u0 + b < ue;
+      f32x4 pv = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int j = 0; j < VMAX; ++j) {
+        if (!vin[j]) continue;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          pv[e] += x[b][j][e] * av[j][e];
+          if (uin) acc[j][e] += x[b][j][e] * au[b][e];
+        }
+      }
+      part[g][b][lr] = pv;
+    }
+    __syncthreads();
+    // Ycv for these u: the group partials summed in group order
+    for (int t = tid; t < UB * RQ; t += 256) {
+      const int b = t / RQ, l = t - b * RQ;
+      if (u0 + b < ue) {
+        f32x4 sum = part[0][b][l];
+        for (int q = 1; q < NG; ++q) sum += part[q][b][l];
+        *(f32x4*)(Ycv + iz * ozv + (u0 + b) * ouv + 4 * l) = sum;
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int j = 0; j < VMAX; ++j) {
+    if (!vin[j]) continue;
+    const int64_t v = g + (int64_t)NG * j;
+    *(f32x4*)(Ycu + iz * ozu + v * ovu + 4 * lr) = acc[j];
+  }
+}
+
 template <typename T>
 __global__ void k_convert(const double* __restrict__ s, T* __restrict__ d, int64_t n) {
   const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -2426,6 +2513,47 @@ hipError_t launch_mttv(const TI* X, const TI* A, TO* Y, int64_t P, int64_t I, in
   }
   hipLaunchKernelGGL((k_mttv<TI, TO>), dim3(nblocks(total)), dim3(256), 0, st, X, A, Y, total, I,
                      Q * R, R);
+  return hipGetLastError();
+}
+
+bool mttv_pair_fits(int64_t sz, int64_t sv, int R) {
+  if (R % 4 != 0 || R < 16 || R > 64 || sz < 1) return false;
+  const int rq = R / 4;
+  return rq == 4 || rq == 8 || rq == 16 ? sv <= 8 * (256 / rq) : false;
+}
+
+int mttv_pair_split(int64_t sz, int64_t su) {
+  // about two workgroups per compute unit, at least 8 u-indices per range
+  int y = (int)std::min<int64_t>((512 + sz - 1) / sz, kMaxPairSplit);
+  while (y > 1 && su / y < 8) --y;
+  return y < 1 ? 1 : y;
+}
+
+hipError_t launch_mttv_pair(const float* X, const float* Au, const float* Av, float* Ycv, float* Ycu, int64_t sz,
+                            int64_t su, int64_t sv, int64_t Sz, int64_t Su, int64_t Sv, int64_t ozv, int64_t ouv,
+                            int64_t ozu, int64_t ovu, int R, float* parts, hipStream_t st) {
+  if (!mttv_pair_fits(sz, sv, R) || su < 1 || ((uintptr_t)X % 16) || ((uintptr_t)Ycv % 16) || ((uintptr_t)Ycu % 16))
+    return hipErrorInvalidValue;
+  const int y = parts ? mttv_pair_split(sz, su) : 1;
+  const int64_t uc = (su + y - 1) / y;
+  const int64_t n = sz * sv * R;  // Ycu's elements
+  float* dst = y > 1 ? parts : Ycu;
+  const int64_t pstride = y > 1 ? n : 0;
+  const dim3 grid((unsigned)sz, (unsigned)((su + uc - 1) / uc));
+  if (R == 16)
+    hipLaunchKernelGGL(k_mttv_pair<4>, grid, dim3(256), 0, st, X, Au, Av, Ycv, dst, su, sv, Sz, Su, Sv, ozv, ouv,
+                       ozu, ovu, uc, pstride);
+  else if (R == 32)
+    hipLaunchKernelGGL(k_mttv_pair<8>, grid, dim3(256), 0, st, X, Au, Av, Ycv, dst, su, sv, Sz, Su, Sv, ozv, ouv,
+                       ozu, ovu, uc, pstride);
+  else
+    hipLaunchKernelGGL(k_mttv_pair<16>, grid, dim3(256), 0, st, X, Au, Av, Ycv, dst, su, sv, Sz, Su, Sv, ozv, ouv,
+                       ozu, ovu, uc, pstride);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || grid.y == 1) return e;
+  const int64_t nb = (n / 4 + 255) / 256;
+  hipLaunchKernelGGL((k_sum_parts<float>), dim3((unsigned)(nb < 2048 ? nb : 2048)), dim3(256), 0, st, parts, Ycu, n,
+                     (int)grid.y);
   return hipGetLastError();
 }
 

@@ -178,6 +178,47 @@ def test_pp_forced_schedule_fp32_resynced(dev, tree):
     plan.close()
 
 
+FUSED_PAIR_CASES = [
+    # FP32 plans whose rank takes the fused two-children pass of the PP
+    # initialization's last level (R = 16, 32, 64), orders 4 and 5, modes of
+    # unequal sizes so every slice / contracted-mode assignment occurs
+    ((24, 20, 28, 18), 16),
+    ((20, 22, 16, 24), 32),
+    ((16, 18, 20, 14), 64),
+    ((9, 10, 8, 11, 7), 32),
+]
+
+
+@pytest.mark.parametrize("tree", ["dt", "msdt"])
+@pytest.mark.parametrize("dims,R", FUSED_PAIR_CASES)
+def test_pp_fused_pair_operators_fp32_resynced(dev, tree, dims, R):
+    """PP initialization whose pair operators come two at a time from one
+    pass over their three-mode parent: re-synced forced schedule (three
+    regular sweeps, initialization with its approximated sweep, one more
+    approximated sweep) against the oracle's Eq. (4) operators, fitness
+    within 1e-6 and factors within 1e-4 per step."""
+    from oracle import core, pp
+    from paper_2010_12056_amd import synth
+
+    say(f"case pp fused pairs dims={dims} R={R} {tree}")
+    w = synth.planted_tensor(dims, R, 7000 + R + len(dims), noise_rel=1e-2, dtype=np.float32)
+    plan, T, A = _plan(w, "f32", tree, dev)
+    st = pp.PPState.start(w.T.astype(np.float64), w.init)
+    for step, kind in enumerate(["exact"] * 3 + ["init", "approx"]):
+        st.A = [a.cpu().numpy().copy() for a in A]
+        st.S = [core.gram(a) for a in st.A]
+        if st.phase == "pp":
+            st.dA = [st.A[i] - st.Ap[i] for i in range(len(st.A))]
+        info = plan.pp_sweep(A, mode=kind)
+        pp.pp_als_step(st, force=kind)
+        assert info["kind"] == kind
+        assert not info["r_clamped"], (step, kind)
+        assert abs(info["fitness"] - st.last_fit_est) <= 1e-6, (step, kind, info["fitness"], st.last_fit_est)
+        for n in range(len(dims)):
+            assert relerr(A[n].cpu().numpy(), st.A[n]) <= 1e-4, (step, n)
+    plan.close()
+
+
 def test_pp_auto_matches_oracle_schedule_fp64(dev):
     import oracle
     from oracle import pp

@@ -137,3 +137,73 @@ def test_batch_graph_replay(dev):
         _ = torch.ones(8, device=dev).sum().item()  # eager work between replays
     b.close()
     bg.close()
+
+
+def test_batch_singular_gamma_flags_only_its_tensor(dev):
+    """A tensor whose two factor columns are equal in modes 1 and 2 makes
+    Gamma0 = S1 * S2 singular at the first update: its status is 1 (its
+    sweeps stop), and the other tensors in the same launch still match the
+    oracle sweep by sweep."""
+    from paper_2010_12056_amd import synth
+
+    say("case batch singular gamma")
+    ws = [synth.planted_tensor(d, R, 7200 + i, kind="uniform", noise_rel=1e-3, dtype=np.float32)
+          for i, (d, R) in enumerate([((30, 20, 25), 2), ((40, 33, 21), 8), ((17, 64, 48), 16)])]
+    bad = ws[0]
+    for m in (1, 2):
+        bad.init[m][:, 1] = bad.init[m][:, 0]
+    b, T, A, fit, status = _run(dev, ws, 4)
+    assert status[0] == 1
+    assert np.all(status[1:] == 0)
+    import oracle
+
+    for i in (1, 2):
+        st = oracle.AlsState.start(ws[i].T.astype(np.float64), ws[i].init)
+        for s in range(4):
+            r = oracle.als_sweep(st)
+            assert abs(fit[i, s] - (1.0 - r)) <= _fit_tol(r), (i, s)
+    b.close()
+
+
+QUEUE_SKIP = ("the work-queue form of the batched kernel (a tensor's contraction stages split into items over "
+              "several workgroups, with dependency waits between workgroups) hung on the GPU twice, its cause "
+              "not found; that kernel is not in the library and these tests of it stay skipped")
+
+
+@pytest.mark.skip(reason=QUEUE_SKIP)
+@pytest.mark.parametrize("parts", [1, 16])
+def test_batch_queue_split_edge_shapes_match_oracle(dev, parts):
+    """Work-queue kernel: the edge shapes with every bucket's contraction
+    stages in `parts` items, against the oracle."""
+    from paper_2010_12056_amd import cpals
+
+    ws = _edge_workloads()
+    b = cpals.Batch([w.dims for w in ws], [w.R for w in ws], device=dev, split={k: parts for k in range(12)})
+    T = b.pack_tensors([w.T for w in ws])
+    A = b.pack_factors([w.init for w in ws])
+    fit, status = b.sweeps(T, A, 5)
+    torch.cuda.synchronize()
+    assert np.all(status.cpu().numpy() == 0)
+    _oracle_check(ws, b, A, fit.cpu().numpy(), 5, 2e-4)
+    b.close()
+
+
+@pytest.mark.skip(reason=QUEUE_SKIP)
+def test_batch_queue_split_changes_rounding_only(dev):
+    """Work-queue kernel: large tensors with one item per stage and with
+    sixteen agree to FP64 rounding of the partial sums after five sweeps."""
+    from paper_2010_12056_amd import cpals, synth
+
+    shapes = [((96, 96, 96), 32), ((90, 71, 83), 16), ((64, 96, 50), 8), ((77, 80, 96), 4)]
+    ws = [synth.planted_tensor(d, R, 7100 + i, kind="uniform", noise_rel=1e-3, dtype=np.float32)
+          for i, (d, R) in enumerate(shapes)]
+    out = []
+    for parts in (1, 16):
+        b = cpals.Batch([w.dims for w in ws], [w.R for w in ws], device=dev, split={k: parts for k in range(12)})
+        T = b.pack_tensors([w.T for w in ws])
+        A = b.pack_factors([w.init for w in ws])
+        fit, _ = b.sweeps(T, A, 5)
+        torch.cuda.synchronize()
+        out.append(fit.cpu().numpy())
+        b.close()
+    assert np.max(np.abs(out[0] - out[1])) <= 1e-10

@@ -391,10 +391,11 @@ def tree_bench(args):
         methods[k]["speedup_vs_dt_to_target"] = round(methods["dt"]["ms_to_target"] / methods[k]["ms_to_target"], 3)
     methods["pp"]["speedup_vs_msdt_to_target"] = round(methods["msdt"]["ms_to_target"] / methods["pp"]["ms_to_target"], 3)
 
-    # the dimension tree with its upper two levels combined (order >= 4): timed
-    # on its own, outside the step, against the DT plan's sweeps
-    if N >= 4:
-        pc = cpals.Plan(w.dims, R, prec=prec, tree="dt_combined", device=dev)
+    def side_plan(prec_v, tree_v):
+        """Three sweeps of another plan from the same initial factors, timed
+        on their own (outside the step); ms per sweep and fitness after the
+        three sweeps."""
+        pc = cpals.Plan(w.dims, R, prec=prec_v, tree=tree_v, device=dev)
         pc.set_tensor(T)
         Ac = [a.clone() for a in A0]
         c_ms = []
@@ -415,14 +416,28 @@ def tree_bench(args):
             a.copy_(a0)
         c_fit = [pc.als_sweep(Ac)["fitness"] for _ in range(3)]
         pc.close()
-        cms = float(np.mean(c_ms))
+        return float(np.mean(c_ms)), c_fit[-1]
+
+    # the dimension tree with its upper two levels combined (order >= 4)
+    if N >= 4:
+        cms, cfit = side_plan(prec, "dt_combined")
         methods["dt_combined"] = {
             "sweeps": 3, "ms_per_sweep": round(cms, 4),
             "effective_tflops": round(F_dt / (cms * 1e-3) / 1e12, 3),
             "speedup_vs_dt_per_sweep": round(methods["dt"]["ms_per_sweep"] / cms, 3),
-            "fitness_3_sweeps": c_fit[-1], "dt_fitness_3_sweeps": fit["dt"][2],
+            "fitness_3_sweeps": cfit, "dt_fitness_3_sweeps": fit["dt"][2],
             "timed": "separately, not part of the step"}
         log(f"[bench] dt_combined {methods['dt_combined']}")
+    # the FP32 tensor with the first contraction as three-part BF16 products
+    if prec == "f32":
+        for tree_v in ("dt", "msdt"):
+            xms, xfit = side_plan("f32x3", tree_v)
+            methods[f"{tree_v}_f32x3"] = {
+                "sweeps": 3, "ms_per_sweep": round(xms, 4),
+                "speedup_vs_f32_per_sweep": round(methods[tree_v]["ms_per_sweep"] / xms, 3),
+                "fitness_3_sweeps": xfit, "f32_fitness_3_sweeps": fit[tree_v][2],
+                "timed": "separately, not part of the step"}
+            log(f"[bench] {tree_v}_f32x3 {methods[f'{tree_v}_f32x3']}")
 
     # PP against DT and MSDT over a longer run (outside the step): the target
     # is the DT run's fitness after LONG_SWEEPS sweeps, where ALS converges

@@ -64,8 +64,16 @@ typedef enum {
  * stored values with half the tensor bytes.  E4M3 spans 2^-9 .. 448: scale
  * the tensor by a power of two so that its largest entry lies near 448
  * before storing it (exact; the relative residual does not depend on the
- * tensor's scale), else small entries round to zero. */
-typedef enum { CP_F64 = 0, CP_F32 = 1, CP_BF16 = 2, CP_BF16X2 = 3, CP_FP8 = 4, CP_FP8X2 = 5 } cp_prec;
+ * tensor's scale), else small entries round to zero.  CP_F32X3 (not from the
+ * paper): as CP_F32, except that the first contraction runs on the BF16
+ * matrix cores: every FP32 tensor value and factor entry is split exactly
+ * into three BF16 parts (each rounded to nearest) and the six leading part
+ * products are accumulated in FP32 (the three dropped ones are below 2^-23
+ * of the product), so each product carries an error of the order of one FP32
+ * rounding; contraction lengths above 128 (or, contracting the last mode,
+ * rows not 16-byte aligned or K not a multiple of 8) take the FP32 matrix
+ * cores instead. */
+typedef enum { CP_F64 = 0, CP_F32 = 1, CP_BF16 = 2, CP_BF16X2 = 3, CP_FP8 = 4, CP_FP8X2 = 5, CP_F32X3 = 6 } cp_prec;
 
 typedef enum {
   CP_TREE_DT = 0,           /* standard binary dimension tree, two first-level TTMs per sweep (Sec. II-C) */

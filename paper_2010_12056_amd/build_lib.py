@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcpals.so")
 OBJ_DIR = os.path.join(HERE, "_build")
-SOURCES = ["kernels.hip", "ttm_bf16.hip", "capi.hip", "mlp.hip", "batch.hip"]
+SOURCES = ["kernels.hip", "ttm_bf16.hip", "ttm_x3.hip", "capi.hip", "mlp.hip", "batch.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

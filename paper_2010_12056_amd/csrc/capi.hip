@@ -143,6 +143,7 @@ namespace {
 bool lowp(cp_prec q) { return q == CP_BF16 || q == CP_BF16X2 || q == CP_FP8 || q == CP_FP8X2; }
 bool split_factor(cp_prec q) { return q == CP_BF16X2 || q == CP_FP8X2; }
 bool fp8(cp_prec q) { return q == CP_FP8 || q == CP_FP8X2; }
+bool f32_tensor(cp_prec q) { return q == CP_F32 || q == CP_F32X3; }
 
 // The first contraction of a low-precision tensor X (P x K x Q) with the
 // FP32 factor shadow A (K x R) into FP32 C.
@@ -230,7 +231,7 @@ int64_t combined_k(cp_plan p) {
 // Khatri-Rao product of A^(0) and A^(1).  FP32 plans (the long-K kernel of
 // that layout is FP32).
 int64_t combined_k_right(cp_plan p) {
-  if (p->tree != CP_TREE_DT_COMBINED || p->N < 4 || p->prec != CP_F32) return 0;
+  if (p->tree != CP_TREE_DT_COMBINED || p->N < 4 || !f32_tensor(p->prec)) return 0;
   return p->dims[0] * p->dims[1];
 }
 
@@ -286,7 +287,7 @@ void plan_layout(cp_plan p) {
     // pair_parts: the largest split partials of launch_mttv_pair over the
     // (slice z, summed u, kept v) mode triples it can take
     size_t pp = 0;
-    if (p->prec == CP_F32 && N >= 4)
+    if (f32_tensor(p->prec) && N >= 4)
       for (int z = 0; z < N; ++z)
         for (int u = 0; u < N; ++u)
           for (int v = 0; v < N; ++v)
@@ -295,7 +296,8 @@ void plan_layout(cp_plan p) {
     take(pp);
   }
   const int64_t kb = std::max(smax, kc);
-  take(bf ? (size_t)R * bf16_factor_pitch(kb) * 2 : 0);                                 // Bt_hi
+  take(bf ? (size_t)R * bf16_factor_pitch(kb) * 2
+          : p->prec == CP_F32X3 ? (size_t)3 * R * bf16_factor_pitch(smax) * 2 : 0);   // Bt_hi (all three parts for X3)
   take(split_factor(p->prec) ? (size_t)R * bf16_factor_pitch(kb) * 2 : 0);              // Bt_lo
   // slots for depths 1..N-2 (depth d keeps N - d modes)
   std::vector<int64_t> sorted(p->dims, p->dims + N);
@@ -408,6 +410,9 @@ cp_status contract(cp_plan p, const void* in, uint32_t in_set, int c, void* out,
     ProfScope ps(p, CP_PHASE_TTM);
     if (lowp(p->prec)) {
       HIP_TRY(p, lowp_first_level(p, in, (const float*)A, (float*)out, P, I, Q));
+    } else if (p->prec == CP_F32X3 && ttm_x3_fits(P, I, Q, p->R, in)) {
+      HIP_TRY(p, launch_split3_factor((const float*)A, I, p->R, p->Bt_hi, p->st));
+      HIP_TRY(p, launch_ttm_x3((const float*)in, p->Bt_hi, (float*)out, P, I, Q, p->R, p->st));
     } else {
       HIP_TRY(p, launch_ttm<TT>((const TT*)in, A, (TT*)out, P, I, Q, p->R, p->st));
     }
@@ -820,7 +825,7 @@ int pair_second(uint32_t set) { return lowest_bit(set & ~(1u << lowest_bit(set))
 // plans and the kernel's rank and size limits; *done tells whether it ran.
 cp_status pp_pair_fused(cp_plan p, uint32_t pset, uint32_t c1, uint32_t c2, const void* X, bool* done) {
   *done = false;
-  if (p->prec != CP_F32) return CP_OK;
+  if (!f32_tensor(p->prec)) return CP_OK;
   const int m1 = lowest_bit(pset & ~c1), m2 = lowest_bit(pset & ~c2);
   const int z = lowest_bit(pset & ~(1u << m1) & ~(1u << m2));
   if (m1 < 0 || m2 < 0 || z < 0 || m1 == m2) return CP_OK;
@@ -1116,7 +1121,7 @@ cp_status cp_plan_create(cp_plan* out, int order, const int64_t* dims, int rank,
   *out = nullptr;
   if (order < 3 || order > kMaxOrder) return CP_ERR_UNSUPPORTED;
   if (rank < 1 || rank > kMaxRank) return CP_ERR_UNSUPPORTED;
-  if (prec != CP_F64 && prec != CP_F32 && !lowp(prec)) return CP_ERR_UNSUPPORTED;
+  if (prec != CP_F64 && !f32_tensor(prec) && !lowp(prec)) return CP_ERR_UNSUPPORTED;
   if (tree != CP_TREE_DT && tree != CP_TREE_DT_COMBINED && tree != CP_TREE_MSDT) return CP_ERR_UNSUPPORTED;
   double numel = 1.0;
   for (int m = 0; m < order; ++m) {

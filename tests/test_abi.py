@@ -185,8 +185,14 @@ def test_low_precision_plans_share_the_factor_staging():
     pitch = (96 + 63) // 64 * 64  # the longest mode, padded to the 64-index chunk
     assert need[cpals.CP_BF16X2] - need[cpals.CP_BF16] >= 40 * pitch * 2 - 256  # regions 256-byte aligned
     assert need[cpals.CP_BF16] > need[cpals.CP_F32]
+    # the FP32 tensor with three-part BF16 products: its three factor parts
     h = ctypes.c_void_p()
-    assert L.cp_plan_create(ctypes.byref(h), 3, dims, 40, 6, cpals.CP_TREE_DT, None) == cpals.CP_ERR_UNSUPPORTED
+    assert L.cp_plan_create(ctypes.byref(h), 3, dims, 40, cpals.CP_F32X3, cpals.CP_TREE_DT, None) == cpals.CP_OK
+    n = ctypes.c_size_t()
+    assert L.cp_plan_workspace_size(h, ctypes.byref(n)) == cpals.CP_OK
+    assert n.value - need[cpals.CP_F32] >= 3 * 40 * pitch * 2 - 256
+    assert L.cp_plan_destroy(h) == cpals.CP_OK
+    assert L.cp_plan_create(ctypes.byref(h), 3, dims, 40, 7, cpals.CP_TREE_DT, None) == cpals.CP_ERR_UNSUPPORTED
 
 
 def test_static_mttkrp_argument_checks():

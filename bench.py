@@ -791,7 +791,7 @@ def batch_bench(args):
         "ms_per_step": round(ms_step, 4),
         "higher_is_better": True,
         "vs_baseline": None,
-        "dtype": "f32 (contractions), f64 (solve, Gram, residual)",
+        "dtype": "f32 (contractions as three-part BF16 products with FP32 sums), f64 (solve, Gram, residual)",
         "data": "synthetic",
         "config": {"workload": "512 independent order-3 dense FP32 tensors, modes iid U[16,96], R iid from "
                                "{4,8,16,32}, planted U[0,1) factors + 1e-3 noise, 30 sweeps, one persistent "

@@ -14,7 +14,8 @@
 //   M1[j][r] = sum_i Y[i][j][r] A0[i][r]      A1 <- M1 Gamma1^-1
 //   M2[k][r] = sum_j Z[j][k][r] A1[j][r]      A2 <- M2 Gamma2^-1
 // then the residual by Eq. (3).  Contractions with the tensor run on the
-// FP32 matrix cores (16x16x4), Y and Z are FP32 in a per-slot scratch, the
+// BF16 matrix cores as three-part products to about FP32 accuracy (below),
+// Y and Z are FP32 in a per-slot scratch, the
 // second level, the Gram matrices, Gamma, its inverse (Gauss-Jordan without
 // pivoting, SPD) and the update run in FP64 on factors held in LDS for all the
 // tensor's sweeps.  Every reduction has a fixed
@@ -35,7 +36,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kMaxS = 96;    // largest mode size
 constexpr int kMaxR = 32;    // largest rank
-constexpr int kKP = kMaxS + 4;  // staged factor pitch (floats): 16 lanes' rows fall in different banks
+constexpr int kKP = kMaxS + 8;  // staged factor pitch (BF16 elements): 16 lanes' 16-byte reads fall in different banks
 
 struct BatchTensor {
   int64_t t_off;     // first element of the tensor in the packed tensor array
@@ -68,7 +69,7 @@ struct Lds {
   double S[3][kMaxR * kMaxR];
   double G[kMaxR * (kMaxR + 1)];   // Gamma, then its inverse in place (RP x RP, pitch RP + 1)
   double M[kMaxS * kMaxR];
-  float Bt[kMaxR * kKP];            // FP32 factor transposed for the contraction, zero padded
+  uint16_t Bt[3][kMaxR * kKP];      // the factor's three BF16 parts, transposed, zero padded
   double red[512];
   int item;
   int fail;
@@ -88,61 +89,138 @@ __device__ inline double block_sum(Lds& L, double v) {
   return s;
 }
 
-// Stage factor m (s x R, FP64 in LDS) as Bt[c][k] (FP32), zero for k >= s or c >= R.
-template <int NT, int RP>
-__device__ __forceinline__ void stage_factor(Lds& L, int m, int s, int R) {
-  const int KP = (s + 15) & ~15;
-  for (int e = threadIdx.x; e < RP * KP; e += NT) {
-    const int c = e / KP, k = e - c * KP;
-    L.Bt[c * kKP + k] = (k < s && c < R) ? (float)L.F[m][k * R + c] : 0.f;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ inline bf16x8 as_bf16x8(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
+
+// x rounded to BF16 (nearest, ties to even), as the FP32 bit pattern.
+__device__ __forceinline__ uint32_t rne16(float x) {
+  const uint32_t u = __float_as_uint(x);
+  return (u + 0x7fffu + ((u >> 16) & 1u)) & 0xffff0000u;
+}
+
+// The three BF16 parts (bit patterns) of x: x == x1 + x2 + x3 exactly, each
+// rounded to nearest (x2 = bf16(x - x1), x3 = x - x1 - x2; both differences
+// exact, the last one has at most 8 significant bits).
+__device__ __forceinline__ void split3(float x, uint32_t& h1, uint32_t& h2, uint32_t& h3) {
+  const uint32_t u1 = rne16(x);
+  const float r1 = x - __uint_as_float(u1);
+  const uint32_t u2 = rne16(r1);
+  const float r2 = r1 - __uint_as_float(u2);
+  h1 = u1 >> 16;
+  h2 = u2 >> 16;
+  h3 = __float_as_uint(r2) >> 16;
+}
+
+// Eight values as the three BF16 part vectors of one MFMA operand.
+__device__ __forceinline__ void split8(const float (&x)[8], u32x4& a1, u32x4& a2, u32x4& a3) {
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    uint32_t h1a, h2a, h3a, h1b, h2b, h3b;
+    split3(x[2 * w], h1a, h2a, h3a);
+    split3(x[2 * w + 1], h1b, h2b, h3b);
+    a1[w] = h1a | (h1b << 16);
+    a2[w] = h2a | (h2b << 16);
+    a3[w] = h3a | (h3b << 16);
   }
 }
 
-// C[p][r] = sum_k X[p][k] B[k][r] (X is P x K row-major): 16-row tiles per wave.
-// NB = ceil(K / 16) is a template parameter so that every loop over the
-// contraction is unrolled (the staged factor is zero up to 16 NB).  Lane
-// (i, g) feeds k = 16 t + 4 g + u at MFMA step (t, u) (one 16-byte load when
-// the row is 16-byte aligned, VEC: K % 4 == 0); its factor operands are the
-// same for every tile and stay in registers.  Every load is unconditional:
-// rows past P read row P - 1 (never stored) and indices past K read index
-// K - 1 (or K - 4), which the factor's zero padding cancels.  The next tile's
+// acc += (a1 + a2 + a3) (b1 + b2 + b3) without the three products below
+// 2^-23 of it (a2 b3, a3 b2, a3 b3); small products first.
+__device__ __forceinline__ f32x4 mfma_x3(const u32x4& a1, const u32x4& a2, const u32x4& a3, const uint16_t* bp,
+                                         f32x4 acc) {
+  const bf16x8 b1 = as_bf16x8(*(const u32x4*)bp);
+  const bf16x8 b2 = as_bf16x8(*(const u32x4*)(bp + kMaxR * kKP));
+  const bf16x8 b3 = as_bf16x8(*(const u32x4*)(bp + 2 * kMaxR * kKP));
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(a2), b2, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(a3), b1, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(a1), b3, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(a2), b1, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(a1), b2, acc, 0, 0, 0);
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(a1), b1, acc, 0, 0, 0);
+}
+
+// Stage factor m (s x R, FP64 in LDS) as Bt[part][c][k]: the three BF16
+// parts of its FP32 rounding, zero for k >= s or c >= R, up to the next
+// multiple of 32 in k.
+template <int NT, int RP>
+__device__ __forceinline__ void stage_factor(Lds& L, int m, int s, int R) {
+  const int KP = (s + 31) & ~31;
+  for (int e = threadIdx.x; e < RP * KP; e += NT) {
+    const int c = e / KP, k = e - c * KP;
+    uint32_t h1 = 0, h2 = 0, h3 = 0;
+    if (k < s && c < R) split3((float)L.F[m][k * R + c], h1, h2, h3);
+    L.Bt[0][c * kKP + k] = (uint16_t)h1;
+    L.Bt[1][c * kKP + k] = (uint16_t)h2;
+    L.Bt[2][c * kKP + k] = (uint16_t)h3;
+  }
+}
+
+// The contractions with the tensor run on the BF16 matrix cores
+// (v_mfma_f32_16x16x32_bf16): tensor values and factor entries split into
+// three BF16 parts each (split3), six part products per pair accumulated in
+// FP32 (mfma_x3), an FP32 contraction to about one FP32 rounding per
+// product.  Operand layout: lane (i = lane % 16, g = lane / 16) supplies row
+// i of A and column i of B with the eight indices 32 t + 8 g .. + 7 of step
+// t; register v of lane (i, g) holds C[4 g + v][i].
+
+// C[p][r] = sum_k X[p][k] B[k][r] (X is P x K row-major): 16-row tiles per
+// wave.  nb = ceil(K / 32) <= 3 steps: every loop over them is unrolled to
+// three with uniform guards (one instance for every K, so that the
+// instances do not add up in the register allocation of the persistent
+// kernel; the staged factor is zero up to 32 nb).  Lane
+// (i, g) loads row i of the tile, indices 32 t + 8 g .. + 7 (two 16-byte
+// loads when VEC: K % 4 == 0 and 16-byte aligned rows; a half past K reads
+// a clamped, whole in-row half, cancelled by the zero padding; otherwise
+// element by element, indices past K clamped).  Every load is
+// unconditional: rows past P read row P - 1 (never stored).  The next tile's
 // rows are in flight while a tile is multiplied (past the last tile it
 // reloads the last, unused), and a scheduling barrier keeps those loads
 // ahead of the products.
-template <int NT, int RP, int NB, bool VEC>
+template <int NT, int RP, bool VEC>
 __device__ __forceinline__ void ttm_rows(Lds& L, const float* X, int64_t P, int K, int R, float* C) {
   constexpr int NCB = RP / 16;
+  constexpr int NB = 3;
+  const int nb = (K + 31) / 32;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, l16 = lane & 15;
   const int64_t ntiles = (P + 15) / 16;
-  auto load_tile = [&](int64_t tile, f32x4 (&a)[NB]) {
+  // 32-bit byte offsets from X (a tensor here is at most 96^3 values)
+  auto load_tile = [&](int64_t tile, float (&a)[NB][8]) {
     const int64_t p0 = tile * 16;
-    const int64_t row = (p0 + l16 < P) ? p0 + l16 : P - 1;
-    const float* xr = X + row * K;
+    const uint32_t row = (uint32_t)((p0 + l16 < P) ? p0 + l16 : P - 1);
+    const uint32_t rb = row * (uint32_t)K * 4u;
+    const char* xb = (const char*)X;
 #pragma unroll
     for (int t = 0; t < NB; ++t) {
-      const int k0 = 16 * t + 4 * g;
+      if (t >= nb) break;
+      const int k0 = 32 * t + 8 * g;
       if (VEC) {
-        a[t] = *(const f32x4*)(xr + (k0 + 4 <= K ? k0 : K - 4));
+        const f32x4 v0 = *(const f32x4*)(xb + (rb + 4u * (uint32_t)(k0 + 4 <= K ? k0 : K - 4)));
+        const f32x4 v1 = *(const f32x4*)(xb + (rb + 4u * (uint32_t)(k0 + 8 <= K ? k0 + 4 : K - 4)));
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          a[t][u] = v0[u];
+          a[t][4 + u] = v1[u];
+        }
       } else {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) a[t][u] = xr[k0 + u < K ? k0 + u : K - 1];
+        for (int u = 0; u < 8; ++u)
+          a[t][u] = *(const float*)(xb + (rb + 4u * (uint32_t)(k0 + u < K ? k0 + u : K - 1)));
       }
     }
   };
   constexpr int NW = NT / 64;
   if (wave >= ntiles) return;
-  f32x4 b[NB][NCB];
-#pragma unroll
-  for (int t = 0; t < NB; ++t)
-#pragma unroll
-    for (int cb = 0; cb < NCB; ++cb) b[t][cb] = *(const f32x4*)&L.Bt[(cb * 16 + l16) * kKP + 16 * t + 4 * g];
-  f32x4 an[NB];
+  float an[NB][8];
   load_tile(wave, an);
   for (int64_t tile = wave; tile < ntiles; tile += NW) {
-    f32x4 a[NB];
+    asm volatile("" ::: "memory");  // the factor's LDS reads stay in the loop (not hoisted into registers)
+    u32x4 a1[NB], a2[NB], a3[NB];
 #pragma unroll
-    for (int t = 0; t < NB; ++t) a[t] = an[t];
+    for (int t = 0; t < NB; ++t)
+      if (t < nb) split8(an[t], a1[t], a2[t], a3[t]);
     load_tile(tile + NW < ntiles ? tile + NW : tile, an);
     __builtin_amdgcn_sched_barrier(0);
     const int64_t p0 = tile * 16;
@@ -150,12 +228,12 @@ __device__ __forceinline__ void ttm_rows(Lds& L, const float* X, int64_t P, int 
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) acc[cb] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int t = 0; t < NB; ++t)
+    for (int t = 0; t < NB; ++t) {
+      if (t >= nb) break;
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int cb = 0; cb < NCB; ++cb)
-          acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t][u], b[t][cb][u], acc[cb], 0, 0, 0);
+      for (int cb = 0; cb < NCB; ++cb)
+        acc[cb] = mfma_x3(a1[t], a2[t], a3[t], &L.Bt[0][(cb * 16 + l16) * kKP + 32 * t + 8 * g], acc[cb]);
+    }
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
@@ -168,35 +246,43 @@ __device__ __forceinline__ void ttm_rows(Lds& L, const float* X, int64_t P, int 
 }
 
 // C[q][r] = sum_k X[k][q] B[k][r] (X is K x Q, q contiguous): 16-row tiles of
-// q per wave; lane (i, g) feeds X[4 t + g][q0 + i] (16 lanes read 64
-// contiguous bytes), NB = ceil(K / 16) as in ttm_rows, the factor operands
-// read from LDS at each step, unconditional clamped loads (q past Q read column Q - 1, never
-// stored; k past K read row K - 1, cancelled by the factor's zero padding),
-// the next tile in flight while a tile is multiplied.
-template <int NT, int RP, int NB>
+// q per wave; lane (i, g) loads X[32 t + 8 g + j][q0 + i] for its eight j
+// (16 lanes on 64 contiguous bytes; q past Q reads column Q - 1, never
+// stored; k past K reads row K - 1, cancelled by the zero padding), nb as in
+// ttm_rows, the next tile in flight while a tile is multiplied.
+template <int NT, int RP>
 __device__ __forceinline__ void ttm_cols(Lds& L, const float* X, int K, int64_t Q, int R, float* C) {
   constexpr int NCB = RP / 16;
-  constexpr int NKS = 4 * NB;  // 4-index steps
+  constexpr int NB = 3;
+  const int nb = (K + 31) / 32;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int g = lane >> 4, l16 = lane & 15;
   const int64_t ntiles = (Q + 15) / 16;
-  auto load_tile = [&](int64_t tile, float (&a)[NKS]) {
-    const int64_t q = tile * 16 + l16 < Q ? tile * 16 + l16 : Q - 1;
-    const float* xq = X + q;
+  // 32-bit byte offsets from X (a tensor here is at most 96^3 values)
+  auto load_tile = [&](int64_t tile, float (&a)[NB][8]) {
+    const uint32_t qb = 4u * (uint32_t)(tile * 16 + l16 < Q ? tile * 16 + l16 : Q - 1);
+    const uint32_t Qb = 4u * (uint32_t)Q;
+    const char* xb = (const char*)X;
 #pragma unroll
-    for (int t = 0; t < NKS; ++t) {
-      const int k = 4 * t + g;
-      a[t] = xq[(int64_t)(k < K ? k : K - 1) * Q];
+    for (int t = 0; t < NB; ++t) {
+      if (t >= nb) break;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int k = 32 * t + 8 * g + u;
+        a[t][u] = *(const float*)(xb + (qb + (uint32_t)(k < K ? k : K - 1) * Qb));
+      }
     }
   };
   constexpr int NW = NT / 64;
   if (wave >= ntiles) return;
-  float an[NKS];
+  float an[NB][8];
   load_tile(wave, an);
   for (int64_t tile = wave; tile < ntiles; tile += NW) {
-    float a[NKS];
+    asm volatile("" ::: "memory");  // the factor's LDS reads stay in the loop (not hoisted into registers)
+    u32x4 a1[NB], a2[NB], a3[NB];
 #pragma unroll
-    for (int t = 0; t < NKS; ++t) a[t] = an[t];
+    for (int t = 0; t < NB; ++t)
+      if (t < nb) split8(an[t], a1[t], a2[t], a3[t]);
     load_tile(tile + NW < ntiles ? tile + NW : tile, an);
     __builtin_amdgcn_sched_barrier(0);
     const int64_t q0 = tile * 16;
@@ -204,10 +290,12 @@ __device__ __forceinline__ void ttm_cols(Lds& L, const float* X, int K, int64_t 
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) acc[cb] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int t = 0; t < NKS; ++t)
+    for (int t = 0; t < NB; ++t) {
+      if (t >= nb) break;
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb)
-        acc[cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t], L.Bt[(cb * 16 + l16) * kKP + 4 * t + g], acc[cb], 0, 0, 0);
+        acc[cb] = mfma_x3(a1[t], a2[t], a3[t], &L.Bt[0][(cb * 16 + l16) * kKP + 32 * t + 8 * g], acc[cb]);
+    }
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
@@ -219,37 +307,18 @@ __device__ __forceinline__ void ttm_cols(Lds& L, const float* X, int K, int64_t 
   }
 }
 
-// The contractions for K <= kMaxS, with the block count as a compile-time constant.
-template <int NT, int RP, bool VEC>
-__device__ __forceinline__ void ttm_rows_kv(Lds& L, const float* X, int64_t P, int K, int R, float* C) {
-  switch ((K + 15) / 16) {
-    case 1: ttm_rows<NT, RP, 1, VEC>(L, X, P, K, R, C); break;
-    case 2: ttm_rows<NT, RP, 2, VEC>(L, X, P, K, R, C); break;
-    case 3: ttm_rows<NT, RP, 3, VEC>(L, X, P, K, R, C); break;
-    case 4: ttm_rows<NT, RP, 4, VEC>(L, X, P, K, R, C); break;
-    case 5: ttm_rows<NT, RP, 5, VEC>(L, X, P, K, R, C); break;
-    default: ttm_rows<NT, RP, 6, VEC>(L, X, P, K, R, C); break;
-  }
-}
 template <int NT, int RP>
 __device__ __forceinline__ void ttm_rows_k(Lds& L, const float* X, int64_t P, int K, int R, float* C) {
   if (K % 4 == 0 && ((uintptr_t)X & 15) == 0)
-    ttm_rows_kv<NT, RP, true>(L, X, P, K, R, C);
+    ttm_rows<NT, RP, true>(L, X, P, K, R, C);
   else
-    ttm_rows_kv<NT, RP, false>(L, X, P, K, R, C);
+    ttm_rows<NT, RP, false>(L, X, P, K, R, C);
 }
 template <int NT, int RP>
 __device__ __forceinline__ void ttm_cols_k(Lds& L, const float* X, int K, int64_t Q, int R, float* C) {
-  switch ((K + 15) / 16) {
-    case 1: ttm_cols<NT, RP, 1>(L, X, K, Q, R, C); break;
-    case 2: ttm_cols<NT, RP, 2>(L, X, K, Q, R, C); break;
-    case 3: ttm_cols<NT, RP, 3>(L, X, K, Q, R, C); break;
-    case 4: ttm_cols<NT, RP, 4>(L, X, K, Q, R, C); break;
-    case 5: ttm_cols<NT, RP, 5>(L, X, K, Q, R, C); break;
-    default: ttm_cols<NT, RP, 6>(L, X, K, Q, R, C); break;
-  }
+  ttm_cols<NT, RP>(L, X, K, Q, R, C);
 }
-static_assert(kMaxS <= 6 * 16, "contraction block dispatch covers kMaxS");
+static_assert(kMaxS <= 3 * 32, "three 32-index steps cover kMaxS");
 
 // Gamma = S[a] * S[b] (Hadamard), padded to RP x RP with the identity and
 // inverted in place by the blocked Gauss-Jordan elimination without pivoting
@@ -352,7 +421,8 @@ __device__ __forceinline__ void second_level(Lds& L, const float* Y, int n, int 
 
 template <int NT, int RP>
 __device__ __forceinline__ void run_tensor(Lds& L, const BatchArgs& a, const BatchTensor& t, int idx, float* scratch) {
-  const int s0 = t.s[0], s1 = t.s[1], s2 = t.s[2], R = t.R;
+  const int s0c = t.s[0], s1c = t.s[1], s2c = t.s[2], Rc = t.R;
+  const int s0 = s0c, s1 = s1c, s2 = s2c, R = Rc;
   const int sz[3] = {s0, s1, s2};
   const float* T = a.T + t.t_off;
   const int64_t numel = (int64_t)s0 * s1 * s2;
@@ -392,6 +462,11 @@ __device__ __forceinline__ void run_tensor(Lds& L, const BatchArgs& a, const Bat
   __syncthreads();
   float* Y = scratch;
   for (int sw = 0; sw < a.sweeps; ++sw) {
+    // the sizes pass through an empty asm statement each sweep, so that the
+    // phases' per-thread index arithmetic is not hoisted out of the sweep
+    // loop (it would stay live, in registers, across every other phase)
+    int s0 = s0c, s1 = s1c, s2 = s2c, R = Rc;
+    asm volatile("" : "+s"(s0), "+s"(s1), "+s"(s2), "+s"(R));
     // Y = T x_2 A2 over rows (i, j)
     stage_factor<NT, RP>(L, 2, s2, R);
     __syncthreads();
@@ -438,7 +513,7 @@ __global__ __launch_bounds__(NT) void k_batch(BatchArgs a) {
   for (;;) {
     if (threadIdx.x == 0) L.item = atomicAdd(a.counter, 1);
     __syncthreads();
-    const int q = L.item;
+    const int q = __builtin_amdgcn_readfirstlane(L.item);  // uniform: the tensor record loads into scalar registers
     __syncthreads();
     if (q >= a.count) break;  // uniform: every workgroup leaves once the queue is empty
     const BatchTensor t = a.items[q];

@@ -42,25 +42,32 @@ def _run(dev, ws, sweeps, waves=4, groups=2, A_init=None):
 
 
 def _fit_tol(r):
-    # The contractions with the tensor run in FP32 (the factor is rounded to
-    # FP32 for them: relative error ~6e-8 per entry), so <M, A> in Eq. (3)
-    # carries a relative error e of a few 1e-8; Eq. (3) subtracts terms of
-    # size ||T||^2, so r moves by about e / r.  A planted tensor that has
-    # converged to its 1e-3 noise level (r ~ 1e-3) therefore shows ~5e-5.
-    return 1e-6 + 2e-7 / max(r, 1e-12)
+    # The contractions with the tensor carry a relative error e of about one
+    # FP32 rounding per product (three-part BF16 products, FP32 sums), so
+    # <M, A> in Eq. (3) is off by a few 1e-8 of ||T||^2; Eq. (3) subtracts
+    # terms of size ||T||^2, so r moves by about e / r.  Measured on these
+    # cases: |df| r <= 6.7e-8.
+    return 1e-7 + 1e-7 / max(r, 1e-12)
 
 
 def _oracle_check(ws, b, A, fit, sweeps, fac_tol):
     import oracle
 
+    worst, worst_r, worst_fac = 0.0, 0.0, 0.0
     for i, w in enumerate(ws):
         st = oracle.AlsState.start(w.T.astype(np.float64), w.init)
         for s in range(sweeps):
             r = oracle.als_sweep(st)
-            assert abs(fit[i, s] - (1.0 - r)) <= _fit_tol(r), (i, w.dims, w.R, s, fit[i, s], 1.0 - r)
+            d = abs(fit[i, s] - (1.0 - r))
+            assert d <= _fit_tol(r), (i, w.dims, w.R, s, fit[i, s], 1.0 - r)
+            worst = max(worst, d / _fit_tol(r))
+            worst_r = max(worst_r, d * r)
         got = [a.cpu().numpy() for a in b.unpack_factors(A, i)]
         for m in range(3):
-            assert relerr(got[m], st.A[m]) <= fac_tol, (i, w.dims, w.R, m)
+            e = relerr(got[m], st.A[m])
+            assert e <= fac_tol, (i, w.dims, w.R, m)
+            worst_fac = max(worst_fac, e)
+    say(f"  fitness error / tolerance <= {worst:.3g}, |df| r <= {worst_r:.3g}, factor relerr <= {worst_fac:.3g}")
 
 
 def test_batch_edge_shapes_match_oracle(dev):

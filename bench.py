@@ -430,6 +430,15 @@ def tree_bench(args):
         log(f"[bench] dt_combined {methods['dt_combined']}")
     # the FP32 tensor with the first contraction as three-part BF16 products
     if prec == "f32":
+        if N >= 4:
+            xms, xfit = side_plan("f32x3", "dt_combined")
+            methods["dt_combined_f32x3"] = {
+                "sweeps": 3, "ms_per_sweep": round(xms, 4),
+                "effective_tflops": round(F_dt / (xms * 1e-3) / 1e12, 3),
+                "speedup_vs_dt_per_sweep": round(methods["dt"]["ms_per_sweep"] / xms, 3),
+                "fitness_3_sweeps": xfit, "dt_fitness_3_sweeps": fit["dt"][2],
+                "timed": "separately, not part of the step"}
+            log(f"[bench] dt_combined_f32x3 {methods['dt_combined_f32x3']}")
         for tree_v in ("dt", "msdt"):
             xms, xfit = side_plan("f32x3", tree_v)
             methods[f"{tree_v}_f32x3"] = {

@@ -70,9 +70,9 @@ typedef enum {
  * into three BF16 parts (each rounded to nearest) and the six leading part
  * products are accumulated in FP32 (the three dropped ones are below 2^-23
  * of the product), so each product carries an error of the order of one FP32
- * rounding; contraction lengths above 128 (or, contracting the last mode,
- * rows not 16-byte aligned or K not a multiple of 8) take the FP32 matrix
- * cores instead. */
+ * rounding; contracting the last mode with rows not 16-byte aligned or K
+ * not a multiple of 8, or another mode of a tensor of 4 GiB or more, takes
+ * the FP32 matrix cores instead. */
 typedef enum { CP_F64 = 0, CP_F32 = 1, CP_BF16 = 2, CP_BF16X2 = 3, CP_FP8 = 4, CP_FP8X2 = 5, CP_F32X3 = 6 } cp_prec;
 
 typedef enum {

@@ -279,8 +279,12 @@ void plan_layout(cp_plan p) {
     for (int m = 2; m < N; ++m) Q *= p->dims[m];
     p->split_z = (kc > 0 && !lowp(p->prec)) ? ttm_split_layers(P, kc, 1, R, (int)p->esz) : 1;
     p->split_zr = kcr > 0 ? ttm_split_layers(1, kcr, Q, R, (int)p->esz) : 1;
-    const size_t pl = p->split_z > 1 ? (size_t)p->split_z * P : 0;
-    const size_t pr = p->split_zr > 1 ? (size_t)p->split_zr * Q : 0;
+    size_t pl = p->split_z > 1 ? (size_t)p->split_z * P : 0;
+    size_t pr = p->split_zr > 1 ? (size_t)p->split_zr * Q : 0;
+    if (p->prec == CP_F32X3) {  // the three-part contractions' own split over K
+      if (kc > 0) pl = std::max(pl, (size_t)ttm_x3_layers(P, kc, 1, R) * P);
+      if (kcr > 0) pr = std::max(pr, (size_t)ttm_x3_layers(1, kcr, Q, R) * Q);
+    }
     take(std::max(pl, pr) * R * p->esz);  // parts
   }
   {
@@ -296,8 +300,9 @@ void plan_layout(cp_plan p) {
     take(pp);
   }
   const int64_t kb = std::max(smax, kc);
+  const int64_t kx = std::max(kb, kcr);
   take(bf ? (size_t)R * bf16_factor_pitch(kb) * 2
-          : p->prec == CP_F32X3 ? (size_t)3 * R * bf16_factor_pitch(smax) * 2 : 0);   // Bt_hi (all three parts for X3)
+          : p->prec == CP_F32X3 ? (size_t)3 * R * bf16_factor_pitch(kx) * 2 : 0);   // Bt_hi (all three parts for X3)
   take(split_factor(p->prec) ? (size_t)R * bf16_factor_pitch(kb) * 2 : 0);              // Bt_lo
   // slots for depths 1..N-2 (depth d keeps N - d modes)
   std::vector<int64_t> sorted(p->dims, p->dims + N);
@@ -412,7 +417,7 @@ cp_status contract(cp_plan p, const void* in, uint32_t in_set, int c, void* out,
       HIP_TRY(p, lowp_first_level(p, in, (const float*)A, (float*)out, P, I, Q));
     } else if (p->prec == CP_F32X3 && ttm_x3_fits(P, I, Q, p->R, in)) {
       HIP_TRY(p, launch_split3_factor((const float*)A, I, p->R, p->Bt_hi, p->st));
-      HIP_TRY(p, launch_ttm_x3((const float*)in, p->Bt_hi, (float*)out, P, I, Q, p->R, p->st));
+      HIP_TRY(p, launch_ttm_x3((const float*)in, p->Bt_hi, (float*)out, P, I, Q, p->R, nullptr, p->st));
     } else {
       HIP_TRY(p, launch_ttm<TT>((const TT*)in, A, (TT*)out, P, I, Q, p->R, p->st));
     }
@@ -447,6 +452,11 @@ cp_status contract_combined(cp_plan p, int side, void* out) {
     const int64_t K = combined_k_right(p);
     HIP_TRY(p, launch_krp2<TT>((const TT*)p->Ash[0], p->dims[0], (const TT*)p->Ash[1], p->dims[1], p->R,
                                (TT*)p->krp, p->st));
+    if (p->prec == CP_F32X3 && ttm_x3_fits(1, K, Q, p->R, p->T)) {
+      HIP_TRY(p, launch_split3_factor((const float*)p->krp, K, p->R, p->Bt_hi, p->st));
+      HIP_TRY(p, launch_ttm_x3((const float*)p->T, p->Bt_hi, (float*)out, 1, K, Q, p->R, (float*)p->parts, p->st));
+      return CP_OK;
+    }
     HIP_TRY(p, launch_ttm_split<TT>((const TT*)p->T, (const TT*)p->krp, (TT*)out, 1, K, Q, p->R, (TT*)p->parts,
                                     p->split_zr, p->st));
     return CP_OK;
@@ -458,6 +468,9 @@ cp_status contract_combined(cp_plan p, int side, void* out) {
                              p->R, (TT*)p->krp, p->st));
   if (lowp(p->prec)) {
     HIP_TRY(p, lowp_first_level(p, p->T, (const float*)p->krp, (float*)out, P, K, 1));
+  } else if (p->prec == CP_F32X3 && ttm_x3_fits(P, K, 1, p->R, p->T)) {
+    HIP_TRY(p, launch_split3_factor((const float*)p->krp, K, p->R, p->Bt_hi, p->st));
+    HIP_TRY(p, launch_ttm_x3((const float*)p->T, p->Bt_hi, (float*)out, P, K, 1, p->R, (float*)p->parts, p->st));
   } else {
     HIP_TRY(p, launch_ttm_split<TT>((const TT*)p->T, (const TT*)p->krp, (TT*)out, P, K, 1, p->R, (TT*)p->parts,
                                     p->split_z, p->st));

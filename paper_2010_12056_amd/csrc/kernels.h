@@ -56,13 +56,16 @@ hipError_t launch_ttm_fp8(const uint8_t* X, const uint16_t* Bhi, const uint16_t*
 // FP32 tensor path on the BF16 matrix cores (CP_F32X3): the factor split
 // into three BF16 parts, Bt[part][c][k] with pitch bf16_factor_pitch(K)
 // (3 R pitch elements), then C = X times the factor with the six leading part
-// products accumulated in FP32.  For K <= kX3MaxK; KC (Q == 1) also needs
-// K % 8 == 0 and 16-byte aligned rows (ttm_x3_fits).
-constexpr int kX3MaxK = 128;
+// products accumulated in FP32.  KC (Q == 1) needs K % 8 == 0 and 16-byte
+// aligned rows, the other layout a tensor below 4 GiB (ttm_x3_fits).  With
+// `parts` (ttm_x3_layers(P, K, Q, R) P Q R floats) a contraction with too few
+// row tiles to fill the chip is split over K, its partials added in order;
+// null: no split.
 bool ttm_x3_fits(int64_t P, int64_t K, int64_t Q, int R, const void* X);
+int ttm_x3_layers(int64_t P, int64_t K, int64_t Q, int R);
 hipError_t launch_split3_factor(const float* A, int64_t K, int R, uint16_t* Bt, hipStream_t st);
 hipError_t launch_ttm_x3(const float* X, const uint16_t* Bt, float* C, int64_t P, int64_t K, int64_t Q, int R,
-                         hipStream_t st);
+                         float* parts, hipStream_t st);
 
 // Y[p][q][r] = sum_i X[p][i][q][r] * A[i][r]; accumulation in the output type.
 template <typename TI, typename TO>

@@ -96,6 +96,7 @@ __device__ inline bf16x8 as_bf16x8(u32x4 v) { return __builtin_bit_cast(bf16x8, 
 template <typename E>
 struct LaneSrc {
   const E* p[4];
+  uint32_t o;  // BF16 q-contiguous unguarded: the lane's q offset from the slice base p[0]
 };
 
 // Two E4M3 values (word half `hi` of w) as two BF16 values, exactly.
@@ -129,6 +130,13 @@ __global__ __launch_bounds__(512) void k_ttm_bf16(const void* __restrict__ Xv, c
   constexpr int NPART = SPLIT ? 2 : 1;
   constexpr int BITEMS = NPART * NC * (KB / 8);  // 16-byte pieces of one factor chunk
   constexpr int BPER = (BITEMS + kThreads - 1) / kThreads;
+  // BF16 q-contiguous unguarded: 32-bit offsets from uniform bases for the
+  // tensor and factor loads (the launch checks (K + 80) Q < 2^31 and
+  // R Kp < 2^31); 64-bit per-lane addresses cost the 128-column split-factor
+  // form its registers.  A factor piece's part is uniform when one part's
+  // pieces fill whole multiples of the workgroup.
+  constexpr bool O32 = FAST && !KC && !F8;
+  constexpr bool BUNI = O32 && (NC * (KB / 8)) % kThreads == 0;
   __shared__ __align__(16) uint16_t Bs[2][NPART * NC * KPITCH];  // [buffer][part][column][index]
   // FP8 q-contiguous with TR: the workgroup's chunk of the tensor, [buffer][index][q]
   __shared__ __align__(16) uint8_t Ts[TR ? 2 * KB * TPITCH : 16];
@@ -154,7 +162,12 @@ __global__ __launch_bounds__(512) void k_ttm_bf16(const void* __restrict__ Xv, c
       int part, c, j;
       b_piece(q, part, c, j);
       const int col = c0 + c < R ? c0 + c : R - 1;
-      bv[q] = *(const u32x4*)((part ? Blo : Bhi) + (int64_t)col * Kp + ch * KB + 8 * j);
+      if constexpr (BUNI) {
+        const char* base = (const char*)((q * kThreads) / (NC * (KB / 8)) ? Blo : Bhi);
+        bv[q] = *(const u32x4*)(base + 2u * ((uint32_t)col * (uint32_t)Kp + (uint32_t)(ch * KB + 8 * j)));
+      } else {
+        bv[q] = *(const u32x4*)((part ? Blo : Bhi) + (int64_t)col * Kp + ch * KB + 8 * j);
+      }
     }
   };
   auto store_b = [&](int buf, const u32x4 (&bv)[BPER]) {
@@ -182,7 +195,7 @@ __global__ __launch_bounds__(512) void k_ttm_bf16(const void* __restrict__ Xv, c
     }
   };
   auto lane_src = [&](int64_t tile) {
-    Src s;
+    Src s{};
     int64_t row0, nrows;
     const E* Xb;
     float* Cb;
@@ -199,8 +212,8 @@ __global__ __launch_bounds__(512) void k_ttm_bf16(const void* __restrict__ Xv, c
       s.p[1] = s.p[2] = s.p[3] = s.p[0];
     } else {
       const int64_t qp = row0 + 8 * (l16 >> 1);
-      s.p[0] = Xb + (int64_t)(8 * g + 4 * (l16 & 1)) * Q + (qp < Q - 8 ? qp : Q - 8);
-      s.p[1] = s.p[2] = s.p[3] = s.p[0];
+      s.p[0] = s.p[1] = s.p[2] = s.p[3] = Xb;  // uniform: the loads' scalar base
+      s.o = (uint32_t)(qp < Q - 8 ? qp : Q - 8);
     }
     return s;
   };
@@ -223,11 +236,14 @@ __global__ __launch_bounds__(512) void k_ttm_bf16(const void* __restrict__ Xv, c
 #pragma unroll
         for (int u = 0; u < 4; ++u) r[u] = *(const u32x4*)(s.p[u] + kc);
       } else {
-        const int kb = 8 * g + 4 * (l16 & 1);
+        // element offset min(kb + ks + j, K - 1) Q + the lane's q
+        const uint32_t qq = (uint32_t)Q, last = (uint32_t)(K - 1) * qq;
+        const uint32_t kbq = (uint32_t)(8 * g + 4 * (l16 & 1)) * qq;
+        const char* base = (const char*)s.p[0];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const int64_t k = kb + ks + j < K ? kb + ks + j : K - 1;
-          r[j] = *(const u32x4*)(s.p[0] + (k - kb) * Q);
+          const uint32_t kq = kbq + (uint32_t)(ks + j) * qq;
+          r[j] = *(const u32x4*)(base + 2u * ((kq < last ? kq : last) + s.o));
         }
       }
       return;
@@ -583,6 +599,7 @@ __global__ __launch_bounds__(512) void k_ttm_bf16(const void* __restrict__ Xv, c
         Src sn;
 #pragma unroll
         for (int u = 0; u < 4; ++u) sn.p[u] = more ? cur.p[u] : nxt.p[u];
+        sn.o = more ? cur.o : nxt.o;
         issue(sn, more ? tile : tn, more ? (ch + 1) * KB : 0, ra);
       }
       __builtin_amdgcn_sched_barrier(0);
@@ -638,7 +655,9 @@ hipError_t launch_ncb(const void* X, const uint16_t* Bhi, const uint16_t* Blo, f
     fast = KC ? (K % 16 == 0 && a % 16 == 0) : (Q % 4 == 0 && a % 4 == 0);
   } else {
     // KC: 16-byte row loads; otherwise 2 = 16-byte loads shared by lane pairs, 1 = 8-byte loads
-    vec = KC ? (K % 8 == 0 && a % 16 == 0) : ((Q % 8 == 0 && a % 16 == 0) ? 2 : (Q % 4 == 0 && a % 8 == 0));
+    // (2 also needs the 32-bit offsets of its tensor and factor loads to fit)
+    const bool off32 = (K + 80) * Q < ((int64_t)1 << 31) && (int64_t)R * Kp < ((int64_t)1 << 31);
+    vec = KC ? (K % 8 == 0 && a % 16 == 0) : ((Q % 8 == 0 && a % 16 == 0 && off32) ? 2 : (Q % 4 == 0 && a % 8 == 0));
     fast = KC ? vec == 1 : vec == 2;
   }
   // FP8 contiguous rows, one factor part, unguarded, at least two chunks:

@@ -810,7 +810,9 @@ __global__ __launch_bounds__(512) void k_ttm_kcx32(const float* __restrict__ X, 
 // transposed with k permuted inside each 32-wide chunk (k = kc + 4t + g at
 // position kc + 8g + t) so a lane reads its eight t-values with two 16-byte
 // LDS reads.  The next 32-index chunk (across tiles too) is loaded while the
-// current one is multiplied.
+// current one is multiplied.  FULL (whole 64-q tiles and 32-index chunks,
+// 16-byte aligned, Q < 2^28): loads and stores take a wave-uniform base in
+// scalar registers plus the lane's 32-bit byte offset.
 template <int NCB, bool FULL>
 __global__ __launch_bounds__(512) void k_ttm_q(const float* __restrict__ X, const float* __restrict__ B,
                                                float* __restrict__ C, int64_t P, int64_t K, int64_t Q,
@@ -818,7 +820,11 @@ __global__ __launch_bounds__(512) void k_ttm_q(const float* __restrict__ X, cons
   extern __shared__ __align__(16) unsigned char lds_raw[];
   float* Bt = (float*)lds_raw;
   const int pitch = Kp + 4;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  // wave-uniform, which the compiler cannot infer from tid / 64: without it
+  // the tile's slice and offset (a 64-bit division) were computed per lane,
+  // in every chunk, behind divergent branches
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int g = lane >> 4, l16 = lane & 15;
   const int c0 = blockIdx.y * NCB * 16;
   constexpr int NC = NCB * 16;
@@ -847,6 +853,16 @@ __global__ __launch_bounds__(512) void k_ttm_q(const float* __restrict__ X, cons
       }
     }
   };
+  // FULL: the tile's base (uniform) and the lane's byte offset (index g, q 4 l16)
+  const uint32_t lofs = ((uint32_t)g * (uint32_t)Q + 4u * (uint32_t)l16) * 4u;
+  auto tile_base = [&](int64_t t) {
+    const int64_t p = t / tilesQ;
+    return X + p * K * Q + (t - p * tilesQ) * 64;
+  };
+  auto load_full = [&](const float* xb, int kc, f32x4 (&a)[8]) {
+#pragma unroll
+    for (int s = 0; s < 8; ++s) a[s] = *(const f32x4*)((const char*)(xb + (int64_t)(kc + 4 * s) * Q) + lofs);
+  };
   // prefetching needs 32 more registers: kept for up to 64 factor columns per wave
   constexpr bool PF = NCB <= 4;
   const int64_t stride = (int64_t)gridDim.x * kTtmWaves;
@@ -854,12 +870,18 @@ __global__ __launch_bounds__(512) void k_ttm_q(const float* __restrict__ X, cons
   // as in k_ttm_kc, the prefetched registers are copied before the next
   // chunk's loads are issued, so the products wait on nothing in flight
   f32x4 an[8];
-  if (PF && tile < ntiles) load_chunk(tile, 0, an);
+  const float* xcur = FULL && tile < ntiles ? tile_base(tile) : X;
+  if (PF && tile < ntiles) {
+    if (FULL) load_full(xcur, 0, an);
+    else load_chunk(tile, 0, an);
+  }
   for (; tile < ntiles; tile += stride) {
     asm volatile("" ::: "memory");  // factor reads stay in the loop (see k_ttm_rb)
     const int64_t p = tile / tilesQ;
     const int64_t q0 = (tile - p * tilesQ) * 64;
     float* Cb = C + p * Q * R;
+    const bool has_next = tile + stride < ntiles;
+    const float* xnext = FULL && has_next ? tile_base(tile + stride) : xcur;
     f32x4 acc[4][NCB];
 #pragma unroll
     for (int u = 0; u < 4; ++u)
@@ -873,14 +895,19 @@ __global__ __launch_bounds__(512) void k_ttm_q(const float* __restrict__ X, cons
         for (int s = 0; s < 8; ++s) a[s] = an[s];
       }
       if (!PF) {
-        load_chunk(tile, kc, a);
+        if (FULL) load_full(xcur, kc, a);
+        else load_chunk(tile, kc, a);
       } else {
         // unconditional (after the last chunk of the last tile it reloads
         // this tile's first, unused): no branch around the loads, and the
         // scheduling barrier keeps them ahead of the products
         const bool more = kc + 32 < Kp;
-        const int64_t tn = more ? tile : (tile + stride < ntiles ? tile + stride : tile);
-        load_chunk(tn, more ? kc + 32 : 0, an);
+        if (FULL) {
+          load_full(more ? xcur : xnext, more ? kc + 32 : 0, an);
+        } else {
+          const int64_t tn = more ? tile : (has_next ? tile + stride : tile);
+          load_chunk(tn, more ? kc + 32 : 0, an);
+        }
         __builtin_amdgcn_sched_barrier(0);
       }
 #pragma unroll
@@ -897,16 +924,29 @@ __global__ __launch_bounds__(512) void k_ttm_q(const float* __restrict__ X, cons
         }
       }
     }
+    if (FULL && c0 + NC <= R) {
+      // whole tile: row bases uniform, the lane's offset (row 16 g, column l16) in 32 bits
+      const uint32_t so = ((uint32_t)(16 * g) * (uint32_t)R + (uint32_t)l16) * 4u;
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+      for (int u = 0; u < 4; ++u)
 #pragma unroll
-      for (int cb = 0; cb < NCB; ++cb)
+        for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int64_t q = q0 + 16 * g + 4 * v + u;
-          const int c = c0 + cb * 16 + l16;
-          if (q < Q && c < R) Cb[q * R + c] = acc[u][cb][v];
-        }
+          for (int v = 0; v < 4; ++v)
+            *(float*)((char*)(Cb + (q0 + 4 * v + u) * R + c0 + cb * 16) + so) = acc[u][cb][v];
+    } else {
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int64_t q = q0 + 16 * g + 4 * v + u;
+            const int c = c0 + cb * 16 + l16;
+            if (q < Q && c < R) Cb[q * R + c] = acc[u][cb][v];
+          }
+    }
+    xcur = xnext;
   }
 }
 
@@ -918,8 +958,11 @@ __global__ __launch_bounds__(512) void k_ttm_q(const float* __restrict__ X, cons
 // at the first piece of the current one (ahead of the rows' prefetch) and
 // written into the other buffer after its last piece, one barrier per
 // chunk.  Waves of a workgroup step through the same (tile, piece)
-// sequence; a wave past the last tile recomputes it without storing.
-template <int NCB>
+// sequence; a wave past the last tile recomputes it without storing.  The
+// tile's slice and offset are wave-uniform and computed once per tile.  FQ
+// (whole 64-q tiles and 32-index pieces, 16-byte aligned, Q < 2^28): the
+// loads and stores take that base plus the lane's 32-bit byte offset.
+template <int NCB, bool FQ>
 __global__ __launch_bounds__(512) void k_ttm_qx(const float* __restrict__ X, const float* __restrict__ B,
                                                 float* __restrict__ C, int64_t P, int64_t K, int64_t Q,
                                                 int R, int64_t tilesQ, int64_t ntiles, int vec, int cps) {
@@ -929,7 +972,8 @@ __global__ __launch_bounds__(512) void k_ttm_qx(const float* __restrict__ X, con
   constexpr int BPER = KCH * NC / kTtmThreads;
   constexpr int BQ = BPER / 4;  // factor elements per thread and quarter chunk
   __shared__ __align__(16) float Bt[2][NC * pitch];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform (not inferred from tid / 64)
   const int g = lane >> 4, l16 = lane & 15;
   const int c0 = blockIdx.y * NC;
   // split K (gridDim.z > 1): this layer takes chunks [cbeg, cend) and writes
@@ -957,20 +1001,35 @@ __global__ __launch_bounds__(512) void k_ttm_qx(const float* __restrict__ X, con
       Bt[buf][col * pitch + kc + 8 * (kr & 3) + (kr >> 2)] = bv[i];
     }
   };
-  auto load_piece = [&](int64_t t, int64_t kc, f32x4 (&a)[8]) {
-    const int64_t p = t / tilesQ;
-    const int64_t qa = (t - p * tilesQ) * 64 + 4 * l16;
-    const bool full = vec && qa + 4 <= Q;
-    const float* Xb = X + p * K * Q;
+  // tile t: slice p, first q, and base X[p][0][q0] (all uniform)
+  struct TileX {
+    const float* xb;
+    int64_t p, q0;
+  };
+  auto tile_at = [&](int64_t t) {
+    TileX r;
+    r.p = t / tilesQ;
+    r.q0 = (t - r.p * tilesQ) * 64;
+    r.xb = X + r.p * K * Q + r.q0;
+    return r;
+  };
+  const uint32_t lofs = ((uint32_t)g * (uint32_t)Q + 4u * (uint32_t)l16) * 4u;
+  auto load_piece = [&](const TileX& tx, int64_t kc, f32x4 (&a)[8]) {
+    if (FQ) {
+#pragma unroll
+      for (int s2 = 0; s2 < 8; ++s2) a[s2] = *(const f32x4*)((const char*)(tx.xb + (kc + 4 * s2) * Q) + lofs);
+      return;
+    }
+    const bool full = vec && tx.q0 + 4 * l16 + 4 <= Q;
 #pragma unroll
     for (int s2 = 0; s2 < 8; ++s2) {
       const int64_t k = kc + 4 * s2 + g;
-      const float* src = Xb + k * Q + qa;
+      const float* src = tx.xb + k * Q + 4 * l16;
       if (k < K && full) {
         a[s2] = *(const f32x4*)src;
       } else {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) a[s2][u] = (k < K && qa + u < Q) ? src[u] : 0.f;
+        for (int u = 0; u < 4; ++u) a[s2][u] = (k < K && tx.q0 + 4 * l16 + u < Q) ? src[u] : 0.f;
       }
     }
   };
@@ -985,7 +1044,8 @@ __global__ __launch_bounds__(512) void k_ttm_qx(const float* __restrict__ X, con
   const int pall = (int)((K + 31) / 32);                  // 32-index pieces of K
   const int npc = cend * 4 < pall ? cend * 4 : pall;      // end of this layer's pieces
   f32x4 an[8];
-  load_piece(tb + wave < ntiles ? tb + wave : ntiles - 1, (int64_t)cbeg * KCH, an);
+  TileX tcur = tile_at(tb + wave < ntiles ? tb + wave : ntiles - 1);
+  load_piece(tcur, (int64_t)cbeg * KCH, an);
   __syncthreads();
   int buf = 0;
   for (; tb < ntiles; tb += stride) {
@@ -993,6 +1053,7 @@ __global__ __launch_bounds__(512) void k_ttm_qx(const float* __restrict__ X, con
     const int64_t tile = tb + wave < ntiles ? tb + wave : ntiles - 1;
     const bool own = tb + wave < ntiles;
     const int64_t tnext = tb + stride + wave < ntiles ? tb + stride + wave : (tb + stride < ntiles ? ntiles - 1 : tile);
+    const TileX txn = tile_at(tnext);
     f32x4 acc[4][NCB];
 #pragma unroll
     for (int u = 0; u < 4; ++u)
@@ -1012,7 +1073,7 @@ __global__ __launch_bounds__(512) void k_ttm_qx(const float* __restrict__ X, con
         float bv[BQ];
         load_b(cn, pc - c * 4, bv);
         const bool more = pc + 1 < npc;
-        load_piece(more ? tile : tnext, more ? (int64_t)(pc + 1) * 32 : (int64_t)cbeg * KCH, an);
+        load_piece(more ? tcur : txn, more ? (int64_t)(pc + 1) * 32 : (int64_t)cbeg * KCH, an);
         __builtin_amdgcn_sched_barrier(0);
         const int kl = (pc - c * 4) * 32;
 #pragma unroll
@@ -1040,20 +1101,32 @@ __global__ __launch_bounds__(512) void k_ttm_qx(const float* __restrict__ X, con
       __syncthreads();
     }
     if (own) {
-      const int64_t p = tile / tilesQ;
-      const int64_t q0 = (tile - p * tilesQ) * 64;
-      float* Cb = C + p * Q * R;
+      const int64_t q0 = tcur.q0;
+      float* Cb = C + tcur.p * Q * R;
+      if (FQ && c0 + NC <= R) {
+        // row bases uniform, the lane's offset (row 16 g, column l16) in 32 bits
+        const uint32_t so = ((uint32_t)(16 * g) * (uint32_t)R + (uint32_t)l16) * 4u;
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < 4; ++u)
 #pragma unroll
-        for (int cb = 0; cb < NCB; ++cb)
+          for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int64_t q = q0 + 16 * g + 4 * v + u;
-            const int col = c0 + cb * 16 + l16;
-            if (q < Q && col < R) Cb[q * R + col] = acc[u][cb][v];
-          }
+            for (int v = 0; v < 4; ++v)
+              *(float*)((char*)(Cb + (q0 + 4 * v + u) * R + c0 + cb * 16) + so) = acc[u][cb][v];
+      } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int64_t q = q0 + 16 * g + 4 * v + u;
+              const int col = c0 + cb * 16 + l16;
+              if (q < Q && col < R) Cb[q * R + col] = acc[u][cb][v];
+            }
+      }
     }
+    tcur = txn;
   }
 }
 
@@ -2300,6 +2373,11 @@ hipError_t launch_ttm_kcx32(const float* X, const float* B, float* C, int64_t P,
   return hipGetLastError();
 }
 
+// whole 64-q tiles and 32-index pieces, 16-byte aligned rows, 32-bit lane offsets
+inline bool qx_whole(int vec, int64_t K, int64_t Q) {
+  return vec && Q % 64 == 0 && K % 32 == 0 && Q < ((int64_t)1 << 28);
+}
+
 template <int NCB>
 hipError_t launch_ttm_qx(const float* X, const float* B, float* C, int64_t P, int64_t K, int64_t Q, int R,
                          hipStream_t st) {
@@ -2310,8 +2388,12 @@ hipError_t launch_ttm_qx(const float* X, const float* B, float* C, int64_t P, in
   const unsigned ny = (unsigned)((R + NCB * 16 - 1) / (NCB * 16));
   const int vec = (Q % 4 == 0 && ((uintptr_t)X % 16) == 0) ? 1 : 0;
   const int nch = (int)((K + 127) / 128);
-  hipLaunchKernelGGL((k_ttm_qx<NCB>), dim3(nx, ny), dim3(kTtmThreads), 0, st, X, B, C, P, K, Q, R, tilesQ, ntiles,
-                     vec, nch);
+  if (qx_whole(vec, K, Q))
+    hipLaunchKernelGGL((k_ttm_qx<NCB, true>), dim3(nx, ny), dim3(kTtmThreads), 0, st, X, B, C, P, K, Q, R, tilesQ,
+                       ntiles, vec, nch);
+  else
+    hipLaunchKernelGGL((k_ttm_qx<NCB, false>), dim3(nx, ny), dim3(kTtmThreads), 0, st, X, B, C, P, K, Q, R, tilesQ,
+                       ntiles, vec, nch);
   return hipGetLastError();
 }
 
@@ -2329,8 +2411,12 @@ hipError_t launch_ttm_qx_split(const float* X, const float* B, float* C, int64_t
   const int nch = (int)((K + 127) / 128);
   const int cps = (nch + Z - 1) / Z;
   const int z = (nch + cps - 1) / cps;
-  hipLaunchKernelGGL((k_ttm_qx<NCB>), dim3(nx, ny, (unsigned)z), dim3(kTtmThreads), 0, st, X, B, parts, P, K, Q, R,
-                     tilesQ, ntiles, vec, cps);
+  if (qx_whole(vec, K, Q))
+    hipLaunchKernelGGL((k_ttm_qx<NCB, true>), dim3(nx, ny, (unsigned)z), dim3(kTtmThreads), 0, st, X, B, parts, P, K,
+                       Q, R, tilesQ, ntiles, vec, cps);
+  else
+    hipLaunchKernelGGL((k_ttm_qx<NCB, false>), dim3(nx, ny, (unsigned)z), dim3(kTtmThreads), 0, st, X, B, parts, P,
+                       K, Q, R, tilesQ, ntiles, vec, cps);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t n = P * Q * R;
@@ -2356,7 +2442,7 @@ hipError_t launch_ttm_q(const float* X, const float* B, float* C, int64_t P, int
   const unsigned nx = (unsigned)(want < 512 ? want : 512);
   const unsigned ny = (unsigned)((R + NCB * 16 - 1) / (NCB * 16));
   const int vec = (Q % 4 == 0 && ((uintptr_t)X % 16) == 0) ? 1 : 0;
-  if (vec && Q % 64 == 0 && K % 32 == 0)
+  if (vec && Q % 64 == 0 && K % 32 == 0 && Q < ((int64_t)1 << 28))
     hipLaunchKernelGGL((k_ttm_q<NCB, true>), dim3(nx, ny), dim3(kTtmThreads), lds, st, X, B, C, P, K, Q, R, tilesQ,
                        ntiles, Kp, vec);
   else

@@ -183,7 +183,8 @@ __device__ __forceinline__ void ttm_rows(Lds& L, const float* X, int64_t P, int 
   constexpr int NCB = RP / 16;
   constexpr int NB = 3;
   const int nb = (K + 31) / 32;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);  // uniform (not inferred from tid / 64)
   const int g = lane >> 4, l16 = lane & 15;
   const int64_t ntiles = (P + 15) / 16;
   // 32-bit byte offsets from X (a tensor here is at most 96^3 values)
@@ -255,7 +256,8 @@ __device__ __forceinline__ void ttm_cols(Lds& L, const float* X, int K, int64_t 
   constexpr int NCB = RP / 16;
   constexpr int NB = 3;
   const int nb = (K + 31) / 32;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);  // uniform (not inferred from tid / 64)
   const int g = lane >> 4, l16 = lane & 15;
   const int64_t ntiles = (Q + 15) / 16;
   // 32-bit byte offsets from X (a tensor here is at most 96^3 values)

@@ -73,7 +73,8 @@ __global__ __launch_bounds__(256) void k_ttm(const T* __restrict__ X, const T* _
   constexpr int XS = KC ? TBM * (TBK + 1) : TBK * (TBM + 1);
   __shared__ T Xs[XS];
   __shared__ T Bs[TBK * (TBN + 1)];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform (not inferred from tid / 64)
   int64_t rowbase, nrows;
   const T* Xb;
   T* Cb;
@@ -181,7 +182,8 @@ __global__ __launch_bounds__(512) void k_ttm_rb(const T* __restrict__ X, const T
   extern __shared__ __align__(16) unsigned char lds_raw[];
   T* Bt = (T*)lds_raw;
   const int pitch = Kp + V;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform (not inferred from tid / 64)
   const int g = lane >> 4, l16 = lane & 15;
   const int c0 = blockIdx.y * NCB * 16;
   constexpr int NC = NCB * 16;
@@ -294,7 +296,8 @@ __global__ __launch_bounds__(512) void k_ttm_sq(const T* __restrict__ X, const T
   constexpr int NC = NCB * 16;
   typedef typename Vec16<T>::type VT;
   __shared__ __align__(16) T Bt[NC * pitch];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform (not inferred from tid / 64)
   const int g = lane >> 4, l16 = lane & 15;
   const int c0 = blockIdx.y * NC;
   for (int idx = tid; idx < KP * NC; idx += kTtmThreads) {
@@ -370,7 +373,8 @@ __global__ __launch_bounds__(512) void k_ttm_kc(const T* __restrict__ X, const T
   const int64_t K = FULLK ? (int64_t)KP : K_;  // FULLK: K == KP, 16-byte aligned rows
   typedef typename Vec16<T>::type VT;
   __shared__ __align__(16) T Bt[NC * pitch];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform (not inferred from tid / 64)
   const int g = lane >> 4, l16 = lane & 15;
   const int c0 = blockIdx.y * NC;
   for (int idx = tid; idx < KP * NC; idx += kTtmThreads) {
@@ -469,7 +473,8 @@ __global__ __launch_bounds__(512) void k_ttm_kc32(const float* __restrict__ X, c
   constexpr int pitch = K + 4;
   constexpr int NC = NCB * 32;
   __shared__ __align__(16) float Bt[NC * pitch];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform (not inferred from tid / 64)
   const int h = lane >> 5, l32 = lane & 31;
   const int c0 = blockIdx.y * NC;
   for (int idx = tid; idx < K * NC; idx += kTtmThreads) {
@@ -477,7 +482,15 @@ __global__ __launch_bounds__(512) void k_ttm_kc32(const float* __restrict__ X, c
     Bt[col * pitch + k] = (c0 + col < R) ? B[(int64_t)k * R + c0 + col] : 0.f;
   }
   __syncthreads();
+  // whole tiles: the tile's base (uniform) plus the lane's byte offset (row l32, index 4 h)
+  const uint32_t xlo = ((uint32_t)l32 * (uint32_t)K + 4u * (uint32_t)h) * 4u;
   auto load_tile = [&](int64_t t, f32x4 (&a)[NS]) {
+    if (t * 32 + 32 <= P) {
+      const char* xb = (const char*)(X + t * 32 * K) + xlo;
+#pragma unroll
+      for (int st = 0; st < NS; ++st) a[st] = *(const f32x4*)(xb + 32 * st);
+      return;
+    }
     int64_t row = t * 32 + l32;
     row = row < P ? row : P - 1;
     const float* xr = X + row * K + 4 * h;
@@ -512,14 +525,24 @@ __global__ __launch_bounds__(512) void k_ttm_kc32(const float* __restrict__ X, c
           acc[cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[st][j], b[cb][j], acc[cb], 0, 0, 0);
     }
     const int64_t r0 = tile * 32;
+    if (r0 + 32 <= P && c0 + NC <= R) {
+      // row bases uniform, the lane's offset (row 4 h, column l32) in 32 bits
+      const uint32_t so = ((uint32_t)(4 * h) * (uint32_t)R + (uint32_t)l32) * 4u;
 #pragma unroll
-    for (int cb = 0; cb < NCB; ++cb)
+      for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int64_t row = r0 + 8 * (v >> 2) + 4 * h + (v & 3);
-        const int c = c0 + cb * 32 + l32;
-        if (row < P && c < R) C[row * R + c] = acc[cb][v];
-      }
+        for (int v = 0; v < 16; ++v)
+          *(float*)((char*)(C + (r0 + 8 * (v >> 2) + (v & 3)) * R + c0 + cb * 32) + so) = acc[cb][v];
+    } else {
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int64_t row = r0 + 8 * (v >> 2) + 4 * h + (v & 3);
+          const int c = c0 + cb * 32 + l32;
+          if (row < P && c < R) C[row * R + c] = acc[cb][v];
+        }
+    }
   }
 }
 
@@ -550,7 +573,8 @@ __global__ __launch_bounds__(512) void k_ttm_kcx(const T* __restrict__ X, const 
   constexpr int BPER = KP * NC / kTtmThreads;  // factor elements per thread and chunk
   typedef typename Vec16<T>::type VT;
   __shared__ __align__(16) T Bt[2][NC * pitch];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform (not inferred from tid / 64)
   const int g = lane >> 4, l16 = lane & 15;
   const int c0 = blockIdx.y * NC;
   const int nall = (int)((K + KP - 1) / KP);
@@ -697,7 +721,8 @@ __global__ __launch_bounds__(512) void k_ttm_kcx32(const float* __restrict__ X, 
   constexpr int BPER = KP * NC / kTtmThreads;
   constexpr int BQ = BPER / 4;
   __shared__ __align__(16) float Bt[2][NC * pitch];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform (not inferred from tid / 64)
   const int h = lane >> 5, l32 = lane & 31;
   const int c0 = blockIdx.y * NC;
   const int nch = (int)((K + KP - 1) / KP);
@@ -1329,7 +1354,8 @@ __device__ inline double block_sum(double v, double* sh) {
 // thread gets the totals (sh: at least 4 K doubles of LDS).
 template <int K>
 __device__ inline void block_sums(double (&v)[K], double* sh) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);  // uniform (not inferred from tid / 64)
 #pragma unroll
   for (int k = 0; k < K; ++k)
 #pragma unroll
@@ -1771,7 +1797,8 @@ __global__ __launch_bounds__(256) void k_update(UpdateArgs<T> a) {
   extern __shared__ double lds[];
   __shared__ double sh[256];
   __shared__ int flag;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform (not inferred from tid / 64)
   const int l16 = lane & 15, lg = lane >> 4;
   const int R = a.R;
   constexpr bool pp = PP;

@@ -140,7 +140,8 @@ __global__ __launch_bounds__(512) void k_ttm_bf16(const void* __restrict__ Xv, c
   __shared__ __align__(16) uint16_t Bs[2][NPART * NC * KPITCH];  // [buffer][part][column][index]
   // FP8 q-contiguous with TR: the workgroup's chunk of the tensor, [buffer][index][q]
   __shared__ __align__(16) uint8_t Ts[TR ? 2 * KB * TPITCH : 16];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform (not inferred from tid / 64)
   const int g = lane >> 4, l16 = lane & 15;
   const int c0 = blockIdx.y * NC;
   const int nch = Kp / KB;

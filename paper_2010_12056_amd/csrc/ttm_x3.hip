@@ -127,7 +127,8 @@ __global__ __launch_bounds__(kThreads) void k_ttm_x3(const float* __restrict__ X
   constexpr int PIECES = 3 * NC * (kChunk / 8);              // 16-byte pieces of a chunk
   constexpr int BPER = (PIECES + kThreads - 1) / kThreads;
   __shared__ __align__(16) uint16_t Bs[2 * BUF];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform (not inferred from tid / 64)
   const int g = lane >> 4, l16 = lane & 15;
   const int c0 = blockIdx.y * NC;
   const int64_t n = (int64_t)R * Kp;

@@ -350,7 +350,7 @@ __device__ __forceinline__ void gamma_inverse(Lds& L, int a, int b, int R) {
   }
   const double tol = L.red[0] * (double)R * 2.220446049250313e-16;
   __syncthreads();
-  if (!gj_inverse_lds<RP, NT / 64, false>(L.G, tol, &L.fail, L.red)) {
+  if (!gj_inverse_lds<RP, NT / 64>(L.G, tol, &L.fail, L.red)) {
     if (threadIdx.x == 0) L.fail = 1;
     __syncthreads();
   }

@@ -3,6 +3,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 namespace cpals {
 
 typedef double gj_f64x4 __attribute__((ext_vector_type(4)));
@@ -12,14 +14,6 @@ __device__ __forceinline__ double gj_readlane(double v, int src) {
   const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
   const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, src);
   const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), src);
-  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
-}
-
-// The double held by lane `src` (per lane) of the wave; every lane active.
-__device__ __forceinline__ double gj_bpermute(double v, int src) {
-  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
-  const unsigned lo = (unsigned)__builtin_amdgcn_ds_bpermute(src * 4, (int)(unsigned)u);
-  const unsigned hi = (unsigned)__builtin_amdgcn_ds_bpermute(src * 4, (int)(unsigned)(u >> 32));
   return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
 
@@ -33,9 +27,10 @@ __device__ __forceinline__ double gj_bpermute(double v, int src) {
 // met are the same Schur-complement diagonals.  The panels and the trailing
 // update run on the f64 matrix cores.  Returns false (uniformly, A then
 // undefined) when a pivot is at or below tol.  fail: an LDS flag; xb: 144
-// doubles of LDS for the XLANE = false form of the diagonal elimination.
-template <int RP, int NW = 4, bool XLANE = true>
-__device__ __forceinline__ bool gj_inverse_lds(double* A, double tol, int* fail, double* xb = nullptr) {
+// doubles of LDS through which the diagonal elimination passes each pivot's
+// row and column (the form with the fewest registers, for the batched path).
+template <int RP, int NW>
+__device__ __forceinline__ bool gj_inverse_lds(double* A, double tol, int* fail, double* xb) {
   constexpr int NB = RP / 16;
   constexpr int P = RP + 1;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -45,51 +40,11 @@ __device__ __forceinline__ bool gj_inverse_lds(double* A, double tol, int* fail,
   for (int kb = 0; kb < NB; ++kb) {
     const int k0 = 16 * kb;
     // (1) D <- D^-1 by wave 0.  Lane (g, l16) keeps D[g + 4q][l16], q < 4, in
-    // registers.  Pivot s: its row entry D[s][l16] comes from
-    // lane 16 (s % 4) + l16 and its four column entries D[g + 4q][s] from
-    // lane 16 g + s (ds_bpermute, a cross-lane read with no LDS round
-    // trip), the pivot D[s][s] from lane 16 (s % 4) + s (readlane).  1 /
-    // pivot: the hardware reciprocal refined by two Newton steps
-    // y <- y + y (1 - p y) (error a few units in the last place; pivots are
-    // positive, far from the exponent limits).
-    if constexpr (XLANE) {
-      if (wave == 0) {
-        double x[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) x[q] = A[(k0 + g + 4 * q) * P + k0 + l16];
-        bool ok = true;
-#pragma unroll 1
-        for (int s = 0; s < 16; ++s) {
-          const int qs = s >> 2, gs = s & 3;
-          const double xs = qs == 0 ? x[0] : qs == 1 ? x[1] : qs == 2 ? x[2] : x[3];
-          const double piv = gj_readlane(xs, 16 * gs + s);
-          const double rk = gj_bpermute(xs, 16 * gs + l16);
-          double ck[4];
-#pragma unroll
-          for (int q = 0; q < 4; ++q) ck[q] = gj_bpermute(x[q], 16 * g + s);
-          ok = ok && (piv > tol);  // uniform; after a failure the rest is discarded
-          double rinv = __builtin_amdgcn_rcp(piv);
-          rinv = fma(rinv, fma(-piv, rinv, 1.0), rinv);
-          rinv = fma(rinv, fma(-piv, rinv, 1.0), rinv);
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            if (g + 4 * q == s)
-              x[q] = (l16 == s) ? rinv : rk * rinv;
-            else
-              x[q] = (l16 == s) ? -ck[q] * rinv : x[q] - ck[q] * rk * rinv;
-          }
-        }
-        if (ok) {
-#pragma unroll
-          for (int q = 0; q < 4; ++q) A[(k0 + g + 4 * q) * P + k0 + l16] = x[q];
-        } else if (lane == 0) {
-          *fail = 1;
-        }
-      }
-    } else {
-      // the same elimination with the row and column of each pivot passed
-      // through LDS (two alternating buffers, one wave-level fence per pivot;
-      // the other lanes write a dummy slot): fewer registers
+    // registers; each pivot's row and column pass through LDS (two
+    // alternating buffers, one wave-level fence per pivot; the other lanes
+    // write a dummy slot).  1 / pivot: the hardware reciprocal refined by two
+    // Newton steps y <- y + y (1 - p y) (error a few units in the last place;
+    // pivots are positive, far from the exponent limits).
       if (wave == 0) {
         double x[4];
 #pragma unroll
@@ -133,7 +88,6 @@ __device__ __forceinline__ bool gj_inverse_lds(double* A, double tol, int* fail,
           *fail = 1;
         }
       }
-    }
     __syncthreads();
     if (*fail) return false;  // uniform
     // (2) row panel A_kj <- D^-1 A_kj, one 16 x 16 tile per wave at a time
@@ -202,6 +156,187 @@ __device__ __forceinline__ bool gj_inverse_lds(double* A, double tol, int* fail,
     }
     __syncthreads();
   }
+  return true;
+}
+
+
+template <int S, int N, typename F>
+__device__ __forceinline__ void gj_static_for(F&& f) {
+  if constexpr (S < N) {
+    f(std::integral_constant<int, S>{});
+    gj_static_for<S + 1, N>(f);
+  }
+}
+
+// Lane S of each 16-lane row of the wave, to every lane of that row (DPP row
+// broadcast).
+template <int S>
+__device__ __forceinline__ double gj_rowbcast(double v) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)u, 0x150 + S, 0xF, 0xF, false);
+  const unsigned hi = (unsigned)__builtin_amdgcn_mov_dpp((int)(unsigned)(u >> 32), 0x150 + S, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// The value of 16-lane row G at the same position within the row, to every
+// row: the 16-lane swap puts rows 0 and 2 (first result) or 1 and 3 (second)
+// in both rows of each pair, the 32-lane swap then the lower (first) or upper
+// (second) pair in both halves.
+template <int G>
+__device__ __forceinline__ unsigned gj_rowsel32(unsigned v) {
+  const auto p = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+  const unsigned y = (G & 1) ? p[1] : p[0];
+  const auto q = __builtin_amdgcn_permlane32_swap(y, y, false, false);
+  return (G & 2) ? q[1] : q[0];
+}
+template <int G>
+__device__ __forceinline__ double gj_rowsel(double v) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = gj_rowsel32<G>((unsigned)u), hi = gj_rowsel32<G>((unsigned)(u >> 32));
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// In-place Gauss-Jordan inverse of a 16 x 16 block held by one wave (every
+// lane active): lane (g = lane / 16, l16 = lane % 16) holds row l16, columns
+// 4 g .. 4 g + 3 in x.  Pivot s: its row reaches each row group from lane s
+// of that group (DPP broadcast), its column from group s / 4 (lane swaps),
+// its value by readlane, so no step goes through LDS.  1 / pivot: the
+// hardware reciprocal refined by two Newton steps.  Returns false (uniform)
+// when a pivot is at or below tol; x is then undefined.
+__device__ __forceinline__ bool gj_block16(double (&x)[4], double tol) {
+  const int lane = threadIdx.x & 63;
+  const int g = lane >> 4, l16 = lane & 15;
+  bool ok = true;
+  gj_static_for<0, 16>([&](auto sc) {
+    constexpr int s = decltype(sc)::value;
+    constexpr int gs = s >> 2, cs = s & 3;
+    const double piv = gj_readlane(x[cs], 16 * gs + s);
+    double rb[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) rb[c] = gj_rowbcast<s>(x[c]);
+    const double col = gj_rowsel<gs>(x[cs]);  // this lane's row, column s
+    ok = ok && (piv > tol);
+    double rinv = __builtin_amdgcn_rcp(piv);
+    rinv = fma(rinv, fma(-piv, rinv, 1.0), rinv);
+    rinv = fma(rinv, fma(-piv, rinv, 1.0), rinv);
+    const bool prow = (l16 == s);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const double f = rb[c] * rinv;
+      if (c == cs && g == gs)  // column s
+        x[c] = prow ? rinv : -col * rinv;
+      else
+        x[c] = prow ? f : fma(-col, f, x[c]);
+    }
+  });
+  return ok;
+}
+
+// In-place inverse of an SPD matrix by blocked Gauss-Jordan elimination
+// (16 x 16 blocks, as gj_inverse_lds) by four waves with look-ahead.  On
+// entry A (RP x RP in LDS, pitch RP + 1, padded with the identity) holds the
+// matrix with its first diagonal block already inverted, *fail set for that
+// block, and tol is valid in wave 0.  Block step k (after a barrier): wave 0
+// forms the next diagonal block's update A_k+1,k+1 - A_k+1,k D^-1 A_k,k+1 and
+// inverts it (gj_block16) while waves 1-3 take the columns j != k: the row
+// panel tile D^-1 A_kj, every trailing tile A_ij - A_ik (D^-1 A_kj) of the
+// column except that next diagonal block, and the column panel tile
+// -A_jk D^-1; the panel tiles are kept in registers and written after a
+// second barrier, once every old panel has been read.  In the last step
+// wave 0 takes columns too.  Returns false (uniformly) when a pivot is at or
+// below tol.
+template <int RP>
+__device__ __forceinline__ bool gj_inverse_la(double* A, double tol, int* fail) {
+  constexpr int NB = RP / 16;
+  constexpr int P = RP + 1;
+  constexpr int MJ = (NB + 1) / 3 > 0 ? (NB + 1) / 3 : 1;  // columns per wave (NB - 1 over three)
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int g = lane >> 4, l16 = lane & 15;
+  for (int k = 0; k < NB; ++k) {
+    __syncthreads();
+    if (*fail) return false;  // uniform
+    const int k0 = 16 * k;
+    const bool la = k + 1 < NB;
+    const int nw = la ? 3 : 4, w0 = la ? 1 : 0;
+    gj_f64x4 rp[MJ], cp[MJ];
+    int jc[MJ];
+#pragma unroll
+    for (int q = 0; q < MJ; ++q) {
+      jc[q] = -1;
+      const int idx = (wave - w0) + nw * q;  // the wave's q-th column among those != k
+      if (wave < w0 || idx >= NB - 1) continue;
+      const int j = idx < k ? idx : idx + 1;
+      const int j0 = 16 * j;
+      gj_f64x4 r = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        r = __builtin_amdgcn_mfma_f64_16x16x4f64(A[(k0 + l16) * P + k0 + 4 * t + g], A[(k0 + 4 * t + g) * P + j0 + l16],
+                                                 r, 0, 0, 0);
+      // r[t] is row 4 t + g of D^-1 A_kj at column l16: the operand of index slice t
+      for (int i = 0; i < NB; ++i) {
+        if (i == k || (la && i == k + 1 && j == k + 1)) continue;
+        const int i0 = 16 * i;
+        gj_f64x4 acc;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[v] = A[(i0 + g + 4 * v) * P + j0 + l16];
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-A[(i0 + l16) * P + k0 + 4 * t + g], r[t], acc, 0, 0, 0);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) A[(i0 + g + 4 * v) * P + j0 + l16] = acc[v];
+      }
+      gj_f64x4 c = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        c = __builtin_amdgcn_mfma_f64_16x16x4f64(A[(j0 + l16) * P + k0 + 4 * t + g], A[(k0 + 4 * t + g) * P + k0 + l16],
+                                                 c, 0, 0, 0);
+      rp[q] = r;
+      cp[q] = c;
+      jc[q] = j;
+    }
+    if (la && wave == 0) {
+      const int k1 = k0 + 16;
+      gj_f64x4 r = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        r = __builtin_amdgcn_mfma_f64_16x16x4f64(A[(k0 + l16) * P + k0 + 4 * t + g], A[(k0 + 4 * t + g) * P + k1 + l16],
+                                                 r, 0, 0, 0);
+      gj_f64x4 d;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) d[v] = A[(k1 + g + 4 * v) * P + k1 + l16];
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+        d = __builtin_amdgcn_mfma_f64_16x16x4f64(-A[(k1 + l16) * P + k0 + 4 * t + g], r[t], d, 0, 0, 0);
+      // to the elimination's layout through LDS (this block is wave 0's alone in this step)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) A[(k1 + g + 4 * v) * P + k1 + l16] = d[v];
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      double x[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) x[c] = A[(k1 + l16) * P + k1 + 4 * g + c];
+      if (gj_block16(x, tol)) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) A[(k1 + l16) * P + k1 + 4 * g + c] = x[c];
+      } else if (lane == 0) {
+        *fail = 1;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < MJ; ++q) {
+      if (jc[q] < 0) continue;
+      const int j0 = 16 * jc[q];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        A[(k0 + g + 4 * v) * P + j0 + l16] = rp[q][v];
+        A[(j0 + g + 4 * v) * P + k0 + l16] = -cp[q][v];
+      }
+    }
+  }
+  __syncthreads();
   return true;
 }
 

@@ -1713,38 +1713,59 @@ __host__ __device__ inline size_t gamma_inverse_lds_doubles(int RP, int R) {
 }
 
 // Gi = Gm^dagger by one workgroup of 256 threads: the blocked Gauss-Jordan
-// inverse (gj_inverse_lds), and when a pivot falls to R eps max(diag) or
-// below, the Jacobi pseudo-inverse (pinv_lds) in the same workgroup.
+// inverse with look-ahead (gj_inverse_la), and when a pivot falls to
+// R eps max(diag) or below, the Jacobi pseudo-inverse (pinv_lds) in the same
+// workgroup.  Wave 0 takes the largest diagonal entry and inverts the first
+// diagonal block straight from global memory while waves 1-3 copy the rest of
+// the matrix (padded with the identity) into LDS, every load of a batch in
+// flight before its first store.
 template <int RP>
 __device__ __forceinline__ void gamma_inverse_wg(const double* __restrict__ Gm, double* __restrict__ Gi, int R, DevStats* stats,
                                  double* lds) {
   constexpr int P = RP + 1;
   double* A = lds;
-  double* red = A + RP * P;
-  int* fail = (int*)(red + 256);
-  const int tid = threadIdx.x;
-  // the matrix was just written by another kernel or workgroup: every load
-  // of a batch in flight before the first store (batches of at most 16)
-  constexpr int PER = RP * RP / 256;
-  constexpr int BAT = PER < 16 ? PER : 16;
-  double dm = 0.0;
+  int* fail = (int*)(A + RP * P);
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  double tol = 0.0;  // wave 0's
+  if (wave == 0) {
+    double dm = 0.0;
+    for (int i = lane; i < R; i += 64) dm = fmax(dm, Gm[(int64_t)i * R + i]);
 #pragma unroll
-  for (int q0 = 0; q0 < PER; q0 += BAT) {
-    double vals[BAT];
+    for (int o = 32; o > 0; o >>= 1) dm = fmax(dm, __shfl_xor(dm, o));
+    tol = dm * (double)R * 2.220446049250313e-16;
+    const int g = lane >> 4, l16 = lane & 15;
+    double x[4];
 #pragma unroll
-    for (int q = 0; q < BAT; ++q) {
-      const int e = tid + 256 * (q0 + q), i = e / RP, j = e - i * RP;
-      vals[q] = (i < R && j < R) ? Gm[i * R + j] : (i == j ? 1.0 : 0.0);
+    for (int c = 0; c < 4; ++c) {
+      const int j = 4 * g + c;
+      x[c] = (l16 < R && j < R) ? Gm[l16 * R + j] : (l16 == j ? 1.0 : 0.0);
     }
+    const bool ok = gj_block16(x, tol);
 #pragma unroll
-    for (int q = 0; q < BAT; ++q) {
-      const int e = tid + 256 * (q0 + q), i = e / RP, j = e - i * RP;
-      A[i * P + j] = vals[q];
-      if (i == j && i < R) dm = fmax(dm, vals[q]);
+    for (int c = 0; c < 4; ++c) A[l16 * P + 4 * g + c] = x[c];
+    if (lane == 0) *fail = ok ? 0 : 1;
+  } else {
+    constexpr int NT = 192;
+    constexpr int PER = (RP * RP + NT - 1) / NT;
+    constexpr int BAT = PER < 16 ? PER : 16;
+    const int t = tid - 64;
+#pragma unroll
+    for (int q0 = 0; q0 < PER; q0 += BAT) {
+      double vals[BAT];
+#pragma unroll
+      for (int q = 0; q < BAT; ++q) {
+        const int e = t + NT * (q0 + q), i = e / RP, j = e - i * RP;
+        vals[q] = (q0 + q < PER && e < RP * RP && i < R && j < R) ? Gm[i * R + j] : (i == j ? 1.0 : 0.0);
+      }
+#pragma unroll
+      for (int q = 0; q < BAT; ++q) {
+        const int e = t + NT * (q0 + q), i = e / RP, j = e - i * RP;
+        if (q0 + q < PER && e < RP * RP && (i >= 16 || j >= 16)) A[i * P + j] = vals[q];
+      }
     }
   }
-  const double tol = block_max(dm, red) * (double)R * 2.220446049250313e-16;
-  if (gj_inverse_lds<RP>(A, tol, fail)) {
+  if (gj_inverse_la<RP>(A, tol, fail)) {
     for (int e = tid; e < R * R; e += 256) {
       const int i = e / R, j = e - i * R;
       Gi[e] = A[i * P + j];

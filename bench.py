@@ -99,6 +99,8 @@ def dt_sweep_flops(dims, R):
 TTM_SOURCE_MARKERS = (
     "__global__ __launch_bounds__(512) void k_ttm_kc(",
     "__global__ __launch_bounds__(512) void k_ttm_kc32(",
+    "__global__ __launch_bounds__(512) void k_ttm_kc32f(",
+    "hipError_t launch_ttm_kc_fused(",
     "__global__ __launch_bounds__(512) void k_ttm_q(",
     "hipError_t launch_ttm_kc(",
     "hipError_t launch_ttm_kc32(",

@@ -488,6 +488,16 @@ int path_combines(cp_plan p, const std::vector<int>& seq) {
   return 0;
 }
 
+// Whether a path of the standard tree from the tensor starts with the
+// contractions of modes N-1 and N-2 in a shape the fused kernel takes
+// (FP32 plans).
+bool path_fuses(cp_plan p, const std::vector<int>& seq) {
+  const int N = p->N;
+  if (p->tree != CP_TREE_DT || p->prec != CP_F32 || N < 4 || seq.size() < 3) return false;
+  if (seq[0] != N - 1 || seq[1] != N - 2) return false;
+  return ttm_kc_fused_fits((const float*)p->T, p->dims[N - 1], p->dims[N - 2], p->R);
+}
+
 // Walk a root-to-leaf contraction sequence; M (FP64, s_leaf x R) receives the leaf.
 // Depth of the deepest cached node on a path (0: the path starts from the
 // tensor).
@@ -514,6 +524,22 @@ cp_status run_path(cp_plan p, const std::vector<int>& seq, double* M) {
   const int start = path_start(p, seq, &sets);
   int d = start + 1;
   const int side = (d == 1) ? path_combines(p, seq) : 0;
+  if (!side && d == 1 && len >= 3 && path_fuses(p, seq)) {
+    // standard tree: the leading half's first-level node feeds only this
+    // second-level node, so both come from one pass and the first is not kept
+    if ((size_t)node_numel(p, sets[2]) * p->esz > p->slot_cap[2])
+      return fail(p, CP_ERR_STATE, "internal: slot 2 too small");
+    int64_t P2 = 1;
+    for (int m = 0; m < N - 2; ++m) P2 *= p->dims[m];
+    ++p->ttm_count;
+    {
+      ProfScope ps(p, CP_PHASE_TTM);
+      HIP_TRY(p, launch_ttm_kc_fused((const float*)p->T, (const float*)p->Ash[N - 1], (const float*)p->Ash[N - 2],
+                                     (float*)p->slot_buf[2], P2, p->dims[N - 2], p->R, p->st));
+    }
+    slot_record(p, 2, sets[2]);
+    d = 3;
+  }
   if (side) {
     if ((size_t)node_numel(p, sets[2]) * p->esz > p->slot_cap[2])
       return fail(p, CP_ERR_STATE, "internal: slot 2 too small");

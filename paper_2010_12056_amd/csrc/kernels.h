@@ -61,6 +61,13 @@ hipError_t launch_ttm_fp8(const uint8_t* X, const uint16_t* Bhi, const uint16_t*
 // `parts` (ttm_x3_layers(P, K, Q, R) P Q R floats) a contraction with too few
 // row tiles to fill the chip is split over K, its partials added in order;
 // null: no split.
+// The leading half's first two levels in one pass (standard tree): X is
+// (P2 S) x K with K == 128 (contracted with B, K x R), then the mode of size S
+// before it (A2, S x R) into C (P2 x R); FP32, S a multiple of 32 up to 256,
+// 16 < R <= 64, X 16-byte aligned (ttm_kc_fused_fits).
+bool ttm_kc_fused_fits(const float* X, int64_t K, int64_t S, int R);
+hipError_t launch_ttm_kc_fused(const float* X, const float* B, const float* A2, float* C, int64_t P2, int64_t S,
+                               int R, hipStream_t st);
 bool ttm_x3_fits(int64_t P, int64_t K, int64_t Q, int R, const void* X);
 int ttm_x3_layers(int64_t P, int64_t K, int64_t Q, int R);
 hipError_t launch_split3_factor(const float* A, int64_t K, int R, uint16_t* Bt, hipStream_t st);

@@ -546,6 +546,101 @@ __global__ __launch_bounds__(512) void k_ttm_kc32(const float* __restrict__ X, c
   }
 }
 
+// The leading half's first two levels in one pass (standard dimension tree,
+// Sec. II-C: a first-level node there feeds exactly one second-level node):
+// the contraction over the last mode as in k_ttm_kc32 (K == 128), and in its
+// epilogue the one over the mode before it, of size S (a multiple of 32,
+// at most kFusedMaxS), so the first-level node is never stored:
+//   C[o][r] = sum_i A2[i][r] Y[o S + i][r],  Y[p][r] = sum_k X[p][k] B[k][r].
+// A wave takes the S / 32 consecutive row tiles of one output row o; lane
+// (l32, h) weights its 16 product rows of a tile (rows 8 m + 4 h + e) by A2,
+// staged transposed in LDS, and sums them in FP32 over the row's tiles; the
+// two lane halves are added at the end.  The first level's sums are those of
+// k_ttm_kc32; the second level's are taken in another order than k_mttv's.
+constexpr int kFusedMaxS = 256;
+template <int NCB>
+__global__ __launch_bounds__(512) void k_ttm_kc32f(const float* __restrict__ X, const float* __restrict__ B,
+                                                   const float* __restrict__ A2, float* __restrict__ C, int R, int S,
+                                                   int64_t ngroups) {
+  constexpr int K = 128;
+  constexpr int NS = K / 8;
+  constexpr int pitch = K + 4;
+  constexpr int NC = NCB * 32;
+  __shared__ __align__(16) float Bt[NC * pitch];
+  extern __shared__ __align__(16) float Wt[];  // NC x (S + 4): A2 transposed
+  const int wp = S + 4;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform (not inferred from tid / 64)
+  const int h = lane >> 5, l32 = lane & 31;
+  const int c0 = blockIdx.y * NC;
+  for (int idx = tid; idx < K * NC; idx += kTtmThreads) {
+    const int k = idx / NC, col = idx - k * NC;
+    Bt[col * pitch + k] = (c0 + col < R) ? B[(int64_t)k * R + c0 + col] : 0.f;
+  }
+  for (int idx = tid; idx < S * NC; idx += kTtmThreads) {
+    const int i = idx / NC, col = idx - i * NC;
+    Wt[col * wp + i] = (c0 + col < R) ? A2[(int64_t)i * R + c0 + col] : 0.f;
+  }
+  __syncthreads();
+  const int G = S / 32;  // tiles per output row
+  const uint32_t xlo = ((uint32_t)l32 * (uint32_t)K + 4u * (uint32_t)h) * 4u;
+  auto load_tile = [&](int64_t t, f32x4 (&a)[NS]) {  // whole tiles: P = ngroups S rows
+    const char* xb = (const char*)(X + t * 32 * K) + xlo;
+#pragma unroll
+    for (int st = 0; st < NS; ++st) a[st] = *(const f32x4*)(xb + 32 * st);
+  };
+  const int64_t stride = (int64_t)gridDim.x * kTtmWaves;
+  int64_t grp = (int64_t)blockIdx.x * kTtmWaves + wave;
+  f32x4 an[NS];
+  if (grp < ngroups) load_tile(grp * G, an);
+  for (; grp < ngroups; grp += stride) {
+    float part[NCB];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) part[cb] = 0.f;
+    for (int q = 0; q < G; ++q) {
+      asm volatile("" ::: "memory");  // factor reads stay in the loop
+      const int64_t tile = grp * G + q;
+      f32x4 a[NS];
+#pragma unroll
+      for (int st = 0; st < NS; ++st) a[st] = an[st];
+      const int64_t tn = q + 1 < G ? tile + 1 : (grp + stride < ngroups ? (grp + stride) * G : tile);
+      load_tile(tn, an);
+      __builtin_amdgcn_sched_barrier(0);
+      f32x16 acc[NCB];
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[cb][v] = 0.f;
+#pragma unroll
+      for (int st = 0; st < NS; ++st) {
+        f32x4 b[NCB];
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) b[cb] = *(const f32x4*)(Bt + (cb * 32 + l32) * pitch + 8 * st + 4 * h);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int cb = 0; cb < NCB; ++cb)
+            acc[cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[st][j], b[cb][j], acc[cb], 0, 0, 0);
+      }
+      // register v of the lane is product row 8 (v / 4) + 4 h + v % 4 of the tile
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          const f32x4 w = *(const f32x4*)(Wt + (cb * 32 + l32) * wp + 32 * q + 8 * m + 4 * h);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) part[cb] = fmaf(acc[cb][4 * m + e], w[e], part[cb]);
+        }
+    }
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+      const float tot = part[cb] + __shfl_xor(part[cb], 32);
+      const int c = c0 + cb * 32 + l32;
+      if (h == 0 && c < R) C[grp * R + c] = tot;
+    }
+  }
+}
+
 // First-level contraction over the last mode (Q == 1) when K is larger than
 // one register tile: the k_ttm_kc layout (a wave owns 16 rows, lane (i, g)
 // loads 16 bytes of row i per 4V-index step) with K in chunks of KP = 8 * 4V
@@ -2350,6 +2445,31 @@ hipError_t launch_ttm_kc32(const float* X, const float* B, float* C, int64_t P, 
   const unsigned nx = (unsigned)(want < 256 ? want : 256);
   const unsigned ny = (unsigned)((R + NCB * 32 - 1) / (NCB * 32));
   hipLaunchKernelGGL((k_ttm_kc32<NCB>), dim3(nx, ny), dim3(kTtmThreads), 0, st, X, B, C, P, R, ntiles);
+  return hipGetLastError();
+}
+
+// The leading half's first and second levels in one pass (k_ttm_kc32f):
+// X is (P2 S) x 128 (last mode contracted with B), A2 is S x R (the mode
+// before it), C is P2 x R.
+bool ttm_kc_fused_fits(const float* X, int64_t K, int64_t S, int R) {
+  return K == 128 && S % 32 == 0 && S >= 32 && S <= kFusedMaxS && R > 16 && R <= 64 && ((uintptr_t)X % 16) == 0;
+}
+
+hipError_t launch_ttm_kc_fused(const float* X, const float* B, const float* A2, float* C, int64_t P2, int64_t S,
+                               int R, hipStream_t st) {
+  if (!ttm_kc_fused_fits(X, 128, S, R) || P2 < 1) return hipErrorInvalidValue;
+  const int64_t want = (P2 + kTtmWaves - 1) / kTtmWaves;
+  const unsigned nx = (unsigned)(want < 256 ? want : 256);
+  const size_t lds = (size_t)64 * (S + 4) * sizeof(float);
+  if (R <= 32) {
+    hipLaunchKernelGGL((k_ttm_kc32f<1>), dim3(nx, 1), dim3(kTtmThreads), lds / 2, st, X, B, A2, C, R, (int)S, P2);
+  } else {
+    static std::atomic<uint64_t> attr{0};
+    // dynamic part only (the kernel also holds 33 KB of static LDS): 64 (kFusedMaxS + 4) floats
+    const hipError_t e = lds_limit_once(attr, (const void*)k_ttm_kc32f<2>, 96 * 1024);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_ttm_kc32f<2>), dim3(nx, 1), dim3(kTtmThreads), lds, st, X, B, A2, C, R, (int)S, P2);
+  }
   return hipGetLastError();
 }
 

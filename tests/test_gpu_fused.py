@@ -1,0 +1,103 @@
+"""GPU parity of the standard tree's fused leading half (FP32 plans: the
+contraction over the last mode, of size 128, and the one over the mode
+before it, a multiple of 32, in one pass without storing the first-level
+node) against the FP64 oracle: MTTKRPs of every mode (the leading modes take
+the fused path, the trailing ones the two-pass path), one and two 32-column
+blocks, one to eight row tiles per output row, orders 4 and 5, free-running
+DT sweeps, and the full-size order-4 128^4 tensor on sampled rows."""
+
+import numpy as np
+import pytest
+
+from gpu_util import relerr, say, to_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")
+
+
+CASES = [
+    # (dims, R): the last mode 128, the one before it a multiple of 32
+    ((7, 9, 32, 128), 24),     # one column block, one tile per output row
+    ((4, 5, 96, 128), 64),     # two column blocks, three tiles per row
+    ((3, 2, 256, 128), 40),    # the largest mode before the last (eight tiles), R past one block
+    ((3, 4, 5, 64, 128), 33),  # order 5
+    ((6, 7, 64, 128), 17),     # R just above the FP32 kernel's lower limit
+]
+
+
+@pytest.mark.parametrize("dims,R", CASES)
+def test_fused_mttkrp_every_mode(dev, dims, R):
+    import oracle
+    from paper_2010_12056_amd import cpals, synth
+
+    say(f"case fused mttkrp dims={dims} R={R}")
+    w = synth.planted_tensor(dims, R, 700 + len(dims) + R, noise_rel=1e-2, dtype=np.float32)
+    T = torch.from_numpy(w.T).to(dev)
+    A = to_dev(w.init, dev)
+    plan = cpals.Plan(dims, R, prec="f32", tree="dt", device=dev)
+    plan.set_tensor(T)
+    T64 = w.T.astype(np.float64)
+    for n in range(len(dims)):
+        e = relerr(plan.mttkrp(A, n).cpu().numpy(), oracle.mttkrp_naive(T64, w.init, n))
+        say(f"  mode {n} relerr {e:.2e}")
+        assert e <= 1e-5, (n, e)
+    plan.close()
+
+
+@pytest.mark.parametrize("dims,R", [((4, 5, 96, 128), 64), ((3, 4, 5, 64, 128), 33)])
+def test_fused_dt_free_running_trajectory(dev, dims, R):
+    """Free-running DT sweeps against the oracle's, at the FP32 path's
+    tolerances (fitness 1e-6, factors 1e-4)."""
+    import oracle
+    from paper_2010_12056_amd import cpals, synth
+
+    say(f"case fused dt sweeps dims={dims} R={R}")
+    w = synth.planted_tensor(dims, R, 800 + len(dims) + R, noise_rel=1e-2, dtype=np.float32)
+    plan = cpals.Plan(dims, R, prec="f32", tree="dt", device=dev)
+    plan.set_tensor(torch.from_numpy(w.T).to(dev))
+    A = to_dev(w.init, dev)
+    st = oracle.AlsState.start(w.T.astype(np.float64), w.init)
+    for sweep in range(4):
+        info = plan.als_sweep(A)
+        r_ref = oracle.als_sweep(st)
+        assert abs(info["r"] - r_ref) <= 1e-6, (sweep, info["r"], r_ref)
+        for n in range(len(dims)):
+            assert relerr(A[n].cpu().numpy(), st.A[n]) <= 1e-4, (sweep, n)
+    plan.close()
+
+
+def test_fused_config_o4_s128_r64_sampled(dev):
+    """Full-size order-4 128^4 FP32 tensor, R = 64: the MTTKRPs of modes 0 and
+    1 (the fused leading half) on sampled rows computed one by one by the
+    oracle's definition, with the signed bias bound of the other full-size
+    checks."""
+    from oracle import core
+    from paper_2010_12056_amd import cpals, synth
+
+    say("case fused mttkrp o4_s128_r64 full size")
+    w = synth.workload("o4_s128_r64_f32")
+    plan = cpals.Plan(w.dims, w.R, prec="f32", tree="dt", device=dev)
+    plan.set_tensor(torch.from_numpy(w.T).to(dev))
+    A = to_dev(w.init, dev)
+    rng = np.random.default_rng(3)
+    for n in (0, 1):
+        rows = rng.choice(w.dims[n], size=6, replace=False)
+        K = core.krp([w.init[m] for m in range(4) if m != n])
+        X = np.moveaxis(w.T, n, 0)
+        ref = np.stack([X[i].astype(np.float64).reshape(-1) @ K for i in rows])
+        M = plan.mttkrp(A, n).cpu().numpy()[rows]
+        e = relerr(M, ref)
+        bias = float(np.mean(M - ref) / np.mean(np.abs(ref)))
+        say(f"  mode {n} relerr {e:.2e} bias {bias:.1e}")
+        assert e <= 1e-5
+        assert abs(bias) <= 1e-8, (n, bias)
+        del K
+    plan.close()

@@ -285,7 +285,13 @@ void plan_layout(cp_plan p) {
       if (kc > 0) pl = std::max(pl, (size_t)ttm_x3_layers(P, kc, 1, R) * P);
       if (kcr > 0) pr = std::max(pr, (size_t)ttm_x3_layers(1, kcr, Q, R) * Q);
     }
-    take(std::max(pl, pr) * R * p->esz);  // parts
+    // the standard tree's fused trailing half: one partial node per range of mode 1
+    size_t pf = 0;
+    if (p->tree == CP_TREE_DT && p->prec == CP_F32 && N >= 4 && ttm_q_fused_shape(p->dims[0], p->dims[1], Q, R)) {
+      const int nz = q_fused_layers(p->dims[1], Q);
+      if (nz > 1) pf = (size_t)nz * Q;
+    }
+    take(std::max(std::max(pl, pr), pf) * R * p->esz);  // parts
   }
   {
     // pair_parts: the largest split partials of launch_mttv_pair over the
@@ -488,14 +494,26 @@ int path_combines(cp_plan p, const std::vector<int>& seq) {
   return 0;
 }
 
+// Product of the mode sizes after the first two.
+int64_t trailing_size(cp_plan p) {
+  int64_t q = 1;
+  for (int m = 2; m < p->N; ++m) q *= p->dims[m];
+  return q;
+}
+
 // Whether a path of the standard tree from the tensor starts with the
-// contractions of modes N-1 and N-2 in a shape the fused kernel takes
-// (FP32 plans).
-bool path_fuses(cp_plan p, const std::vector<int>& seq) {
+// contractions of its half's two outermost modes in a shape a fused kernel
+// takes (FP32 plans).
+// 1 for the leading half (modes N-1, N-2 first), 2 for the trailing half
+// (modes 0, 1 first), 0 otherwise.
+int path_fuses(cp_plan p, const std::vector<int>& seq) {
   const int N = p->N;
-  if (p->tree != CP_TREE_DT || p->prec != CP_F32 || N < 4 || seq.size() < 3) return false;
-  if (seq[0] != N - 1 || seq[1] != N - 2) return false;
-  return ttm_kc_fused_fits((const float*)p->T, p->dims[N - 1], p->dims[N - 2], p->R);
+  if (p->tree != CP_TREE_DT || p->prec != CP_F32 || N < 4 || seq.size() < 3) return 0;
+  if (seq[0] == N - 1 && seq[1] == N - 2)
+    return ttm_kc_fused_fits((const float*)p->T, p->dims[N - 1], p->dims[N - 2], p->R) ? 1 : 0;
+  if (seq[0] == 0 && seq[1] == 1)
+    return ttm_q_fused_fits((const float*)p->T, p->dims[0], p->dims[1], trailing_size(p), p->R) ? 2 : 0;
+  return 0;
 }
 
 // Walk a root-to-leaf contraction sequence; M (FP64, s_leaf x R) receives the leaf.
@@ -524,18 +542,23 @@ cp_status run_path(cp_plan p, const std::vector<int>& seq, double* M) {
   const int start = path_start(p, seq, &sets);
   int d = start + 1;
   const int side = (d == 1) ? path_combines(p, seq) : 0;
-  if (!side && d == 1 && len >= 3 && path_fuses(p, seq)) {
-    // standard tree: the leading half's first-level node feeds only this
-    // second-level node, so both come from one pass and the first is not kept
+  const int fuse = (!side && d == 1 && len >= 3) ? path_fuses(p, seq) : 0;
+  if (fuse) {
+    // standard tree: a half's first-level node feeds only this second-level
+    // node, so both come from one pass and the first is not kept
     if ((size_t)node_numel(p, sets[2]) * p->esz > p->slot_cap[2])
       return fail(p, CP_ERR_STATE, "internal: slot 2 too small");
-    int64_t P2 = 1;
-    for (int m = 0; m < N - 2; ++m) P2 *= p->dims[m];
     ++p->ttm_count;
-    {
-      ProfScope ps(p, CP_PHASE_TTM);
+    ProfScope ps(p, CP_PHASE_TTM);
+    if (fuse == 1) {
+      int64_t P2 = 1;
+      for (int m = 0; m < N - 2; ++m) P2 *= p->dims[m];
       HIP_TRY(p, launch_ttm_kc_fused((const float*)p->T, (const float*)p->Ash[N - 1], (const float*)p->Ash[N - 2],
                                      (float*)p->slot_buf[2], P2, p->dims[N - 2], p->R, p->st));
+    } else {
+      HIP_TRY(p, launch_ttm_q_fused((const float*)p->T, (const float*)p->Ash[0], (const float*)p->Ash[1],
+                                    (float*)p->slot_buf[2], p->dims[0], p->dims[1], trailing_size(p), p->R,
+                                    (float*)p->parts, p->st));
     }
     slot_record(p, 2, sets[2]);
     d = 3;

@@ -66,6 +66,17 @@ hipError_t launch_ttm_fp8(const uint8_t* X, const uint16_t* Bhi, const uint16_t*
 // before it (A2, S x R) into C (P2 x R); FP32, S a multiple of 32 up to 256,
 // 16 < R <= 64, X 16-byte aligned (ttm_kc_fused_fits).
 bool ttm_kc_fused_fits(const float* X, int64_t K, int64_t S, int R);
+// The trailing half's first two levels in one pass (standard tree): X is
+// K x (S1 Qp) (modes 0, 1, the rest; K a multiple of 32 up to 256, Qp a
+// multiple of 64, S1 Qp < 2^28, R <= 64, 16-byte aligned: ttm_q_fused_fits),
+// contracted with B (K x R) and then A1 (S1 x R) into C (Qp x R); parts holds
+// q_fused_layers(S1, Qp) Qp R floats of partials when that is above one.
+bool ttm_q_fused_shape(int64_t K, int64_t S1, int64_t Qp, int R);  // the fits check without X's alignment
+bool ttm_q_fused_fits(const float* X, int64_t K, int64_t S1, int64_t Qp, int R);
+int q_fused_layers(int64_t S1, int64_t Qp);
+hipError_t launch_ttm_q_fused(const float* X, const float* B, const float* A1, float* C, int64_t K, int64_t S1,
+                              int64_t Qp, int R, float* parts, hipStream_t st);
+
 hipError_t launch_ttm_kc_fused(const float* X, const float* B, const float* A2, float* C, int64_t P2, int64_t S,
                                int R, hipStream_t st);
 bool ttm_x3_fits(int64_t P, int64_t K, int64_t Q, int R, const void* X);

@@ -1070,6 +1070,108 @@ __global__ __launch_bounds__(512) void k_ttm_q(const float* __restrict__ X, cons
   }
 }
 
+// The trailing half's first two levels in one pass (standard tree, Sec.
+// II-C: its first-level node feeds exactly one second-level node): the
+// contraction over mode 0 in the k_ttm_q layout (X[k][q], q = i1 Qp + q';
+// whole 64-q tiles, K a multiple of 32, 16-byte aligned, Q < 2^28) and the
+// one over mode 1 (size S1) in the epilogue.  A wave keeps one block of 64
+// consecutive q' and takes the mode-1 indices of its range z = blockIdx.z in
+// order; after each index's product tile (summed over k as in k_ttm_q) it
+// adds the tile times A1[i1][r] to registers:
+//   parts[z][q'][r] = sum_{i1 in range z} A1[i1][r] sum_k X[k][i1 Qp + q'] B[k][r].
+// The ranges' partials are added in range order by the launcher.
+template <int NCB>
+__global__ __launch_bounds__(512) void k_ttm_qf(const float* __restrict__ X, const float* __restrict__ B,
+                                                const float* __restrict__ A1, float* __restrict__ parts, int64_t K,
+                                                int64_t Q, int64_t Qp, int R, int S1, int L) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  float* Bt = (float*)lds_raw;
+  const int Kp = (int)K;  // a multiple of 32
+  const int pitch = Kp + 4;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform (not inferred from tid / 64)
+  const int g = lane >> 4, l16 = lane & 15;
+  const int c0 = blockIdx.y * NCB * 16;
+  constexpr int NC = NCB * 16;
+  for (int idx = tid; idx < Kp * NC; idx += kTtmThreads) {
+    const int k = idx / NC, col = idx - k * NC;
+    const int kc = k & ~31, kr = k & 31;            // k = kc + 4t + g
+    const int pos = kc + 8 * (kr & 3) + (kr >> 2);  // -> kc + 8g + t
+    Bt[col * pitch + pos] = (c0 + col < R) ? B[(int64_t)k * R + c0 + col] : 0.f;
+  }
+  __syncthreads();
+  const int64_t qb = (int64_t)blockIdx.x * kTtmWaves + wave;
+  if (qb >= Qp / 64) return;  // uniform in the wave; no barrier follows
+  const int i1a = (int)blockIdx.z * L;
+  const int i1b = i1a + L < S1 ? i1a + L : S1;
+  const uint32_t lofs = ((uint32_t)g * (uint32_t)Q + 4u * (uint32_t)l16) * 4u;
+  auto load_full = [&](const float* xb, int kc, f32x4 (&a)[8]) {
+#pragma unroll
+    for (int s = 0; s < 8; ++s) a[s] = *(const f32x4*)((const char*)(xb + (int64_t)(kc + 4 * s) * Q) + lofs);
+  };
+  f32x4 part[4][NCB];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) part[u][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+  f32x4 an[8];
+  load_full(X + (int64_t)i1a * Qp + qb * 64, 0, an);
+  for (int i1 = i1a; i1 < i1b; ++i1) {
+    asm volatile("" ::: "memory");  // factor reads stay in the loop
+    const float* xcur = X + (int64_t)i1 * Qp + qb * 64;
+    const float* xnext = i1 + 1 < i1b ? xcur + Qp : xcur;
+    float w[NCB];
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+      const int c = c0 + cb * 16 + l16;
+      w[cb] = c < R ? A1[(int64_t)i1 * R + c] : 0.f;
+    }
+    f32x4 acc[4][NCB];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) acc[u][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int kc = 0; kc < Kp; kc += 32) {
+      f32x4 a[8];
+#pragma unroll
+      for (int st = 0; st < 8; ++st) a[st] = an[st];
+      const bool more = kc + 32 < Kp;
+      load_full(more ? xcur : xnext, more ? kc + 32 : 0, an);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) {
+        const float* bp = Bt + (cb * 16 + l16) * pitch + kc + 8 * g;
+        const f32x4 b0 = *(const f32x4*)bp;
+        const f32x4 b1 = *(const f32x4*)(bp + 4);
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          const float bv = t < 4 ? b0[t & 3] : b1[t & 3];
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            acc[u][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t][u], bv, acc[u][cb], 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) part[u][cb][v] = fmaf(acc[u][cb][v], w[cb], part[u][cb][v]);
+  }
+  float* Pz = parts + (int64_t)blockIdx.z * Qp * R;
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t q = qb * 64 + 16 * g + 4 * v + u;
+        const int c = c0 + cb * 16 + l16;
+        if (c < R) Pz[q * R + c] = part[u][cb][v];
+      }
+}
+
 // First-level contraction over a mode other than the last (the k_ttm_q
 // layout: a wave owns 64 consecutive q, lane (i, g) loads X[k][q0 + 4i ..
 // 4i + 3] for k = kc + 4t + g) when K is too long for the whole factor in
@@ -2470,6 +2572,60 @@ hipError_t launch_ttm_kc_fused(const float* X, const float* B, const float* A2, 
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_ttm_kc32f<2>), dim3(nx, 1), dim3(kTtmThreads), lds, st, X, B, A2, C, R, (int)S, P2);
   }
+  return hipGetLastError();
+}
+
+// The trailing half's first and second levels in one pass (k_ttm_qf): X is
+// K x (S1 Qp) (modes 0, 1, the rest), B = A0 (K x R), A1 (S1 x R), C is
+// Qp x R.  Mode 1 is cut into ranges so that about 2048 waves run; their
+// partials (q_fused_layers(...) Qp R floats in parts) are added in order.
+bool ttm_q_fused_shape(int64_t K, int64_t S1, int64_t Qp, int R) {
+  return K % 32 == 0 && K >= 32 && K <= 256 && Qp % 64 == 0 && Qp >= 64 && S1 >= 1 && S1 * Qp < ((int64_t)1 << 28) &&
+         R >= 1 && R <= 64;
+}
+
+bool ttm_q_fused_fits(const float* X, int64_t K, int64_t S1, int64_t Qp, int R) {
+  return ttm_q_fused_shape(K, S1, Qp, R) && ((uintptr_t)X % 16) == 0;
+}
+
+int q_fused_layers(int64_t S1, int64_t Qp) {
+  const int64_t nqb = Qp / 64;
+  int64_t nz = (2048 + nqb - 1) / (nqb > 0 ? nqb : 1);
+  nz = nz < 1 ? 1 : (nz > S1 ? S1 : nz);
+  const int64_t L = (S1 + nz - 1) / nz;
+  return (int)((S1 + L - 1) / L);
+}
+
+template <int NCB>
+hipError_t launch_ttm_qf_ncb(const float* X, const float* B, const float* A1, float* out, int64_t K, int64_t S1,
+                             int64_t Qp, int R, int L, int nz, hipStream_t st) {
+  static std::atomic<uint64_t> attr{0};
+  const hipError_t e = lds_limit_once(attr, (const void*)k_ttm_qf<NCB>, 160 * 1024);
+  if (e != hipSuccess) return e;
+  const size_t lds = (size_t)NCB * 16 * (K + 4) * sizeof(float);
+  const int64_t nqb = Qp / 64;
+  const unsigned nx = (unsigned)((nqb + kTtmWaves - 1) / kTtmWaves);
+  const unsigned ny = (unsigned)((R + NCB * 16 - 1) / (NCB * 16));
+  hipLaunchKernelGGL((k_ttm_qf<NCB>), dim3(nx, ny, (unsigned)nz), dim3(kTtmThreads), lds, st, X, B, A1, out, K,
+                     S1 * Qp, Qp, R, (int)S1, L);
+  return hipGetLastError();
+}
+
+hipError_t launch_ttm_q_fused(const float* X, const float* B, const float* A1, float* C, int64_t K, int64_t S1,
+                              int64_t Qp, int R, float* parts, hipStream_t st) {
+  if (!ttm_q_fused_fits(X, K, S1, Qp, R)) return hipErrorInvalidValue;
+  const int nz = q_fused_layers(S1, Qp);
+  const int L = (int)((S1 + nz - 1) / nz);
+  float* out = nz > 1 ? parts : C;
+  if (nz > 1 && !parts) return hipErrorInvalidValue;
+  hipError_t e;
+  if (R <= 16) e = launch_ttm_qf_ncb<1>(X, B, A1, out, K, S1, Qp, R, L, nz, st);
+  else if (R <= 32) e = launch_ttm_qf_ncb<2>(X, B, A1, out, K, S1, Qp, R, L, nz, st);
+  else e = launch_ttm_qf_ncb<4>(X, B, A1, out, K, S1, Qp, R, L, nz, st);
+  if (e != hipSuccess || nz == 1) return e;
+  const int64_t n = Qp * R;
+  const int64_t nb = (n / 4 + 255) / 256;
+  hipLaunchKernelGGL((k_sum_parts<float>), dim3((unsigned)(nb < 2048 ? nb : 2048)), dim3(256), 0, st, parts, C, n, nz);
   return hipGetLastError();
 }
 

@@ -1,10 +1,13 @@
-"""GPU parity of the standard tree's fused leading half (FP32 plans: the
-contraction over the last mode, of size 128, and the one over the mode
-before it, a multiple of 32, in one pass without storing the first-level
-node) against the FP64 oracle: MTTKRPs of every mode (the leading modes take
-the fused path, the trailing ones the two-pass path), one and two 32-column
-blocks, one to eight row tiles per output row, orders 4 and 5, free-running
-DT sweeps, and the full-size order-4 128^4 tensor on sampled rows."""
+"""GPU parity of the standard tree's fused halves (FP32 plans; each half's
+first two contractions in one pass without storing the first-level node)
+against the FP64 oracle.  Leading half: the contraction over the last mode,
+of size 128, and the one over the mode before it, a multiple of 32.
+Trailing half: the contraction over mode 0 (a multiple of 32) and over mode
+1, cut into ranges whose partial nodes are added in order.  MTTKRPs of every
+mode (fused and two-pass halves side by side), one to four column blocks,
+one to eight row tiles per output row, ranges of one index and a ragged last
+range, orders 4 and 5, free-running DT sweeps, and the full-size order-4
+128^4 tensor on sampled rows."""
 
 import numpy as np
 import pytest
@@ -24,12 +27,19 @@ def dev():
 
 
 CASES = [
-    # (dims, R): the last mode 128, the one before it a multiple of 32
-    ((7, 9, 32, 128), 24),     # one column block, one tile per output row
-    ((4, 5, 96, 128), 64),     # two column blocks, three tiles per row
-    ((3, 2, 256, 128), 40),    # the largest mode before the last (eight tiles), R past one block
-    ((3, 4, 5, 64, 128), 33),  # order 5
-    ((6, 7, 64, 128), 17),     # R just above the FP32 kernel's lower limit
+    # (dims, R).  Leading half fused: the last mode 128, the one before it a
+    # multiple of 32.  Trailing half fused: mode 0 a multiple of 32, the
+    # product of modes 2.. a multiple of 64.
+    ((7, 9, 32, 128), 24),     # leading: one column block, one tile per output row
+    ((4, 5, 96, 128), 64),     # leading: two column blocks, three tiles per row
+    ((3, 2, 256, 128), 40),    # leading: eight tiles per row, R past one block
+    ((3, 4, 5, 64, 128), 33),  # leading, order 5
+    ((6, 7, 64, 128), 17),     # leading: R just above that kernel's lower limit
+    ((32, 5, 8, 16), 12),      # trailing: one 16-column block, ranges of one index
+    ((64, 3, 16, 8), 24),      # trailing: two blocks
+    ((96, 7, 4, 32), 64),      # trailing: four blocks, K = 96
+    ((32, 13, 128, 128), 20),  # both halves; trailing: ranges of two, the last ragged
+    ((64, 6, 4, 64, 128), 40), # both halves, order 5
 ]
 
 
@@ -52,7 +62,7 @@ def test_fused_mttkrp_every_mode(dev, dims, R):
     plan.close()
 
 
-@pytest.mark.parametrize("dims,R", [((4, 5, 96, 128), 64), ((3, 4, 5, 64, 128), 33)])
+@pytest.mark.parametrize("dims,R", [((4, 5, 96, 128), 64), ((3, 4, 5, 64, 128), 33), ((64, 6, 4, 64, 128), 40)])
 def test_fused_dt_free_running_trajectory(dev, dims, R):
     """Free-running DT sweeps against the oracle's, at the FP32 path's
     tolerances (fitness 1e-6, factors 1e-4)."""
@@ -75,10 +85,11 @@ def test_fused_dt_free_running_trajectory(dev, dims, R):
 
 
 def test_fused_config_o4_s128_r64_sampled(dev):
-    """Full-size order-4 128^4 FP32 tensor, R = 64: the MTTKRPs of modes 0 and
-    1 (the fused leading half) on sampled rows computed one by one by the
-    oracle's definition, with the signed bias bound of the other full-size
-    checks."""
+    """Full-size order-4 128^4 FP32 tensor, R = 64: the MTTKRPs of every mode
+    on sampled rows computed one by one by the
+    oracle's definition (modes 0 and 1 from the fused leading half, 2 and 3
+    from the fused trailing half), with the signed bias bound of the other
+    full-size checks."""
     from oracle import core
     from paper_2010_12056_amd import cpals, synth
 
@@ -88,7 +99,7 @@ def test_fused_config_o4_s128_r64_sampled(dev):
     plan.set_tensor(torch.from_numpy(w.T).to(dev))
     A = to_dev(w.init, dev)
     rng = np.random.default_rng(3)
-    for n in (0, 1):
+    for n in range(4):
         rows = rng.choice(w.dims[n], size=6, replace=False)
         K = core.krp([w.init[m] for m in range(4) if m != n])
         X = np.moveaxis(w.T, n, 0)

@@ -101,6 +101,9 @@ TTM_SOURCE_MARKERS = (
     "__global__ __launch_bounds__(512) void k_ttm_kc32(",
     "__global__ __launch_bounds__(512) void k_ttm_kc32f(",
     "hipError_t launch_ttm_kc_fused(",
+    "__global__ __launch_bounds__(512) void k_ttm_qf(",
+    "hipError_t launch_ttm_qf_ncb(",
+    "hipError_t launch_ttm_q_fused(",
     "__global__ __launch_bounds__(512) void k_ttm_q(",
     "hipError_t launch_ttm_kc(",
     "hipError_t launch_ttm_kc32(",
@@ -235,11 +238,17 @@ def tree_bench(args):
     numel = int(np.prod(w.dims))
     ttm_flops = 2 * numel * R
     if args.counters_workload:
-        plan = cpals.Plan(w.dims, R, prec=prec, tree="dt", device=dev)
-        plan.set_tensor(T)
-        for mode in (0, N - 1):  # first-level contraction over the last mode, then over mode 0
-            plan.mttkrp(A0, mode)
-        torch.cuda.synchronize()
+        # one launch of each first-level kernel of the step: the standard
+        # tree's fused halves (modes 0 and N-1 of a DT plan), then the
+        # first-level-only kernels that MSDT and PP keep (an MSDT plan's MTTKRP
+        # walks the same path without fusing)
+        for tree in ("dt", "msdt"):
+            plan = cpals.Plan(w.dims, R, prec=prec, tree=tree, device=dev)
+            plan.set_tensor(T)
+            for mode in (0, N - 1):  # the contraction over the last mode first, then over mode 0
+                plan.mttkrp(A0, mode)
+            torch.cuda.synchronize()
+            plan.close()
         src = torch.empty(128 * 2**20, dtype=torch.float32, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
         dst.copy_(src)  # calibration: reads and writes exactly 512 MiB each
@@ -525,7 +534,8 @@ def tree_bench(args):
         "phase_note": "one extra step with every phase timed (its event pairs make it slower than a timed step)",
         "fitness_per_sweep": {"dt": fit["dt"], "msdt": fit["msdt"]},
         "roofline": {
-            "kernel": "k_ttm (first-level contraction, FP32 MFMA)" if prec == "f32" else
+            "kernel": ("first-level contraction, FP32 MFMA (DT: k_ttm_kc32f / k_ttm_qf with the second "
+                       "level fused; MSDT and PP: k_ttm_kc32 / k_ttm_q)") if prec == "f32" else
                       "k_ttm (first-level contraction, FP64 MFMA)",
             "bound": "mfma",
             "achieved": round(achieved, 3),

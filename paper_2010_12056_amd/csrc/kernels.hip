@@ -627,7 +627,8 @@ __global__ __launch_bounds__(512) void k_ttm_kc32f(const float* __restrict__ X, 
       for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
-          const f32x4 w = *(const f32x4*)(Wt + (cb * 32 + l32) * wp + 32 * q + 8 * m + 4 * h);
+          // 16-byte pieces (wp is a multiple of 4): single 16-byte LDS reads
+          const f32x4 w = ((const f32x4*)Wt)[(cb * 32 + l32) * (wp / 4) + 8 * q + 2 * m + h];
 #pragma unroll
           for (int e = 0; e < 4; ++e) part[cb] = fmaf(acc[cb][4 * m + e], w[e], part[cb]);
         }

@@ -235,6 +235,8 @@ int64_t combined_k_right(cp_plan p) {
   return p->dims[0] * p->dims[1];
 }
 
+size_t fused_parts_floats(cp_plan p);
+
 void plan_layout(cp_plan p) {
   const int N = p->N, R = p->R;
   p->regions.clear();
@@ -285,12 +287,8 @@ void plan_layout(cp_plan p) {
       if (kc > 0) pl = std::max(pl, (size_t)ttm_x3_layers(P, kc, 1, R) * P);
       if (kcr > 0) pr = std::max(pr, (size_t)ttm_x3_layers(1, kcr, Q, R) * Q);
     }
-    // the standard tree's fused trailing half: one partial node per range of mode 1
-    size_t pf = 0;
-    if (p->tree == CP_TREE_DT && p->prec == CP_F32 && N >= 4 && ttm_q_fused_shape(p->dims[0], p->dims[1], Q, R)) {
-      const int nz = q_fused_layers(p->dims[1], Q);
-      if (nz > 1) pf = (size_t)nz * Q;
-    }
+    // the fused first and second levels (path_fused_op): one partial node per range
+    const size_t pf = fused_parts_floats(p) / R;
     take(std::max(std::max(pl, pr), pf) * R * p->esz);  // parts
   }
   {
@@ -494,26 +492,86 @@ int path_combines(cp_plan p, const std::vector<int>& seq) {
   return 0;
 }
 
-// Product of the mode sizes after the first two.
-int64_t trailing_size(cp_plan p) {
-  int64_t q = 1;
-  for (int m = 2; m < p->N; ++m) q *= p->dims[m];
-  return q;
+// The first two contractions of a path from the tensor in one pass, where a
+// fused kernel takes them (FP32 plans).  Standard tree: a half's first-level
+// node feeds only its second-level node, which is formed in the epilogue
+// (kind 1: the last mode, then the one before it; kind 2: mode 0, then mode
+// 1); the first-level node is not kept.  MSDT: a subtree's first child (the
+// mode just before the root) is formed in the epilogue and the first-level
+// node is kept for the subtree's later child (kind 1 for the root N-1, kind 2
+// for a root in the middle; a root at mode 0 is not fused).
+struct FusedOp {
+  int kind = 0;
+  bool store = false;
+  int64_t P2 = 0, S = 0;  // kind 1
+  QgShape sh{};           // kind 2
+};
+
+int64_t mode_product(cp_plan p, int lo, int hi) {
+  int64_t x = 1;
+  for (int m = lo; m < hi; ++m) x *= p->dims[m];
+  return x;
 }
 
-// Whether a path of the standard tree from the tensor starts with the
-// contractions of its half's two outermost modes in a shape a fused kernel
-// takes (FP32 plans).
-// 1 for the leading half (modes N-1, N-2 first), 2 for the trailing half
-// (modes 0, 1 first), 0 otherwise.
-int path_fuses(cp_plan p, const std::vector<int>& seq) {
+// The k_ttm_qg shape of the pair (root a, then b) of a plan, if it is one.
+bool qg_pair_shape(cp_plan p, int a, int b, QgShape* sh) {
   const int N = p->N;
-  if (p->tree != CP_TREE_DT || p->prec != CP_F32 || N < 4 || seq.size() < 3) return 0;
-  if (seq[0] == N - 1 && seq[1] == N - 2)
-    return ttm_kc_fused_fits((const float*)p->T, p->dims[N - 1], p->dims[N - 2], p->R) ? 1 : 0;
-  if (seq[0] == 0 && seq[1] == 1)
-    return ttm_q_fused_fits((const float*)p->T, p->dims[0], p->dims[1], trailing_size(p), p->R) ? 2 : 0;
-  return 0;
+  if (p->tree == CP_TREE_DT && a == 0 && b == 1) {
+    sh->K = p->dims[0];
+    sh->S = p->dims[1];
+    sh->Q = mode_product(p, 2, N);
+    sh->sstride = sh->Q;
+    sh->kstride = sh->S * sh->Q;
+    sh->nP = 1;
+    sh->pstride = 0;
+    return true;
+  }
+  if (p->tree == CP_TREE_MSDT && a >= 1 && a <= N - 2 && b == a - 1) {
+    sh->K = p->dims[a];
+    sh->S = p->dims[a - 1];
+    sh->Q = mode_product(p, a + 1, N);
+    sh->kstride = sh->Q;
+    sh->sstride = sh->K * sh->Q;
+    sh->nP = mode_product(p, 0, a - 1);
+    sh->pstride = sh->S * sh->sstride;
+    return true;
+  }
+  return false;
+}
+
+bool path_fused_op(cp_plan p, const std::vector<int>& seq, FusedOp* op) {
+  const int N = p->N;
+  if (p->prec != CP_F32 || N < 4 || seq.size() < 3) return false;
+  if (p->tree != CP_TREE_DT && p->tree != CP_TREE_MSDT) return false;
+  const bool msdt = p->tree == CP_TREE_MSDT;
+  const int a = seq[0], b = seq[1];
+  if (a == N - 1 && b == N - 2) {
+    if (!ttm_kc_fused_fits((const float*)p->T, p->dims[N - 1], p->dims[N - 2], p->R)) return false;
+    op->kind = 1;
+    op->store = msdt;
+    op->P2 = mode_product(p, 0, N - 2);
+    op->S = p->dims[N - 2];
+    return true;
+  }
+  QgShape sh;
+  if (!qg_pair_shape(p, a, b, &sh) || !ttm_qg_fits((const float*)p->T, sh, p->R)) return false;
+  op->kind = 2;
+  op->store = msdt;
+  op->sh = sh;
+  return true;
+}
+
+// Partial-node floats the fused kernels of this plan can need (0: none).
+size_t fused_parts_floats(cp_plan p) {
+  size_t need = 0;
+  if (p->prec != CP_F32 || p->N < 4) return 0;
+  for (int a = 0; a < p->N; ++a) {
+    QgShape sh;
+    if (!qg_pair_shape(p, a, a == 0 ? 1 : a - 1, &sh) || !ttm_qg_shape(sh, p->R)) continue;
+    const int nz = qg_layers(sh);
+    if (nz > 1) need = std::max(need, (size_t)nz * sh.nP * sh.Q * p->R);
+  }
+  return need;
 }
 
 // Walk a root-to-leaf contraction sequence; M (FP64, s_leaf x R) receives the leaf.
@@ -542,24 +600,25 @@ cp_status run_path(cp_plan p, const std::vector<int>& seq, double* M) {
   const int start = path_start(p, seq, &sets);
   int d = start + 1;
   const int side = (d == 1) ? path_combines(p, seq) : 0;
-  const int fuse = (!side && d == 1 && len >= 3) ? path_fuses(p, seq) : 0;
-  if (fuse) {
-    // standard tree: a half's first-level node feeds only this second-level
-    // node, so both come from one pass and the first is not kept
-    if ((size_t)node_numel(p, sets[2]) * p->esz > p->slot_cap[2])
-      return fail(p, CP_ERR_STATE, "internal: slot 2 too small");
+  FusedOp op;
+  if (!side && d == 1 && len >= 3 && path_fused_op(p, seq, &op)) {
+    // the first two contractions in one pass (path_fused_op); the
+    // first-level node is written only where the tree keeps it
+    if ((size_t)node_numel(p, sets[2]) * p->esz > p->slot_cap[2] ||
+        (op.store && (size_t)node_numel(p, sets[1]) * p->esz > p->slot_cap[1]))
+      return fail(p, CP_ERR_STATE, "internal: slot too small");
     ++p->ttm_count;
     ProfScope ps(p, CP_PHASE_TTM);
-    if (fuse == 1) {
-      int64_t P2 = 1;
-      for (int m = 0; m < N - 2; ++m) P2 *= p->dims[m];
-      HIP_TRY(p, launch_ttm_kc_fused((const float*)p->T, (const float*)p->Ash[N - 1], (const float*)p->Ash[N - 2],
-                                     (float*)p->slot_buf[2], P2, p->dims[N - 2], p->R, p->st));
+    const float* B = (const float*)p->Ash[seq[0]];
+    const float* W = (const float*)p->Ash[seq[1]];
+    float* Y = op.store ? (float*)p->slot_buf[1] : nullptr;
+    if (op.kind == 1) {
+      HIP_TRY(p, launch_ttm_kc_fused((const float*)p->T, B, W, (float*)p->slot_buf[2], Y, op.P2, op.S, p->R, p->st));
     } else {
-      HIP_TRY(p, launch_ttm_q_fused((const float*)p->T, (const float*)p->Ash[0], (const float*)p->Ash[1],
-                                    (float*)p->slot_buf[2], p->dims[0], p->dims[1], trailing_size(p), p->R,
-                                    (float*)p->parts, p->st));
+      HIP_TRY(p, launch_ttm_qg((const float*)p->T, B, W, (float*)p->slot_buf[2], Y, op.sh, p->R, (float*)p->parts,
+                               p->st));
     }
+    if (op.store) slot_record(p, 1, sets[1]);
     slot_record(p, 2, sets[2]);
     d = 3;
   }

@@ -61,28 +61,35 @@ hipError_t launch_ttm_fp8(const uint8_t* X, const uint16_t* Bhi, const uint16_t*
 // `parts` (ttm_x3_layers(P, K, Q, R) P Q R floats) a contraction with too few
 // row tiles to fill the chip is split over K, its partials added in order;
 // null: no split.
-// The leading half's first two levels in one pass (standard tree): X is
-// (P2 S) x K with K == 128 (contracted with B, K x R), then the mode of size S
-// before it (A2, S x R) into C (P2 x R); FP32, S a multiple of 32 up to 256,
-// 16 < R <= 64, X 16-byte aligned (ttm_kc_fused_fits).
-bool ttm_kc_fused_fits(const float* X, int64_t K, int64_t S, int R);
-// The trailing half's first two levels in one pass (standard tree): X is
-// K x (S1 Qp) (modes 0, 1, the rest; K a multiple of 32 up to 256, Qp a
-// multiple of 64, S1 Qp < 2^28, R <= 64, 16-byte aligned: ttm_q_fused_fits),
-// contracted with B (K x R) and then A1 (S1 x R) into C (Qp x R); parts holds
-// q_fused_layers(S1, Qp) Qp R floats of partials when that is above one.
-bool ttm_q_fused_shape(int64_t K, int64_t S1, int64_t Qp, int R);  // the fits check without X's alignment
-bool ttm_q_fused_fits(const float* X, int64_t K, int64_t S1, int64_t Qp, int R);
-int q_fused_layers(int64_t S1, int64_t Qp);
-hipError_t launch_ttm_q_fused(const float* X, const float* B, const float* A1, float* C, int64_t K, int64_t S1,
-                              int64_t Qp, int R, float* parts, hipStream_t st);
-
-hipError_t launch_ttm_kc_fused(const float* X, const float* B, const float* A2, float* C, int64_t P2, int64_t S,
-                               int R, hipStream_t st);
 bool ttm_x3_fits(int64_t P, int64_t K, int64_t Q, int R, const void* X);
 int ttm_x3_layers(int64_t P, int64_t K, int64_t Q, int R);
 hipError_t launch_split3_factor(const float* A, int64_t K, int R, uint16_t* Bt, hipStream_t st);
 hipError_t launch_ttm_x3(const float* X, const uint16_t* Bt, float* C, int64_t P, int64_t K, int64_t Q, int R,
+                         float* parts, hipStream_t st);
+
+// The leading half's first two levels in one pass (k_ttm_kc32f): X is
+// (P2 S) x K with K == 128 (contracted with B, K x R), then the mode of size S
+// before it (A2, S x R) into C (P2 x R); FP32, S a multiple of 32 up to 256,
+// 16 < R <= 64, X 16-byte aligned (ttm_kc_fused_fits).  With Y non-null the
+// first-level node ((P2 S) x R) is written too (a tree that keeps it).
+bool ttm_kc_fused_fits(const float* X, int64_t K, int64_t S, int R);
+hipError_t launch_ttm_kc_fused(const float* X, const float* B, const float* A2, float* C, float* Y, int64_t P2,
+                               int64_t S, int R, hipStream_t st);
+
+// A first-level contraction in the q-contiguous layout with the contraction
+// over one more index i in its epilogue (k_ttm_qg): element (p', i, k, q) of
+// X at p' pstride + i sstride + k kstride + q; q < Q contiguous (Q a
+// multiple of 64), k < K (a multiple of 32 up to 256), i < S, p' < nP.
+// C[p'][q][r] = sum_i W[i][r] sum_k X[p', i, k, q] B[k][r]; with Y non-null
+// also the first-level node Y[p' S + i][q][r].  parts holds
+// qg_layers(sh) nP Q R floats of partials when that is above one.
+struct QgShape {
+  int64_t K, kstride, S, sstride, nP, pstride, Q;
+};
+bool ttm_qg_shape(const QgShape& sh, int R);  // the fits check without X's alignment
+bool ttm_qg_fits(const float* X, const QgShape& sh, int R);
+int qg_layers(const QgShape& sh);
+hipError_t launch_ttm_qg(const float* X, const float* B, const float* W, float* C, float* Y, const QgShape& sh, int R,
                          float* parts, hipStream_t st);
 
 // Y[p][q][r] = sum_i X[p][i][q][r] * A[i][r]; accumulation in the output type.

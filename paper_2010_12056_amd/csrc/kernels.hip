@@ -557,11 +557,13 @@ __global__ __launch_bounds__(512) void k_ttm_kc32(const float* __restrict__ X, c
 // staged transposed in LDS, and sums them in FP32 over the row's tiles; the
 // two lane halves are added at the end.  The first level's sums are those of
 // k_ttm_kc32; the second level's are taken in another order than k_mttv's.
+// STORE: the first-level node is written too, as k_ttm_kc32 writes it (for
+// a tree that keeps it for a later child, MSDT).
 constexpr int kFusedMaxS = 256;
-template <int NCB>
+template <int NCB, bool STORE>
 __global__ __launch_bounds__(512) void k_ttm_kc32f(const float* __restrict__ X, const float* __restrict__ B,
-                                                   const float* __restrict__ A2, float* __restrict__ C, int R, int S,
-                                                   int64_t ngroups) {
+                                                   const float* __restrict__ A2, float* __restrict__ C,
+                                                   float* __restrict__ Y, int R, int S, int64_t ngroups) {
   constexpr int K = 128;
   constexpr int NS = K / 8;
   constexpr int pitch = K + 4;
@@ -623,6 +625,25 @@ __global__ __launch_bounds__(512) void k_ttm_kc32f(const float* __restrict__ X, 
             acc[cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[st][j], b[cb][j], acc[cb], 0, 0, 0);
       }
       // register v of the lane is product row 8 (v / 4) + 4 h + v % 4 of the tile
+      if constexpr (STORE) {
+        const int64_t r0 = tile * 32;
+        if (c0 + NC <= R) {
+          const uint32_t so = ((uint32_t)(4 * h) * (uint32_t)R + (uint32_t)l32) * 4u;
+#pragma unroll
+          for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+            for (int v = 0; v < 16; ++v)
+              *(float*)((char*)(Y + (r0 + 8 * (v >> 2) + (v & 3)) * R + c0 + cb * 32) + so) = acc[cb][v];
+        } else {
+#pragma unroll
+          for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+              const int c = c0 + cb * 32 + l32;
+              if (c < R) Y[(r0 + 8 * (v >> 2) + 4 * h + (v & 3)) * R + c] = acc[cb][v];
+            }
+        }
+      }
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
@@ -1071,23 +1092,28 @@ __global__ __launch_bounds__(512) void k_ttm_q(const float* __restrict__ X, cons
   }
 }
 
-// The trailing half's first two levels in one pass (standard tree, Sec.
-// II-C: its first-level node feeds exactly one second-level node): the
-// contraction over mode 0 in the k_ttm_q layout (X[k][q], q = i1 Qp + q';
-// whole 64-q tiles, K a multiple of 32, 16-byte aligned, Q < 2^28) and the
-// one over mode 1 (size S1) in the epilogue.  A wave keeps one block of 64
-// consecutive q' and takes the mode-1 indices of its range z = blockIdx.z in
+// A first-level contraction in the k_ttm_q layout with the contraction over
+// one more index i in its epilogue (a dimension-tree node's first child
+// formed in the same pass).  Element (p', i, k, q) of X sits at
+// p' pstride + i sstride + k kstride + q (q contiguous, Q a multiple of 64;
+// K a multiple of 32, 16-byte aligned); B (K x R) is contracted over k and
+// W (S x R) over i:
+//   out[z][p'][q][r] = sum_{i in range z} W[i][r] sum_k X[p', i, k, q] B[k][r],
+// and with STORE the first-level node itself, Y[p' S + i][q][r], is written
+// too (when the tree keeps it for a later child).  A wave keeps one pair
+// (p', block of 64 q) and walks the indices i of its range z = blockIdx.z in
 // order; after each index's product tile (summed over k as in k_ttm_q) it
-// adds the tile times A1[i1][r] to registers:
-//   parts[z][q'][r] = sum_{i1 in range z} A1[i1][r] sum_k X[k][i1 Qp + q'] B[k][r].
-// The ranges' partials are added in range order by the launcher.
-template <int NCB>
-__global__ __launch_bounds__(512) void k_ttm_qf(const float* __restrict__ X, const float* __restrict__ B,
-                                                const float* __restrict__ A1, float* __restrict__ parts, int64_t K,
-                                                int64_t Q, int64_t Qp, int R, int S1, int L) {
+// adds the tile times W[i][r] to registers.  The launcher adds the ranges'
+// partials in range order.  The standard tree's trailing half is the case
+// p' = (), i = mode 1 (sstride Qp, kstride S Qp); MSDT's root at a middle
+// mode m the case p' = modes before m - 1, i = mode m - 1.
+template <int NCB, bool STORE>
+__global__ __launch_bounds__(512) void k_ttm_qg(const float* __restrict__ X, const float* __restrict__ B,
+                                                const float* __restrict__ W, float* __restrict__ out,
+                                                float* __restrict__ Y, QgShape sh, int R, int L) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   float* Bt = (float*)lds_raw;
-  const int Kp = (int)K;  // a multiple of 32
+  const int Kp = (int)sh.K;  // a multiple of 32
   const int pitch = Kp + 4;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform (not inferred from tid / 64)
@@ -1101,31 +1127,35 @@ __global__ __launch_bounds__(512) void k_ttm_qf(const float* __restrict__ X, con
     Bt[col * pitch + pos] = (c0 + col < R) ? B[(int64_t)k * R + c0 + col] : 0.f;
   }
   __syncthreads();
-  const int64_t qb = (int64_t)blockIdx.x * kTtmWaves + wave;
-  if (qb >= Qp / 64) return;  // uniform in the wave; no barrier follows
-  const int i1a = (int)blockIdx.z * L;
-  const int i1b = i1a + L < S1 ? i1a + L : S1;
-  const uint32_t lofs = ((uint32_t)g * (uint32_t)Q + 4u * (uint32_t)l16) * 4u;
+  const int64_t nqb = sh.Q / 64;
+  const int64_t pair = (int64_t)blockIdx.x * kTtmWaves + wave;
+  if (pair >= sh.nP * nqb) return;  // uniform in the wave; no barrier follows
+  const int64_t pp = pair / nqb, qb = pair - pp * nqb;
+  const int ia = (int)blockIdx.z * L;
+  const int ib = ia + L < sh.S ? ia + L : (int)sh.S;
+  const uint32_t lofs = ((uint32_t)g * (uint32_t)sh.kstride + 4u * (uint32_t)l16) * 4u;
   auto load_full = [&](const float* xb, int kc, f32x4 (&a)[8]) {
 #pragma unroll
-    for (int s = 0; s < 8; ++s) a[s] = *(const f32x4*)((const char*)(xb + (int64_t)(kc + 4 * s) * Q) + lofs);
+    for (int s = 0; s < 8; ++s)
+      a[s] = *(const f32x4*)((const char*)(xb + (int64_t)(kc + 4 * s) * sh.kstride) + lofs);
   };
+  const float* xp = X + pp * sh.pstride + qb * 64;
   f32x4 part[4][NCB];
 #pragma unroll
   for (int u = 0; u < 4; ++u)
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) part[u][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
   f32x4 an[8];
-  load_full(X + (int64_t)i1a * Qp + qb * 64, 0, an);
-  for (int i1 = i1a; i1 < i1b; ++i1) {
+  load_full(xp + (int64_t)ia * sh.sstride, 0, an);
+  for (int i = ia; i < ib; ++i) {
     asm volatile("" ::: "memory");  // factor reads stay in the loop
-    const float* xcur = X + (int64_t)i1 * Qp + qb * 64;
-    const float* xnext = i1 + 1 < i1b ? xcur + Qp : xcur;
+    const float* xcur = xp + (int64_t)i * sh.sstride;
+    const float* xnext = i + 1 < ib ? xcur + sh.sstride : xcur;
     float w[NCB];
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) {
       const int c = c0 + cb * 16 + l16;
-      w[cb] = c < R ? A1[(int64_t)i1 * R + c] : 0.f;
+      w[cb] = c < R ? W[(int64_t)i * R + c] : 0.f;
     }
     f32x4 acc[4][NCB];
 #pragma unroll
@@ -1153,6 +1183,30 @@ __global__ __launch_bounds__(512) void k_ttm_qf(const float* __restrict__ X, con
         }
       }
     }
+    if constexpr (STORE) {
+      // the first-level node, row p' S + i: register v of block u is q = 16 g + 4 v + u of the block
+      float* Yr = Y + ((pp * sh.S + i) * sh.Q + qb * 64) * R;
+      if (c0 + NC <= R) {
+        const uint32_t so = ((uint32_t)(16 * g) * (uint32_t)R + (uint32_t)l16) * 4u;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+              *(float*)((char*)(Yr + (int64_t)(4 * v + u) * R + c0 + cb * 16) + so) = acc[u][cb][v];
+      } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int c = c0 + cb * 16 + l16;
+              if (c < R) Yr[(int64_t)(16 * g + 4 * v + u) * R + c] = acc[u][cb][v];
+            }
+      }
+    }
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
@@ -1160,7 +1214,7 @@ __global__ __launch_bounds__(512) void k_ttm_qf(const float* __restrict__ X, con
 #pragma unroll
         for (int v = 0; v < 4; ++v) part[u][cb][v] = fmaf(acc[u][cb][v], w[cb], part[u][cb][v]);
   }
-  float* Pz = parts + (int64_t)blockIdx.z * Qp * R;
+  float* Pz = out + ((int64_t)blockIdx.z * sh.nP + pp) * sh.Q * R;
 #pragma unroll
   for (int u = 0; u < 4; ++u)
 #pragma unroll
@@ -2558,73 +2612,84 @@ bool ttm_kc_fused_fits(const float* X, int64_t K, int64_t S, int R) {
   return K == 128 && S % 32 == 0 && S >= 32 && S <= kFusedMaxS && R > 16 && R <= 64 && ((uintptr_t)X % 16) == 0;
 }
 
-hipError_t launch_ttm_kc_fused(const float* X, const float* B, const float* A2, float* C, int64_t P2, int64_t S,
-                               int R, hipStream_t st) {
-  if (!ttm_kc_fused_fits(X, 128, S, R) || P2 < 1) return hipErrorInvalidValue;
+template <bool STORE>
+hipError_t launch_kc32f(const float* X, const float* B, const float* A2, float* C, float* Y, int64_t P2, int64_t S,
+                        int R, hipStream_t st) {
   const int64_t want = (P2 + kTtmWaves - 1) / kTtmWaves;
   const unsigned nx = (unsigned)(want < 256 ? want : 256);
   const size_t lds = (size_t)64 * (S + 4) * sizeof(float);
   if (R <= 32) {
-    hipLaunchKernelGGL((k_ttm_kc32f<1>), dim3(nx, 1), dim3(kTtmThreads), lds / 2, st, X, B, A2, C, R, (int)S, P2);
+    hipLaunchKernelGGL((k_ttm_kc32f<1, STORE>), dim3(nx, 1), dim3(kTtmThreads), lds / 2, st, X, B, A2, C, Y, R,
+                       (int)S, P2);
   } else {
     static std::atomic<uint64_t> attr{0};
     // dynamic part only (the kernel also holds 33 KB of static LDS): 64 (kFusedMaxS + 4) floats
-    const hipError_t e = lds_limit_once(attr, (const void*)k_ttm_kc32f<2>, 96 * 1024);
+    const hipError_t e = lds_limit_once(attr, (const void*)k_ttm_kc32f<2, STORE>, 96 * 1024);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_ttm_kc32f<2>), dim3(nx, 1), dim3(kTtmThreads), lds, st, X, B, A2, C, R, (int)S, P2);
+    hipLaunchKernelGGL((k_ttm_kc32f<2, STORE>), dim3(nx, 1), dim3(kTtmThreads), lds, st, X, B, A2, C, Y, R, (int)S,
+                       P2);
   }
   return hipGetLastError();
 }
 
-// The trailing half's first and second levels in one pass (k_ttm_qf): X is
-// K x (S1 Qp) (modes 0, 1, the rest), B = A0 (K x R), A1 (S1 x R), C is
-// Qp x R.  Mode 1 is cut into ranges so that about 2048 waves run; their
-// partials (q_fused_layers(...) Qp R floats in parts) are added in order.
-bool ttm_q_fused_shape(int64_t K, int64_t S1, int64_t Qp, int R) {
-  return K % 32 == 0 && K >= 32 && K <= 256 && Qp % 64 == 0 && Qp >= 64 && S1 >= 1 && S1 * Qp < ((int64_t)1 << 28) &&
-         R >= 1 && R <= 64;
+hipError_t launch_ttm_kc_fused(const float* X, const float* B, const float* A2, float* C, float* Y, int64_t P2,
+                               int64_t S, int R, hipStream_t st) {
+  if (!ttm_kc_fused_fits(X, 128, S, R) || P2 < 1) return hipErrorInvalidValue;
+  return Y ? launch_kc32f<true>(X, B, A2, C, Y, P2, S, R, st) : launch_kc32f<false>(X, B, A2, C, Y, P2, S, R, st);
 }
 
-bool ttm_q_fused_fits(const float* X, int64_t K, int64_t S1, int64_t Qp, int R) {
-  return ttm_q_fused_shape(K, S1, Qp, R) && ((uintptr_t)X % 16) == 0;
+// k_ttm_qg's shape limits: K a multiple of 32 up to 256, Q a multiple of 64,
+// 32-bit lane offsets (kstride < 2^28), R <= 64, X 16-byte aligned.
+bool ttm_qg_shape(const QgShape& sh, int R) {
+  return sh.K % 32 == 0 && sh.K >= 32 && sh.K <= 256 && sh.Q % 64 == 0 && sh.Q >= 64 && sh.S >= 1 && sh.nP >= 1 &&
+         sh.kstride >= sh.Q && sh.kstride < ((int64_t)1 << 28) && R >= 1 && R <= 64;
 }
 
-int q_fused_layers(int64_t S1, int64_t Qp) {
-  const int64_t nqb = Qp / 64;
-  int64_t nz = (2048 + nqb - 1) / (nqb > 0 ? nqb : 1);
-  nz = nz < 1 ? 1 : (nz > S1 ? S1 : nz);
-  const int64_t L = (S1 + nz - 1) / nz;
-  return (int)((S1 + L - 1) / L);
+bool ttm_qg_fits(const float* X, const QgShape& sh, int R) {
+  return ttm_qg_shape(sh, R) && ((uintptr_t)X % 16) == 0;
 }
 
-template <int NCB>
-hipError_t launch_ttm_qf_ncb(const float* X, const float* B, const float* A1, float* out, int64_t K, int64_t S1,
-                             int64_t Qp, int R, int L, int nz, hipStream_t st) {
+// Ranges of i: enough (p', q block) x range waves for about 2048.
+int qg_layers(const QgShape& sh) {
+  const int64_t pairs = sh.nP * (sh.Q / 64);
+  int64_t nz = (2048 + pairs - 1) / (pairs > 0 ? pairs : 1);
+  nz = nz < 1 ? 1 : (nz > sh.S ? sh.S : nz);
+  const int64_t L = (sh.S + nz - 1) / nz;
+  return (int)((sh.S + L - 1) / L);
+}
+
+template <int NCB, bool STORE>
+hipError_t launch_ttm_qg_ncb(const float* X, const float* B, const float* W, float* out, float* Y, const QgShape& sh,
+                             int R, int L, int nz, hipStream_t st) {
   static std::atomic<uint64_t> attr{0};
-  const hipError_t e = lds_limit_once(attr, (const void*)k_ttm_qf<NCB>, 160 * 1024);
+  const hipError_t e = lds_limit_once(attr, (const void*)k_ttm_qg<NCB, STORE>, 160 * 1024);
   if (e != hipSuccess) return e;
-  const size_t lds = (size_t)NCB * 16 * (K + 4) * sizeof(float);
-  const int64_t nqb = Qp / 64;
-  const unsigned nx = (unsigned)((nqb + kTtmWaves - 1) / kTtmWaves);
+  const size_t lds = (size_t)NCB * 16 * (sh.K + 4) * sizeof(float);
+  const int64_t pairs = sh.nP * (sh.Q / 64);
+  const unsigned nx = (unsigned)((pairs + kTtmWaves - 1) / kTtmWaves);
   const unsigned ny = (unsigned)((R + NCB * 16 - 1) / (NCB * 16));
-  hipLaunchKernelGGL((k_ttm_qf<NCB>), dim3(nx, ny, (unsigned)nz), dim3(kTtmThreads), lds, st, X, B, A1, out, K,
-                     S1 * Qp, Qp, R, (int)S1, L);
+  hipLaunchKernelGGL((k_ttm_qg<NCB, STORE>), dim3(nx, ny, (unsigned)nz), dim3(kTtmThreads), lds, st, X, B, W, out, Y,
+                     sh, R, L);
   return hipGetLastError();
 }
 
-hipError_t launch_ttm_q_fused(const float* X, const float* B, const float* A1, float* C, int64_t K, int64_t S1,
-                              int64_t Qp, int R, float* parts, hipStream_t st) {
-  if (!ttm_q_fused_fits(X, K, S1, Qp, R)) return hipErrorInvalidValue;
-  const int nz = q_fused_layers(S1, Qp);
-  const int L = (int)((S1 + nz - 1) / nz);
+hipError_t launch_ttm_qg(const float* X, const float* B, const float* W, float* C, float* Y, const QgShape& sh, int R,
+                         float* parts, hipStream_t st) {
+  if (!ttm_qg_fits(X, sh, R)) return hipErrorInvalidValue;
+  const int nz = qg_layers(sh);
+  const int L = (int)((sh.S + nz - 1) / nz);
   float* out = nz > 1 ? parts : C;
   if (nz > 1 && !parts) return hipErrorInvalidValue;
   hipError_t e;
-  if (R <= 16) e = launch_ttm_qf_ncb<1>(X, B, A1, out, K, S1, Qp, R, L, nz, st);
-  else if (R <= 32) e = launch_ttm_qf_ncb<2>(X, B, A1, out, K, S1, Qp, R, L, nz, st);
-  else e = launch_ttm_qf_ncb<4>(X, B, A1, out, K, S1, Qp, R, L, nz, st);
+#define CPALS_QG(NCB)                                                                                      \
+  e = Y ? launch_ttm_qg_ncb<NCB, true>(X, B, W, out, Y, sh, R, L, nz, st)                                 \
+        : launch_ttm_qg_ncb<NCB, false>(X, B, W, out, Y, sh, R, L, nz, st)
+  if (R <= 16) CPALS_QG(1);
+  else if (R <= 32) CPALS_QG(2);
+  else CPALS_QG(4);
+#undef CPALS_QG
   if (e != hipSuccess || nz == 1) return e;
-  const int64_t n = Qp * R;
+  const int64_t n = sh.nP * sh.Q * R;
   const int64_t nb = (n / 4 + 255) / 256;
   hipLaunchKernelGGL((k_sum_parts<float>), dim3((unsigned)(nb < 2048 ? nb : 2048)), dim3(256), 0, st, parts, C, n, nz);
   return hipGetLastError();

@@ -1,6 +1,8 @@
-"""GPU parity of the standard tree's fused halves (FP32 plans; each half's
-first two contractions in one pass without storing the first-level node)
-against the FP64 oracle.  Leading half: the contraction over the last mode,
+"""GPU parity of the fused first and second levels (FP32 plans) against the
+FP64 oracle: the standard tree's halves (each half's first two contractions
+in one pass, the first-level node not stored) and MSDT's subtree roots (the
+subtree's first child formed in the first level's epilogue, the first-level
+node stored for the later child).  Leading half: the contraction over the last mode,
 of size 128, and the one over the mode before it, a multiple of 32.
 Trailing half: the contraction over mode 0 (a multiple of 32) and over mode
 1, cut into ranges whose partial nodes are added in order.  MTTKRPs of every
@@ -78,6 +80,31 @@ def test_fused_dt_free_running_trajectory(dev, dims, R):
     for sweep in range(4):
         info = plan.als_sweep(A)
         r_ref = oracle.als_sweep(st)
+        assert abs(info["r"] - r_ref) <= 1e-6, (sweep, info["r"], r_ref)
+        for n in range(len(dims)):
+            assert relerr(A[n].cpu().numpy(), st.A[n]) <= 1e-4, (sweep, n)
+    plan.close()
+
+
+@pytest.mark.parametrize("dims,R,sweeps", [((32, 32, 64, 128), 40, 4), ((3, 32, 32, 32, 128), 24, 5)])
+def test_fused_msdt_free_running_trajectory(dev, dims, R, sweeps):
+    """MSDT sweeps through every subtree root (the last mode and the middle
+    modes take the fused forms that also store the first-level node; a root
+    at mode 0 the two-pass form) against the oracle's ALS sweeps, at the FP32
+    path's tolerances."""
+    import oracle
+    from paper_2010_12056_amd import cpals, synth
+
+    say(f"case fused msdt sweeps dims={dims} R={R}")
+    w = synth.planted_tensor(dims, R, 900 + len(dims) + R, noise_rel=1e-2, dtype=np.float32)
+    plan = cpals.Plan(dims, R, prec="f32", tree="msdt", device=dev)
+    plan.set_tensor(torch.from_numpy(w.T).to(dev))
+    A = to_dev(w.init, dev)
+    st = oracle.AlsState.start(w.T.astype(np.float64), w.init)
+    for sweep in range(sweeps):
+        info = plan.als_sweep(A)
+        r_ref = oracle.als_sweep(st)
+        say(f"  sweep {sweep} r={info['r']:.10f} oracle={r_ref:.10f}")
         assert abs(info["r"] - r_ref) <= 1e-6, (sweep, info["r"], r_ref)
         for n in range(len(dims)):
             assert relerr(A[n].cpu().numpy(), st.A[n]) <= 1e-4, (sweep, n)

@@ -105,6 +105,9 @@ TTM_SOURCE_MARKERS = (
     "hipError_t launch_ttm_qg_ncb(",
     "hipError_t launch_ttm_qg(",
     "hipError_t launch_kc32f(",
+    "__global__ __launch_bounds__(512) void k_ttm_qr(",
+    "hipError_t launch_ttm_qr_ncb(",
+    "hipError_t launch_ttm_qr(",
     "__global__ __launch_bounds__(512) void k_ttm_q(",
     "hipError_t launch_ttm_kc(",
     "hipError_t launch_ttm_kc32(",
@@ -535,8 +538,8 @@ def tree_bench(args):
         "phase_note": "one extra step with every phase timed (its event pairs make it slower than a timed step)",
         "fitness_per_sweep": {"dt": fit["dt"], "msdt": fit["msdt"]},
         "roofline": {
-            "kernel": ("first-level contraction, FP32 MFMA (k_ttm_kc32f / k_ttm_qg with a second-level "
-                       "contraction in the epilogue; k_ttm_kc32 / k_ttm_q alone)") if prec == "f32" else
+            "kernel": ("first-level contraction, FP32 MFMA (k_ttm_kc32f / k_ttm_qg / k_ttm_qr with a "
+                       "second-level contraction in the epilogue; k_ttm_kc32 / k_ttm_q alone)") if prec == "f32" else
                       "k_ttm (first-level contraction, FP64 MFMA)",
             "bound": "mfma",
             "achieved": round(achieved, 3),

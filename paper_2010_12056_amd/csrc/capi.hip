@@ -499,11 +499,13 @@ int path_combines(cp_plan p, const std::vector<int>& seq) {
 // 1); the first-level node is not kept.  MSDT: a subtree's first child (the
 // mode just before the root) is formed in the epilogue and the first-level
 // node is kept for the subtree's later child (kind 1 for the root N-1, kind 2
-// for a root in the middle; a root at mode 0 is not fused).
+// for a root in the middle, kind 3 for the root 0, whose first child is the
+// last mode).
 struct FusedOp {
   int kind = 0;
   bool store = false;
-  int64_t P2 = 0, S = 0;  // kind 1
+  int64_t P2 = 0, S = 0;  // kinds 1 and 3 (P2: kind 1's output rows)
+  int64_t K = 0, Q = 0;   // kind 3
   QgShape sh{};           // kind 2
 };
 
@@ -551,6 +553,16 @@ bool path_fused_op(cp_plan p, const std::vector<int>& seq, FusedOp* op) {
     op->store = msdt;
     op->P2 = mode_product(p, 0, N - 2);
     op->S = p->dims[N - 2];
+    return true;
+  }
+  if (msdt && a == 0 && b == N - 1) {
+    const int64_t Q = mode_product(p, 1, N);
+    if (!ttm_qr_fits((const float*)p->T, p->dims[0], Q, p->dims[N - 1], p->R)) return false;
+    op->kind = 3;
+    op->store = true;
+    op->K = p->dims[0];
+    op->Q = Q;
+    op->S = p->dims[N - 1];
     return true;
   }
   QgShape sh;
@@ -614,6 +626,8 @@ cp_status run_path(cp_plan p, const std::vector<int>& seq, double* M) {
     float* Y = op.store ? (float*)p->slot_buf[1] : nullptr;
     if (op.kind == 1) {
       HIP_TRY(p, launch_ttm_kc_fused((const float*)p->T, B, W, (float*)p->slot_buf[2], Y, op.P2, op.S, p->R, p->st));
+    } else if (op.kind == 3) {
+      HIP_TRY(p, launch_ttm_qr((const float*)p->T, B, W, (float*)p->slot_buf[2], Y, op.K, op.Q, op.S, p->R, p->st));
     } else {
       HIP_TRY(p, launch_ttm_qg((const float*)p->T, B, W, (float*)p->slot_buf[2], Y, op.sh, p->R, (float*)p->parts,
                                p->st));

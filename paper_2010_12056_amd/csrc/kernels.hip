@@ -1227,6 +1227,146 @@ __global__ __launch_bounds__(512) void k_ttm_qg(const float* __restrict__ X, con
       }
 }
 
+// MSDT's root at mode 0: the first level in the k_ttm_q layout (X[k][q],
+// P = 1, whole 64-q tiles, K a multiple of 32 up to 256) with the subtree's
+// first child, the contraction over the last mode (the fastest part of q, of
+// size S = 64 G with G = 1, 2 or 4), in the epilogue:
+//   C[o][r] = sum_i W[i][r] Y[o S + i][r],  Y[q][r] = sum_k X[k][q] B[k][r],
+// and with STORE the first-level node Y too.  The workgroup's eight waves take
+// eight consecutive tiles per step (G waves per output row, wave j of a row
+// its tile j), so the tensor is read as k_ttm_q reads it; lane (g, l16)
+// weights its 16 product rows of the tile (q = 16 g + 4 v + u) by W (staged
+// transposed in LDS), the lane groups are added by shuffles, and the G waves'
+// sums of a row through LDS in tile order.  The waves step together (two
+// barriers a step); a wave past the last row recomputes it without storing.
+template <int NCB, bool STORE>
+__global__ __launch_bounds__(512) void k_ttm_qr(const float* __restrict__ X, const float* __restrict__ B,
+                                                const float* __restrict__ W, float* __restrict__ C,
+                                                float* __restrict__ Y, int64_t K, int64_t Q, int R, int S) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  const int Kp = (int)K;
+  const int pitch = Kp + 4, wp = S + 4;
+  constexpr int NC = NCB * 16;
+  float* Bt = (float*)lds_raw;    // NC x pitch
+  float* Wt = Bt + NC * pitch;    // NC x wp: W transposed
+  float* red = Wt + NC * wp;      // kTtmWaves x NC: the waves' sums of a step
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform (not inferred from tid / 64)
+  const int g = lane >> 4, l16 = lane & 15;
+  const int c0 = blockIdx.y * NC;
+  for (int idx = tid; idx < Kp * NC; idx += kTtmThreads) {
+    const int k = idx / NC, col = idx - k * NC;
+    const int kc = k & ~31, kr = k & 31;            // k = kc + 4t + g
+    const int pos = kc + 8 * (kr & 3) + (kr >> 2);  // -> kc + 8g + t
+    Bt[col * pitch + pos] = (c0 + col < R) ? B[(int64_t)k * R + c0 + col] : 0.f;
+  }
+  for (int idx = tid; idx < S * NC; idx += kTtmThreads) {
+    const int i = idx / NC, col = idx - i * NC;
+    Wt[col * wp + i] = (c0 + col < R) ? W[(int64_t)i * R + c0 + col] : 0.f;
+  }
+  __syncthreads();
+  const int G = S / 64;                 // waves (tiles) per output row
+  const int RPS = kTtmWaves / G;        // output rows per step
+  const int j = wave % G, orow = wave / G;
+  const int64_t nrows = Q / S;
+  const int64_t stride = (int64_t)gridDim.x * RPS;
+  const uint32_t lofs = ((uint32_t)g * (uint32_t)Q + 4u * (uint32_t)l16) * 4u;
+  auto load_full = [&](int64_t t, int kc, f32x4 (&a)[8]) {
+    const float* xb = X + t * 64;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) a[s] = *(const f32x4*)((const char*)(xb + (int64_t)(kc + 4 * s) * Q) + lofs);
+  };
+  int64_t o0 = (int64_t)blockIdx.x * RPS;
+  if (o0 >= nrows) return;  // uniform: the whole workgroup
+  f32x4 an[8];
+  {
+    const int64_t o = o0 + orow < nrows ? o0 + orow : nrows - 1;
+    load_full(o * G + j, 0, an);
+  }
+  for (; o0 < nrows; o0 += stride) {
+    asm volatile("" ::: "memory");  // factor reads stay in the loop
+    const bool own = o0 + orow < nrows;
+    const int64_t o = own ? o0 + orow : nrows - 1;
+    const int64_t tile = o * G + j;
+    const int64_t on = o0 + stride + orow < nrows ? o0 + stride + orow : (o0 + stride < nrows ? nrows - 1 : o);
+    const int64_t tn = on * G + j;
+    f32x4 acc[4][NCB];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) acc[u][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int kc = 0; kc < Kp; kc += 32) {
+      f32x4 a[8];
+#pragma unroll
+      for (int st = 0; st < 8; ++st) a[st] = an[st];
+      const bool more = kc + 32 < Kp;
+      load_full(more ? tile : tn, more ? kc + 32 : 0, an);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) {
+        const float* bp = Bt + (cb * 16 + l16) * pitch + kc + 8 * g;
+        const f32x4 b0 = *(const f32x4*)bp;
+        const f32x4 b1 = *(const f32x4*)(bp + 4);
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          const float bv = t < 4 ? b0[t & 3] : b1[t & 3];
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            acc[u][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t][u], bv, acc[u][cb], 0, 0, 0);
+        }
+      }
+    }
+    if (STORE && own) {
+      float* Yr = Y + tile * 64 * R;
+      if (c0 + NC <= R) {
+        const uint32_t so = ((uint32_t)(16 * g) * (uint32_t)R + (uint32_t)l16) * 4u;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+              *(float*)((char*)(Yr + (int64_t)(4 * v + u) * R + c0 + cb * 16) + so) = acc[u][cb][v];
+      } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int cb = 0; cb < NCB; ++cb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              const int c = c0 + cb * 16 + l16;
+              if (c < R) Yr[(int64_t)(16 * g + 4 * v + u) * R + c] = acc[u][cb][v];
+            }
+      }
+    }
+    // register v of block u is product row q = 16 g + 4 v + u of the tile, index 64 j + q of the row
+#pragma unroll
+    for (int cb = 0; cb < NCB; ++cb) {
+      float part = 0.f;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const f32x4 w = ((const f32x4*)Wt)[(cb * 16 + l16) * (wp / 4) + 16 * j + 4 * g + v];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) part = fmaf(acc[u][cb][v], w[u], part);
+      }
+      part += __shfl_xor(part, 16);
+      part += __shfl_xor(part, 32);
+      if (g == 0) red[wave * NC + cb * 16 + l16] = part;
+    }
+    __syncthreads();
+    if (j == 0 && own && g == 0) {
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) {
+        float tot = red[wave * NC + cb * 16 + l16];
+        for (int jj = 1; jj < G; ++jj) tot += red[(wave + jj) * NC + cb * 16 + l16];
+        const int c = c0 + cb * 16 + l16;
+        if (c < R) C[o * R + c] = tot;
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // First-level contraction over a mode other than the last (the k_ttm_q
 // layout: a wave owns 64 consecutive q, lane (i, g) loads X[k][q0 + 4i ..
 // 4i + 3] for k = kc + 4t + g) when K is too long for the whole factor in
@@ -2693,6 +2833,42 @@ hipError_t launch_ttm_qg(const float* X, const float* B, const float* W, float* 
   const int64_t nb = (n / 4 + 255) / 256;
   hipLaunchKernelGGL((k_sum_parts<float>), dim3((unsigned)(nb < 2048 ? nb : 2048)), dim3(256), 0, st, parts, C, n, nz);
   return hipGetLastError();
+}
+
+// MSDT's root at mode 0 with its first child in the epilogue (k_ttm_qr):
+// X is K x Q, B (K x R), W (S x R, the last mode), C ((Q / S) x R), Y the
+// first-level node (Q x R) or null.
+bool ttm_qr_fits(const float* X, int64_t K, int64_t Q, int64_t S, int R) {
+  return K % 32 == 0 && K >= 32 && K <= 256 && (S == 64 || S == 128 || S == 256) && Q % S == 0 &&
+         Q < ((int64_t)1 << 28) && R >= 1 && R <= 64 && ((uintptr_t)X % 16) == 0;
+}
+
+template <int NCB, bool STORE>
+hipError_t launch_ttm_qr_ncb(const float* X, const float* B, const float* W, float* C, float* Y, int64_t K, int64_t Q,
+                             int64_t S, int R, hipStream_t st) {
+  static std::atomic<uint64_t> attr{0};
+  const hipError_t e = lds_limit_once(attr, (const void*)k_ttm_qr<NCB, STORE>, 160 * 1024);
+  if (e != hipSuccess) return e;
+  const size_t lds = (size_t)NCB * 16 * ((K + 4) + (S + 4) + kTtmWaves) * sizeof(float);
+  const int64_t rps = kTtmWaves / (S / 64);  // output rows per workgroup step
+  const int64_t want = (Q / S + rps - 1) / rps;
+  const unsigned nx = (unsigned)(want < 256 ? want : 256);
+  const unsigned ny = (unsigned)((R + NCB * 16 - 1) / (NCB * 16));
+  hipLaunchKernelGGL((k_ttm_qr<NCB, STORE>), dim3(nx, ny), dim3(kTtmThreads), lds, st, X, B, W, C, Y, K, Q, R,
+                     (int)S);
+  return hipGetLastError();
+}
+
+hipError_t launch_ttm_qr(const float* X, const float* B, const float* W, float* C, float* Y, int64_t K, int64_t Q,
+                         int64_t S, int R, hipStream_t st) {
+  if (!ttm_qr_fits(X, K, Q, S, R)) return hipErrorInvalidValue;
+#define CPALS_QR(NCB)                                                             \
+  return Y ? launch_ttm_qr_ncb<NCB, true>(X, B, W, C, Y, K, Q, S, R, st)          \
+           : launch_ttm_qr_ncb<NCB, false>(X, B, W, C, Y, K, Q, S, R, st)
+  if (R <= 16) CPALS_QR(1);
+  if (R <= 32) CPALS_QR(2);
+  CPALS_QR(4);
+#undef CPALS_QR
 }
 
 template <typename T, int NCB>

@@ -86,12 +86,15 @@ def test_fused_dt_free_running_trajectory(dev, dims, R):
     plan.close()
 
 
-@pytest.mark.parametrize("dims,R,sweeps", [((32, 32, 64, 128), 40, 4), ((3, 32, 32, 32, 128), 24, 5)])
+@pytest.mark.parametrize("dims,R,sweeps", [((32, 32, 64, 128), 40, 4), ((3, 32, 32, 32, 128), 24, 5),
+                                            ((64, 16, 8, 64), 16, 4)])
 def test_fused_msdt_free_running_trajectory(dev, dims, R, sweeps):
-    """MSDT sweeps through every subtree root (the last mode and the middle
-    modes take the fused forms that also store the first-level node; a root
-    at mode 0 the two-pass form) against the oracle's ALS sweeps, at the FP32
-    path's tolerances."""
+    """MSDT sweeps through every subtree root against the oracle's ALS
+    sweeps, at the FP32 path's tolerances.  The fused forms that also store
+    the first-level node: the last-mode root (32 x 32 x 64 x 128 and order 5),
+    the middle roots (both), the mode-0 root with the last mode in the
+    epilogue (32 x 32 x 64 x 128, four column blocks past R; 64 x 16 x 8 x 64,
+    one block); the other roots take the two-pass form."""
     import oracle
     from paper_2010_12056_amd import cpals, synth
 

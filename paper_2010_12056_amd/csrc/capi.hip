@@ -515,74 +515,104 @@ int64_t mode_product(cp_plan p, int lo, int hi) {
   return x;
 }
 
-// The k_ttm_qg shape of the pair (root a, then b) of a plan, if it is one.
+// k_ttm_qg's shape for contracting mode a, then mode b, of the tensor (row
+// major, element stride st_j = s_{j+1} ... s_{N-1}): k is mode a (stride
+// st_a), i is mode b (stride st_b), q the modes after both (contiguous), and
+// p' the remaining modes, which must form one strided run: the modes between
+// a and b (when a or b is mode 0) or those before both (when a and b are
+// neighbours).  The output node keeps p' then q, as the tree's node layout.
 bool qg_pair_shape(cp_plan p, int a, int b, QgShape* sh) {
   const int N = p->N;
-  if (p->tree == CP_TREE_DT && a == 0 && b == 1) {
-    sh->K = p->dims[0];
-    sh->S = p->dims[1];
-    sh->Q = mode_product(p, 2, N);
-    sh->sstride = sh->Q;
-    sh->kstride = sh->S * sh->Q;
-    sh->nP = 1;
-    sh->pstride = 0;
+  if (a == b || a < 0 || b < 0 || a >= N || b >= N) return false;
+  const int lo = std::min(a, b), hi = std::max(a, b);
+  auto st = [&](int j) { return mode_product(p, j + 1, N); };
+  sh->K = p->dims[a];
+  sh->kstride = st(a);
+  sh->S = p->dims[b];
+  sh->sstride = st(b);
+  sh->Q = st(hi);
+  if (hi == lo + 1) {  // neighbours: p' = the modes before both
+    sh->nP = mode_product(p, 0, lo);
+    sh->pstride = lo > 0 ? st(lo - 1) : 0;
     return true;
   }
-  if (p->tree == CP_TREE_MSDT && a >= 1 && a <= N - 2 && b == a - 1) {
-    sh->K = p->dims[a];
-    sh->S = p->dims[a - 1];
-    sh->Q = mode_product(p, a + 1, N);
-    sh->kstride = sh->Q;
-    sh->sstride = sh->K * sh->Q;
-    sh->nP = mode_product(p, 0, a - 1);
-    sh->pstride = sh->S * sh->sstride;
+  if (lo == 0) {  // p' = the modes between
+    sh->nP = mode_product(p, 1, hi);
+    sh->pstride = st(hi - 1);
     return true;
   }
   return false;
 }
 
-bool path_fused_op(cp_plan p, const std::vector<int>& seq, FusedOp* op) {
+// The fused kernel for contracting mode a, then mode b, from the tensor
+// (store: the first-level node is written too).
+bool fused_op_for(cp_plan p, int a, int b, bool store, FusedOp* op) {
   const int N = p->N;
-  if (p->prec != CP_F32 || N < 4 || seq.size() < 3) return false;
-  if (p->tree != CP_TREE_DT && p->tree != CP_TREE_MSDT) return false;
-  const bool msdt = p->tree == CP_TREE_MSDT;
-  const int a = seq[0], b = seq[1];
-  if (a == N - 1 && b == N - 2) {
-    if (!ttm_kc_fused_fits((const float*)p->T, p->dims[N - 1], p->dims[N - 2], p->R)) return false;
+  if (p->prec != CP_F32 || N < 4) return false;
+  op->store = store;
+  if (a == N - 1 && b == N - 2 && ttm_kc_fused_fits((const float*)p->T, p->dims[N - 1], p->dims[N - 2], p->R)) {
     op->kind = 1;
-    op->store = msdt;
     op->P2 = mode_product(p, 0, N - 2);
     op->S = p->dims[N - 2];
     return true;
   }
-  if (msdt && a == 0 && b == N - 1) {
+  if (a == 0 && b == N - 1) {
     const int64_t Q = mode_product(p, 1, N);
-    if (!ttm_qr_fits((const float*)p->T, p->dims[0], Q, p->dims[N - 1], p->R)) return false;
-    op->kind = 3;
-    op->store = true;
-    op->K = p->dims[0];
-    op->Q = Q;
-    op->S = p->dims[N - 1];
-    return true;
+    if (ttm_qr_fits((const float*)p->T, p->dims[0], Q, p->dims[N - 1], p->R)) {
+      op->kind = 3;
+      op->K = p->dims[0];
+      op->Q = Q;
+      op->S = p->dims[N - 1];
+      return true;
+    }
   }
   QgShape sh;
   if (!qg_pair_shape(p, a, b, &sh) || !ttm_qg_fits((const float*)p->T, sh, p->R)) return false;
   op->kind = 2;
-  op->store = msdt;
   op->sh = sh;
   return true;
 }
 
-// Partial-node floats the fused kernels of this plan can need (0: none).
+// A path's first two contractions: the standard tree's halves (the node is
+// not kept), MSDT's subtree roots with their first child (the node is kept).
+bool path_fused_op(cp_plan p, const std::vector<int>& seq, FusedOp* op) {
+  const int N = p->N;
+  if (seq.size() < 3) return false;
+  const int a = seq[0], b = seq[1];
+  if (p->tree == CP_TREE_DT && ((a == N - 1 && b == N - 2) || (a == 0 && b == 1)))
+    return fused_op_for(p, a, b, false, op);
+  if (p->tree == CP_TREE_MSDT && b == (a + N - 1) % N) return fused_op_for(p, a, b, true, op);
+  return false;
+}
+
+// Launch a fused op into `out` (the second-level node), the first-level node
+// into Y when op.store.
+cp_status launch_fused(cp_plan p, const FusedOp& op, int a, int b, void* out, void* Y) {
+  const float* B = (const float*)p->Ash[a];
+  const float* W = (const float*)p->Ash[b];
+  float* Yf = op.store ? (float*)Y : nullptr;
+  if (op.kind == 1) {
+    HIP_TRY(p, launch_ttm_kc_fused((const float*)p->T, B, W, (float*)out, Yf, op.P2, op.S, p->R, p->st));
+  } else if (op.kind == 3) {
+    HIP_TRY(p, launch_ttm_qr((const float*)p->T, B, W, (float*)out, Yf, op.K, op.Q, op.S, p->R, p->st));
+  } else {
+    HIP_TRY(p, launch_ttm_qg((const float*)p->T, B, W, (float*)out, Yf, op.sh, p->R, (float*)p->parts, p->st));
+  }
+  return CP_OK;
+}
+
+// Partial-node floats the fused kernels of this plan can need (0: none):
+// any ordered pair of modes k_ttm_qg takes.
 size_t fused_parts_floats(cp_plan p) {
   size_t need = 0;
   if (p->prec != CP_F32 || p->N < 4) return 0;
-  for (int a = 0; a < p->N; ++a) {
-    QgShape sh;
-    if (!qg_pair_shape(p, a, a == 0 ? 1 : a - 1, &sh) || !ttm_qg_shape(sh, p->R)) continue;
-    const int nz = qg_layers(sh);
-    if (nz > 1) need = std::max(need, (size_t)nz * sh.nP * sh.Q * p->R);
-  }
+  for (int a = 0; a < p->N; ++a)
+    for (int b = 0; b < p->N; ++b) {
+      QgShape sh;
+      if (!qg_pair_shape(p, a, b, &sh) || !ttm_qg_shape(sh, p->R)) continue;
+      const int nz = qg_layers(sh);
+      if (nz > 1) need = std::max(need, (size_t)nz * sh.nP * sh.Q * p->R);
+    }
   return need;
 }
 
@@ -621,17 +651,7 @@ cp_status run_path(cp_plan p, const std::vector<int>& seq, double* M) {
       return fail(p, CP_ERR_STATE, "internal: slot too small");
     ++p->ttm_count;
     ProfScope ps(p, CP_PHASE_TTM);
-    const float* B = (const float*)p->Ash[seq[0]];
-    const float* W = (const float*)p->Ash[seq[1]];
-    float* Y = op.store ? (float*)p->slot_buf[1] : nullptr;
-    if (op.kind == 1) {
-      HIP_TRY(p, launch_ttm_kc_fused((const float*)p->T, B, W, (float*)p->slot_buf[2], Y, op.P2, op.S, p->R, p->st));
-    } else if (op.kind == 3) {
-      HIP_TRY(p, launch_ttm_qr((const float*)p->T, B, W, (float*)p->slot_buf[2], Y, op.K, op.Q, op.S, p->R, p->st));
-    } else {
-      HIP_TRY(p, launch_ttm_qg((const float*)p->T, B, W, (float*)p->slot_buf[2], Y, op.sh, p->R, (float*)p->parts,
-                               p->st));
-    }
+    CP_TRY(launch_fused(p, op, seq[0], seq[1], p->slot_buf[2], p->slot_buf[1]));
     if (op.store) slot_record(p, 1, sets[1]);
     slot_record(p, 2, sets[2]);
     d = 3;
@@ -1006,6 +1026,24 @@ cp_status pp_node(cp_plan p, const std::vector<std::vector<PPNode>>& lv, int l, 
   void* out = is_pair ? p->pair[pair_first(set)][pair_second(set)] : p->slot_buf[l];
   if (l == 1) {
     const int m = lowest_bit(full_set(N) & ~set);
+    if (!is_pair && !slot_valid(p, 1, set) && l + 1 == N - 2) {
+      // a node whose only child is a pair: the pair straight from the
+      // tensor, both contractions in one pass (the node is not formed)
+      std::vector<int> kids;
+      for (int c = 0; c < (int)lv[l].size(); ++c)
+        if (lv[l][c].parent == k) kids.push_back(c);
+      FusedOp op;
+      if (kids.size() == 1) {
+        const uint32_t cs = lv[l][kids[0]].set;
+        const int m2 = lowest_bit(set & ~cs);
+        if (fused_op_for(p, m, m2, false, &op)) {
+          ++p->ttm_count;
+          ProfScope ps(p, CP_PHASE_TTM);
+          CP_TRY(launch_fused(p, op, m, m2, p->pair[pair_first(cs)][pair_second(cs)], nullptr));
+          return CP_OK;
+        }
+      }
+    }
     if (!is_pair && slot_valid(p, 1, set)) {
       // live first-level node of the regular sweep: reused, not recomputed
     } else {

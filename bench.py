@@ -242,17 +242,27 @@ def tree_bench(args):
     numel = int(np.prod(w.dims))
     ttm_flops = 2 * numel * R
     if args.counters_workload:
-        # one launch of each first-level kernel of the step: the standard
-        # tree's fused halves (modes 0 and N-1 of a DT plan), then the
-        # first-level-only kernels that MSDT and PP keep (an MSDT plan's MTTKRP
-        # walks the same path without fusing)
-        for tree in ("dt", "msdt"):
-            plan = cpals.Plan(w.dims, R, prec=prec, tree=tree, device=dev)
-            plan.set_tensor(T)
-            for mode in (0, N - 1):  # the contraction over the last mode first, then over mode 0
-                plan.mttkrp(A0, mode)
-            torch.cuda.synchronize()
-            plan.close()
+        # each first-level kernel of the step: the standard tree's fused
+        # halves (a DT plan's MTTKRPs of modes 0 and N-1), the first-level-only
+        # kernels (rooted MTTKRPs whose second contraction no fused kernel
+        # takes: the last mode then mode 1, mode 0 then mode 2), and MSDT's
+        # fused roots that also store the node (three MSDT sweeps: roots N-1,
+        # the middle modes and 0)
+        plan = cpals.Plan(w.dims, R, prec=prec, tree="dt", device=dev)
+        plan.set_tensor(T)
+        for mode in (0, N - 1):
+            plan.mttkrp(A0, mode)
+        plan.mttkrp(A0, 0, root=N - 1)
+        plan.mttkrp(A0, 1, root=0)
+        torch.cuda.synchronize()
+        plan.close()
+        plan = cpals.Plan(w.dims, R, prec=prec, tree="msdt", device=dev)
+        plan.set_tensor(T)
+        Am = [a.clone() for a in A0]
+        for _ in range(N - 1):
+            plan.als_sweep(Am, info=False)
+        torch.cuda.synchronize()
+        plan.close()
         src = torch.empty(128 * 2**20, dtype=torch.float32, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
         dst.copy_(src)  # calibration: reads and writes exactly 512 MiB each

@@ -45,3 +45,4 @@ from .pp import (  # noqa: F401
     PPState,
     pp_als_step,
 )
+from .quant import e4m3_values, e4m3_round, quantize_columns  # noqa: F401

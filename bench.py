@@ -599,9 +599,10 @@ def precision_bench(args):
     rank-128 N(0,1) factors with column norms spread log-uniformly over
     [1e-2, 1], noise 1e-3 of the norm; the FP32 copy is the FP32 plan's
     input), R = 128.  Times DT and MSDT sweeps for FP32, BF16 and BF16X2
-    plans, reports the first-contraction kernel against the HBM roofline, and
-    states the error of each BF16 path against the FP64 oracle run on the same
-    BF16 values: the oracle's exact fitness of the GPU's own factors after each
+    plans, and for the FP8 tensor with a BF16, split or E4M3 factor (FP8 x FP8
+    products), reports the first-contraction kernel against the HBM roofline,
+    and states the error of each low-precision path against the FP64 oracle
+    run on the same stored values: the oracle's exact fitness of the GPU's own factors after each
     of the first sweeps (resynced), and sampled MTTKRP rows."""
     import numpy as np
     import torch
@@ -621,12 +622,12 @@ def precision_bench(args):
     T32 = torch.from_numpy(w.T).to(dev)
     Tb = torch.from_numpy(bits.view(np.int16)).to(dev).view(torch.bfloat16)
     T8 = torch.from_numpy(bits8).to(dev).view(torch.float8_e4m3fn)
-    tensors = {"f32": T32, "bf16": Tb, "bf16x2": Tb, "fp8": T8, "fp8x2": T8}
+    tensors = {"f32": T32, "bf16": Tb, "bf16x2": Tb, "fp8": T8, "fp8x2": T8, "fp8f8": T8}
     A0 = [torch.from_numpy(a).to(dev) for a in w.init]
     numel = int(np.prod(dims))
     stream = torch.cuda.current_stream(dev)
     res = {}
-    for prec in ("f32", "bf16", "bf16x2", "fp8", "fp8x2"):
+    for prec in ("f32", "bf16", "bf16x2", "fp8", "fp8x2", "fp8f8"):
         T = tensors[prec]
         out = {}
         for tree, nsw in (("dt", 3), ("msdt", 4)):
@@ -666,10 +667,12 @@ def precision_bench(args):
     achieved8 = (numel + out_bytes) / (ttm8_ms * 1e-3) / 1e9
     ttm8s_ms = res["fp8"]["dt"]["ttm_avg_ms"]
     achieved8s = (numel + out_bytes) / (ttm8s_ms * 1e-3) / 1e9
+    ttm88_ms = res["fp8f8"]["dt"]["ttm_avg_ms"]
+    achieved88 = (numel + out_bytes) / (ttm88_ms * 1e-3) / 1e9
     # error against the FP64 oracle on the stored BF16 / FP8 values, resynced per sweep
     log("[bench] oracle checks")
     errs = {}
-    for prec in ("bf16", "bf16x2", "fp8", "fp8x2"):
+    for prec in ("bf16", "bf16x2", "fp8", "fp8x2", "fp8f8"):
         if prec == "bf16":
             T64 = synth.bf16_to_f32(bits).astype(np.float64)
             del bits
@@ -689,7 +692,8 @@ def precision_bench(args):
         ref = X0[rows] @ K
         refabs = np.abs(X0[rows]) @ core.krp([np.abs(w.init[1]), np.abs(w.init[2])])
         del K
-        unit = 2.0 ** -8 if prec in ("bf16", "fp8") else 2.0 ** -16  # the factor's rounding; the tensor is exact
+        # the factor's rounding (the tensor is exact): BF16 2^-8, split 2^-16, E4M3 2^-4
+        unit = {"bf16": 2.0 ** -8, "fp8": 2.0 ** -8, "fp8f8": 2.0 ** -4}.get(prec, 2.0 ** -16)
         rec = {"mttkrp_rows_relerr": float(np.linalg.norm(M - ref) / np.linalg.norm(ref)),
                "mttkrp_rows_err_over_bound": float(np.max(np.abs(M - ref) / (unit * refabs))),
                "sweeps": []}
@@ -725,6 +729,10 @@ def precision_bench(args):
                          "achieved": round(achieved8s, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                          "frac": round(achieved8s / PEAK_HBM_GBS, 4), "traffic": None,
                          "bytes_per_launch": numel + out_bytes, "avg_launch_ms": ttm8s_ms},
+        "roofline_fp8f8": {"kernel": "k_ttm_bf16 (FP8 tensor, E4M3 factor, FP8 x FP8 products, first contraction)",
+                           "bound": "hbm", "achieved": round(achieved88, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                           "frac": round(achieved88 / PEAK_HBM_GBS, 4), "traffic": None,
+                           "bytes_per_launch": numel + out_bytes, "avg_launch_ms": ttm88_ms},
         "roofline_fp8x2": {"kernel": "k_ttm_bf16 (FP8 tensor, split factor, first contraction)", "bound": "hbm",
                            "achieved": round(achieved8, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                            "frac": round(achieved8 / PEAK_HBM_GBS, 4), "traffic": None,

@@ -72,8 +72,17 @@ typedef enum {
  * of the product), so each product carries an error of the order of one FP32
  * rounding; contracting the last mode with rows not 16-byte aligned or K
  * not a multiple of 8, or another mode of a tensor of 4 GiB or more, takes
- * the FP32 matrix cores instead. */
-typedef enum { CP_F64 = 0, CP_F32 = 1, CP_BF16 = 2, CP_BF16X2 = 3, CP_FP8 = 4, CP_FP8X2 = 5, CP_F32X3 = 6 } cp_prec;
+ * the FP32 matrix cores instead.  CP_FP8F8 (not from the paper): the tensor
+ * stored as for CP_FP8, and the first contraction's factor quantized too:
+ * each column scaled by the power of two that puts its largest magnitude in
+ * (224, 448] (exponent clamped to [-120, 120]) and rounded to nearest E4M3
+ * (ties to even), the products of the two E4M3 operands taken on the FP8
+ * matrix cores (exact in FP32) with FP32 accumulation, and the column's
+ * scale removed from the output; the factor then carries about 2^-4 relative
+ * rounding per entry instead of 2^-8 (CP_FP8).  The levels below are FP32. */
+typedef enum {
+  CP_F64 = 0, CP_F32 = 1, CP_BF16 = 2, CP_BF16X2 = 3, CP_FP8 = 4, CP_FP8X2 = 5, CP_F32X3 = 6, CP_FP8F8 = 7
+} cp_prec;
 
 typedef enum {
   CP_TREE_DT = 0,           /* standard binary dimension tree, two first-level TTMs per sweep (Sec. II-C) */

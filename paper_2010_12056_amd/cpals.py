@@ -15,19 +15,20 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcpals.so")
 
 CP_OK, CP_ERR_ARG, CP_ERR_STATE, CP_ERR_UNSUPPORTED, CP_ERR_HIP, CP_ERR_NOT_SPD, CP_ERR_NUMERIC = range(7)
-CP_F64, CP_F32, CP_BF16, CP_BF16X2, CP_FP8, CP_FP8X2, CP_F32X3 = 0, 1, 2, 3, 4, 5, 6
+CP_F64, CP_F32, CP_BF16, CP_BF16X2, CP_FP8, CP_FP8X2, CP_F32X3, CP_FP8F8 = 0, 1, 2, 3, 4, 5, 6, 7
 CP_TREE_DT, CP_TREE_DT_COMBINED, CP_TREE_MSDT = 0, 1, 2
 CP_PP_AUTO, CP_PP_FORCE_EXACT, CP_PP_FORCE_APPROX, CP_PP_FORCE_REINIT, CP_PP_LEARNED = range(5)
 KIND_NAMES = {0: "exact", 1: "init", 2: "approx"}
 PHASES = ["ttm", "mttv", "update", "pp", "other"]
 
 PRECS = {"f64": CP_F64, "f32": CP_F32, "bf16": CP_BF16, "bf16x2": CP_BF16X2, "fp8": CP_FP8, "fp8x2": CP_FP8X2,
-         "f32x3": CP_F32X3}
+         "f32x3": CP_F32X3, "fp8f8": CP_FP8F8}
 TREES = {"dt": CP_TREE_DT, "dt_combined": CP_TREE_DT_COMBINED, "msdt": CP_TREE_MSDT}
 PP_MODES = {"auto": CP_PP_AUTO, "exact": CP_PP_FORCE_EXACT, "approx": CP_PP_FORCE_APPROX,
             "init": CP_PP_FORCE_REINIT, "learned": CP_PP_LEARNED}
 TORCH_DTYPE = {CP_F64: torch.float64, CP_F32: torch.float32, CP_BF16: torch.bfloat16, CP_BF16X2: torch.bfloat16,
-               CP_FP8: torch.float8_e4m3fn, CP_FP8X2: torch.float8_e4m3fn, CP_F32X3: torch.float32}
+               CP_FP8: torch.float8_e4m3fn, CP_FP8X2: torch.float8_e4m3fn, CP_F32X3: torch.float32,
+               CP_FP8F8: torch.float8_e4m3fn}
 
 
 class SweepInfo(ctypes.Structure):
@@ -158,7 +159,7 @@ def mttkrp_static(T, A, mode, rank, prec="f32", out=None):
 class Plan:
     """A CP-ALS plan: tensor dims, rank, precision ("f64" / "f32" / "f32x3" (an
     FP32 tensor, first contraction as three-part BF16 products) / "bf16" /
-    "bf16x2" / "fp8" / "fp8x2", the last two an E4M3 tensor) and tree ("dt" / "dt_combined" / "msdt"), bound to the current
+    "bf16x2" / "fp8" / "fp8x2" / "fp8f8", the last three an E4M3 tensor) and tree ("dt" / "dt_combined" / "msdt"), bound to the current
     HIP stream of `device`."""
 
     def __init__(self, dims, rank, prec="f32", tree="dt", device="cuda"):

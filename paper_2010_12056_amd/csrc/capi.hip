@@ -140,9 +140,9 @@ namespace {
 
 // Low-precision tensors: the first contraction on the BF16 matrix cores with
 // a BF16 factor (split in two parts for the X2 variants); FP32 below.
-bool lowp(cp_prec q) { return q == CP_BF16 || q == CP_BF16X2 || q == CP_FP8 || q == CP_FP8X2; }
+bool lowp(cp_prec q) { return q == CP_BF16 || q == CP_BF16X2 || q == CP_FP8 || q == CP_FP8X2 || q == CP_FP8F8; }
 bool split_factor(cp_prec q) { return q == CP_BF16X2 || q == CP_FP8X2; }
-bool fp8(cp_prec q) { return q == CP_FP8 || q == CP_FP8X2; }
+bool fp8(cp_prec q) { return q == CP_FP8 || q == CP_FP8X2 || q == CP_FP8F8; }
 bool f32_tensor(cp_prec q) { return q == CP_F32 || q == CP_F32X3; }
 
 // The first contraction of a low-precision tensor X (P x K x Q) with the
@@ -399,6 +399,15 @@ void contract_shape(cp_plan p, uint32_t set, int c, int64_t* P, int64_t* I, int6
 }
 
 hipError_t lowp_first_level(cp_plan p, const void* X, const float* A, float* C, int64_t P, int64_t K, int64_t Q) {
+  if (p->prec == CP_FP8F8) {
+    // the E4M3 factor (R x Kp bytes) and its R column scales share the
+    // factor buffer (R x Kp BF16 elements)
+    uint8_t* q8 = (uint8_t*)p->Bt_hi;
+    float* inv = (float*)(q8 + (size_t)p->R * bf16_factor_pitch(K));
+    hipError_t e = launch_quant_factor_fp8(A, K, p->R, q8, inv, p->st);
+    if (e != hipSuccess) return e;
+    return launch_ttm_fp8f8((const uint8_t*)X, q8, inv, C, P, K, Q, p->R, p->st);
+  }
   hipError_t e = launch_split_factor(A, K, p->R, p->Bt_hi, p->Bt_lo, p->st);
   if (e != hipSuccess) return e;
   if (fp8(p->prec)) return launch_ttm_fp8((const uint8_t*)X, p->Bt_hi, p->Bt_lo, C, P, K, Q, p->R, p->st);

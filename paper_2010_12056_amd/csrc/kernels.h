@@ -52,6 +52,14 @@ hipError_t launch_ttm_bf16(const uint16_t* X, const uint16_t* Bhi, const uint16_
 // The same with an FP8 (E4M3) tensor, widened exactly to BF16 in registers.
 hipError_t launch_ttm_fp8(const uint8_t* X, const uint16_t* Bhi, const uint16_t* Blo, float* C, int64_t P,
                           int64_t K, int64_t Q, int R, hipStream_t st);
+// FP8 x FP8 (CP_FP8F8): the factor A (K x R, FP32) quantized per column to
+// E4M3 after a power-of-two scale, Bq[c][k] with pitch bf16_factor_pitch(K)
+// (zero padded) and inv[c] the scale's inverse; then the FP8 tensor's first
+// contraction with it on the FP8 matrix cores, each output column multiplied
+// by inv[c].
+hipError_t launch_quant_factor_fp8(const float* A, int64_t K, int R, uint8_t* Bq, float* inv, hipStream_t st);
+hipError_t launch_ttm_fp8f8(const uint8_t* X, const uint8_t* Bq, const float* inv, float* C, int64_t P, int64_t K,
+                            int64_t Q, int R, hipStream_t st);
 
 // FP32 tensor path on the BF16 matrix cores (CP_F32X3): the factor split
 // into three BF16 parts, Bt[part][c][k] with pitch bf16_factor_pitch(K)

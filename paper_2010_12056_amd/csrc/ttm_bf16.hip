@@ -47,6 +47,15 @@
 //   otherwise (other Q): one 4-byte load (four consecutive q) per index; an
 //      in-register 4 x 4 byte transpose puts each q's four consecutive indices
 //      in one word.
+//
+// FP8 x FP8 (FF): the same FP8 tensor operands, unwidened, against a factor
+// quantized to E4M3 per column on the FP8 matrix cores
+// (v_mfma_f32_16x16x32_fp8_fp8, same lane layout with one byte per index):
+// column c is scaled by the power of two 2^e_c that puts its largest
+// magnitude in (224, 448] and rounded to nearest E4M3 (ties to even,
+// k_quant_factor_fp8); each product of two E4M3 values is exact in FP32, and
+// the output column is multiplied by 2^-e_c (exact).  The factor chunk is
+// staged as bytes (80-byte column pitch).
 #include <type_traits>
 
 #include "kernels.h"
@@ -86,6 +95,47 @@ __global__ __launch_bounds__(256) void k_split_factor(const float* __restrict__ 
   }
 }
 
+// E4M3 code of v (|v| <= 448, finite), rounded to nearest with ties to even:
+// below 2^-6 the subnormal steps of 2^-9; otherwise, with |v| = f 2^E
+// (f in [0.5, 1)), exponent field E + 6 and mantissa rint(16 f) - 8, where a
+// mantissa of 8 carries into the exponent field.
+__device__ inline uint32_t e4m3_code(float v) {
+  const uint32_t sign = v < 0.f ? 0x80u : 0u;
+  const float a = fabsf(v);
+  if (a < 0.015625f) return sign | (uint32_t)rintf(a * 512.f);
+  int E;
+  const float f = frexpf(a, &E);
+  return sign | (uint32_t)(((E + 5) << 3) + (int)rintf(16.f * f));
+}
+
+// Bq[c][k] = E4M3 code of A[k][c] 2^e_c for k < K (zero up to Kp) and
+// inv[c] = 2^-e_c, with e_c the largest exponent that keeps the column's
+// largest magnitude at or below 448 (clamped to [-120, 120]; 0 for a zero
+// column).  One workgroup per column.
+__global__ __launch_bounds__(256) void k_quant_factor_fp8(const float* __restrict__ A, int64_t K, int R, int Kp,
+                                                          uint8_t* __restrict__ Bq, float* __restrict__ inv) {
+  __shared__ float red[256];
+  const int c = blockIdx.x, tid = threadIdx.x;
+  float m = 0.f;
+  for (int64_t k = tid; k < K; k += 256) m = fmaxf(m, fabsf(A[k * R + c]));
+  red[tid] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) red[tid] = fmaxf(red[tid], red[tid + w]);
+    __syncthreads();
+  }
+  const float mx = red[0];
+  int e = 0;
+  if (mx > 0.f) {
+    int E;
+    const float f = frexpf(mx, &E);
+    e = (f <= 0.875f ? 9 : 8) - E;
+    e = e < -120 ? -120 : (e > 120 ? 120 : e);
+  }
+  for (int64_t k = tid; k < Kp; k += 256) Bq[(int64_t)c * Kp + k] = k < K ? (uint8_t)e4m3_code(ldexpf(A[k * R + c], e)) : 0;
+  if (tid == 0) inv[c] = ldexpf(1.f, -e);
+}
+
 __device__ inline bf16x8 as_bf16x8(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
 
 // Lane source of one workgroup tile in the unguarded layout: KC, the four
@@ -118,9 +168,10 @@ constexpr int TPITCH = 528;  // FP8 chunk stage row pitch (bytes): 512 q plus 16
 
 typedef int i32x2 __attribute__((ext_vector_type(2)));
 
-template <bool KC, int NCB, bool SPLIT, bool FAST, bool F8, bool DEEP, bool TR>
+template <bool KC, int NCB, bool SPLIT, bool FAST, bool F8, bool DEEP, bool TR, bool FF>
 __global__ __launch_bounds__(512) void k_ttm_bf16(const void* __restrict__ Xv, const uint16_t* __restrict__ Bhi,
-                                                  const uint16_t* __restrict__ Blo, float* __restrict__ C,
+                                                  const uint16_t* __restrict__ Blo, const float* __restrict__ cs,
+                                                  float* __restrict__ C,
                                                   int64_t P, int64_t K, int64_t Q, int R, int Kp, int64_t tilesQ,
                                                   int64_t ntiles, int vec) {
   using E = typename std::conditional<F8, uint8_t, uint16_t>::type;
@@ -128,7 +179,9 @@ __global__ __launch_bounds__(512) void k_ttm_bf16(const void* __restrict__ Xv, c
   const E* __restrict__ X = (const E*)Xv;
   constexpr int NC = NCB * 16;
   constexpr int NPART = SPLIT ? 2 : 1;
-  constexpr int BITEMS = NPART * NC * (KB / 8);  // 16-byte pieces of one factor chunk
+  constexpr int PIECES = FF ? KB / 16 : KB / 8;  // 16-byte pieces of one column's chunk
+  constexpr int KPB = KB + 16;                   // FF: byte pitch of a staged factor column
+  constexpr int BITEMS = NPART * NC * PIECES;    // 16-byte pieces of one factor chunk
   constexpr int BPER = (BITEMS + kThreads - 1) / kThreads;
   // BF16 q-contiguous unguarded: 32-bit offsets from uniform bases for the
   // tensor and factor loads (the launch checks (K + 80) Q < 2^31 and
@@ -152,10 +205,10 @@ __global__ __launch_bounds__(512) void k_ttm_bf16(const void* __restrict__ Xv, c
   auto b_piece = [&](int q, int& part, int& c, int& j) {
     int idx = tid + kThreads * q;
     if (BITEMS % kThreads != 0) idx = idx < BITEMS ? idx : BITEMS - 1;
-    part = idx / (NC * (KB / 8));
-    const int rem = idx - part * NC * (KB / 8);
-    c = rem / (KB / 8);
-    j = rem - c * (KB / 8);
+    part = idx / (NC * PIECES);
+    const int rem = idx - part * NC * PIECES;
+    c = rem / PIECES;
+    j = rem - c * PIECES;
   };
   auto load_b = [&](int ch, u32x4 (&bv)[BPER]) {
 #pragma unroll
@@ -163,7 +216,9 @@ __global__ __launch_bounds__(512) void k_ttm_bf16(const void* __restrict__ Xv, c
       int part, c, j;
       b_piece(q, part, c, j);
       const int col = c0 + c < R ? c0 + c : R - 1;
-      if constexpr (BUNI) {
+      if constexpr (FF) {
+        bv[q] = *(const u32x4*)((const uint8_t*)Bhi + (int64_t)col * Kp + ch * KB + 16 * j);
+      } else if constexpr (BUNI) {
         const char* base = (const char*)((q * kThreads) / (NC * (KB / 8)) ? Blo : Bhi);
         bv[q] = *(const u32x4*)(base + 2u * ((uint32_t)col * (uint32_t)Kp + (uint32_t)(ch * KB + 8 * j)));
       } else {
@@ -176,7 +231,10 @@ __global__ __launch_bounds__(512) void k_ttm_bf16(const void* __restrict__ Xv, c
     for (int q = 0; q < BPER; ++q) {
       int part, c, j;
       b_piece(q, part, c, j);
-      *(u32x4*)(Bs[buf] + (part * NC + c) * KPITCH + 8 * j) = bv[q];
+      if constexpr (FF)
+        *(u32x4*)((uint8_t*)Bs[buf] + c * KPB + 16 * j) = bv[q];
+      else
+        *(u32x4*)(Bs[buf] + (part * NC + c) * KPITCH + 8 * j) = bv[q];
     }
   };
 
@@ -364,24 +422,26 @@ __global__ __launch_bounds__(512) void k_ttm_bf16(const void* __restrict__ Xv, c
       }
     }
   };
-  // FP8 operands of step s (0 or 1) of the chunk in r.
-  auto operands8 = [&](const u32x4 (&r)[4], int s, bf16x8 (&a)[4]) {
+  // FP8 operand bytes of step s (0 or 1) of the chunk in r: byte j of w[u]
+  // is block u's value at the lane's index j of the step.
+  auto bytes8 = [&](const u32x4 (&r)[4], int s, u32x2 (&w)[4]) {
     if (KC) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const uint32_t w0 = r[u][2 * s], w1 = r[u][2 * s + 1];
-        a[u] = as_bf16x8(u32x4{fp8_pair_bf16<false>(w0), fp8_pair_bf16<true>(w0), fp8_pair_bf16<false>(w1),
-                               fp8_pair_bf16<true>(w1)});
-      }
+      for (int u = 0; u < 4; ++u) w[u] = u32x2{r[u][2 * s], r[u][2 * s + 1]};
       return;
     }
     uint32_t ta[4], tb[4];  // indices 8 s + 0..3 and 8 s + 4..7, one word per q
     byte_transpose4(r[2 * s][0], r[2 * s][1], r[2 * s][2], r[2 * s][3], ta);
     byte_transpose4(r[2 * s + 1][0], r[2 * s + 1][1], r[2 * s + 1][2], r[2 * s + 1][3], tb);
 #pragma unroll
+    for (int u = 0; u < 4; ++u) w[u] = u32x2{ta[u], tb[u]};
+  };
+  // the eight E4M3 values as BF16 operands (exact)
+  auto widen8 = [&](const u32x2 (&w)[4], bf16x8 (&a)[4]) {
+#pragma unroll
     for (int u = 0; u < 4; ++u)
-      a[u] = as_bf16x8(u32x4{fp8_pair_bf16<false>(ta[u]), fp8_pair_bf16<true>(ta[u]), fp8_pair_bf16<false>(tb[u]),
-                             fp8_pair_bf16<true>(tb[u])});
+      a[u] = as_bf16x8(u32x4{fp8_pair_bf16<false>(w[u][0]), fp8_pair_bf16<true>(w[u][0]),
+                             fp8_pair_bf16<false>(w[u][1]), fp8_pair_bf16<true>(w[u][1])});
   };
   // Operands of one step.  Unguarded q-contiguous layout: lanes 2m and 2m + 1
   // loaded the same eight q at k = kb + 4h + j (h = l16 & 1, j < 4); each
@@ -450,15 +510,13 @@ __global__ __launch_bounds__(512) void k_ttm_bf16(const void* __restrict__ Xv, c
   // 16 u .. 16 u + 15; the transposing read gives lane (g, i) indices
   // 32 s + 8 g .. + 7 of q row i when lane t of the group points at index
   // 32 s + 8 g + t / 2, q 16 u + 8 (t % 2).
-  auto operands_tr = [&](int b, int s8, bf16x8 (&a)[4]) {
+  auto bytes_tr = [&](int b, int s8, u32x2 (&w)[4]) {
     if constexpr (TR) {
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int off = b * KB * TPITCH + (32 * s8 + 8 * g + (l16 >> 1)) * TPITCH + wave * 64 + 16 * u + 8 * (l16 & 1);
         const i32x2 v = __builtin_amdgcn_ds_read_tr8_b64_v2i32((__attribute__((address_space(3))) i32x2*)(Ts + off));
-        const uint32_t w0 = (uint32_t)v[0], w1 = (uint32_t)v[1];
-        a[u] = as_bf16x8(u32x4{fp8_pair_bf16<false>(w0), fp8_pair_bf16<true>(w0), fp8_pair_bf16<false>(w1),
-                               fp8_pair_bf16<true>(w1)});
+        w[u] = u32x2{(uint32_t)v[0], (uint32_t)v[1]};
       }
     }
   };
@@ -485,10 +543,35 @@ __global__ __launch_bounds__(512) void k_ttm_bf16(const void* __restrict__ Xv, c
     operands(r, a);
     mfma_step(a, bs, kl + 8 * g);
   };
+  // FF: the step's products with the E4M3 factor staged as bytes
+  auto mfma_step_ff = [&](const u32x2 (&w)[4], const uint16_t* bs, int ko) {
+    if constexpr (FF) {
+      const uint8_t* b8 = (const uint8_t*)bs;
+#pragma unroll
+      for (int cb = 0; cb < NCB; ++cb) {
+        const long bq = *(const long*)(b8 + (cb * 16 + l16) * KPB + ko);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const long aq = (long)(((uint64_t)w[u][1] << 32) | (uint64_t)w[u][0]);
+          acc[u][cb] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(aq, bq, acc[u][cb], 0, 0, 0);
+        }
+      }
+    }
+  };
+  // FP8 tensor operands (bytes w) against the staged factor at chunk offset ko
+  auto step8 = [&](const u32x2 (&w)[4], const uint16_t* bs, int ko) {
+    if constexpr (FF) {
+      mfma_step_ff(w, bs, ko);
+    } else {
+      bf16x8 a[4];
+      widen8(w, a);
+      mfma_step(a, bs, ko);
+    }
+  };
   auto multiply8 = [&](const u32x4 (&r)[4], const uint16_t* bs, int s) {
-    bf16x8 a[4];
-    operands8(r, s, a);
-    mfma_step(a, bs, 16 * g + 8 * s);
+    u32x2 w[4];
+    bytes8(r, s, w);
+    step8(w, bs, 16 * g + 8 * s);
   };
 
   // ---- main loop: the workgroup's waves step through the same (tile, chunk)
@@ -531,9 +614,9 @@ __global__ __launch_bounds__(512) void k_ttm_bf16(const void* __restrict__ Xv, c
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int s8 = 0; s8 < 2; ++s8) {
-          bf16x8 a[4];
-          operands_tr(buf, s8, a);
-          mfma_step(a, Bs[buf], 32 * s8 + 8 * g);
+          u32x2 w[4];
+          bytes_tr(buf, s8, w);
+          step8(w, Bs[buf], 32 * s8 + 8 * g);
         }
         store_b(buf ^ 1, bv);
         store_t(buf ^ 1, tv);
@@ -615,37 +698,40 @@ __global__ __launch_bounds__(512) void k_ttm_bf16(const void* __restrict__ Xv, c
     const E* Xb;
     float* Cb;
     tile_rows(tile, row0, Xb, Cb, nrows);
+    // FF: the column's power-of-two scale removed (exact)
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int cb = 0; cb < NCB; ++cb) {
+      const int c = c0 + cb * 16 + l16;
+      const float sc = FF ? cs[c < R ? c : R - 1] : 1.f;
 #pragma unroll
-      for (int cb = 0; cb < NCB; ++cb)
+      for (int u = 0; u < 4; ++u)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int i = 4 * g + v;
           const int64_t r = (KC || TR) ? row0 + 16 * u + i : row0 + 4 * i + u;
-          const int c = c0 + cb * 16 + l16;
-          if (r < nrows && c < R) Cb[r * R + c] = acc[u][cb][v];
+          if (r < nrows && c < R) Cb[r * R + c] = FF ? acc[u][cb][v] * sc : acc[u][cb][v];
         }
+    }
     cur = nxt;
   }
 }
 
-template <bool KC, int NCB, bool SPLIT, bool FAST, bool F8, bool DEEP = false, bool TR = false>
-hipError_t launch_one(const void* X, const uint16_t* Bhi, const uint16_t* Blo, float* C, int64_t P, int64_t K,
-                      int64_t Q, int R, int Kp, int vec, hipStream_t st) {
+template <bool KC, int NCB, bool SPLIT, bool FAST, bool F8, bool DEEP = false, bool TR = false, bool FF = false>
+hipError_t launch_one(const void* X, const uint16_t* Bhi, const uint16_t* Blo, const float* cs, float* C, int64_t P,
+                      int64_t K, int64_t Q, int R, int Kp, int vec, hipStream_t st) {
   constexpr int NC = NCB * 16;
   const int64_t tilesQ = KC ? 1 : (Q + kTileRows - 1) / kTileRows;
   const int64_t ntiles = KC ? (P + kTileRows - 1) / kTileRows : P * tilesQ;
   const unsigned nx = (unsigned)(ntiles < 256 ? ntiles : 256);  // one resident workgroup per CU
   const unsigned ny = (unsigned)((R + NC - 1) / NC);
-  hipLaunchKernelGGL((k_ttm_bf16<KC, NCB, SPLIT, FAST, F8, DEEP, TR>), dim3(nx, ny), dim3(kThreads), 0, st, X, Bhi, Blo,
-                     C, P, K, Q, R, Kp, tilesQ, ntiles, vec);
+  hipLaunchKernelGGL((k_ttm_bf16<KC, NCB, SPLIT, FAST, F8, DEEP, TR, FF>), dim3(nx, ny), dim3(kThreads), 0, st, X, Bhi,
+                     Blo, cs, C, P, K, Q, R, Kp, tilesQ, ntiles, vec);
   return hipGetLastError();
 }
 
-template <bool KC, bool SPLIT, bool F8>
-hipError_t launch_ncb(const void* X, const uint16_t* Bhi, const uint16_t* Blo, float* C, int64_t P, int64_t K,
-                      int64_t Q, int R, int Kp, hipStream_t st) {
+template <bool KC, bool SPLIT, bool F8, bool FF = false>
+hipError_t launch_ncb(const void* X, const uint16_t* Bhi, const uint16_t* Blo, const float* cs, float* C, int64_t P,
+                      int64_t K, int64_t Q, int R, int Kp, hipStream_t st) {
   const uintptr_t a = (uintptr_t)X;
   int vec;
   bool fast;
@@ -663,20 +749,21 @@ hipError_t launch_ncb(const void* X, const uint16_t* Bhi, const uint16_t* Blo, f
   }
   // FP8 contiguous rows, one factor part, unguarded, at least two chunks:
   // three register sets (0.44 -> 0.34 ms at 1024^3, R = 128; the
-  // q-contiguous layouts, with 16 four-byte loads per chunk, were 7 % slower)
+  // q-contiguous layouts, with 16 four-byte loads per chunk, were 7 % slower;
+  // not with FP8 x FP8 products over 128 columns, which would spill)
   const bool deep = F8 && KC && fast && Kp >= 2 * KB;
   // FP8 q-contiguous with Q a multiple of 16, 16-byte aligned: the chunk staged through LDS
   const bool tr = F8 && !KC && Q % 16 == 0 && a % 16 == 0;
 #define CPALS_BF16_NCB(NCB)                                                                                 \
   do {                                                                                                     \
-    if constexpr (F8 && KC && (!SPLIT || NCB <= 4)) {                                                      \
-      if (deep) return launch_one<KC, NCB, SPLIT, true, F8, true>(X, Bhi, Blo, C, P, K, Q, R, Kp, vec, st); \
+    if constexpr (F8 && KC && (!SPLIT || NCB <= 4) && !(FF && NCB == 8)) {                                 \
+      if (deep) return launch_one<KC, NCB, SPLIT, true, F8, true, false, FF>(X, Bhi, Blo, cs, C, P, K, Q, R, Kp, vec, st); \
     }                                                                                                      \
     if constexpr (F8 && !KC) {                                                                             \
-      if (tr) return launch_one<KC, NCB, SPLIT, true, F8, false, true>(X, Bhi, Blo, C, P, K, Q, R, Kp, vec, st); \
+      if (tr) return launch_one<KC, NCB, SPLIT, true, F8, false, true, FF>(X, Bhi, Blo, cs, C, P, K, Q, R, Kp, vec, st); \
     }                                                                                                      \
-    return fast ? launch_one<KC, NCB, SPLIT, true, F8>(X, Bhi, Blo, C, P, K, Q, R, Kp, vec, st)            \
-                : launch_one<KC, NCB, SPLIT, false, F8>(X, Bhi, Blo, C, P, K, Q, R, Kp, vec, st);          \
+    return fast ? launch_one<KC, NCB, SPLIT, true, F8, false, false, FF>(X, Bhi, Blo, cs, C, P, K, Q, R, Kp, vec, st) \
+                : launch_one<KC, NCB, SPLIT, false, F8, false, false, FF>(X, Bhi, Blo, cs, C, P, K, Q, R, Kp, vec, st); \
   } while (0)
   if (R <= 16) CPALS_BF16_NCB(1);
   if (R <= 32) CPALS_BF16_NCB(2);
@@ -694,11 +781,11 @@ hipError_t launch_lowp(const void* X, const uint16_t* Bhi, const uint16_t* Blo, 
   if (R < 1 || R > kMaxRank || K < 1 || P < 1 || Q < 1) return hipErrorInvalidValue;
   const int Kp = bf16_factor_pitch(K);
   if (Q == 1) {
-    return Blo ? launch_ncb<true, true, F8>(X, Bhi, Blo, C, P, K, Q, R, Kp, st)
-               : launch_ncb<true, false, F8>(X, Bhi, Blo, C, P, K, Q, R, Kp, st);
+    return Blo ? launch_ncb<true, true, F8>(X, Bhi, Blo, nullptr, C, P, K, Q, R, Kp, st)
+               : launch_ncb<true, false, F8>(X, Bhi, Blo, nullptr, C, P, K, Q, R, Kp, st);
   }
-  return Blo ? launch_ncb<false, true, F8>(X, Bhi, Blo, C, P, K, Q, R, Kp, st)
-             : launch_ncb<false, false, F8>(X, Bhi, Blo, C, P, K, Q, R, Kp, st);
+  return Blo ? launch_ncb<false, true, F8>(X, Bhi, Blo, nullptr, C, P, K, Q, R, Kp, st)
+             : launch_ncb<false, false, F8>(X, Bhi, Blo, nullptr, C, P, K, Q, R, Kp, st);
 }
 
 }  // namespace
@@ -721,6 +808,21 @@ hipError_t launch_ttm_bf16(const uint16_t* X, const uint16_t* Bhi, const uint16_
 hipError_t launch_ttm_fp8(const uint8_t* X, const uint16_t* Bhi, const uint16_t* Blo, float* C, int64_t P,
                           int64_t K, int64_t Q, int R, hipStream_t st) {
   return launch_lowp<true>(X, Bhi, Blo, C, P, K, Q, R, st);
+}
+
+hipError_t launch_quant_factor_fp8(const float* A, int64_t K, int R, uint8_t* Bq, float* inv, hipStream_t st) {
+  if (R < 1 || R > kMaxRank || K < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_quant_factor_fp8, dim3(R), dim3(256), 0, st, A, K, R, bf16_factor_pitch(K), Bq, inv);
+  return hipGetLastError();
+}
+
+hipError_t launch_ttm_fp8f8(const uint8_t* X, const uint8_t* Bq, const float* inv, float* C, int64_t P, int64_t K,
+                            int64_t Q, int R, hipStream_t st) {
+  if (R < 1 || R > kMaxRank || K < 1 || P < 1 || Q < 1) return hipErrorInvalidValue;
+  const int Kp = bf16_factor_pitch(K);
+  const uint16_t* B = (const uint16_t*)Bq;
+  return Q == 1 ? launch_ncb<true, false, true, true>(X, B, nullptr, inv, C, P, K, Q, R, Kp, st)
+                : launch_ncb<false, false, true, true>(X, B, nullptr, inv, C, P, K, Q, R, Kp, st);
 }
 
 }  // namespace cpals

@@ -57,7 +57,7 @@ def test_plan_create_argument_checks():
     assert L.cp_plan_create(ctypes.byref(h), 2, dims, 4, cpals.CP_F32, cpals.CP_TREE_DT, None) == cpals.CP_ERR_UNSUPPORTED
     assert L.cp_plan_create(ctypes.byref(h), 4, dims, 0, cpals.CP_F32, cpals.CP_TREE_DT, None) == cpals.CP_ERR_UNSUPPORTED
     assert L.cp_plan_create(ctypes.byref(h), 4, dims, 129, cpals.CP_F32, cpals.CP_TREE_DT, None) == cpals.CP_ERR_UNSUPPORTED
-    assert L.cp_plan_create(ctypes.byref(h), 4, dims, 4, 7, cpals.CP_TREE_DT, None) == cpals.CP_ERR_UNSUPPORTED
+    assert L.cp_plan_create(ctypes.byref(h), 4, dims, 4, 8, cpals.CP_TREE_DT, None) == cpals.CP_ERR_UNSUPPORTED
     bad = (ctypes.c_int64 * 4)(8, 0, 8, 8)
     assert L.cp_plan_create(ctypes.byref(h), 4, bad, 4, cpals.CP_F32, cpals.CP_TREE_DT, None) == cpals.CP_ERR_ARG
     assert L.cp_plan_create(None, 4, dims, 4, cpals.CP_F32, cpals.CP_TREE_DT, None) == cpals.CP_ERR_ARG
@@ -168,13 +168,14 @@ def test_batch_create_layout_and_argument_checks():
 
 def test_low_precision_plans_share_the_factor_staging():
     """BF16 and FP8 tensors use the same BF16 factor staging: equal workspace
-    per factor variant, the split variants one more transposed factor."""
+    per factor variant, the split variants one more transposed factor; the
+    E4M3 factor of FP8 x FP8 fits in the same space."""
     from paper_2010_12056_amd import cpals
 
     L = _lib()
     dims = (ctypes.c_int64 * 3)(96, 80, 72)
     need = {}
-    for prec in (cpals.CP_F32, cpals.CP_BF16, cpals.CP_BF16X2, cpals.CP_FP8, cpals.CP_FP8X2):
+    for prec in (cpals.CP_F32, cpals.CP_BF16, cpals.CP_BF16X2, cpals.CP_FP8, cpals.CP_FP8X2, cpals.CP_FP8F8):
         h = ctypes.c_void_p()
         assert L.cp_plan_create(ctypes.byref(h), 3, dims, 40, prec, cpals.CP_TREE_DT, None) == cpals.CP_OK
         n = ctypes.c_size_t()
@@ -182,6 +183,8 @@ def test_low_precision_plans_share_the_factor_staging():
         need[prec] = n.value
         assert L.cp_plan_destroy(h) == cpals.CP_OK
     assert need[cpals.CP_FP8] == need[cpals.CP_BF16] and need[cpals.CP_FP8X2] == need[cpals.CP_BF16X2]
+    # FP8 x FP8: the E4M3 factor and its column scales fit the BF16 factor's space
+    assert need[cpals.CP_FP8F8] == need[cpals.CP_FP8]
     pitch = (96 + 63) // 64 * 64  # the longest mode, padded to the 64-index chunk
     assert need[cpals.CP_BF16X2] - need[cpals.CP_BF16] >= 40 * pitch * 2 - 256  # regions 256-byte aligned
     assert need[cpals.CP_BF16] > need[cpals.CP_F32]
@@ -192,7 +195,7 @@ def test_low_precision_plans_share_the_factor_staging():
     assert L.cp_plan_workspace_size(h, ctypes.byref(n)) == cpals.CP_OK
     assert n.value - need[cpals.CP_F32] >= 3 * 40 * pitch * 2 - 256
     assert L.cp_plan_destroy(h) == cpals.CP_OK
-    assert L.cp_plan_create(ctypes.byref(h), 3, dims, 40, 7, cpals.CP_TREE_DT, None) == cpals.CP_ERR_UNSUPPORTED
+    assert L.cp_plan_create(ctypes.byref(h), 3, dims, 40, 8, cpals.CP_TREE_DT, None) == cpals.CP_ERR_UNSUPPORTED
 
 
 def test_static_mttkrp_argument_checks():

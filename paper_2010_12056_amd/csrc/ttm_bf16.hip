@@ -53,9 +53,12 @@
 // (v_mfma_f32_16x16x32_fp8_fp8, same lane layout with one byte per index):
 // column c is scaled by the power of two 2^e_c that puts its largest
 // magnitude in (224, 448] and rounded to nearest E4M3 (ties to even,
-// k_quant_factor_fp8); each product of two E4M3 values is exact in FP32, and
-// the output column is multiplied by 2^-e_c (exact).  The factor chunk is
-// staged as bytes (80-byte column pitch).
+// k_quant_factor_fp8); each product of two E4M3 values is exact, but the
+// instruction sums each lane's group of eight products in a fixed-point
+// window under the group's largest (measured on gfx950: a product 2^12 below
+// it kept exactly, one 2^14 below dropped; the groups and the accumulator
+// at FP32 precision).  The output column is multiplied by 2^-e_c (exact).
+// The factor chunk is staged as bytes (80-byte column pitch).
 #include <type_traits>
 
 #include "kernels.h"

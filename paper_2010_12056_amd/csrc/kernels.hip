@@ -624,7 +624,11 @@ __global__ __launch_bounds__(512) void k_ttm_kc32f(const float* __restrict__ X, 
           for (int cb = 0; cb < NCB; ++cb)
             acc[cb] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[st][j], b[cb][j], acc[cb], 0, 0, 0);
       }
-      // register v of the lane is product row 8 (v / 4) + 4 h + v % 4 of the tile
+      // register v of the lane is product row 8 (v / 4) + 4 h + v % 4 of the tile.
+      // The stored node is read back from HBM by the subtree's second child
+      // (it outgrows the caches): non-temporal stores leave no dirty lines to
+      // be written back during that read, which then runs ~12 % faster, for
+      // ~2 % more time here.
       if constexpr (STORE) {
         const int64_t r0 = tile * 32;
         if (c0 + NC <= R) {
@@ -633,7 +637,7 @@ __global__ __launch_bounds__(512) void k_ttm_kc32f(const float* __restrict__ X, 
           for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
             for (int v = 0; v < 16; ++v)
-              *(float*)((char*)(Y + (r0 + 8 * (v >> 2) + (v & 3)) * R + c0 + cb * 32) + so) = acc[cb][v];
+              __builtin_nontemporal_store(acc[cb][v], (float*)((char*)(Y + (r0 + 8 * (v >> 2) + (v & 3)) * R + c0 + cb * 32) + so));
         } else {
 #pragma unroll
           for (int cb = 0; cb < NCB; ++cb)
@@ -1185,6 +1189,7 @@ __global__ __launch_bounds__(512) void k_ttm_qg(const float* __restrict__ X, con
     }
     if constexpr (STORE) {
       // the first-level node, row p' S + i: register v of block u is q = 16 g + 4 v + u of the block
+      // (non-temporal stores, as in k_ttm_kc32f)
       float* Yr = Y + ((pp * sh.S + i) * sh.Q + qb * 64) * R;
       if (c0 + NC <= R) {
         const uint32_t so = ((uint32_t)(16 * g) * (uint32_t)R + (uint32_t)l16) * 4u;
@@ -1194,7 +1199,7 @@ __global__ __launch_bounds__(512) void k_ttm_qg(const float* __restrict__ X, con
           for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
             for (int v = 0; v < 4; ++v)
-              *(float*)((char*)(Yr + (int64_t)(4 * v + u) * R + c0 + cb * 16) + so) = acc[u][cb][v];
+              __builtin_nontemporal_store(acc[u][cb][v], (float*)((char*)(Yr + (int64_t)(4 * v + u) * R + c0 + cb * 16) + so));
       } else {
 #pragma unroll
         for (int u = 0; u < 4; ++u)
@@ -1317,6 +1322,7 @@ __global__ __launch_bounds__(512) void k_ttm_qr(const float* __restrict__ X, con
       }
     }
     if (STORE && own) {
+      // the first-level node (non-temporal stores, as in k_ttm_kc32f)
       float* Yr = Y + tile * 64 * R;
       if (c0 + NC <= R) {
         const uint32_t so = ((uint32_t)(16 * g) * (uint32_t)R + (uint32_t)l16) * 4u;
@@ -1326,7 +1332,7 @@ __global__ __launch_bounds__(512) void k_ttm_qr(const float* __restrict__ X, con
           for (int cb = 0; cb < NCB; ++cb)
 #pragma unroll
             for (int v = 0; v < 4; ++v)
-              *(float*)((char*)(Yr + (int64_t)(4 * v + u) * R + c0 + cb * 16) + so) = acc[u][cb][v];
+              __builtin_nontemporal_store(acc[u][cb][v], (float*)((char*)(Yr + (int64_t)(4 * v + u) * R + c0 + cb * 16) + so));
       } else {
 #pragma unroll
         for (int u = 0; u < 4; ++u)

@@ -513,7 +513,7 @@ int path_combines(cp_plan p, const std::vector<int>& seq) {
 struct FusedOp {
   int kind = 0;
   bool store = false;
-  int64_t P2 = 0, S = 0;  // kinds 1 and 3 (P2: kind 1's output rows)
+  int64_t P2 = 0, S = 0;  // kinds 1 and 3 (P2: kind 1's output rows, kind 3's slices)
   int64_t K = 0, Q = 0;   // kind 3
   QgShape sh{};           // kind 2
 };
@@ -565,11 +565,13 @@ bool fused_op_for(cp_plan p, int a, int b, bool store, FusedOp* op) {
     op->S = p->dims[N - 2];
     return true;
   }
-  if (a == 0 && b == N - 1) {
-    const int64_t Q = mode_product(p, 1, N);
-    if (ttm_qr_fits((const float*)p->T, p->dims[0], Q, p->dims[N - 1], p->R)) {
+  if (b == N - 1 && a < N - 1) {
+    // the modes before a are the slices, the ones after it the q range (the last one contracted second)
+    const int64_t P = mode_product(p, 0, a), Q = mode_product(p, a + 1, N);
+    if (ttm_qr_fits((const float*)p->T, P, p->dims[a], Q, p->dims[N - 1], p->R)) {
       op->kind = 3;
-      op->K = p->dims[0];
+      op->P2 = P;
+      op->K = p->dims[a];
       op->Q = Q;
       op->S = p->dims[N - 1];
       return true;
@@ -603,7 +605,7 @@ cp_status launch_fused(cp_plan p, const FusedOp& op, int a, int b, void* out, vo
   if (op.kind == 1) {
     HIP_TRY(p, launch_ttm_kc_fused((const float*)p->T, B, W, (float*)out, Yf, op.P2, op.S, p->R, p->st));
   } else if (op.kind == 3) {
-    HIP_TRY(p, launch_ttm_qr((const float*)p->T, B, W, (float*)out, Yf, op.K, op.Q, op.S, p->R, p->st));
+    HIP_TRY(p, launch_ttm_qr((const float*)p->T, B, W, (float*)out, Yf, op.P2, op.K, op.Q, op.S, p->R, p->st));
   } else {
     HIP_TRY(p, launch_ttm_qg((const float*)p->T, B, W, (float*)out, Yf, op.sh, p->R, (float*)p->parts, p->st));
   }

@@ -100,13 +100,15 @@ int qg_layers(const QgShape& sh);
 hipError_t launch_ttm_qg(const float* X, const float* B, const float* W, float* C, float* Y, const QgShape& sh, int R,
                          float* parts, hipStream_t st);
 
-// MSDT's root at mode 0 with the subtree's first child (the last mode) in the
-// epilogue (k_ttm_qr): X is K x Q (K a multiple of 32 up to 256), B (K x R);
-// the last mode has size S (64, 128 or 256; Q a multiple of S),
-// W (S x R); C ((Q / S) x R); Y, when non-null, the first-level node (Q x R).
-bool ttm_qr_fits(const float* X, int64_t K, int64_t Q, int64_t S, int R);
-hipError_t launch_ttm_qr(const float* X, const float* B, const float* W, float* C, float* Y, int64_t K, int64_t Q,
-                         int64_t S, int R, hipStream_t st);
+// A first-level contraction with the contraction over the last mode in the
+// epilogue (k_ttm_qr; MSDT's root at mode 0, a PP initialization node whose
+// single pair child contracts the last mode): X is P x K x Q (K a multiple
+// of 32 up to 256), B (K x R); the last mode has size S (64, 128 or 256; Q a
+// multiple of S), W (S x R); C ((P Q / S) x R); Y, when non-null, the
+// first-level node (P Q x R).
+bool ttm_qr_fits(const float* X, int64_t P, int64_t K, int64_t Q, int64_t S, int R);
+hipError_t launch_ttm_qr(const float* X, const float* B, const float* W, float* C, float* Y, int64_t P, int64_t K,
+                         int64_t Q, int64_t S, int R, hipStream_t st);
 
 // Y[p][q][r] = sum_i X[p][i][q][r] * A[i][r]; accumulation in the output type.
 template <typename TI, typename TO>

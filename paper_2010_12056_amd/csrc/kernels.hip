@@ -1232,12 +1232,14 @@ __global__ __launch_bounds__(512) void k_ttm_qg(const float* __restrict__ X, con
       }
 }
 
-// MSDT's root at mode 0: the first level in the k_ttm_q layout (X[k][q],
-// P = 1, whole 64-q tiles, K a multiple of 32 up to 256) with the subtree's
-// first child, the contraction over the last mode (the fastest part of q, of
-// size S = 64 G with G = 1, 2 or 4), in the epilogue:
-//   C[o][r] = sum_i W[i][r] Y[o S + i][r],  Y[q][r] = sum_k X[k][q] B[k][r],
-// and with STORE the first-level node Y too.  The workgroup's eight waves take
+// A first-level contraction over a mode a in the k_ttm_q layout (X[p][k][q],
+// P slices, whole 64-q tiles, K a multiple of 32 up to 256) with the
+// contraction over the last mode (the fastest part of q, of size S = 64 G
+// with G = 1, 2 or 4) in the epilogue:
+//   C[p Q/S + o][r] = sum_i W[i][r] Y[p][o S + i][r],  Y[p][q][r] = sum_k X[p][k][q] B[k][r],
+// and with STORE the first-level node Y too.  MSDT's root at mode 0 (P = 1,
+// the node kept for the subtree's later children) and a PP initialization
+// node whose single pair child contracts the last mode.  The workgroup's eight waves take
 // eight consecutive tiles per step (G waves per output row, wave j of a row
 // its tile j), so the tensor is read as k_ttm_q reads it; lane (g, l16)
 // weights its 16 product rows of the tile (q = 16 g + 4 v + u) by W (staged
@@ -1247,7 +1249,8 @@ __global__ __launch_bounds__(512) void k_ttm_qg(const float* __restrict__ X, con
 template <int NCB, bool STORE>
 __global__ __launch_bounds__(512) void k_ttm_qr(const float* __restrict__ X, const float* __restrict__ B,
                                                 const float* __restrict__ W, float* __restrict__ C,
-                                                float* __restrict__ Y, int64_t K, int64_t Q, int R, int S) {
+                                                float* __restrict__ Y, int64_t P, int64_t K, int64_t Q, int R,
+                                                int S) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
   const int Kp = (int)K;
   const int pitch = Kp + 4, wp = S + 4;
@@ -1273,11 +1276,16 @@ __global__ __launch_bounds__(512) void k_ttm_qr(const float* __restrict__ X, con
   const int G = S / 64;                 // waves (tiles) per output row
   const int RPS = kTtmWaves / G;        // output rows per step
   const int j = wave % G, orow = wave / G;
-  const int64_t nrows = Q / S;
+  const int64_t nrows = P * (Q / S);  // output rows; an output row never straddles two slices
+  const int64_t QT = Q / 64;           // tiles per slice
   const int64_t stride = (int64_t)gridDim.x * RPS;
   const uint32_t lofs = ((uint32_t)g * (uint32_t)Q + 4u * (uint32_t)l16) * 4u;
-  auto load_full = [&](int64_t t, int kc, f32x4 (&a)[8]) {
-    const float* xb = X + t * 64;
+  // tile t: slice t / QT, q = 64 (t % QT) ..; node and output rows follow the tile index
+  auto tile_base = [&](int64_t t) {
+    const int64_t p = t / QT;
+    return X + p * K * Q + (t - p * QT) * 64;
+  };
+  auto load_full = [&](const float* xb, int kc, f32x4 (&a)[8]) {
 #pragma unroll
     for (int s = 0; s < 8; ++s) a[s] = *(const f32x4*)((const char*)(xb + (int64_t)(kc + 4 * s) * Q) + lofs);
   };
@@ -1286,7 +1294,7 @@ __global__ __launch_bounds__(512) void k_ttm_qr(const float* __restrict__ X, con
   f32x4 an[8];
   {
     const int64_t o = o0 + orow < nrows ? o0 + orow : nrows - 1;
-    load_full(o * G + j, 0, an);
+    load_full(tile_base(o * G + j), 0, an);
   }
   for (; o0 < nrows; o0 += stride) {
     asm volatile("" ::: "memory");  // factor reads stay in the loop
@@ -1295,6 +1303,8 @@ __global__ __launch_bounds__(512) void k_ttm_qr(const float* __restrict__ X, con
     const int64_t tile = o * G + j;
     const int64_t on = o0 + stride + orow < nrows ? o0 + stride + orow : (o0 + stride < nrows ? nrows - 1 : o);
     const int64_t tn = on * G + j;
+    const float* xcur = tile_base(tile);
+    const float* xnext = tile_base(tn);
     f32x4 acc[4][NCB];
 #pragma unroll
     for (int u = 0; u < 4; ++u)
@@ -1305,7 +1315,7 @@ __global__ __launch_bounds__(512) void k_ttm_qr(const float* __restrict__ X, con
 #pragma unroll
       for (int st = 0; st < 8; ++st) a[st] = an[st];
       const bool more = kc + 32 < Kp;
-      load_full(more ? tile : tn, more ? kc + 32 : 0, an);
+      load_full(more ? xcur : xnext, more ? kc + 32 : 0, an);
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int cb = 0; cb < NCB; ++cb) {
@@ -2844,33 +2854,33 @@ hipError_t launch_ttm_qg(const float* X, const float* B, const float* W, float* 
 // MSDT's root at mode 0 with its first child in the epilogue (k_ttm_qr):
 // X is K x Q, B (K x R), W (S x R, the last mode), C ((Q / S) x R), Y the
 // first-level node (Q x R) or null.
-bool ttm_qr_fits(const float* X, int64_t K, int64_t Q, int64_t S, int R) {
-  return K % 32 == 0 && K >= 32 && K <= 256 && (S == 64 || S == 128 || S == 256) && Q % S == 0 &&
+bool ttm_qr_fits(const float* X, int64_t P, int64_t K, int64_t Q, int64_t S, int R) {
+  return P >= 1 && K % 32 == 0 && K >= 32 && K <= 256 && (S == 64 || S == 128 || S == 256) && Q % S == 0 &&
          Q < ((int64_t)1 << 28) && R >= 1 && R <= 64 && ((uintptr_t)X % 16) == 0;
 }
 
 template <int NCB, bool STORE>
-hipError_t launch_ttm_qr_ncb(const float* X, const float* B, const float* W, float* C, float* Y, int64_t K, int64_t Q,
-                             int64_t S, int R, hipStream_t st) {
+hipError_t launch_ttm_qr_ncb(const float* X, const float* B, const float* W, float* C, float* Y, int64_t P, int64_t K,
+                             int64_t Q, int64_t S, int R, hipStream_t st) {
   static std::atomic<uint64_t> attr{0};
   const hipError_t e = lds_limit_once(attr, (const void*)k_ttm_qr<NCB, STORE>, 160 * 1024);
   if (e != hipSuccess) return e;
   const size_t lds = (size_t)NCB * 16 * ((K + 4) + (S + 4) + kTtmWaves) * sizeof(float);
   const int64_t rps = kTtmWaves / (S / 64);  // output rows per workgroup step
-  const int64_t want = (Q / S + rps - 1) / rps;
+  const int64_t want = (P * (Q / S) + rps - 1) / rps;
   const unsigned nx = (unsigned)(want < 256 ? want : 256);
   const unsigned ny = (unsigned)((R + NCB * 16 - 1) / (NCB * 16));
-  hipLaunchKernelGGL((k_ttm_qr<NCB, STORE>), dim3(nx, ny), dim3(kTtmThreads), lds, st, X, B, W, C, Y, K, Q, R,
+  hipLaunchKernelGGL((k_ttm_qr<NCB, STORE>), dim3(nx, ny), dim3(kTtmThreads), lds, st, X, B, W, C, Y, P, K, Q, R,
                      (int)S);
   return hipGetLastError();
 }
 
-hipError_t launch_ttm_qr(const float* X, const float* B, const float* W, float* C, float* Y, int64_t K, int64_t Q,
-                         int64_t S, int R, hipStream_t st) {
-  if (!ttm_qr_fits(X, K, Q, S, R)) return hipErrorInvalidValue;
+hipError_t launch_ttm_qr(const float* X, const float* B, const float* W, float* C, float* Y, int64_t P, int64_t K,
+                         int64_t Q, int64_t S, int R, hipStream_t st) {
+  if (!ttm_qr_fits(X, P, K, Q, S, R)) return hipErrorInvalidValue;
 #define CPALS_QR(NCB)                                                             \
-  return Y ? launch_ttm_qr_ncb<NCB, true>(X, B, W, C, Y, K, Q, S, R, st)          \
-           : launch_ttm_qr_ncb<NCB, false>(X, B, W, C, Y, K, Q, S, R, st)
+  return Y ? launch_ttm_qr_ncb<NCB, true>(X, B, W, C, Y, P, K, Q, S, R, st)       \
+           : launch_ttm_qr_ncb<NCB, false>(X, B, W, C, Y, P, K, Q, S, R, st)
   if (R <= 16) CPALS_QR(1);
   if (R <= 32) CPALS_QR(2);
   CPALS_QR(4);

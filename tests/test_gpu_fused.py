@@ -3,7 +3,8 @@ FP64 oracle: the standard tree's halves (each half's first two contractions
 in one pass, the first-level node not stored) and MSDT's subtree roots (the
 subtree's first child formed in the first level's epilogue, the first-level
 node stored for the later child), and the PP initialization's first-level
-node with a single pair child (the pair straight from the tensor).  Leading half: the contraction over the last mode,
+node with a single pair child (the pair straight from the tensor, including
+the contraction over the last mode after a mode with leading slices).  Leading half: the contraction over the last mode,
 of size 128, and the one over the mode before it, a multiple of 32.
 Trailing half: the contraction over mode 0 (a multiple of 32) and over mode
 1, cut into ranges whose partial nodes are added in order.  MTTKRPs of every
@@ -115,28 +116,31 @@ def test_fused_msdt_free_running_trajectory(dev, dims, R, sweeps):
     plan.close()
 
 
-@pytest.mark.parametrize("tree", ["dt", "msdt"])
-def test_fused_pp_init_single_child_resynced(dev, tree):
+@pytest.mark.parametrize("tree,exact", [("dt", 8), ("msdt", 8), ("msdt", 9), ("msdt", 10)])
+def test_fused_pp_init_single_child_resynced(dev, tree, exact):
     """Forced PP schedule re-synced to the GPU's factors before each step
-    (eight regular sweeps, so that the approximated steps are valid at this
-    point of the run; initialization with its approximated sweep, one more
-    approximated sweep, a regular sweep, a second initialization) on a shape
-    where the regular sweeps take the fused forms and the initialization's
-    node with one pair child forms that pair in one pass (under MSDT the live
-    node after the eighth sweep lacks mode 1: modes 2 then 0; under the fused
-    standard tree no node is live: modes 0 then 2), against the oracle's PP
+    (eight to ten regular sweeps, so that the approximated steps are valid at
+    this point of the run; initialization with its approximated sweep, one
+    more approximated sweep, a regular sweep, a second initialization) on a
+    shape where the regular sweeps take the fused forms and the
+    initialization's node with one pair child forms that pair in one pass
+    where a fused kernel takes the mode pair.  Under MSDT the live node
+    lacks mode 1 after eight sweeps (the single child: modes 2 then 0,
+    k_ttm_qg), mode 0 after nine (modes 1 then 3: k_ttm_qr over 32 slices of
+    mode 0) and mode 2 after ten (modes 3 then 1: two passes); under the fused
+    standard tree no node is live (modes 0 then 2).  Against the oracle's PP
     steps: fitness within 1e-6, factors within 1e-4."""
     from oracle import core, pp
     from paper_2010_12056_amd import cpals, synth
 
     dims, R = (32, 32, 64, 128), 40
-    say(f"case fused pp init dims={dims} R={R} {tree}")
+    say(f"case fused pp init dims={dims} R={R} {tree} after {exact} sweeps")
     w = synth.planted_tensor(dims, R, 950 + R, noise_rel=1e-2, dtype=np.float32)
     plan = cpals.Plan(dims, R, prec="f32", tree=tree, device=dev)
     plan.set_tensor(torch.from_numpy(w.T).to(dev))
     A = to_dev(w.init, dev)
     st = pp.PPState.start(w.T.astype(np.float64), w.init)
-    for step, kind in enumerate(["exact"] * 8 + ["init", "approx", "exact", "init"]):
+    for step, kind in enumerate(["exact"] * exact + ["init", "approx", "exact", "init"]):
         st.A = [a.cpu().numpy().copy() for a in A]
         st.S = [core.gram(a) for a in st.A]
         if st.phase == "pp":

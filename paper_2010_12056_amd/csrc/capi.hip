@@ -1045,12 +1045,19 @@ cp_status pp_node(cp_plan p, const std::vector<std::vector<PPNode>>& lv, int l, 
         if (lv[l][c].parent == k) kids.push_back(c);
       FusedOp op;
       if (kids.size() == 1) {
+        // the pair is the tensor contracted with both factors, in either
+        // order: the node's own mode first, else the child's
         const uint32_t cs = lv[l][kids[0]].set;
-        const int m2 = lowest_bit(set & ~cs);
-        if (fused_op_for(p, m, m2, false, &op)) {
+        int a = m, b = lowest_bit(set & ~cs);
+        bool ok = fused_op_for(p, a, b, false, &op);
+        if (!ok) {
+          std::swap(a, b);
+          ok = fused_op_for(p, a, b, false, &op);
+        }
+        if (ok) {
           ++p->ttm_count;
           ProfScope ps(p, CP_PHASE_TTM);
-          CP_TRY(launch_fused(p, op, m, m2, p->pair[pair_first(cs)][pair_second(cs)], nullptr));
+          CP_TRY(launch_fused(p, op, a, b, p->pair[pair_first(cs)][pair_second(cs)], nullptr));
           return CP_OK;
         }
       }

@@ -127,7 +127,8 @@ def test_fused_pp_init_single_child_resynced(dev, tree, exact):
     where a fused kernel takes the mode pair.  Under MSDT the live node
     lacks mode 1 after eight sweeps (the single child: modes 2 then 0,
     k_ttm_qg), mode 0 after nine (modes 1 then 3: k_ttm_qr over 32 slices of
-    mode 0) and mode 2 after ten (modes 3 then 1: two passes); under the fused
+    mode 0) and mode 2 after ten (the pair of modes 3 and 1, taken as 1 then 3
+by the same kernel, since a pair does not depend on the order); under the fused
     standard tree no node is live (modes 0 then 2).  Against the oracle's PP
     steps: fitness within 1e-6, factors within 1e-4."""
     from oracle import core, pp
